@@ -1,0 +1,226 @@
+"""Pins of the CPU oracle against things other than itself.
+
+* brute force: an independent pure-Python tally and exact integer K2
+  (ln of Q = prod (r+1) * C(r, r_1)) on tiny inputs;
+* invariants: per-class table sums, consistency with independently tallied
+  pairwise tables, equivariance under reordering the SNPs;
+* closed forms: single-cell data, single-class data, pure rows;
+* a library routine: log factorials against math.lgamma;
+* a planted signal that must come out on top.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from synth import SplitMix64, make_dataset, make_parity_fixture
+
+
+def tiny(seed, M, N, p_case=0.5):
+    u = SplitMix64(seed, 11).uniform(0, M * N + N)
+    geno = np.minimum((u[: M * N] * 3).astype(np.uint8), 2).reshape(M, N)
+    pheno = (u[M * N:] < p_case).astype(np.uint8)
+    return geno, pheno
+
+
+def _tables_and_k2_vs_brute(lib, seeds=range(40)):
+    """Every table of every triplet equals the brute-force tally, K2 equals ln Q."""
+    for seed in seeds:
+        M = 3 + seed % 6
+        N = 1 + (seed * 7) % 48
+        geno, pheno = tiny(seed, M, N, p_case=(seed % 5) / 4.0)
+        k2, cc = oracle.scan_all(geno, pheno, lib=lib, nthreads=2)
+        for x, snps in enumerate(itertools.combinations(range(M), 3)):
+            t = brute.table(geno.tolist(), pheno.tolist(), snps)
+            assert cc[x].tolist() == t, (seed, snps)
+            want = brute.k2_exact(t)
+            assert abs(k2[x] - want) <= 1e-12 * max(1.0, abs(want)), (seed, snps, k2[x], want)
+
+
+def test_tables_and_k2_match_bruteforce():
+    _tables_and_k2_vs_brute(oracle.load())
+
+
+def test_score_list_and_table_agree_with_scan_all():
+    geno, pheno = tiny(99, 9, 40)
+    k2, cc = oracle.scan_all(geno, pheno)
+    ijk = oracle.lex_triplets(9)
+    cc2, k22 = oracle.score_list(geno, pheno, ijk)
+    assert np.array_equal(cc, cc2)
+    assert np.array_equal(k2, k22)
+    assert np.array_equal(oracle.table(geno, pheno, *ijk[17]), cc[17])
+
+
+def test_table_invariants_against_pairwise_tallies():
+    d = make_dataset(12, 1000, 0.37, 0.05, seed=5)
+    G, ph = d.geno, d.pheno
+    n1 = int(ph.sum())
+    n0 = ph.size - n1
+    k2, cc = oracle.scan_all(G, ph)
+    ijk = oracle.lex_triplets(12)
+
+    def pair(x, y):
+        out = np.zeros((2, 3, 3), dtype=np.int64)
+        for s in range(ph.size):  # plain tally, independent of the oracle's row index
+            out[ph[s], G[x, s], G[y, s]] += 1
+        return out
+
+    pairs = {xy: pair(*xy) for xy in itertools.combinations(range(12), 2)}
+    for x, (i, j, k) in enumerate(ijk):
+        t = cc[x].reshape(2, 3, 3, 3)
+        assert t[0].sum() == n0 and t[1].sum() == n1
+        assert np.array_equal(t.sum(axis=3), pairs[(i, j)])
+        assert np.array_equal(t.sum(axis=2), pairs[(i, k)])
+        assert np.array_equal(t.sum(axis=1), pairs[(j, k)])
+
+
+def test_equivariance_under_snp_reordering():
+    d = make_dataset(10, 300, 0.5, 0.05, seed=8)
+    perm = np.array([7, 2, 9, 0, 4, 1, 8, 3, 6, 5])
+    G2 = d.geno[perm]
+    inv = np.argsort(perm)
+    for (i, j, k) in [(0, 1, 2), (1, 5, 8), (3, 4, 9), (0, 6, 7)]:
+        t = oracle.table(d.geno, d.pheno, i, j, k).reshape(2, 3, 3, 3)
+        pos = sorted([(inv[i], 'i'), (inv[j], 'j'), (inv[k], 'k')])
+        t2 = oracle.table(G2, d.pheno, *[p for p, _ in pos]).reshape(2, 3, 3, 3)
+        back = np.transpose(t2, [0] + [1 + [n for _, n in pos].index(a) for a in 'ijk'])
+        assert np.array_equal(back, t)
+        L = oracle.log_factorial(301)
+        a = oracle.k2(t, L)
+        b = oracle.k2(t2, L)
+        assert abs(a - b) <= 1e-12 * a
+
+
+def test_log_factorial_against_lgamma():
+    L = oracle.log_factorial(70000)
+    n = np.arange(L.size)
+    ref = np.array([math.lgamma(v + 1.0) for v in n])
+    assert L[0] == 0.0 and L[1] == 0.0
+    assert np.all(np.abs(L - ref) <= 1e-11 * np.maximum(ref, 1.0))
+
+
+@pytest.mark.parametrize("N,n1", [(1, 0), (1, 1), (64, 0), (64, 64), (1000, 413), (16384, 8192)])
+def test_single_cell_closed_form(N, n1):
+    """All samples in one row: K2 = ln((N+1)! / (N0! N1!)); the other 26 rows add ln 1 = 0."""
+    G = np.zeros((3, N), dtype=np.uint8)
+    G[1] = 2  # any constant genotypes keep every sample in one row
+    ph = np.zeros(N, dtype=np.uint8)
+    ph[:n1] = 1
+    _, k2, cc = oracle.scan_topk(G, ph, 1)
+    want = math.lgamma(N + 2) - math.lgamma(N - n1 + 1) - math.lgamma(n1 + 1)
+    assert abs(k2[0] - want) <= 1e-12 * max(1.0, want)
+    assert cc[0].reshape(2, 27)[:, 9 * 0 + 3 * 2 + 0].tolist() == [N - n1, n1]
+
+
+def test_single_class_and_pure_rows_closed_form():
+    """If every row holds one class only, each row contributes ln(r + 1)."""
+    d = make_dataset(6, 500, 0.5, 0.05, seed=3)
+    for ph in (np.zeros(500, np.uint8), np.ones(500, np.uint8)):
+        k2, cc = oracle.scan_all(d.geno, ph)
+        r = cc.sum(axis=1)
+        want = np.log(r + 1.0).sum(axis=1)
+        assert np.allclose(k2, want, rtol=1e-13, atol=0)
+    # pure rows: phenotype is a function of the genotype row of (0, 1, 2)
+    row = 9 * d.geno[0].astype(int) + 3 * d.geno[1] + d.geno[2]
+    ph = (row % 2).astype(np.uint8)
+    t = oracle.table(d.geno, ph, 0, 1, 2)
+    assert np.all((t[0] == 0) | (t[1] == 0))
+    assert abs(oracle.k2(t, oracle.log_factorial(501)) - np.log(t.sum(axis=0) + 1.0).sum()) < 1e-10
+
+
+def test_topk_matches_exact_integer_order():
+    for seed in range(12):
+        M, N = 8 + seed % 3, 24 + seed
+        geno, pheno = tiny(1000 + seed, M, N)
+        kk = 15
+        ijk, k2, cc = oracle.scan_topk(geno, pheno, kk, nthreads=3)
+        full = brute.scan(geno.tolist(), pheno.tolist())
+        full.sort(key=lambda r: (r[0], r[1]))
+        ref = full[:kk]
+        # the K2 order is the exact Q order (equal Q: equal up to rounding)
+        got_q = [brute.q_value(c.tolist()) for c in cc]
+        assert got_q == [q for q, _, _ in ref]
+        for x in range(len(ref)):
+            assert cc[x].tolist() == brute.table(geno.tolist(), pheno.tolist(), tuple(ijk[x]))
+        # where a Q value is unique over all combinations the index must agree
+        allq = [r[0] for r in full]
+        for x in range(len(ref)):
+            if allq.count(ref[x][0]) == 1:
+                assert tuple(ijk[x]) == ref[x][1]
+
+
+def test_topk_edge_sizes():
+    geno, pheno = tiny(4, 5, 20)
+    ijk, k2, _ = oracle.scan_topk(geno, pheno, 100)
+    assert len(ijk) == 10  # C(5,3): k larger than the number of combinations
+    ijk, _, _ = oracle.scan_topk(geno[:2], pheno, 5)
+    assert len(ijk) == 0   # fewer than three SNPs
+    ijk, _, _ = oracle.scan_topk(geno, pheno, 0)
+    assert len(ijk) == 0
+
+
+def test_ties_broken_by_index():
+    """Identical SNP rows give identical tables: equal K2 sorted by (i, j, k)."""
+    base, pheno = tiny(21, 1, 50)
+    G = np.repeat(base, 6, axis=0)
+    ijk, k2, _ = oracle.scan_topk(G, pheno, 20)
+    assert np.all(k2 == k2[0])
+    assert [tuple(x) for x in ijk] == list(itertools.combinations(range(6), 3))
+
+
+@pytest.mark.parametrize("seed", range(1, 7))
+def test_planted_triplet_recovered(seed):
+    d = make_parity_fixture(seed)
+    ijk, k2, _ = oracle.scan_topk(d.geno, d.pheno, 2)
+    assert tuple(ijk[0]) == tuple(d.planted)
+    assert k2[1] - k2[0] > 20.0
+
+
+# ---- the pins above must catch plausible mistakes planted in the oracle ----
+
+MUTANTS = {
+    "transposed_digits": ("9 * gi[s] + 3 * gj[s] + gk[s]", "9 * gi[s] + gj[s] + 3 * gk[s]"),
+    "dropped_plus_one": ("L[r0 + r1 + 1] - (L[r0] + L[r1])", "L[r0 + r1] - (L[r0] + L[r1])"),
+    "sign_error": ("L[r0 + r1 + 1] - (L[r0] + L[r1])", "L[r0 + r1 + 1] - L[r0] + L[r1]"),
+    "class_swap": ("t[ph[s] * ROWS +", "t[(1 - ph[s]) * ROWS +"),
+    "log_index": ("L[n - 1] + log((double)n)", "L[n - 1] + log((double)n + 1.0)"),
+    "row_digit_k": ("t[row[s] + gk[s]] += 1;", "t[row[s] + (gk[s] ? 1 : 0)] += 1;"),
+    "guard_j": ("for (int32_t j = i + 1; j < M - 1; ++j) {", "for (int32_t j = i; j < M - 1; ++j) {"),
+}
+
+
+def _pin_suite(lib) -> None:
+    _tables_and_k2_vs_brute(lib, seeds=range(12))
+    for seed in range(6):
+        M, N = 8, 30
+        geno, pheno = tiny(500 + seed, M, N)
+        ijk, k2, cc = oracle.scan_topk(geno, pheno, 10, lib=lib, nthreads=2)
+        ref = brute.topk(geno.tolist(), pheno.tolist(), 10)
+        assert [brute.q_value(c.tolist()) for c in cc] == [r[0] for r in ref]
+        for x in range(len(ref)):
+            assert cc[x].tolist() == brute.table(geno.tolist(), pheno.tolist(), tuple(ijk[x]))
+    L = oracle.log_factorial(5000, lib=lib)
+    assert abs(L[4000] - math.lgamma(4001.0)) < 1e-8
+
+
+def test_pin_suite_passes_on_oracle():
+    _pin_suite(oracle.load())
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    src = open(os.path.join(os.path.dirname(oracle.__file__), "epi3_oracle.c")).read()
+    a, b = MUTANTS[name]
+    assert src.count(a) >= 1, name
+    mut = src.replace(a, b)
+    p = tmp_path / "mut.c"
+    p.write_text(mut)
+    from oracle.build import build_oracle
+    lib_path = build_oracle(str(p), str(tmp_path / f"lib_{name}.so"))
+    lib = oracle.load(lib_path)
+    with pytest.raises(AssertionError):
+        _pin_suite(lib)
