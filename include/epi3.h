@@ -1,0 +1,216 @@
+/*
+ * epi3 -- exhaustive three-way epistasis scan (K2 score) on AMD MI355X (gfx950).
+ *
+ * C ABI of libepi3.so.  The library implements the hot path of
+ * Marques et al., "Three-way Gene Interaction Study on modern CPUs and GPUs"
+ * (arXiv 2201.10956):
+ *
+ *   data set D            Problem Formulation section: M SNPs x N samples,
+ *                         genotype 0/1/2 per (SNP, sample), phenotype 0
+ *                         (control) / 1 (case) per sample;
+ *   frequency table       same section: 27 genotype rows x 2 classes per SNP
+ *                         triplet, filled by AND + POPCNT over per-genotype
+ *                         sample bit-planes (binarized format, Fig. 1 text);
+ *   K2 score              Eq. 1 (natural log, J = 2 classes, I = 27 rows);
+ *   solution              the triplet with the lowest K2; generalised here to
+ *                         the k lowest under the total order (K2, i, j, k).
+ *
+ * Conventions shared by every call:
+ *   - Indices are 0-based; a triplet is (i, j, k) with i < j < k < M.
+ *   - Table row of genotype combination (g_i, g_j, g_k) is 9 g_i + 3 g_j + g_k;
+ *     column 0 counts controls, column 1 counts cases.
+ *   - Every `*_dev` pointer and every buffer named "device" is device memory
+ *     owned by the caller; the library never allocates, frees or retains it
+ *     beyond the call (except the cached graphs noted at epi3_scan_batched).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *     their GPU work on it.  Calls that return host results (epi3_topk,
+ *     epi3_scan_batched) and epi3_encode synchronise that stream before
+ *     returning; the others are asynchronous.
+ *   - Return value: EPI3_OK or a negative EPI3_E_* code; no exception crosses
+ *     the ABI.  Data errors detected on the device (a genotype byte outside
+ *     {0,1,2}) are reported by the next call that returns host results.
+ *   - Calls on distinct streams with distinct workspaces may run concurrently.
+ *
+ * K2 is screened in FP32 from a table of log factorials and the returned
+ * order is decided by an FP64 re-score of every candidate that the FP32
+ * error bound cannot exclude, so the hits equal the exact-order top-k of an
+ * FP64 evaluation of Eq. 1; table counts are exact integers.
+ */
+#ifndef EPI3_H
+#define EPI3_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    EPI3_OK = 0,
+    EPI3_E_INVALID = -1,    /* null pointer, negative size, k <= 0, bad layout, mixed batch */
+    EPI3_E_GENOTYPE = -2,   /* a genotype byte outside {0,1,2} (device-detected) */
+    EPI3_E_PHENOTYPE = -3,  /* a phenotype byte outside {0,1} */
+    EPI3_E_WORKSPACE = -4,  /* buffer smaller than the matching *_bytes() query */
+    EPI3_E_CAPACITY = -5,   /* more FP32-screen candidates than the workspace holds */
+    EPI3_E_HIP = -6,        /* a HIP runtime call failed */
+    EPI3_E_UNSUPPORTED = -7 /* variant not available for this layout */
+};
+
+/* Plane layouts produced by epi3_encode. */
+enum {
+    /* Samples split by class (paper, CPU approaches section: controls array
+     * and cases array per SNP; plane 2 is never stored because it is implied
+     * by planes 0 and 1). */
+    EPI3_LAYOUT_SPLIT = 0,
+    /* All samples in one set of planes; the class of each sample comes from a
+     * case mask supplied per job (used for phenotype permutations). */
+    EPI3_LAYOUT_MASKED = 1
+};
+
+/* Count-stage kernels. */
+enum {
+    EPI3_VARIANT_AUTO = 0,  /* library choice (MFMA where available) */
+    EPI3_VARIANT_VALU = 1,  /* AND + v_bcnt popcount on the vector ALU */
+    EPI3_VARIANT_MFMA = 2   /* 0/1 byte matrices on int8 matrix cores */
+};
+
+/* An encoded data set.  Plain data; every pointer points into the caller's
+ * buffer passed to epi3_encode.  Filled by epi3_encode, read by the scans. */
+typedef struct {
+    int32_t n_snps;       /* M */
+    int32_t n_samples;    /* N */
+    int32_t n_cases;      /* N1 */
+    int32_t n_controls;   /* N0 */
+    int32_t words[2];     /* 32-sample words of controls, cases (MASKED: all samples in both) */
+    int32_t layout;       /* EPI3_LAYOUT_* */
+    int32_t snp_stride;   /* padded SNP count of the plane arrays */
+    int32_t byte_stride;  /* padded sample count of the byte planes (MASKED), else 0 */
+    int32_t reserved;
+    void *planes;         /* device: bit planes  [word][snp_stride][2] uint32 */
+    void *bytes;          /* device: byte planes [snp_stride][2][byte_stride] (MASKED), else NULL */
+    int32_t *pairs;       /* device: pairwise tables [class][snp_stride][snp_stride][4] */
+    double *lf64;         /* device: log factorials L[0..N+1] in FP64 */
+    float *lf32;          /* device: the same rounded to FP32 */
+    int32_t *status;      /* device: status word (bit 0: bad genotype byte) */
+} epi3_dataset;
+
+/* One hit of the top-k.  counts[c][9 g_i + 3 g_j + g_k], c = 0 controls, 1 cases. */
+typedef struct {
+    uint32_t i, j, k;
+    float k2_f32;         /* FP32 screen value computed by the scan */
+    double k2;            /* FP64 value of Eq. 1 (rows summed in row order) */
+    uint32_t counts[2][27];
+} epi3_hit;
+
+/* One job of a batched scan: a data set, optionally with its own case mask. */
+typedef struct {
+    const epi3_dataset *d;
+    const uint32_t *case_mask; /* device, MASKED only: bit s of word s/32 = 1 if sample s is a case */
+    int32_t k;                 /* hits wanted for this job */
+    int32_t reserved;
+} epi3_job;
+
+/* ---------------------------------------------------------------------------
+ * Encoding (binarized format: Problem Formulation section and Fig. 1 text;
+ * reduced format: CPU approaches section -- plane 2 implied by planes 0 and 1,
+ * samples split into controls and cases; 32-bit words: start of the
+ * Approaches section; SNP-minor order so that lanes owning consecutive SNPs
+ * read consecutive words: GPU approaches section).
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of device buffer epi3_encode needs.  Returns < 0 on bad arguments. */
+int64_t epi3_encode_bytes(int32_t n_snps, int32_t n_cases, int32_t n_controls, int32_t layout);
+
+/*
+ * Encode a genotype matrix.
+ *   geno_dev   device uint8 [n_snps][ld], row = SNP, values {0,1,2}; ld >= n_samples.
+ *   pheno_host host uint8 [n_samples], values {0,1}; read before return.
+ *   buf_dev    device buffer of at least epi3_encode_bytes(...) bytes, 256-byte aligned;
+ *              holds planes, pairwise tables, log-factorial tables and the status word,
+ *              and must outlive every use of *out.
+ *   out        host struct filled on success.
+ * Also computes the pairwise tables the scans need (pairs of SNPs, per class).
+ * Synchronises `stream`.  Genotype errors are flagged in out->status and returned
+ * by the next epi3_topk / epi3_scan_batched.
+ */
+int epi3_encode(const uint8_t *geno_dev, int64_t ld, const uint8_t *pheno_host,
+                int32_t n_snps, int32_t n_samples, int32_t layout,
+                void *buf_dev, int64_t buf_bytes, void *stream, epi3_dataset *out);
+
+/* ---------------------------------------------------------------------------
+ * Plain scan (one data set, SPLIT layout): every triplet's table and K2
+ * (Alg. 2 semantics: all i < j < k, private table per triplet, score after all
+ * samples), then the k lowest.
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes for epi3_scan + epi3_topk.  cand_cap <= 0 picks a default
+ * capacity for FP32-screen candidates. */
+int64_t epi3_workspace_bytes(const epi3_dataset *d, int32_t k, int64_t cand_cap);
+
+/* Count + score every triplet and select candidates; asynchronous.
+ * variant: EPI3_VARIANT_*.  ws_dev: device workspace (256-byte aligned). */
+int epi3_scan(const epi3_dataset *d, int32_t k, int32_t variant, int64_t cand_cap,
+              void *ws_dev, int64_t ws_bytes, void *stream);
+
+/* Re-score candidates in FP64, order them and copy min(k, C(M,3)) hits to
+ * hits_host [k]; *n_out receives the count.  Synchronises `stream`.
+ * EPI3_E_CAPACITY: *n_out receives the candidate count needed; retry with
+ * cand_cap >= that value. */
+int epi3_topk(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
+              epi3_hit *hits_host, int32_t *n_out, void *stream);
+
+/* Device address of the FP32 score plane inside a plain-scan workspace:
+ * K2_fp32 of every triplet in lexicographic (i, j, k) order, C(M,3) floats,
+ * valid once the stream has run epi3_scan (and until the workspace is reused). */
+int epi3_score_plane(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
+                     float **plane_dev);
+
+/* ---------------------------------------------------------------------------
+ * Batched scans in one persistent launch, captured into a HIP graph that is
+ * cached per job signature (released by epi3_release).  Not in the paper,
+ * which scans one data set per run.
+ *   - SPLIT jobs: independent data sets of any shape (own phenotype).
+ *   - MASKED jobs: all jobs share one data set; each job's case_mask is one
+ *     phenotype (e.g. a permutation).
+ * hits_host holds sum_j k_j hits, job after job; n_out_host [n_jobs].
+ * ------------------------------------------------------------------------ */
+
+int64_t epi3_batched_workspace_bytes(const epi3_job *jobs, int32_t n_jobs, int64_t cand_cap);
+
+int epi3_scan_batched(const epi3_job *jobs, int32_t n_jobs, int32_t variant, int64_t cand_cap,
+                      void *ws_dev, int64_t ws_bytes, epi3_hit *hits_host,
+                      int32_t *n_out_host, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Test hooks.
+ * ------------------------------------------------------------------------ */
+
+/* Run the count kernel of `variant` over every triplet of a SPLIT data set and
+ * write each triplet's table and FP32 K2 in lexicographic (i, j, k) order:
+ * counts_dev [C(M,3)][2][27] uint32 (may be NULL), k2_dev [C(M,3)] float.
+ * ws_dev: a workspace of epi3_workspace_bytes(d, 1, 0) bytes.  Asynchronous. */
+int epi3_scan_tables(const epi3_dataset *d, int32_t variant, uint32_t *counts_dev,
+                     float *k2_dev, void *ws_dev, int64_t ws_bytes, void *stream);
+
+/* Tables and K2 of explicit triplets: ijk_dev [n][3] uint32 (i < j < k),
+ * counts_dev [n][2][27] (may be NULL), k2_f32_dev [n], k2_dev [n] (FP64).
+ * Asynchronous. */
+int epi3_score_triplets(const epi3_dataset *d, const uint32_t *ijk_dev, int64_t n,
+                        uint32_t *counts_dev, float *k2_f32_dev, double *k2_dev, void *stream);
+
+/* Upper bound e(N) on |K2_fp32 - K2_fp64| used by the candidate screen. */
+double epi3_k2_error_bound(int32_t n_samples);
+
+/* Number of triplets C(M,3). */
+int64_t epi3_n_triplets(int32_t n_snps);
+
+/* Release cached graphs. */
+void epi3_release(void);
+
+/* Library version string. */
+const char *epi3_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EPI3_H */

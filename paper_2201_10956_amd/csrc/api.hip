@@ -1,0 +1,400 @@
+// C ABI of libepi3 (declared in include/epi3.h): argument checks, buffer
+// carving and kernel sequencing.  All arithmetic of the scan runs in the
+// kernels; the host computes sizes, the class split of the samples and the
+// log-factorial tables.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "epi3_internal.h"
+
+using namespace epi3;
+
+namespace {
+
+constexpr int64_t kAlign = 256;
+
+struct Carver {
+  char *base;
+  int64_t off = 0;
+  explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+  template <typename T>
+  T *take(int64_t n) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += n * (int64_t)sizeof(T);
+    return p;
+  }
+  int64_t size() const { return (off + kAlign - 1) / kAlign * kAlign; }
+};
+
+int32_t snp_stride(int32_t M) { return (M + kSnpPad - 1) / kSnpPad * kSnpPad + kSnpPad; }
+int32_t words_of(int64_t n) { return (int32_t)((n + 31) / 32); }
+int32_t byte_stride(int32_t N) { return (N + 255) / 256 * 256; }
+
+struct EncodeLayout {
+  int32_t Mp, W0, W1, Wtot, classes, S;
+  uint32_t *planes;
+  uint8_t *bytes;
+  int32_t *pairs;
+  double *lf64;
+  float *lf32;
+  int32_t *list;
+  int32_t *status;
+  int64_t total;
+};
+
+EncodeLayout encode_layout(void *buf, int32_t M, int32_t n1, int32_t n0, int32_t layout) {
+  EncodeLayout L{};
+  const int32_t N = n0 + n1;
+  L.Mp = snp_stride(M);
+  if (layout == EPI3_LAYOUT_SPLIT) {
+    L.W0 = words_of(n0);
+    L.W1 = words_of(n1);
+    L.Wtot = L.W0 + L.W1;
+    L.classes = 2;
+    L.S = 0;
+  } else {
+    L.W0 = L.W1 = words_of(N);
+    L.Wtot = L.W0;
+    L.classes = 1;
+    L.S = byte_stride(N);
+  }
+  Carver c(buf);
+  L.status = c.take<int32_t>(64);
+  L.planes = c.take<uint32_t>((int64_t)L.Wtot * L.Mp * 2);
+  L.bytes = c.take<uint8_t>((int64_t)L.Mp * 2 * L.S);
+  L.pairs = c.take<int32_t>((int64_t)L.classes * L.Mp * L.Mp * 4);
+  L.lf64 = c.take<double>((int64_t)N + 2);
+  L.lf32 = c.take<float>((int64_t)N + 2);
+  L.list = c.take<int32_t>((int64_t)L.Wtot * 32);
+  L.total = c.size();
+  return L;
+}
+
+// Log factorials L[n] = sum_{b=1}^{n} log b, summed in increasing b (the
+// inner sums of Eq. 1), n = 0..nmax.
+void host_log_factorials(int64_t nmax, std::vector<double> &L64, std::vector<float> &L32) {
+  L64.assign(nmax + 1, 0.0);
+  L32.assign(nmax + 1, 0.f);
+  double acc = 0.0;
+  for (int64_t n = 1; n <= nmax; ++n) {
+    acc = acc + log((double)n);
+    L64[n] = acc;
+  }
+  for (int64_t n = 0; n <= nmax; ++n) L32[n] = (float)L64[n];
+}
+
+double log_factorial_at(int64_t n) {
+  double acc = 0.0;
+  for (int64_t b = 1; b <= n; ++b) acc = acc + log((double)b);
+  return acc;
+}
+
+// Workspace of one plain scan.
+struct ScanLayout {
+  Job *job;
+  int64_t *jprefix;
+  unsigned long long *queue;
+  SelJob *sel;
+  SelState *st;
+  uint32_t *hist;
+  float *score;
+  int64_t *cand;
+  CandRec *rec;
+  epi3_hit *hits;
+  int64_t cap;
+  int64_t total;
+};
+
+int64_t default_cap(int64_t T, int32_t k, int64_t cand_cap) {
+  int64_t cap = cand_cap > 0 ? cand_cap : std::max<int64_t>(4096, 4 * (int64_t)k);
+  if (T > 0 && cap > T) cap = T;
+  return std::max<int64_t>(cap, 1);
+}
+
+ScanLayout scan_layout(void *ws, const epi3_dataset &d, int32_t k, int64_t cand_cap) {
+  ScanLayout L{};
+  const int64_t T = epi3_n_triplets(d.n_snps);
+  L.cap = default_cap(T, k, cand_cap);
+  Carver c(ws);
+  L.job = c.take<Job>(1);
+  L.jprefix = c.take<int64_t>((int64_t)d.n_snps + 1);
+  L.queue = c.take<unsigned long long>(4);
+  L.sel = c.take<SelJob>(1);
+  L.st = c.take<SelState>(1);
+  L.hist = c.take<uint32_t>(kHistBins);
+  L.score = c.take<float>(T);
+  L.cand = c.take<int64_t>(L.cap);
+  L.rec = c.take<CandRec>(L.cap);
+  L.hits = c.take<epi3_hit>(std::max<int32_t>(k, 1));
+  L.total = c.size();
+  return L;
+}
+
+bool valid_dataset(const epi3_dataset *d) {
+  return d && d->n_snps >= 0 && d->n_samples > 0 && d->planes && d->pairs && d->lf64 && d->lf32 &&
+         d->status && (d->layout == EPI3_LAYOUT_SPLIT || d->layout == EPI3_LAYOUT_MASKED);
+}
+
+#define HIP_OK(expr)                        \
+  do {                                      \
+    if ((expr) != hipSuccess) return EPI3_E_HIP; \
+  } while (0)
+
+Job make_job(const epi3_dataset &d, float *score, uint32_t *counts, int64_t *jprefix,
+             uint32_t *keyrange, int P) {
+  Job J{};
+  J.planes = static_cast<const uint32_t *>(d.planes);
+  J.pairs = d.pairs;
+  J.score = score;
+  J.jprefix = jprefix;
+  J.counts = counts;
+  J.keyrange = keyrange;
+  J.tile_begin = 0;
+  J.n_tiles = host_tiles(d.n_snps, P);
+  J.T = epi3_n_triplets(d.n_snps);
+  J.M = d.n_snps;
+  J.Mp = d.snp_stride;
+  J.W0 = d.words[0];
+  J.W1 = d.words[1];
+  J.N0 = d.n_controls;
+  J.N1 = d.n_cases;
+  return J;
+}
+
+SelJob make_seljob(const epi3_dataset &d, const float *score, int64_t T, SelState *st,
+                   uint32_t *hist, int64_t *cand, CandRec *rec, epi3_hit *hits, int64_t cap,
+                   int32_t k) {
+  SelJob S{};
+  S.score = score;
+  S.T = T;
+  S.st = st;
+  S.hist = hist;
+  S.cand = cand;
+  S.rec = rec;
+  S.hits = hits;
+  S.cap = cap;
+  S.err2 = 2.0 * epi3_k2_error_bound(d.n_samples);
+  S.planes = static_cast<const uint32_t *>(d.planes);
+  S.pairs = d.pairs;
+  S.case_pairs = nullptr;
+  S.case_mask = nullptr;
+  S.lf64 = d.lf64;
+  S.M = d.n_snps;
+  S.Mp = d.snp_stride;
+  S.W0 = d.words[0];
+  S.W1 = d.words[1];
+  S.N0 = d.n_controls;
+  S.N1 = d.n_cases;
+  S.layout = d.layout;
+  S.k = k;
+  return S;
+}
+
+int pick_P(const epi3_dataset &d) { return tile_P_default(d.n_snps, d.n_samples); }
+
+}  // namespace
+
+extern "C" {
+
+const char *epi3_version(void) { return "epi3 0.1 (gfx950)"; }
+
+int64_t epi3_n_triplets(int32_t n_snps) { return c3(n_snps); }
+
+double epi3_k2_error_bound(int32_t n_samples) {
+  // Per row the FP32 evaluation of L[r+1] - (L[r0] + L[r1]) with table entries
+  // rounded to FP32 errs by at most 4u L[r+1] (u = 2^-24; L is superadditive so
+  // L[r0] + L[r1] <= L[r+1]); summing 27 rows adds at most 26u sum_rows L[r+1];
+  // and sum_rows L[r+1] <= L[N + 27].  32u L[N + 27] covers both plus the
+  // second-order terms and the FP64 evaluation's own rounding.
+  if (n_samples < 0) return 0.0;
+  return 32.0 * ldexp(1.0, -24) * log_factorial_at((int64_t)n_samples + 27);
+}
+
+int64_t epi3_encode_bytes(int32_t n_snps, int32_t n_cases, int32_t n_controls, int32_t layout) {
+  if (n_snps < 0 || n_cases < 0 || n_controls < 0 || n_cases + n_controls <= 0) return EPI3_E_INVALID;
+  if (layout != EPI3_LAYOUT_SPLIT && layout != EPI3_LAYOUT_MASKED) return EPI3_E_INVALID;
+  return encode_layout(nullptr, n_snps, n_cases, n_controls, layout).total;
+}
+
+int epi3_encode(const uint8_t *geno_dev, int64_t ld, const uint8_t *pheno_host, int32_t n_snps,
+                int32_t n_samples, int32_t layout, void *buf_dev, int64_t buf_bytes, void *stream,
+                epi3_dataset *out) {
+  if (!out || !pheno_host || !buf_dev || n_snps < 0 || n_samples <= 0 || ld < n_samples ||
+      (n_snps > 0 && !geno_dev))
+    return EPI3_E_INVALID;
+  if (layout != EPI3_LAYOUT_SPLIT && layout != EPI3_LAYOUT_MASKED) return EPI3_E_INVALID;
+  if (reinterpret_cast<uintptr_t>(buf_dev) % kAlign) return EPI3_E_INVALID;
+  int32_t n1 = 0;
+  for (int32_t s = 0; s < n_samples; ++s) {
+    if (pheno_host[s] > 1) return EPI3_E_PHENOTYPE;
+    n1 += pheno_host[s];
+  }
+  const int32_t n0 = n_samples - n1;
+  EncodeLayout L = encode_layout(buf_dev, n_snps, n1, n0, layout);
+  if (buf_bytes < L.total) return EPI3_E_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  // sample list per output word: controls then cases (SPLIT), or all (MASKED)
+  std::vector<int32_t> list((size_t)L.Wtot * 32, -1);
+  if (layout == EPI3_LAYOUT_SPLIT) {
+    int32_t p0 = 0, p1 = L.W0 * 32;
+    for (int32_t x = 0; x < n_samples; ++x) {
+      if (pheno_host[x]) list[p1++] = x; else list[p0++] = x;
+    }
+  } else {
+    for (int32_t x = 0; x < n_samples; ++x) list[x] = x;
+  }
+  std::vector<double> L64;
+  std::vector<float> L32;
+  host_log_factorials((int64_t)n_samples + 1, L64, L32);
+
+  HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(L.status), 0u, 64, s));
+  HIP_OK(hipMemcpyAsync(L.list, list.data(), list.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(L.lf64, L64.data(), L64.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(L.lf32, L32.data(), L32.size() * sizeof(float), hipMemcpyHostToDevice, s));
+  HIP_OK(launch_encode(geno_dev, ld, L.list, n_snps, L.Mp, layout == EPI3_LAYOUT_SPLIT ? L.W0 : L.Wtot,
+                       layout == EPI3_LAYOUT_SPLIT ? L.W1 : 0, L.planes, L.status, s));
+  if (layout == EPI3_LAYOUT_MASKED)
+    HIP_OK(launch_encode_bytes(geno_dev, ld, n_snps, n_samples, L.Mp, L.S, L.bytes, s));
+  HIP_OK(launch_pairs(L.planes, L.Mp, n_snps, L.W0, layout == EPI3_LAYOUT_SPLIT ? L.W1 : 0,
+                      L.classes, nullptr, L.pairs, s));
+  HIP_OK(hipStreamSynchronize(s));  // host vectors above must outlive the copies
+
+  memset(out, 0, sizeof(*out));
+  out->n_snps = n_snps;
+  out->n_samples = n_samples;
+  out->n_cases = n1;
+  out->n_controls = n0;
+  out->words[0] = L.W0;
+  out->words[1] = L.W1;
+  out->layout = layout;
+  out->snp_stride = L.Mp;
+  out->byte_stride = L.S;
+  out->planes = L.planes;
+  out->bytes = layout == EPI3_LAYOUT_MASKED ? L.bytes : nullptr;
+  out->pairs = L.pairs;
+  out->lf64 = L.lf64;
+  out->lf32 = L.lf32;
+  out->status = L.status;
+  return EPI3_OK;
+}
+
+int64_t epi3_workspace_bytes(const epi3_dataset *d, int32_t k, int64_t cand_cap) {
+  if (!valid_dataset(d) || k <= 0) return EPI3_E_INVALID;
+  return scan_layout(nullptr, *d, k, cand_cap).total;
+}
+
+static int enqueue_count(const epi3_dataset &d, int32_t variant, float *score, uint32_t *counts,
+                         const ScanLayout &W, hipStream_t s) {
+  if (variant == EPI3_VARIANT_MFMA) return EPI3_E_UNSUPPORTED;
+  const int P = pick_P(d);
+  Job J = make_job(d, score, counts, W.jprefix, &W.st->kmin, P);
+  HIP_OK(launch_write_jobs(&J, 1, W.job, s));
+  HIP_OK(launch_tile_prefix(W.job, 1, P, s));
+  HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
+  HIP_OK(launch_count_valu(W.job, 1, J.n_tiles, W.queue, d.lf32, d.n_samples + 2, P,
+                           counts != nullptr, s));
+  return EPI3_OK;
+}
+
+int epi3_scan(const epi3_dataset *d, int32_t k, int32_t variant, int64_t cand_cap, void *ws_dev,
+              int64_t ws_bytes, void *stream) {
+  if (!valid_dataset(d) || k <= 0 || !ws_dev) return EPI3_E_INVALID;
+  if (d->layout != EPI3_LAYOUT_SPLIT) return EPI3_E_INVALID;
+  if (reinterpret_cast<uintptr_t>(ws_dev) % kAlign) return EPI3_E_INVALID;
+  ScanLayout W = scan_layout(ws_dev, *d, k, cand_cap);
+  if (ws_bytes < W.total) return EPI3_E_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t T = epi3_n_triplets(d->n_snps);
+  SelJob S = make_seljob(*d, W.score, T, W.st, W.hist, W.cand, W.rec, W.hits, W.cap, k);
+  HIP_OK(launch_write_seljobs(&S, 1, W.sel, s));
+  HIP_OK(launch_init_select(W.sel, 1, s));
+  if (T > 0) {
+    const int rc = enqueue_count(*d, variant, W.score, nullptr, W, s);
+    if (rc != EPI3_OK) return rc;
+  }
+  HIP_OK(launch_select(W.sel, 1, T, W.cap, k, s));
+  return EPI3_OK;
+}
+
+int epi3_topk(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev, epi3_hit *hits_host,
+              int32_t *n_out, void *stream) {
+  if (!valid_dataset(d) || k <= 0 || !ws_dev || !hits_host || !n_out) return EPI3_E_INVALID;
+  ScanLayout W = scan_layout(ws_dev, *d, k, cand_cap);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SelState st;
+  int32_t status = 0;
+  HIP_OK(hipMemcpyAsync(&st, W.st, sizeof(st), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(&status, d->status, sizeof(status), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  *n_out = 0;
+  if (status & 1) return EPI3_E_GENOTYPE;
+  if ((int64_t)st.ncand > W.cap) {
+    *n_out = (int32_t)std::min<unsigned long long>(st.ncand, 0x7fffffffull);
+    return EPI3_E_CAPACITY;
+  }
+  const int64_t keff = st.keff;
+  if (keff > 0) {
+    HIP_OK(hipMemcpyAsync(hits_host, W.hits, keff * sizeof(epi3_hit), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+  }
+  *n_out = (int32_t)keff;
+  return EPI3_OK;
+}
+
+int epi3_score_plane(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
+                     float **plane_dev) {
+  if (!valid_dataset(d) || k <= 0 || !ws_dev || !plane_dev) return EPI3_E_INVALID;
+  *plane_dev = scan_layout(ws_dev, *d, k, cand_cap).score;
+  return EPI3_OK;
+}
+
+int epi3_scan_tables(const epi3_dataset *d, int32_t variant, uint32_t *counts_dev, float *k2_dev,
+                     void *ws_dev, int64_t ws_bytes, void *stream) {
+  if (!valid_dataset(d) || !k2_dev || !ws_dev) return EPI3_E_INVALID;
+  if (d->layout != EPI3_LAYOUT_SPLIT) return EPI3_E_INVALID;
+  ScanLayout W = scan_layout(ws_dev, *d, 1, 0);
+  if (ws_bytes < W.total) return EPI3_E_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t T = epi3_n_triplets(d->n_snps);
+  if (T == 0) return EPI3_OK;
+  HIP_OK(launch_fill_u32(&W.st->kmin, 0xffffffffu, 1, s));
+  HIP_OK(launch_fill_u32(&W.st->kmax, 0u, 1, s));
+  // counts requested: the kernel variant that writes tables
+  return enqueue_count(*d, variant, k2_dev, counts_dev ? counts_dev : nullptr, W, s) == EPI3_OK
+             ? EPI3_OK
+             : EPI3_E_UNSUPPORTED;
+}
+
+int epi3_score_triplets(const epi3_dataset *d, const uint32_t *ijk_dev, int64_t n,
+                        uint32_t *counts_dev, float *k2_f32_dev, double *k2_dev, void *stream) {
+  if (!valid_dataset(d) || n < 0 || (n > 0 && !ijk_dev)) return EPI3_E_INVALID;
+  if (d->layout != EPI3_LAYOUT_SPLIT) return EPI3_E_INVALID;
+  HIP_OK(launch_score_triplets(*d, ijk_dev, n, counts_dev, k2_f32_dev, k2_dev,
+                               static_cast<hipStream_t>(stream)));
+  return EPI3_OK;
+}
+
+int64_t epi3_batched_workspace_bytes(const epi3_job *jobs, int32_t n_jobs, int64_t cand_cap) {
+  (void)jobs; (void)n_jobs; (void)cand_cap;
+  return EPI3_E_UNSUPPORTED;
+}
+
+int epi3_scan_batched(const epi3_job *jobs, int32_t n_jobs, int32_t variant, int64_t cand_cap,
+                      void *ws_dev, int64_t ws_bytes, epi3_hit *hits_host, int32_t *n_out_host,
+                      void *stream) {
+  (void)jobs; (void)n_jobs; (void)variant; (void)cand_cap; (void)ws_dev; (void)ws_bytes;
+  (void)hits_host; (void)n_out_host; (void)stream;
+  return EPI3_E_UNSUPPORTED;
+}
+
+void epi3_release(void) {}
+
+}  // extern "C"

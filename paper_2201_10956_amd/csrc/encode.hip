@@ -1,0 +1,155 @@
+// Encoding kernels: genotype bytes -> per-genotype sample bit-planes, byte
+// planes for the matrix-core path, and pairwise tables.
+//
+// Binarized format (Problem Formulation section, Fig. 1 text): SNP x is held
+// as one bit-plane per genotype value, one bit per sample.  Reduced format
+// (CPU approaches section): plane 2 is never stored because a sample is in
+// plane 2 exactly when it is in neither plane 0 nor plane 1, and samples are
+// split into a controls array and a cases array.  32-bit words (start of the
+// Approaches section).  SNP-minor order (GPU approaches section: consecutive
+// SNPs adjacent in memory so that lanes owning consecutive SNPs coalesce).
+#include "epi3_internal.h"
+
+namespace epi3 {
+
+// planes[w][m][0..1]: bit b of word w = sample list[w * 32 + b] has genotype
+// 0 (plane 0) / 1 (plane 1).  list < 0 marks padding; padding bits stay 0 in
+// both planes.  SNP slots m >= M are zero.
+__global__ void __launch_bounds__(256) encode_kernel(const uint8_t *__restrict__ geno, int64_t ld,
+                                                     const int32_t *__restrict__ list, int32_t M,
+                                                     int32_t Mp, int32_t Wtot,
+                                                     uint32_t *__restrict__ planes,
+                                                     int32_t *__restrict__ status) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const int w = blockIdx.y;
+  if (m >= Mp || w >= Wtot) return;
+  uint32_t b0 = 0, b1 = 0;
+  bool bad = false;
+  if (m < M) {
+    const uint8_t *row = geno + (int64_t)m * ld;
+    const int32_t *ls = list + (int64_t)w * 32;
+#pragma unroll 8
+    for (int b = 0; b < 32; ++b) {
+      const int s = ls[b];
+      if (s >= 0) {
+        const uint32_t g = row[s];
+        bad |= g > 2u;
+        b0 |= (uint32_t)(g == 0u) << b;
+        b1 |= (uint32_t)(g == 1u) << b;
+      }
+    }
+  }
+  reinterpret_cast<uint2 *>(planes)[(int64_t)w * Mp + m] = make_uint2(b0, b1);
+  if (bad) atomicOr(status, 1);
+}
+
+// bytes[m][p][s] = 1 if sample s of SNP m has genotype p (p = 0, 1), else 0;
+// samples s >= N and SNPs m >= M are 0.  S is a multiple of 4.
+__global__ void __launch_bounds__(256) encode_bytes_kernel(const uint8_t *__restrict__ geno,
+                                                           int64_t ld, int32_t M, int32_t N,
+                                                           int32_t Mp, int32_t S,
+                                                           uint32_t *__restrict__ bytes) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;  // dword within a row
+  const int S4 = S >> 2;
+  if (q >= S4) return;
+  for (int m = blockIdx.y; m < Mp; m += gridDim.y) {
+    uint32_t v0 = 0, v1 = 0;
+    if (m < M) {
+      const uint8_t *row = geno + (int64_t)m * ld;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int s = 4 * q + b;
+        if (s < N) {
+          const uint32_t g = row[s];
+          v0 |= (uint32_t)(g == 0u) << (8 * b);
+          v1 |= (uint32_t)(g == 1u) << (8 * b);
+        }
+      }
+    }
+    bytes[((int64_t)m * 2 + 0) * S4 + q] = v0;
+    bytes[((int64_t)m * 2 + 1) * S4 + q] = v1;
+  }
+}
+
+// Pairwise tables: pairs[c][x][y] = (n(0,0), n(0,1), n(1,0), n(1,1)) with
+// n(a,b) = number of class-c samples where SNP x has genotype a and SNP y has
+// genotype b.  The diagonal holds the per-SNP counts (n_x(0), 0, 0, n_x(1)).
+// With `mask`, only samples whose mask bit is set are counted (one class).
+// One wave per (x, 64 consecutive y); x is wave-uniform so its words are
+// scalar loads.
+__global__ void __launch_bounds__(256) pairs_kernel(const uint32_t *__restrict__ planes, int32_t Mp,
+                                                    int32_t W0, int32_t W1,
+                                                    const uint32_t *__restrict__ mask,
+                                                    int32_t *__restrict__ pairs) {
+  const int lane = threadIdx.x & 63;
+  const int x = __builtin_amdgcn_readfirstlane(blockIdx.y * 4 + (threadIdx.x >> 6));
+  const int y = blockIdx.x * 64 + lane;
+  const int c = blockIdx.z;
+  if (x >= Mp) return;
+  const int w0 = c == 0 ? 0 : W0;
+  const int w1 = c == 0 ? W0 : W0 + W1;
+  uint32_t n00 = 0, n01 = 0, n10 = 0, n11 = 0;
+  cptr<uint32_t> pc = as_const(planes);
+  const uint2 *pv = reinterpret_cast<const uint2 *>(planes);
+  for (int w = w0; w < w1; ++w) {
+    uint32_t x0 = pc[((int64_t)w * Mp + x) * 2 + 0];
+    uint32_t x1 = pc[((int64_t)w * Mp + x) * 2 + 1];
+    if (mask) {
+      const uint32_t mk = as_const(mask)[w];
+      x0 &= mk;
+      x1 &= mk;
+    }
+    const uint2 yv = (y < Mp) ? pv[(int64_t)w * Mp + y] : make_uint2(0u, 0u);
+    n00 += __builtin_popcount(x0 & yv.x);
+    n01 += __builtin_popcount(x0 & yv.y);
+    n10 += __builtin_popcount(x1 & yv.x);
+    n11 += __builtin_popcount(x1 & yv.y);
+  }
+  if (y < Mp)
+    reinterpret_cast<int4 *>(pairs)[((int64_t)c * Mp + x) * Mp + y] =
+        make_int4((int)n00, (int)n01, (int)n10, (int)n11);
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
+       x += (int64_t)gridDim.x * blockDim.x)
+    p[x] = v;
+}
+
+hipError_t launch_encode(const uint8_t *geno, int64_t ld, const int32_t *sample_list, int32_t M,
+                         int32_t Mp, int32_t W0, int32_t W1, uint32_t *planes, int32_t *status,
+                         hipStream_t s) {
+  const int Wtot = W0 + W1;
+  if (Wtot <= 0) return hipSuccess;
+  dim3 grid((Mp + 255) / 256, Wtot);
+  hipLaunchKernelGGL(encode_kernel, grid, dim3(256), 0, s, geno, ld, sample_list, M, Mp, Wtot,
+                     planes, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_bytes(const uint8_t *geno, int64_t ld, int32_t M, int32_t N, int32_t Mp,
+                               int32_t S, uint8_t *bytes, hipStream_t s) {
+  const int S4 = S / 4;
+  dim3 grid((S4 + 255) / 256, Mp < 65535 ? Mp : 65535);
+  hipLaunchKernelGGL(encode_bytes_kernel, grid, dim3(256), 0, s, geno, ld, M, N, Mp, S,
+                     reinterpret_cast<uint32_t *>(bytes));
+  return hipGetLastError();
+}
+
+hipError_t launch_pairs(const uint32_t *planes, int32_t Mp, int32_t M, int32_t W0, int32_t W1,
+                        int32_t n_classes, const uint32_t *mask, int32_t *pairs, hipStream_t s) {
+  (void)M;
+  dim3 grid((Mp + 63) / 64, (Mp + 3) / 4, n_classes);
+  hipLaunchKernelGGL(pairs_kernel, grid, dim3(256), 0, s, planes, Mp, W0, W1, mask, pairs);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+}  // namespace epi3

@@ -1,0 +1,182 @@
+// Internal declarations shared by the HIP translation units of libepi3.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/epi3.h"
+
+namespace epi3 {
+
+constexpr int kWave = 64;        // CDNA wavefront width
+constexpr int kSnpPad = 64;      // plane arrays hold roundup(M, 64) + 64 SNP slots
+constexpr int kHistBins = 2048;  // radix-select bins per pass
+constexpr int kHistPasses = 3;   // 3 x 11 bits >= 32-bit keys
+
+// Pointer into the constant address space: uniform loads through it become
+// scalar (s_load) instructions.  Only used for memory no kernel writes while
+// the reading kernel runs.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T *p) {
+  return (cptr<T>)p;
+}
+
+__host__ __device__ __forceinline__ int64_t c2(int64_t x) { return x < 2 ? 0 : x * (x - 1) / 2; }
+__host__ __device__ __forceinline__ int64_t c3(int64_t x) {
+  return x < 3 ? 0 : x * (x - 1) / 2 * (x - 2) / 3;
+}
+
+// Lexicographic rank of i < j < k < M among all triplets.
+__host__ __device__ __forceinline__ int64_t lex_base(int64_t M, int64_t i, int64_t j) {
+  return c3(M) - c3(M - i) + c2(M - 1 - i) - c2(M - j) - j - 1;  // + k gives the rank
+}
+
+// Order-preserving map of a float to an unsigned key (and back).
+__host__ __device__ __forceinline__ uint32_t f2key(float f) {
+  uint32_t b;
+  __builtin_memcpy(&b, &f, 4);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__host__ __device__ __forceinline__ float key2f(uint32_t k) {
+  uint32_t b = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+  float f;
+  __builtin_memcpy(&f, &b, 4);
+  return f;
+}
+
+// One scan job as seen by the count kernels: a SPLIT data set, its score
+// plane and its share of the global tile queue.
+struct Job {
+  const uint32_t *planes;  // [W0 + W1][Mp][2]
+  const int32_t *pairs;    // [2][Mp][Mp][4]
+  float *score;            // [T] FP32 K2 by lexicographic rank
+  const int64_t *jprefix;  // [M + 1] job-local tiles before pivot j
+  uint32_t *counts;        // optional [T][2][27]
+  uint32_t *keyrange;      // [2] atomic min / max of f2key(score)
+  int64_t tile_begin;      // first global tile of this job
+  int64_t n_tiles;
+  int64_t T;
+  int32_t M, Mp, W0, W1, N0, N1;
+};
+
+// Per-job radix-select state.
+struct SelState {
+  uint32_t kmin, kmax;     // key range of the score plane (written by the count kernel)
+  uint32_t lo;             // lower end of the key window holding the k-th key
+  int32_t shift;           // bin width of the current pass = 1 << shift
+  uint64_t krem;           // 1-based rank of the k-th key inside the window
+  uint32_t done;           // window collapsed to one key
+  uint32_t kth;            // key of the k-th smallest score
+  float thr;               // candidate threshold (FP32, rounded up)
+  uint32_t overflow;       // candidates beyond capacity
+  unsigned long long ncand;
+  int64_t keff;            // min(k, T)
+  int64_t T;
+  int32_t k;
+  int32_t pad;
+};
+
+// One scored candidate.
+struct CandRec {
+  uint64_t key;            // bit pattern of the FP64 K2 (non-negative => ordered)
+  int64_t rank;            // lexicographic rank (tie-break)
+  uint32_t i, j, k;
+  float k2f;
+  double k2;
+  uint32_t counts[54];
+};
+
+// Selection job: one score plane plus its candidate buffers.
+struct SelJob {
+  const float *score;
+  int64_t T;
+  SelState *st;
+  uint32_t *hist;          // [kHistBins]
+  int64_t *cand;           // [cap] ranks
+  CandRec *rec;            // [cap]
+  epi3_hit *hits;          // [k]
+  int64_t cap;
+  double err2;             // 2 e(N)
+  // data needed to recount a candidate
+  const uint32_t *planes;
+  const int32_t *pairs;    // [classes][Mp][Mp][4]; MASKED: totals at class 0
+  const int32_t *case_pairs; // MASKED: [Mp][Mp][4] case pairs of the job's mask, else NULL
+  const uint32_t *case_mask; // MASKED: [W] mask words, else NULL
+  const double *lf64;
+  int32_t M, Mp, W0, W1, N0, N1;
+  int32_t layout;
+  int32_t k;
+};
+
+// The 27 cells of one class from the 8 counted corner cells n[4a + 2b + c]
+// (a, b, c in {0, 1}), the pairwise tables pij[2a + b], pik[2a + c],
+// pjk[2b + c], the per-SNP counts mi[a], mj[b], mk[c] and the class size.
+// Every sample of the class is in exactly one row, so each missing cell is
+// a margin minus the cells already known.
+__device__ __forceinline__ void complete_table(const uint32_t n[8], const int pij[4],
+                                               const int pik[4], const int pjk[4], const int mi[2],
+                                               const int mj[2], const int mk[2], int Nc, int t[27]) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) t[9 * a + 3 * b + c] = (int)n[4 * a + 2 * b + c];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+      t[9 * a + 3 * b + 2] = pij[2 * a + b] - t[9 * a + 3 * b] - t[9 * a + 3 * b + 1];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+      t[9 * a + 6 + c] = pik[2 * a + c] - t[9 * a + c] - t[9 * a + 3 + c];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+      t[18 + 3 * b + c] = pjk[2 * b + c] - t[3 * b + c] - t[9 + 3 * b + c];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+    t[9 * a + 8] = mi[a] - pij[2 * a] - pij[2 * a + 1] - t[9 * a + 6] - t[9 * a + 7];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+    t[18 + 3 * b + 2] = mj[b] - pij[b] - pij[2 + b] - t[18 + 3 * b] - t[18 + 3 * b + 1];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+    t[24 + c] = mk[c] - pik[c] - pik[2 + c] - t[18 + c] - t[21 + c];
+  int s = 0;
+#pragma unroll
+  for (int x = 0; x < 26; ++x) s += t[x];
+  t[26] = Nc - s;
+}
+
+// ---- host-side launchers (defined in the .hip files) ----
+hipError_t launch_encode(const uint8_t *geno, int64_t ld, const int32_t *sample_list,
+                         int32_t M, int32_t Mp, int32_t W0, int32_t W1, uint32_t *planes,
+                         int32_t *status, hipStream_t s);
+hipError_t launch_encode_bytes(const uint8_t *geno, int64_t ld, int32_t M, int32_t N, int32_t Mp,
+                               int32_t S, uint8_t *bytes, hipStream_t s);
+hipError_t launch_pairs(const uint32_t *planes, int32_t Mp, int32_t M, int32_t W0, int32_t W1,
+                        int32_t n_classes, const uint32_t *mask, int32_t *pairs, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_tile_prefix(Job *jobs_dev, int32_t n_jobs, int32_t P, hipStream_t s);
+int64_t host_tiles(int64_t M, int P);
+hipError_t launch_write_jobs(const Job *jobs_host, int32_t n, Job *dst_dev, hipStream_t s);
+hipError_t launch_count_valu(const Job *jobs_dev, int32_t n_jobs, int64_t total_tiles,
+                             unsigned long long *queue, const float *lf32, int32_t lf_len,
+                             int32_t P, bool counts, hipStream_t s);
+hipError_t launch_select(SelJob *sel_dev, int32_t n_jobs, int64_t max_T, int64_t max_cap,
+                         int32_t max_k, hipStream_t s);
+hipError_t launch_write_seljobs(const SelJob *h, int32_t n, SelJob *dst_dev, hipStream_t s);
+hipError_t launch_init_select(SelJob *sel_dev, int32_t n_jobs, hipStream_t s);
+hipError_t launch_score_triplets(const epi3_dataset &d, const uint32_t *ijk, int64_t n,
+                                 uint32_t *counts, float *k2f, double *k2, hipStream_t s);
+
+int tile_P_default(int32_t M, int32_t N);
+
+}  // namespace epi3

@@ -1,0 +1,426 @@
+// Selection of the k lowest K2 (paper: the solution is the combination with
+// the lowest K2, end of the Problem Formulation section; GPU approaches
+// section: each thread keeps its best, the host picks the final one).
+//
+// Here, for k >= 1 and exactly:
+//   1. radix select over the FP32 score plane finds the k-th smallest FP32
+//      value T32 (3 passes of 2048 bins over a window that starts at the
+//      plane's key range);
+//   2. every triplet with K2_fp32 <= T32 + 2 e(N) is a candidate, where e(N)
+//      bounds |K2_fp32 - K2_fp64| for any table of N samples, so the candidate
+//      set contains every member of the FP64 top-k;
+//   3. each candidate's table is recounted and K2 re-evaluated in FP64 with
+//      Eq. 1's bracketing, rows summed in row order;
+//   4. each candidate's position under (K2_fp64, i, j, k) is counted against
+//      all others and the first k are written out.
+#include "epi3_internal.h"
+
+namespace epi3 {
+
+// ---------------------------------------------------------------- init ----
+__global__ void init_select_kernel(SelJob *sj, int n) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  SelState *st = sj[x].st;
+  st->kmin = 0xffffffffu;
+  st->kmax = 0u;
+  st->lo = 0u;
+  st->shift = 0;
+  st->krem = 0;
+  st->done = 0u;
+  st->kth = 0u;
+  st->thr = 0.f;
+  st->overflow = 0u;
+  st->ncand = 0ull;
+  st->T = sj[x].T;
+  st->k = sj[x].k;
+  st->keff = sj[x].k < sj[x].T ? sj[x].k : sj[x].T;
+  for (int b = 0; b < kHistBins; ++b) sj[x].hist[b] = 0u;
+}
+
+// After the count kernel: first window = [kmin, kmax].
+__global__ void window_kernel(SelJob *sj, int n) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  SelState *st = sj[x].st;
+  if (st->keff <= 0) {
+    st->done = 2u;  // nothing to select
+    return;
+  }
+  const uint32_t range = st->kmax - st->kmin;
+  st->lo = st->kmin;
+  st->krem = (uint64_t)st->keff;
+  if (range == 0u) {
+    st->done = 1u;
+    st->kth = st->kmin;
+    return;
+  }
+  const int bl = 32 - __builtin_clz(range);  // bits of range
+  st->shift = bl > 11 ? bl - 11 : 0;
+}
+
+__global__ void __launch_bounds__(256) hist_kernel(const SelJob *__restrict__ sj) {
+  const SelJob &J = sj[blockIdx.y];
+  const SelState *st = J.st;
+  if (st->done) return;
+  const uint32_t lo = st->lo;
+  const int shift = st->shift;
+  __shared__ uint32_t h[kHistBins];
+  for (int b = threadIdx.x; b < kHistBins; b += blockDim.x) h[b] = 0u;
+  __syncthreads();
+  const float *score = J.score;
+  const int64_t T = J.T;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < T;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t key = f2key(score[x]);
+    if (key >= lo) {
+      const uint32_t d = (key - lo) >> shift;
+      if (d < (uint32_t)kHistBins) atomicAdd(&h[d], 1u);
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kHistBins; b += blockDim.x)
+    if (h[b]) atomicAdd(&J.hist[b], h[b]);
+}
+
+// One block per job: find the bin holding the krem-th key, narrow the window.
+__global__ void __launch_bounds__(1024) find_kernel(SelJob *sj) {
+  SelJob &J = sj[blockIdx.x];
+  SelState *st = J.st;
+  if (st->done) return;
+  __shared__ unsigned long long cum[kHistBins];
+  const int t = threadIdx.x;
+  // every thread reads the state before any thread updates it (barriers below)
+  const uint64_t krem = st->krem;
+  const int shift = st->shift;
+  const uint32_t lo0 = st->lo;
+  for (int b = t; b < kHistBins; b += blockDim.x) cum[b] = J.hist[b];
+  __syncthreads();
+  for (int off = 1; off < kHistBins; off <<= 1) {
+    unsigned long long v0 = 0, v1 = 0;
+    const int b0 = t, b1 = t + 1024;
+    if (b0 >= off) v0 = cum[b0 - off];
+    if (b1 >= off) v1 = cum[b1 - off];
+    __syncthreads();
+    cum[b0] += v0;
+    cum[b1] += v1;
+    __syncthreads();
+  }
+  for (int b = t; b < kHistBins; b += blockDim.x) {
+    const unsigned long long before = b ? cum[b - 1] : 0ull;
+    if (before < krem && cum[b] >= krem) {  // exactly one bin satisfies this
+      const uint32_t lo = lo0 + ((uint32_t)b << shift);
+      st->lo = lo;
+      st->krem = krem - before;
+      if (shift == 0) {
+        st->done = 1u;
+        st->kth = lo;
+      } else {
+        st->shift = shift > 11 ? shift - 11 : 0;
+      }
+    }
+  }
+  __syncthreads();
+  for (int b = t; b < kHistBins; b += blockDim.x) J.hist[b] = 0u;
+}
+
+// Threshold T32 + 2 e(N), rounded up to the next float.
+__global__ void threshold_kernel(SelJob *sj, int n) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  SelState *st = sj[x].st;
+  if (st->done != 1u) return;
+  const double thr = (double)key2f(st->kth) + sj[x].err2;
+  float f = (float)thr;
+  if ((double)f < thr) f = __uint_as_float(__float_as_uint(f) + 1u);  // f >= 0: next float up
+  st->thr = f;
+}
+
+__global__ void __launch_bounds__(256) collect_kernel(const SelJob *__restrict__ sj) {
+  const SelJob &J = sj[blockIdx.y];
+  SelState *st = J.st;
+  if (st->done != 1u) return;
+  const float thr = st->thr;
+  const float *score = J.score;
+  const int64_t T = J.T, cap = J.cap;
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); base < T;
+       base += stride) {
+    const int64_t x = base + lane;
+    const bool pred = x < T && score[x] <= thr;
+    const unsigned long long m = __ballot(pred);
+    if (m == 0ull) continue;
+    unsigned long long pos0 = 0;
+    if (lane == 0) pos0 = atomicAdd(&st->ncand, (unsigned long long)__popcll(m));
+    pos0 = __shfl(pos0, 0);
+    const unsigned long long pos = pos0 + __popcll(m & ((1ull << lane) - 1ull));
+    if (pred && (int64_t)pos < cap) J.cand[pos] = x;
+  }
+}
+
+// ----------------------------------------------------- FP64 re-score ----
+__device__ __forceinline__ void decode_rank(int64_t M, int64_t rank, int &i, int &j, int &k) {
+  const int64_t C = c3(M);
+  int lo = 0, hi = (int)M - 3;  // last i with first rank <= rank
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (C - c3(M - mid) <= rank) lo = mid; else hi = mid - 1;
+  }
+  i = lo;
+  const int64_t r1 = rank - (C - c3(M - i));
+  // within i: pivots j > i, each with M - 1 - j values of k
+  int jl = i + 1, jh = (int)M - 2;
+  while (jl < jh) {
+    const int mid = (jl + jh + 1) >> 1;
+    if (c2(M - 1 - i) - c2(M - mid) <= r1) jl = mid; else jh = mid - 1;
+  }
+  j = jl;
+  k = (int)(rank - lex_base(M, i, j));
+}
+
+__device__ __forceinline__ unsigned wave_sum(unsigned v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Corner cells n[4a + 2b + c] over words [w0, w1) by the lanes of one wave,
+// optionally restricted to mask bits.
+__device__ __forceinline__ void corners(const uint32_t *planes, int64_t Mp, int w0, int w1, int i,
+                                        int j, int k, const uint32_t *mask, uint32_t n[8]) {
+  const int lane = threadIdx.x & 63;
+  uint32_t a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int w = w0 + lane; w < w1; w += 64) {
+    const uint2 *row = reinterpret_cast<const uint2 *>(planes) + (int64_t)w * Mp;
+    const uint2 xi = row[i], xj = row[j], xk = row[k];
+    const uint32_t mk = mask ? mask[w] : 0xffffffffu;
+    const uint32_t xiv[2] = {xi.x & mk, xi.y & mk}, xjv[2] = {xj.x, xj.y}, xkv[2] = {xk.x, xk.y};
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+      a[p] += __builtin_popcount(xiv[p >> 2] & xjv[(p >> 1) & 1] & xkv[p & 1]);
+  }
+#pragma unroll
+  for (int p = 0; p < 8; ++p) n[p] = wave_sum(a[p]);
+}
+
+__device__ __forceinline__ void pair_args(const int32_t *pairs, int64_t Mp, int i, int j, int k,
+                                          int aij[4], int aik[4], int ajk[4], int mi[2], int mj[2],
+                                          int mk[2]) {
+  const int4 *pr = reinterpret_cast<const int4 *>(pairs);
+  const int4 pij = pr[(int64_t)i * Mp + j], pik = pr[(int64_t)i * Mp + k],
+             pjk = pr[(int64_t)j * Mp + k];
+  const int4 ii = pr[(int64_t)i * Mp + i], jj = pr[(int64_t)j * Mp + j],
+             kk = pr[(int64_t)k * Mp + k];
+  aij[0] = pij.x; aij[1] = pij.y; aij[2] = pij.z; aij[3] = pij.w;
+  aik[0] = pik.x; aik[1] = pik.y; aik[2] = pik.z; aik[3] = pik.w;
+  ajk[0] = pjk.x; ajk[1] = pjk.y; ajk[2] = pjk.z; ajk[3] = pjk.w;
+  mi[0] = ii.x; mi[1] = ii.w; mj[0] = jj.x; mj[1] = jj.w; mk[0] = kk.x; mk[1] = kk.w;
+}
+
+// Full table [2][27] of one triplet, computed by the lanes of one wave.
+// SPLIT: class words [0, W0) and [W0, W0 + W1), pairs [2][Mp][Mp].
+// MASKED: totals from all words and pairs[0]; cases with the mask and
+// case_pairs; controls = totals - cases.
+__device__ void triplet_table(const uint32_t *planes, const int32_t *pairs,
+                              const int32_t *case_pairs, const uint32_t *mask, int layout,
+                              int64_t Mp, int W0, int W1, int N0, int N1, int i, int j, int k,
+                              int tab[2][27]) {
+  int aij[4], aik[4], ajk[4], mi[2], mj[2], mk[2];
+  uint32_t n[8];
+  if (layout == EPI3_LAYOUT_SPLIT) {
+    for (int c = 0; c < 2; ++c) {
+      corners(planes, Mp, c ? W0 : 0, c ? W0 + W1 : W0, i, j, k, nullptr, n);
+      pair_args(pairs + (int64_t)c * Mp * Mp * 4, Mp, i, j, k, aij, aik, ajk, mi, mj, mk);
+      complete_table(n, aij, aik, ajk, mi, mj, mk, c ? N1 : N0, tab[c]);
+    }
+  } else {
+    int tot[27];
+    corners(planes, Mp, 0, W0, i, j, k, nullptr, n);
+    pair_args(pairs, Mp, i, j, k, aij, aik, ajk, mi, mj, mk);
+    complete_table(n, aij, aik, ajk, mi, mj, mk, N0 + N1, tot);
+    corners(planes, Mp, 0, W0, i, j, k, mask, n);
+    pair_args(case_pairs, Mp, i, j, k, aij, aik, ajk, mi, mj, mk);
+    complete_table(n, aij, aik, ajk, mi, mj, mk, N1, tab[1]);
+    for (int x = 0; x < 27; ++x) tab[0][x] = tot[x] - tab[1][x];
+  }
+}
+
+// Eq. 1 in FP64: rows in order, each row L[r + 1] - (L[r_0] + L[r_1]).
+__device__ __forceinline__ double k2_fp64(const int tab[2][27], const double *L) {
+  double k2 = 0.0;
+  for (int x = 0; x < 27; ++x) {
+    const int r0 = tab[0][x], r1 = tab[1][x];
+    k2 += L[r0 + r1 + 1] - (L[r0] + L[r1]);
+  }
+  return k2;
+}
+
+__global__ void __launch_bounds__(256) rescore_kernel(const SelJob *__restrict__ sj) {
+  const SelJob &J = sj[blockIdx.y];
+  SelState *st = J.st;
+  if (st->done != 1u) return;
+  const int64_t n = (int64_t)st->ncand < J.cap ? (int64_t)st->ncand : J.cap;
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t c = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); c < n;
+       c += waves) {
+    const int64_t rank = J.cand[c];
+    int i, j, k;
+    decode_rank(J.M, rank, i, j, k);
+    int tab[2][27];
+    triplet_table(J.planes, J.pairs, J.case_pairs, J.case_mask, J.layout, J.Mp, J.W0, J.W1, J.N0,
+                  J.N1, i, j, k, tab);
+    if (lane == 0) {
+      CandRec &R = J.rec[c];
+      const double k2 = k2_fp64(tab, J.lf64);
+      R.key = (uint64_t)__double_as_longlong(k2);
+      R.rank = rank;
+      R.i = i; R.j = j; R.k = k;
+      R.k2f = J.score[rank];
+      R.k2 = k2;
+      for (int x = 0; x < 27; ++x) {
+        R.counts[x] = (uint32_t)tab[0][x];
+        R.counts[27 + x] = (uint32_t)tab[1][x];
+      }
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (int64_t)st->ncand > J.cap) st->overflow = 1u;
+}
+
+// Position of each candidate under (key, rank); the first keff go out.
+__global__ void __launch_bounds__(256) rank_kernel(const SelJob *__restrict__ sj) {
+  const SelJob &J = sj[blockIdx.y];
+  SelState *st = J.st;
+  if (st->done != 1u) return;
+  const int64_t n = (int64_t)st->ncand < J.cap ? (int64_t)st->ncand : J.cap;
+  const int64_t keff = st->keff;
+  __shared__ uint64_t skey[256];
+  __shared__ int64_t srank[256];
+  for (int64_t xb = blockIdx.x; xb * 256 < n; xb += gridDim.x) {
+    const int64_t x = xb * 256 + threadIdx.x;
+    uint64_t mykey = ~0ull;
+    int64_t myrank = 0;
+    if (x < n) {
+      mykey = J.rec[x].key;
+      myrank = J.rec[x].rank;
+    }
+    int64_t pos = 0;
+    for (int64_t yb = 0; yb < n; yb += 256) {
+      const int64_t y = yb + threadIdx.x;
+      __syncthreads();
+      skey[threadIdx.x] = y < n ? J.rec[y].key : ~0ull;
+      srank[threadIdx.x] = y < n ? J.rec[y].rank : INT64_MAX;
+      __syncthreads();
+      const int lim = (n - yb) < 256 ? (int)(n - yb) : 256;
+      for (int z = 0; z < lim; ++z) {
+        const uint64_t kz = skey[z];
+        pos += (kz < mykey) || (kz == mykey && srank[z] < myrank);
+      }
+    }
+    if (x < n && pos < keff) {
+      const CandRec &R = J.rec[x];
+      epi3_hit &H = J.hits[pos];
+      H.i = R.i; H.j = R.j; H.k = R.k;
+      H.k2_f32 = R.k2f;
+      H.k2 = R.k2;
+      for (int q = 0; q < 27; ++q) {
+        H.counts[0][q] = R.counts[q];
+        H.counts[1][q] = R.counts[27 + q];
+      }
+    }
+  }
+}
+
+__global__ void write_seljob_kernel(SelJob j0, SelJob *dst) { if (threadIdx.x == 0) *dst = j0; }
+
+hipError_t launch_write_seljobs(const SelJob *h, int32_t n, SelJob *dst_dev, hipStream_t s) {
+  for (int x = 0; x < n; ++x)
+    hipLaunchKernelGGL(write_seljob_kernel, dim3(1), dim3(64), 0, s, h[x], dst_dev + x);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_select(SelJob *sel_dev, int32_t n_jobs, hipStream_t s) {
+  hipLaunchKernelGGL(init_select_kernel, dim3((n_jobs + 63) / 64), dim3(64), 0, s, sel_dev,
+                     n_jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_select(SelJob *sel_dev, int32_t n_jobs, int64_t max_T, int64_t max_cap,
+                         int32_t max_k, hipStream_t s) {
+  (void)max_k;
+  const unsigned nj = (unsigned)n_jobs;
+  hipLaunchKernelGGL(window_kernel, dim3((n_jobs + 63) / 64), dim3(64), 0, s, sel_dev, n_jobs);
+  int64_t hb = (max_T + 256 * 16 - 1) / (256 * 16);
+  if (hb > 2048) hb = 2048;
+  if (hb < 1) hb = 1;
+  for (int p = 0; p < kHistPasses; ++p) {
+    hipLaunchKernelGGL(hist_kernel, dim3((unsigned)hb, nj), dim3(256), 0, s, sel_dev);
+    hipLaunchKernelGGL(find_kernel, dim3(nj), dim3(1024), 0, s, sel_dev);
+  }
+  hipLaunchKernelGGL(threshold_kernel, dim3((n_jobs + 63) / 64), dim3(64), 0, s, sel_dev, n_jobs);
+  hipLaunchKernelGGL(collect_kernel, dim3((unsigned)hb, nj), dim3(256), 0, s, sel_dev);
+  int64_t rb = (max_cap + 3) / 4;
+  if (rb > 4096) rb = 4096;
+  if (rb < 1) rb = 1;
+  hipLaunchKernelGGL(rescore_kernel, dim3((unsigned)rb, nj), dim3(256), 0, s, sel_dev);
+  int64_t kb = (max_cap + 255) / 256;
+  if (kb > 1024) kb = 1024;
+  if (kb < 1) kb = 1;
+  hipLaunchKernelGGL(rank_kernel, dim3((unsigned)kb, nj), dim3(256), 0, s, sel_dev);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- test hook ----
+__global__ void __launch_bounds__(256) score_triplets_kernel(
+    const uint32_t *__restrict__ planes, const int32_t *__restrict__ pairs,
+    const double *__restrict__ lf64, const float *__restrict__ lf32, int M, int64_t Mp, int W0,
+    int W1, int N0, int N1, const uint32_t *__restrict__ ijk, int64_t n,
+    uint32_t *__restrict__ counts, float *__restrict__ k2f, double *__restrict__ k2d) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t c = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); c < n;
+       c += waves) {
+    const uint32_t i = ijk[3 * c], j = ijk[3 * c + 1], k = ijk[3 * c + 2];
+    if (!(i < j && j < k && k < (uint32_t)M)) {  // not a triplet of this data set
+      if (lane == 0) {
+        if (k2f) k2f[c] = __builtin_nanf("");
+        if (k2d) k2d[c] = __builtin_nan("");
+        if (counts)
+          for (int x = 0; x < 54; ++x) counts[c * 54 + x] = 0xffffffffu;
+      }
+      continue;
+    }
+    int tab[2][27];
+    triplet_table(planes, pairs, nullptr, nullptr, EPI3_LAYOUT_SPLIT, Mp, W0, W1, N0, N1, i, j, k,
+                  tab);
+    if (lane == 0) {
+      float f = 0.f;
+      for (int x = 0; x < 27; ++x) {
+        const int r0 = tab[0][x], r1 = tab[1][x];
+        f += lf32[r0 + r1 + 1] - (lf32[r0] + lf32[r1]);
+      }
+      if (k2f) k2f[c] = f;
+      if (k2d) k2d[c] = k2_fp64(tab, lf64);
+      if (counts)
+        for (int x = 0; x < 27; ++x) {
+          counts[c * 54 + x] = (uint32_t)tab[0][x];
+          counts[c * 54 + 27 + x] = (uint32_t)tab[1][x];
+        }
+    }
+  }
+}
+
+hipError_t launch_score_triplets(const epi3_dataset &d, const uint32_t *ijk, int64_t n,
+                                 uint32_t *counts, float *k2f, double *k2, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 3) / 4;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(score_triplets_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                     (const uint32_t *)d.planes, d.pairs, d.lf64, d.lf32, d.n_snps,
+                     (int64_t)d.snp_stride,
+                     d.words[0], d.words[1], d.n_controls, d.n_cases, ijk, n, counts, k2f, k2);
+  return hipGetLastError();
+}
+
+}  // namespace epi3

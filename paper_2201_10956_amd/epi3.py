@@ -1,0 +1,268 @@
+"""Python binding of libepi3 (ctypes).  Argument marshalling only: device
+buffers come from torch, every step of the scan runs in the library's HIP
+kernels.  Importing this module fails when libepi3.so has not been built;
+there is no fallback."""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libepi3.so")
+
+OK, E_INVALID, E_GENOTYPE, E_PHENOTYPE, E_WORKSPACE, E_CAPACITY, E_HIP, E_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6, -7
+LAYOUT_SPLIT, LAYOUT_MASKED = 0, 1
+VARIANT_AUTO, VARIANT_VALU, VARIANT_MFMA = 0, 1, 2
+_VARIANTS = {"auto": VARIANT_AUTO, "valu": VARIANT_VALU, "mfma": VARIANT_MFMA}
+_ERRORS = {E_INVALID: "invalid argument", E_GENOTYPE: "genotype byte outside {0,1,2}",
+           E_PHENOTYPE: "phenotype byte outside {0,1}", E_WORKSPACE: "workspace too small",
+           E_CAPACITY: "candidate capacity exceeded", E_HIP: "HIP runtime error",
+           E_UNSUPPORTED: "unsupported variant/layout"}
+
+
+class Epi3Error(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {_ERRORS.get(code, 'error')} ({code})")
+        self.code = code
+
+
+class CDataset(ctypes.Structure):
+    _fields_ = [("n_snps", ctypes.c_int32), ("n_samples", ctypes.c_int32),
+                ("n_cases", ctypes.c_int32), ("n_controls", ctypes.c_int32),
+                ("words", ctypes.c_int32 * 2), ("layout", ctypes.c_int32),
+                ("snp_stride", ctypes.c_int32), ("byte_stride", ctypes.c_int32),
+                ("reserved", ctypes.c_int32),
+                ("planes", ctypes.c_void_p), ("bytes", ctypes.c_void_p),
+                ("pairs", ctypes.c_void_p), ("lf64", ctypes.c_void_p),
+                ("lf32", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+
+class CHit(ctypes.Structure):
+    _fields_ = [("i", ctypes.c_uint32), ("j", ctypes.c_uint32), ("k", ctypes.c_uint32),
+                ("k2_f32", ctypes.c_float), ("k2", ctypes.c_double),
+                ("counts", (ctypes.c_uint32 * 27) * 2)]
+
+
+class CJob(ctypes.Structure):
+    _fields_ = [("d", ctypes.POINTER(CDataset)), ("case_mask", ctypes.c_void_p),
+                ("k", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+HIT_DTYPE = np.dtype([("i", "<u4"), ("j", "<u4"), ("k", "<u4"), ("k2_f32", "<f4"),
+                      ("k2", "<f8"), ("counts", "<u4", (2, 27))])
+assert HIT_DTYPE.itemsize == ctypes.sizeof(CHit) == 240
+assert ctypes.sizeof(CDataset) == 88 and ctypes.sizeof(CJob) == 24
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2201_10956_amd.build "
+                          "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    P = ctypes.POINTER
+    sigs = {
+        "epi3_encode_bytes": (i64, [i32, i32, i32, i32]),
+        "epi3_encode": (ctypes.c_int, [vp, i64, vp, i32, i32, i32, vp, i64, vp, P(CDataset)]),
+        "epi3_workspace_bytes": (i64, [P(CDataset), i32, i64]),
+        "epi3_scan": (ctypes.c_int, [P(CDataset), i32, i32, i64, vp, i64, vp]),
+        "epi3_topk": (ctypes.c_int, [P(CDataset), i32, i64, vp, vp, P(i32), vp]),
+        "epi3_batched_workspace_bytes": (i64, [P(CJob), i32, i64]),
+        "epi3_scan_batched": (ctypes.c_int, [P(CJob), i32, i32, i64, vp, i64, vp, vp, vp]),
+        "epi3_scan_tables": (ctypes.c_int, [P(CDataset), i32, vp, vp, vp, i64, vp]),
+        "epi3_score_triplets": (ctypes.c_int, [P(CDataset), vp, i64, vp, vp, vp, vp]),
+        "epi3_score_plane": (ctypes.c_int, [P(CDataset), i32, i64, vp, P(vp)]),
+        "epi3_k2_error_bound": (ctypes.c_double, [i32]),
+        "epi3_n_triplets": (i64, [i32]),
+        "epi3_release": (None, []),
+        "epi3_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTS = ("epi3_encode_bytes", "epi3_encode", "epi3_workspace_bytes", "epi3_scan", "epi3_topk",
+           "epi3_batched_workspace_bytes", "epi3_scan_batched", "epi3_scan_tables",
+           "epi3_score_triplets", "epi3_score_plane", "epi3_k2_error_bound", "epi3_n_triplets", "epi3_release",
+           "epi3_version")
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != OK:
+        raise Epi3Error(rc, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _buffer(nbytes: int, device):
+    torch = _torch()
+    # 256-byte aligned device buffer (torch's caching allocator aligns to >= 512 B)
+    t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+    assert t.data_ptr() % 256 == 0
+    return t
+
+
+def version() -> str:
+    return _lib.epi3_version().decode()
+
+
+def n_triplets(M: int) -> int:
+    return int(_lib.epi3_n_triplets(M))
+
+
+def k2_error_bound(N: int) -> float:
+    return float(_lib.epi3_k2_error_bound(N))
+
+
+@dataclass
+class Dataset:
+    c: CDataset
+    buf: object          # torch uint8 tensor owning the device memory
+    geno: object         # keeps the source alive until encode returned
+
+    @property
+    def M(self) -> int:
+        return self.c.n_snps
+
+    @property
+    def N(self) -> int:
+        return self.c.n_samples
+
+
+def encode(geno, pheno, layout: str = "split", stream=None) -> Dataset:
+    """geno: torch uint8 [M][N] on the GPU (rows may be strided); pheno: host uint8 [N]."""
+    torch = _torch()
+    assert geno.dtype == torch.uint8 and geno.dim() == 2 and geno.is_cuda
+    assert geno.stride(1) == 1
+    ph = np.ascontiguousarray(np.asarray(pheno, dtype=np.uint8))
+    M, N = int(geno.shape[0]), int(geno.shape[1])
+    lay = LAYOUT_SPLIT if layout == "split" else LAYOUT_MASKED
+    n1 = int(ph.sum()) if ph.size else 0
+    nbytes = _lib.epi3_encode_bytes(M, n1, N - n1, lay)
+    _check(int(nbytes) if nbytes < 0 else OK, "epi3_encode_bytes")
+    buf = _buffer(nbytes, geno.device)
+    c = CDataset()
+    rc = _lib.epi3_encode(ctypes.c_void_p(geno.data_ptr()), geno.stride(0),
+                          ph.ctypes.data_as(ctypes.c_void_p), M, N, lay,
+                          ctypes.c_void_p(buf.data_ptr()), buf.numel(), _stream(stream),
+                          ctypes.byref(c))
+    _check(rc, "epi3_encode")
+    return Dataset(c=c, buf=buf, geno=geno)
+
+
+def hits_to_numpy(hits: ctypes.Array, n: int) -> np.ndarray:
+    raw = np.frombuffer(hits, dtype=HIT_DTYPE, count=len(hits))
+    return raw[:n].copy()
+
+
+class Scanner:
+    """Workspace + calls for repeated plain scans of one data set."""
+
+    def __init__(self, ds: Dataset, k: int, variant: str = "auto", cand_cap: int = 0):
+        self.ds, self.k, self.variant, self.cand_cap = ds, int(k), _VARIANTS[variant], int(cand_cap)
+        self._alloc()
+
+    def _alloc(self):
+        nbytes = _lib.epi3_workspace_bytes(ctypes.byref(self.ds.c), self.k, self.cand_cap)
+        _check(int(nbytes) if nbytes < 0 else OK, "epi3_workspace_bytes")
+        self.ws = _buffer(nbytes, self.ds.buf.device)
+        self.hits = (CHit * max(self.k, 1))()
+
+    def scan(self, stream=None) -> None:
+        rc = _lib.epi3_scan(ctypes.byref(self.ds.c), self.k, self.variant, self.cand_cap,
+                            ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), _stream(stream))
+        _check(rc, "epi3_scan")
+
+    def topk(self, stream=None) -> np.ndarray:
+        n = ctypes.c_int32(0)
+        rc = _lib.epi3_topk(ctypes.byref(self.ds.c), self.k, self.cand_cap,
+                            ctypes.c_void_p(self.ws.data_ptr()), ctypes.cast(self.hits, ctypes.c_void_p),
+                            ctypes.byref(n), _stream(stream))
+        if rc == E_CAPACITY:
+            raise Epi3Error(rc, f"epi3_topk (needs cand_cap >= {n.value})")
+        _check(rc, "epi3_topk")
+        return hits_to_numpy(self.hits, n.value)
+
+    def run(self, stream=None, retry: bool = True) -> np.ndarray:
+        self.scan(stream)
+        n = ctypes.c_int32(0)
+        rc = _lib.epi3_topk(ctypes.byref(self.ds.c), self.k, self.cand_cap,
+                            ctypes.c_void_p(self.ws.data_ptr()), ctypes.cast(self.hits, ctypes.c_void_p),
+                            ctypes.byref(n), _stream(stream))
+        if rc == E_CAPACITY and retry:
+            self.cand_cap = int(n.value)
+            self._alloc()
+            return self.run(stream, retry=False)
+        _check(rc, "epi3_topk")
+        return hits_to_numpy(self.hits, n.value)
+
+    def score_plane(self):
+        """FP32 K2 of every triplet (lexicographic order): a torch view into the workspace,
+        valid after scan()."""
+        torch = _torch()
+        ptr = ctypes.c_void_p(0)
+        rc = _lib.epi3_score_plane(ctypes.byref(self.ds.c), self.k, self.cand_cap,
+                                   ctypes.c_void_p(self.ws.data_ptr()), ctypes.byref(ptr))
+        _check(rc, "epi3_score_plane")
+        off = (ptr.value or 0) - self.ws.data_ptr()
+        T = n_triplets(self.ds.M)
+        return self.ws[off: off + 4 * T].view(torch.float32)
+
+
+def scan_topk(ds: Dataset, k: int, variant: str = "auto", cand_cap: int = 0, stream=None):
+    return Scanner(ds, k, variant, cand_cap).run(stream)
+
+
+def scan_tables(ds: Dataset, variant: str = "auto", counts: bool = True, stream=None):
+    """(counts [T][2][27] uint32 or None, k2 [T] float32) as torch tensors, lexicographic order."""
+    torch = _torch()
+    T = n_triplets(ds.M)
+    dev = ds.buf.device
+    k2 = torch.empty(max(T, 1), dtype=torch.float32, device=dev)
+    cc = torch.empty((max(T, 1), 2, 27), dtype=torch.int32, device=dev) if counts else None
+    nbytes = _lib.epi3_workspace_bytes(ctypes.byref(ds.c), 1, 0)
+    _check(int(nbytes) if nbytes < 0 else OK, "epi3_workspace_bytes")
+    ws = _buffer(nbytes, dev)
+    rc = _lib.epi3_scan_tables(ctypes.byref(ds.c), _VARIANTS[variant],
+                               ctypes.c_void_p(cc.data_ptr()) if cc is not None else None,
+                               ctypes.c_void_p(k2.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                               ws.numel(), _stream(stream))
+    _check(rc, "epi3_scan_tables")
+    torch.cuda.current_stream().synchronize()
+    return (cc[:T] if cc is not None else None), k2[:T]
+
+
+def score_triplets(ds: Dataset, ijk, stream=None):
+    """Tables, FP32 and FP64 K2 of explicit triplets (numpy int [n][3])."""
+    torch = _torch()
+    idx = torch.as_tensor(np.ascontiguousarray(np.asarray(ijk, dtype=np.uint32).reshape(-1, 3)).view(np.int32),
+                          device=ds.buf.device)
+    n = idx.shape[0]
+    dev = ds.buf.device
+    cc = torch.empty((max(n, 1), 2, 27), dtype=torch.int32, device=dev)
+    kf = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+    kd = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    rc = _lib.epi3_score_triplets(ctypes.byref(ds.c), ctypes.c_void_p(idx.data_ptr()), n,
+                                  ctypes.c_void_p(cc.data_ptr()), ctypes.c_void_p(kf.data_ptr()),
+                                  ctypes.c_void_p(kd.data_ptr()), _stream(stream))
+    _check(rc, "epi3_score_triplets")
+    torch.cuda.current_stream().synchronize()
+    return cc[:n], kf[:n], kd[:n]

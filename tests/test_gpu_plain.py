@@ -1,0 +1,198 @@
+"""GPU parity of the plain scan (encode -> count + K2 -> top-k) against the oracle."""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import CONFIGS, SplitMix64, make_config, make_dataset, manifest_sha256
+from tests.gpu_util import (assert_hits_equal_oracle, assert_k2_close, hits_ijk, lex_rank,
+                            lex_unrank, require_gpu, to_dev)
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def env():
+    return require_gpu()
+
+
+def _tiny(seed, M, N, p_case):
+    u = SplitMix64(seed, 21).uniform(0, M * N + N)
+    geno = np.minimum((u[: M * N] * 3).astype(np.uint8), 2).reshape(M, N)
+    pheno = (u[M * N:] < p_case).astype(np.uint8)
+    return geno, pheno
+
+
+def test_cfg1_every_table_and_score(env):
+    torch, epi3 = env
+    d = make_config(1)
+    ds = epi3.encode(to_dev(d.geno), d.pheno)
+    cc, k2 = epi3.scan_tables(ds, "valu")
+    ref_k2, ref_cc = oracle.scan_all(d.geno, d.pheno)
+    np.testing.assert_array_equal(cc.cpu().numpy(), ref_cc)
+    assert_k2_close(k2.cpu().numpy(), ref_k2, d.n_samples, epi3)
+
+
+def test_cfg1_topk(env):
+    torch, epi3 = env
+    c = CONFIGS[1]
+    d = make_config(1)
+    ds = epi3.encode(to_dev(d.geno), d.pheno)
+    h = epi3.scan_topk(ds, c["k"], "valu")
+    ijk, k2, cc = oracle.scan_topk(d.geno, d.pheno, c["k"])
+    assert_hits_equal_oracle(h, ijk, k2, cc)
+
+
+@pytest.mark.parametrize("M,N,p", [(3, 1, 0.5), (3, 64, 0.0), (4, 33, 1.0), (5, 31, 0.3),
+                                   (9, 95, 0.5), (17, 257, 0.7), (66, 130, 0.45), (130, 70, 0.5)])
+def test_ragged_shapes_every_table(env, M, N, p):
+    torch, epi3 = env
+    geno, pheno = _tiny(1000 * M + N, M, N, p)
+    ds = epi3.encode(to_dev(geno), pheno)
+    cc, k2 = epi3.scan_tables(ds, "valu")
+    ref_k2, ref_cc = oracle.scan_all(geno, pheno)
+    np.testing.assert_array_equal(cc.cpu().numpy(), ref_cc)
+    assert_k2_close(k2.cpu().numpy(), ref_k2, N, epi3)
+    k = min(25, len(ref_k2))
+    h = epi3.scan_topk(ds, k, "valu")
+    ijk, rk2, rcc = oracle.scan_topk(geno, pheno, k)
+    assert_hits_equal_oracle(h, ijk, rk2, rcc)
+
+
+def test_strided_rows_and_identical_snps(env):
+    torch, epi3 = env
+    base, pheno = _tiny(5, 1, 77, 0.5)
+    geno = np.repeat(base, 7, axis=0)
+    big = np.zeros((7, 200), dtype=np.uint8)
+    big[:, :77] = geno
+    g = to_dev(big)[:, :77]          # row stride 200
+    ds = epi3.encode(g, pheno)
+    h = epi3.scan_topk(ds, 35, "valu")
+    assert [tuple(x) for x in hits_ijk(h)] == list(itertools.combinations(range(7), 3))
+    assert np.all(h["k2"] == h["k2"][0])
+
+
+def test_k_larger_than_triplets_and_too_few_snps(env):
+    torch, epi3 = env
+    geno, pheno = _tiny(8, 6, 40, 0.5)
+    ds = epi3.encode(to_dev(geno), pheno)
+    h = epi3.scan_topk(ds, 100, "valu")
+    ijk, k2, cc = oracle.scan_topk(geno, pheno, 100)
+    assert len(h) == 20
+    assert_hits_equal_oracle(h, ijk, k2, cc)
+    ds2 = epi3.encode(to_dev(geno[:2]), pheno)
+    assert len(epi3.scan_topk(ds2, 5, "valu")) == 0
+
+
+def test_bad_genotype_and_phenotype(env):
+    torch, epi3 = env
+    geno, pheno = _tiny(9, 5, 40, 0.5)
+    geno[3, 17] = 3
+    ds = epi3.encode(to_dev(geno), pheno)
+    with pytest.raises(epi3.Epi3Error) as e:
+        epi3.scan_topk(ds, 3, "valu")
+    assert e.value.code == epi3.E_GENOTYPE
+    geno[3, 17] = 1
+    bad = pheno.copy()
+    bad[4] = 2
+    with pytest.raises(epi3.Epi3Error) as e:
+        epi3.encode(to_dev(geno), bad)
+    assert e.value.code == epi3.E_PHENOTYPE
+
+
+def test_capacity_overflow_then_retry(env):
+    torch, epi3 = env
+    d = make_config(1)
+    ds = epi3.encode(to_dev(d.geno), d.pheno)
+    sc = epi3.Scanner(ds, 10, "valu", cand_cap=3)
+    sc.scan()
+    with pytest.raises(epi3.Epi3Error) as e:
+        sc.topk()
+    assert e.value.code == epi3.E_CAPACITY
+    h = sc.run()               # retries with the reported capacity
+    ijk, k2, cc = oracle.scan_topk(d.geno, d.pheno, 10)
+    assert_hits_equal_oracle(h, ijk, k2, cc)
+
+
+def test_cfg2_score_plane_and_topk(env):
+    torch, epi3 = env
+    c = CONFIGS[2]
+    d = make_config(2)
+    ds = epi3.encode(to_dev(d.geno), d.pheno)
+    sc = epi3.Scanner(ds, c["k"], "valu")
+    h = sc.run()
+    ijk, k2, cc = oracle.scan_topk(d.geno, d.pheno, c["k"])
+    assert_hits_equal_oracle(h, ijk, k2, cc)
+    plane = sc.score_plane().cpu().numpy()
+    ref_k2, _ = oracle.scan_all(d.geno, d.pheno, counts=False)
+    assert_k2_close(plane, ref_k2, d.n_samples, epi3)
+    # the FP32 value carried by each hit is the plane's value
+    ranks = [lex_rank(d.n_snps, *x) for x in ijk]
+    np.testing.assert_array_equal(h["k2_f32"], plane[ranks])
+
+
+def test_score_triplets_sampled(env):
+    torch, epi3 = env
+    d = make_config(2)
+    ds = epi3.encode(to_dev(d.geno), d.pheno)
+    u = SplitMix64(77, 0).uniform(0, 3 * 3000).reshape(-1, 3)
+    ijk = np.sort((u * d.n_snps).astype(np.int64), axis=1)
+    keep = (ijk[:, 0] < ijk[:, 1]) & (ijk[:, 1] < ijk[:, 2])
+    ijk = ijk[keep].astype(np.int32)
+    cc, kf, kd = epi3.score_triplets(ds, ijk)
+    rc, rk = oracle.score_list(d.geno, d.pheno, ijk)
+    np.testing.assert_array_equal(cc.cpu().numpy(), rc)
+    np.testing.assert_array_equal(kd.cpu().numpy(), rk)
+    assert_k2_close(kf.cpu().numpy(), rk, d.n_samples, epi3)
+
+
+def test_repeat_runs_bit_identical(env):
+    torch, epi3 = env
+    d = make_config(1)
+    ds = epi3.encode(to_dev(d.geno), d.pheno)
+    sc = epi3.Scanner(ds, 50, "valu")
+    a = sc.run()
+    p1 = sc.score_plane().clone()
+    b = sc.run()
+    p2 = sc.score_plane().clone()
+    assert a.tobytes() == b.tobytes()
+    assert torch.equal(p1, p2)
+
+
+def test_cfg3_full_size(env):
+    """2048 SNPs x 16384 samples, top-1000: hits equal the stored oracle result;
+    sampled scores of the whole plane and sampled tables equal the oracle's."""
+    torch, epi3 = env
+    c = CONFIGS[3]
+    d = make_config(3)
+    ds = epi3.encode(to_dev(d.geno), d.pheno)
+    sc = epi3.Scanner(ds, c["k"], "valu")
+    h = sc.run()
+    fx = os.path.join(GOLDEN, f"oracle_cfg3_top{c['k']}.npz")
+    if os.path.exists(fx):
+        z = np.load(fx)
+        assert str(z["sha256"]) == manifest_sha256([d.geno, d.pheno])
+        assert_hits_equal_oracle(h, z["ijk"], z["k2"], z["counts"])
+    else:  # no stored result: check the hits one by one against the oracle
+        rc, rk = oracle.score_list(d.geno, d.pheno, hits_ijk(h))
+        np.testing.assert_array_equal(h["k2"], rk)
+        np.testing.assert_array_equal(h["counts"].astype(np.int64), rc)
+    plane = sc.score_plane()
+    T = epi3.n_triplets(d.n_snps)
+    u = SplitMix64(33, 0).uniform(0, 4000)
+    ranks = np.unique((u * T).astype(np.int64))
+    M = d.n_snps
+    lex = lex_unrank(M, ranks)
+    rc, rk = oracle.score_list(d.geno, d.pheno, lex)
+    got = plane[torch.as_tensor(ranks, device=plane.device)].cpu().numpy()
+    assert_k2_close(got, rk, d.n_samples, epi3)
+    # every sampled triplet that beats the returned k-th best is among the hits
+    hit_set = set(map(tuple, hits_ijk(h).tolist()))
+    for x in np.nonzero(rk < h["k2"][-1])[0]:
+        assert tuple(lex[x].tolist()) in hit_set
+    cc, kf, kd = epi3.score_triplets(ds, lex)
+    np.testing.assert_array_equal(cc.cpu().numpy(), rc)
+    np.testing.assert_array_equal(kf.cpu().numpy(), got)
