@@ -207,6 +207,15 @@ int64_t epi3_n_triplets(int32_t n_snps);
 /* Release cached graphs. */
 void epi3_release(void);
 
+/* Kernel timing for measurement: while enabled, the library records a HIP
+ * event pair on the call's stream around each launch of the count stage
+ * (which = 0) and of the selection pipeline (which = 1).  epi3_timing_query
+ * waits for the recorded events and returns the summed milliseconds and the
+ * number of launches since the last reset.  Off by default. */
+void epi3_timing_enable(int enable);
+int epi3_timing_query(int32_t which, double *ms, int64_t *launches);
+void epi3_timing_reset(void);
+
 /* Library version string. */
 const char *epi3_version(void);
 

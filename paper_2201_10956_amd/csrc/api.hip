@@ -199,6 +199,52 @@ SelJob make_seljob(const epi3_dataset &d, const float *score, int64_t T, SelStat
 
 int pick_P(const epi3_dataset &d) { return tile_P_default(d.n_snps, d.n_samples); }
 
+// ---- optional kernel timing: HIP events on the call's stream ----
+struct Timing {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[2];  // 0: count kernel, 1: selection
+};
+Timing &timing() {
+  static Timing t;
+  return t;
+}
+
+hipEvent_t take_event() {
+  Timing &t = timing();
+  if (!t.pool.empty()) {
+    hipEvent_t e = t.pool.back();
+    t.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records an event pair around `fn` when timing is on.
+template <typename F>
+int timed(int which, hipStream_t s, F &&fn) {
+  Timing &t = timing();
+  hipEvent_t a = nullptr, b = nullptr;
+  {
+    std::lock_guard<std::mutex> g(t.mu);
+    if (t.on) {
+      a = take_event();
+      b = take_event();
+    }
+  }
+  if (a && b && hipEventRecord(a, s) != hipSuccess) return EPI3_E_HIP;
+  const int rc = fn();
+  if (a && b) {
+    if (hipEventRecord(b, s) != hipSuccess) return EPI3_E_HIP;
+    std::lock_guard<std::mutex> g(t.mu);
+    t.rec[which].push_back({a, b});
+  }
+  return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -299,9 +345,12 @@ static int enqueue_count(const epi3_dataset &d, int32_t variant, float *score, u
   HIP_OK(launch_write_jobs(&J, 1, W.job, s));
   HIP_OK(launch_tile_prefix(W.job, 1, P, s));
   HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
-  HIP_OK(launch_count_valu(W.job, 1, J.n_tiles, W.queue, d.lf32, d.n_samples + 2, P,
-                           counts != nullptr, s));
-  return EPI3_OK;
+  return timed(0, s, [&]() {
+    return launch_count_valu(W.job, 1, J.n_tiles, W.queue, d.lf32, d.n_samples + 2, P,
+                             counts != nullptr, s) == hipSuccess
+               ? EPI3_OK
+               : EPI3_E_HIP;
+  });
 }
 
 int epi3_scan(const epi3_dataset *d, int32_t k, int32_t variant, int64_t cand_cap, void *ws_dev,
@@ -320,8 +369,9 @@ int epi3_scan(const epi3_dataset *d, int32_t k, int32_t variant, int64_t cand_ca
     const int rc = enqueue_count(*d, variant, W.score, nullptr, W, s);
     if (rc != EPI3_OK) return rc;
   }
-  HIP_OK(launch_select(W.sel, 1, T, W.cap, k, s));
-  return EPI3_OK;
+  return timed(1, s, [&]() {
+    return launch_select(W.sel, 1, T, W.cap, k, s) == hipSuccess ? EPI3_OK : EPI3_E_HIP;
+  });
 }
 
 int epi3_topk(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev, epi3_hit *hits_host,
@@ -396,5 +446,40 @@ int epi3_scan_batched(const epi3_job *jobs, int32_t n_jobs, int32_t variant, int
 }
 
 void epi3_release(void) {}
+
+void epi3_timing_enable(int enable) {
+  Timing &t = timing();
+  std::lock_guard<std::mutex> g(t.mu);
+  t.on = enable != 0;
+}
+
+int epi3_timing_query(int32_t which, double *ms, int64_t *launches) {
+  if (which < 0 || which > 1 || !ms || !launches) return EPI3_E_INVALID;
+  Timing &t = timing();
+  std::lock_guard<std::mutex> g(t.mu);
+  double sum = 0.0;
+  for (auto &p : t.rec[which]) {
+    if (hipEventSynchronize(p.second) != hipSuccess) return EPI3_E_HIP;
+    float x = 0.f;
+    if (hipEventElapsedTime(&x, p.first, p.second) != hipSuccess) return EPI3_E_HIP;
+    sum += x;
+  }
+  *ms = sum;
+  *launches = (int64_t)t.rec[which].size();
+  return EPI3_OK;
+}
+
+void epi3_timing_reset(void) {
+  Timing &t = timing();
+  std::lock_guard<std::mutex> g(t.mu);
+  for (auto &r : t.rec) {
+    for (auto &p : r) {
+      hipEventSynchronize(p.second);
+      t.pool.push_back(p.first);
+      t.pool.push_back(p.second);
+    }
+    r.clear();
+  }
+}
 
 }  // extern "C"

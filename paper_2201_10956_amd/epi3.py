@@ -80,6 +80,9 @@ def _load():
         "epi3_k2_error_bound": (ctypes.c_double, [i32]),
         "epi3_n_triplets": (i64, [i32]),
         "epi3_release": (None, []),
+        "epi3_timing_enable": (None, [ctypes.c_int]),
+        "epi3_timing_query": (ctypes.c_int, [i32, P(ctypes.c_double), P(i64)]),
+        "epi3_timing_reset": (None, []),
         "epi3_version": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sigs.items():
@@ -93,7 +96,7 @@ _lib = _load()
 EXPORTS = ("epi3_encode_bytes", "epi3_encode", "epi3_workspace_bytes", "epi3_scan", "epi3_topk",
            "epi3_batched_workspace_bytes", "epi3_scan_batched", "epi3_scan_tables",
            "epi3_score_triplets", "epi3_score_plane", "epi3_k2_error_bound", "epi3_n_triplets", "epi3_release",
-           "epi3_version")
+           "epi3_version", "epi3_timing_enable", "epi3_timing_query", "epi3_timing_reset")
 
 
 def _check(rc: int, where: str) -> None:
@@ -122,6 +125,22 @@ def _buffer(nbytes: int, device):
 
 def version() -> str:
     return _lib.epi3_version().decode()
+
+
+def timing_enable(on: bool = True) -> None:
+    _lib.epi3_timing_enable(1 if on else 0)
+
+
+def timing_reset() -> None:
+    _lib.epi3_timing_reset()
+
+
+def timing_query(which: int = 0):
+    """(summed ms, launches) of the count stage (0) or selection (1) since the last reset."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(_lib.epi3_timing_query(which, ctypes.byref(ms), ctypes.byref(n)), "epi3_timing_query")
+    return ms.value, n.value
 
 
 def n_triplets(M: int) -> int:
