@@ -185,6 +185,8 @@ SelJob make_seljob(const epi3_dataset &d, const float *score, int64_t T, SelStat
   S.pairs = d.pairs;
   S.case_pairs = nullptr;
   S.case_mask = nullptr;
+  S.n1_dev = nullptr;
+  S.case_stride = 1;
   S.lf64 = d.lf64;
   S.M = d.n_snps;
   S.Mp = d.snp_stride;
@@ -204,7 +206,7 @@ struct Timing {
   std::mutex mu;
   bool on = false;
   std::vector<hipEvent_t> pool;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[2];  // 0: count kernel, 1: selection
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[3];  // 0: count, 1: selection, 2: batched graph
 };
 Timing &timing() {
   static Timing t;
@@ -432,20 +434,322 @@ int epi3_score_triplets(const epi3_dataset *d, const uint32_t *ijk_dev, int64_t 
   return EPI3_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+constexpr int kPermGroup = 64;  // phenotypes per matrix-core launch
+
+// Workspace of a batched scan.
+struct BatchLayout {
+  int n = 0, layout = 0, groups = 0;
+  Job *jobs = nullptr;            // SPLIT
+  PermJob *pjobs = nullptr;       // MASKED, one per group of 64 phenotypes
+  SelJob *sel = nullptr;
+  SelState *st = nullptr;
+  uint32_t *hist = nullptr;
+  unsigned long long *queue = nullptr;
+  const uint32_t **masks = nullptr;
+  uint8_t *ph = nullptr;          // MASKED: [groups][64][S]
+  int32_t *n1 = nullptr;          // MASKED: [groups][64]
+  int32_t *case_pairs = nullptr;  // MASKED: [groups][Mp][Mp][64][4]
+  int64_t *perm_prefix = nullptr; // MASKED: [M + 1]
+  epi3_hit *hits = nullptr;       // [sum k]
+  std::vector<int64_t *> jprefix; // SPLIT, per job
+  std::vector<float *> score;
+  std::vector<int64_t *> cand;
+  std::vector<CandRec *> rec;
+  std::vector<int64_t> cap, hit_off, T;
+  int64_t total_k = 0, total = 0;
+};
+
+bool same_dataset(const epi3_dataset *a, const epi3_dataset *b) {
+  return a->planes == b->planes && a->n_snps == b->n_snps && a->n_samples == b->n_samples &&
+         a->layout == b->layout;
+}
+
+int check_jobs(const epi3_job *jobs, int32_t n) {
+  if (!jobs || n <= 0) return EPI3_E_INVALID;
+  const int layout = jobs[0].d ? jobs[0].d->layout : -1;
+  for (int x = 0; x < n; ++x) {
+    const epi3_job &J = jobs[x];
+    if (!valid_dataset(J.d) || J.k <= 0 || J.d->layout != layout) return EPI3_E_INVALID;
+    if (layout == EPI3_LAYOUT_SPLIT && J.case_mask) return EPI3_E_INVALID;
+    if (layout == EPI3_LAYOUT_MASKED) {
+      if (!J.case_mask || !J.d->bytes || !same_dataset(J.d, jobs[0].d)) return EPI3_E_INVALID;
+    }
+  }
+  return EPI3_OK;
+}
+
+BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand_cap) {
+  BatchLayout L;
+  L.n = n;
+  L.layout = jobs[0].d->layout;
+  Carver c(ws);
+  L.sel = c.take<SelJob>(n);
+  L.st = c.take<SelState>(n);
+  L.hist = c.take<uint32_t>((int64_t)n * kHistBins);
+  L.queue = c.take<unsigned long long>(4);
+  L.hit_off.resize(n);
+  for (int x = 0; x < n; ++x) {
+    L.hit_off[x] = L.total_k;
+    L.total_k += jobs[x].k;
+  }
+  L.hits = c.take<epi3_hit>(L.total_k);
+  if (L.layout == EPI3_LAYOUT_SPLIT) {
+    L.jobs = c.take<Job>(n);
+  } else {
+    const epi3_dataset &d = *jobs[0].d;
+    L.groups = (n + kPermGroup - 1) / kPermGroup;
+    L.pjobs = c.take<PermJob>(L.groups);
+    L.masks = c.take<const uint32_t *>((int64_t)L.groups * kPermGroup);
+    L.ph = c.take<uint8_t>((int64_t)L.groups * kPermGroup * d.byte_stride);
+    L.n1 = c.take<int32_t>((int64_t)L.groups * kPermGroup);
+    L.case_pairs = c.take<int32_t>((int64_t)L.groups * d.snp_stride * d.snp_stride * kPermGroup * 4);
+    L.perm_prefix = c.take<int64_t>((int64_t)d.n_snps + 1);
+  }
+  L.jprefix.resize(n);
+  L.score.resize(n);
+  L.cand.resize(n);
+  L.rec.resize(n);
+  L.cap.resize(n);
+  L.T.resize(n);
+  for (int x = 0; x < n; ++x) {
+    L.T[x] = epi3_n_triplets(jobs[x].d->n_snps);
+    L.cap[x] = default_cap(L.T[x], jobs[x].k, cand_cap);
+  }
+  if (L.layout == EPI3_LAYOUT_MASKED) {
+    // one block [n][T]: the matrix-core kernel addresses phenotype q at q * T
+    float *all = c.take<float>((int64_t)n * L.T[0]);
+    for (int x = 0; x < n; ++x) L.score[x] = all ? all + (int64_t)x * L.T[0] : nullptr;
+  }
+  for (int x = 0; x < n; ++x) {
+    const epi3_dataset &d = *jobs[x].d;
+    if (L.layout == EPI3_LAYOUT_SPLIT) {
+      L.jprefix[x] = c.take<int64_t>((int64_t)d.n_snps + 1);
+      L.score[x] = c.take<float>(L.T[x]);
+    }
+    L.cand[x] = c.take<int64_t>(L.cap[x]);
+    L.rec[x] = c.take<CandRec>(L.cap[x]);
+  }
+  L.total = c.size();
+  return L;
+}
+
+// Enqueues the whole batched scan (no host synchronisation inside).
+int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, hipStream_t s) {
+  // selection state first: the count kernels write each job's key range into it
+  std::vector<SelJob> sj(n);
+  for (int x = 0; x < n; ++x) {
+    const epi3_dataset &d = *jobs[x].d;
+    sj[x] = make_seljob(d, W.score[x], W.T[x], W.st + x, W.hist + (int64_t)x * kHistBins,
+                        W.cand[x], W.rec[x], W.hits + W.hit_off[x], W.cap[x], jobs[x].k);
+    if (W.layout == EPI3_LAYOUT_MASKED) {
+      const int g = x / kPermGroup, q = x % kPermGroup;
+      sj[x].case_mask = jobs[x].case_mask;
+      sj[x].case_pairs = W.case_pairs +
+                         ((int64_t)g * d.snp_stride * d.snp_stride * kPermGroup + q) * 4;
+      sj[x].case_stride = kPermGroup;
+      sj[x].n1_dev = W.n1 + (int64_t)g * kPermGroup + q;
+    }
+  }
+  HIP_OK(launch_write_seljobs(sj.data(), n, W.sel, s));
+  HIP_OK(launch_init_select(W.sel, n, s));
+
+  int64_t max_T = 0, max_cap = 0;
+  int32_t max_k = 0;
+  for (int x = 0; x < n; ++x) {
+    max_T = std::max(max_T, W.T[x]);
+    max_cap = std::max(max_cap, W.cap[x]);
+    max_k = std::max(max_k, jobs[x].k);
+  }
+
+  if (W.layout == EPI3_LAYOUT_SPLIT) {
+    // one persistent launch over every job's tiles; jobs with the most
+    // samples per tile first so the queue ends on the cheapest tiles
+    std::vector<int> order(n);
+    for (int x = 0; x < n; ++x) order[x] = x;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      const epi3_dataset &da = *jobs[a].d, &db = *jobs[b].d;
+      return da.words[0] + da.words[1] > db.words[0] + db.words[1];
+    });
+    int P = 8;
+    int32_t lf_len = 2;
+    const float *lf32 = nullptr;
+    for (int x = 0; x < n; ++x) {
+      P = std::min(P, pick_P(*jobs[x].d));
+      if (jobs[x].d->n_samples + 2 > lf_len) {
+        lf_len = jobs[x].d->n_samples + 2;
+        lf32 = jobs[x].d->lf32;
+      }
+    }
+    std::vector<Job> J(n);
+    int64_t begin = 0;
+    for (int y = 0; y < n; ++y) {
+      const int x = order[y];
+      J[y] = make_job(*jobs[x].d, W.score[x], nullptr, W.jprefix[x], &W.st[x].kmin, P);
+      J[y].tile_begin = begin;
+      begin += J[y].n_tiles;
+    }
+    HIP_OK(launch_write_jobs(J.data(), n, W.jobs, s));
+    HIP_OK(launch_tile_prefix(W.jobs, n, P, s));
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
+    if (begin > 0) HIP_OK(launch_count_valu(W.jobs, n, begin, W.queue, lf32, lf_len, P, false, s));
+  } else {
+    const epi3_dataset &d = *jobs[0].d;
+    std::vector<const uint32_t *> masks((size_t)W.groups * kPermGroup, nullptr);
+    for (int x = 0; x < n; ++x) masks[x] = jobs[x].case_mask;
+    for (int x = n; x < (int)masks.size(); ++x) masks[x] = jobs[0].case_mask;  // never read
+    HIP_OK(launch_write_ptrs(masks.data(), (int32_t)masks.size(), W.masks, s));
+    const int64_t tiles = host_perm_tiles(d.n_snps);
+    for (int g = 0; g < W.groups; ++g) {
+      const int Q = std::min(kPermGroup, n - g * kPermGroup);
+      PermJob pj{};
+      pj.bytes = static_cast<const uint8_t *>(d.bytes);
+      pj.ph = W.ph + (int64_t)g * kPermGroup * d.byte_stride;
+      pj.tot_pairs = d.pairs;
+      pj.case_pairs = W.case_pairs + (int64_t)g * d.snp_stride * d.snp_stride * kPermGroup * 4;
+      pj.n1 = W.n1 + (int64_t)g * kPermGroup;
+      pj.score = W.score[g * kPermGroup];
+      pj.jprefix = W.perm_prefix;
+      pj.n_tiles = tiles;
+      pj.T = epi3_n_triplets(d.n_snps);
+      pj.M = d.n_snps;
+      pj.Mp = d.snp_stride;
+      pj.S = d.byte_stride;
+      pj.N = d.n_samples;
+      pj.Q = Q;
+      pj.Qp = kPermGroup;
+      HIP_OK(launch_write_permjob(pj, W.pjobs + g, s));
+      HIP_OK(launch_mask_bytes(W.masks + (int64_t)g * kPermGroup, Q, kPermGroup, d.n_samples,
+                               d.byte_stride, const_cast<uint8_t *>(pj.ph),
+                               const_cast<int32_t *>(pj.n1), s));
+      HIP_OK(launch_case_pairs(static_cast<const uint32_t *>(d.planes), d.snp_stride, d.words[0],
+                               W.masks + (int64_t)g * kPermGroup, Q, kPermGroup,
+                               const_cast<int32_t *>(pj.case_pairs), s));
+      if (g == 0) HIP_OK(launch_perm_prefix(W.pjobs, s));
+      HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
+      if (tiles > 0)
+        HIP_OK(launch_count_mfma_perm(W.pjobs + g, tiles, W.st + (int64_t)g * kPermGroup, W.queue,
+                                      d.lf32, d.n_samples + 2, s));
+    }
+  }
+  HIP_OK(launch_select(W.sel, n, max_T, max_cap, max_k, s));
+  return EPI3_OK;
+}
+
+// Graphs cached per job signature.
+struct GraphCache {
+  std::mutex mu;
+  std::map<std::vector<uint64_t>, hipGraphExec_t> exec;
+  hipStream_t capture = nullptr;
+};
+GraphCache &graphs() {
+  static GraphCache g;
+  return g;
+}
+
+std::vector<uint64_t> signature(const epi3_job *jobs, int32_t n, int32_t variant, int64_t cap,
+                                void *ws, int64_t ws_bytes) {
+  std::vector<uint64_t> sig;
+  sig.push_back((uint64_t)n);
+  sig.push_back((uint64_t)variant);
+  sig.push_back((uint64_t)cap);
+  sig.push_back((uint64_t)(uintptr_t)ws);
+  sig.push_back((uint64_t)ws_bytes);
+  for (int x = 0; x < n; ++x) {
+    const epi3_dataset &d = *jobs[x].d;
+    const uint64_t *raw = reinterpret_cast<const uint64_t *>(&d);
+    for (size_t w = 0; w < sizeof(epi3_dataset) / 8; ++w) sig.push_back(raw[w]);
+    sig.push_back((uint64_t)(uintptr_t)jobs[x].case_mask);
+    sig.push_back((uint64_t)jobs[x].k);
+  }
+  return sig;
+}
+
+}  // namespace
+
+extern "C" {
+
 int64_t epi3_batched_workspace_bytes(const epi3_job *jobs, int32_t n_jobs, int64_t cand_cap) {
-  (void)jobs; (void)n_jobs; (void)cand_cap;
-  return EPI3_E_UNSUPPORTED;
+  const int rc = check_jobs(jobs, n_jobs);
+  if (rc != EPI3_OK) return rc;
+  return batch_layout(nullptr, jobs, n_jobs, cand_cap).total;
 }
 
 int epi3_scan_batched(const epi3_job *jobs, int32_t n_jobs, int32_t variant, int64_t cand_cap,
                       void *ws_dev, int64_t ws_bytes, epi3_hit *hits_host, int32_t *n_out_host,
                       void *stream) {
-  (void)jobs; (void)n_jobs; (void)variant; (void)cand_cap; (void)ws_dev; (void)ws_bytes;
-  (void)hits_host; (void)n_out_host; (void)stream;
-  return EPI3_E_UNSUPPORTED;
+  int rc = check_jobs(jobs, n_jobs);
+  if (rc != EPI3_OK) return rc;
+  if (!ws_dev || !hits_host || !n_out_host) return EPI3_E_INVALID;
+  if (reinterpret_cast<uintptr_t>(ws_dev) % kAlign) return EPI3_E_INVALID;
+  const int layout = jobs[0].d->layout;
+  if (layout == EPI3_LAYOUT_SPLIT && variant == EPI3_VARIANT_MFMA) return EPI3_E_UNSUPPORTED;
+  if (layout == EPI3_LAYOUT_MASKED && variant == EPI3_VARIANT_VALU) return EPI3_E_UNSUPPORTED;
+  BatchLayout W = batch_layout(ws_dev, jobs, n_jobs, cand_cap);
+  if (ws_bytes < W.total) return EPI3_E_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  GraphCache &G = graphs();
+  hipGraphExec_t exec = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(G.mu);
+    const auto sig = signature(jobs, n_jobs, variant, cand_cap, ws_dev, ws_bytes);
+    auto it = G.exec.find(sig);
+    if (it != G.exec.end()) {
+      exec = it->second;
+    } else {
+      if (!G.capture) HIP_OK(hipStreamCreateWithFlags(&G.capture, hipStreamNonBlocking));
+      HIP_OK(hipStreamBeginCapture(G.capture, hipStreamCaptureModeRelaxed));
+      rc = enqueue_batched(jobs, n_jobs, W, G.capture);
+      hipGraph_t graph = nullptr;
+      const hipError_t e = hipStreamEndCapture(G.capture, &graph);
+      if (rc != EPI3_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc != EPI3_OK ? rc : EPI3_E_HIP;
+      }
+      const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) return EPI3_E_HIP;
+      G.exec[sig] = exec;
+    }
+  }
+  rc = timed(2, s, [&]() { return hipGraphLaunch(exec, s) == hipSuccess ? EPI3_OK : EPI3_E_HIP; });
+  if (rc != EPI3_OK) return rc;
+
+  std::vector<SelState> st(n_jobs);
+  HIP_OK(hipMemcpyAsync(st.data(), W.st, sizeof(SelState) * n_jobs, hipMemcpyDeviceToHost, s));
+  std::vector<int32_t> status(n_jobs, 0);
+  for (int x = 0; x < n_jobs; ++x)
+    HIP_OK(hipMemcpyAsync(&status[x], jobs[x].d->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(hits_host, W.hits, sizeof(epi3_hit) * W.total_k, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  int worst = EPI3_OK;
+  for (int x = 0; x < n_jobs; ++x) {
+    n_out_host[x] = (int32_t)st[x].keff;
+    if (status[x] & 1) {
+      n_out_host[x] = 0;
+      worst = EPI3_E_GENOTYPE;
+    } else if ((int64_t)st[x].ncand > W.cap[x]) {
+      n_out_host[x] = -(int32_t)std::min<unsigned long long>(st[x].ncand, 0x7fffffffull);
+      if (worst == EPI3_OK) worst = EPI3_E_CAPACITY;
+    }
+  }
+  return worst;
 }
 
-void epi3_release(void) {}
+void epi3_release(void) {
+  GraphCache &G = graphs();
+  std::lock_guard<std::mutex> lk(G.mu);
+  for (auto &kv : G.exec) (void)hipGraphExecDestroy(kv.second);
+  G.exec.clear();
+  if (G.capture) {
+    (void)hipStreamDestroy(G.capture);
+    G.capture = nullptr;
+  }
+}
 
 void epi3_timing_enable(int enable) {
   Timing &t = timing();
@@ -454,7 +758,7 @@ void epi3_timing_enable(int enable) {
 }
 
 int epi3_timing_query(int32_t which, double *ms, int64_t *launches) {
-  if (which < 0 || which > 1 || !ms || !launches) return EPI3_E_INVALID;
+  if (which < 0 || which > 2 || !ms || !launches) return EPI3_E_INVALID;
   Timing &t = timing();
   std::lock_guard<std::mutex> g(t.mu);
   double sum = 0.0;

@@ -89,6 +89,20 @@ struct CandRec {
   uint32_t counts[54];
 };
 
+// Phenotype batch for the matrix-core kernel: one MASKED data set and up to
+// 64 phenotypes (case masks).
+struct PermJob {
+  const uint8_t *bytes;       // [Mp][2][S] 0/1 genotype bytes
+  const uint8_t *ph;          // [64][S] 0/1 case bytes per phenotype
+  const int32_t *tot_pairs;   // [Mp][Mp][4] pairwise tables over all samples
+  const int32_t *case_pairs;  // [Mp][Mp][Qp][4] pairwise tables over each phenotype's cases
+  const int32_t *n1;          // [Qp] cases per phenotype
+  float *score;               // [Q][T]
+  const int64_t *jprefix;     // [M + 1]
+  int64_t n_tiles, T;
+  int32_t M, Mp, S, N, Q, Qp;
+};
+
 // Selection job: one score plane plus its candidate buffers.
 struct SelJob {
   const float *score;
@@ -103,8 +117,11 @@ struct SelJob {
   // data needed to recount a candidate
   const uint32_t *planes;
   const int32_t *pairs;    // [classes][Mp][Mp][4]; MASKED: totals at class 0
-  const int32_t *case_pairs; // MASKED: [Mp][Mp][4] case pairs of the job's mask, else NULL
+  const int32_t *case_pairs; // MASKED: case pairs of the job's mask (pair (x,y) at
+                             // int4 index (x * Mp + y) * case_stride), else NULL
   const uint32_t *case_mask; // MASKED: [W] mask words, else NULL
+  const int32_t *n1_dev;     // MASKED: device count of cases (overrides N1), else NULL
+  int64_t case_stride;
   const double *lf64;
   int32_t M, Mp, W0, W1, N0, N1;
   int32_t layout;
@@ -176,6 +193,20 @@ hipError_t launch_write_seljobs(const SelJob *h, int32_t n, SelJob *dst_dev, hip
 hipError_t launch_init_select(SelJob *sel_dev, int32_t n_jobs, hipStream_t s);
 hipError_t launch_score_triplets(const epi3_dataset &d, const uint32_t *ijk, int64_t n,
                                  uint32_t *counts, float *k2f, double *k2, hipStream_t s);
+
+hipError_t launch_perm_prefix(PermJob *pj_dev, hipStream_t s);
+hipError_t launch_mask_bytes(const uint32_t *const *masks_dev, int32_t Q, int32_t Qp, int32_t N,
+                             int32_t S, uint8_t *ph, int32_t *n1, hipStream_t s);
+hipError_t launch_case_pairs(const uint32_t *planes, int32_t Mp, int32_t W,
+                             const uint32_t *const *masks_dev, int32_t Q, int32_t Qp, int32_t *out,
+                             hipStream_t s);
+int64_t host_perm_tiles(int64_t M);
+hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t n_tiles, SelState *st,
+                                  unsigned long long *queue, const float *lf32, int32_t lf_len,
+                                  hipStream_t s);
+hipError_t launch_write_permjob(const PermJob &h, PermJob *dst_dev, hipStream_t s);
+hipError_t launch_write_ptrs(const uint32_t *const *h, int32_t n, const uint32_t **dst_dev,
+                             hipStream_t s);
 
 int tile_P_default(int32_t M, int32_t N);
 

@@ -206,12 +206,12 @@ __device__ __forceinline__ void corners(const uint32_t *planes, int64_t Mp, int 
 
 __device__ __forceinline__ void pair_args(const int32_t *pairs, int64_t Mp, int i, int j, int k,
                                           int aij[4], int aik[4], int ajk[4], int mi[2], int mj[2],
-                                          int mk[2]) {
+                                          int mk[2], int64_t st = 1) {
   const int4 *pr = reinterpret_cast<const int4 *>(pairs);
-  const int4 pij = pr[(int64_t)i * Mp + j], pik = pr[(int64_t)i * Mp + k],
-             pjk = pr[(int64_t)j * Mp + k];
-  const int4 ii = pr[(int64_t)i * Mp + i], jj = pr[(int64_t)j * Mp + j],
-             kk = pr[(int64_t)k * Mp + k];
+  const int4 pij = pr[((int64_t)i * Mp + j) * st], pik = pr[((int64_t)i * Mp + k) * st],
+             pjk = pr[((int64_t)j * Mp + k) * st];
+  const int4 ii = pr[((int64_t)i * Mp + i) * st], jj = pr[((int64_t)j * Mp + j) * st],
+             kk = pr[((int64_t)k * Mp + k) * st];
   aij[0] = pij.x; aij[1] = pij.y; aij[2] = pij.z; aij[3] = pij.w;
   aik[0] = pik.x; aik[1] = pik.y; aik[2] = pik.z; aik[3] = pik.w;
   ajk[0] = pjk.x; ajk[1] = pjk.y; ajk[2] = pjk.z; ajk[3] = pjk.w;
@@ -223,9 +223,9 @@ __device__ __forceinline__ void pair_args(const int32_t *pairs, int64_t Mp, int 
 // MASKED: totals from all words and pairs[0]; cases with the mask and
 // case_pairs; controls = totals - cases.
 __device__ void triplet_table(const uint32_t *planes, const int32_t *pairs,
-                              const int32_t *case_pairs, const uint32_t *mask, int layout,
-                              int64_t Mp, int W0, int W1, int N0, int N1, int i, int j, int k,
-                              int tab[2][27]) {
+                              const int32_t *case_pairs, int64_t case_stride,
+                              const uint32_t *mask, int layout, int64_t Mp, int W0, int W1,
+                              int N0, int N1, int i, int j, int k, int tab[2][27]) {
   int aij[4], aik[4], ajk[4], mi[2], mj[2], mk[2];
   uint32_t n[8];
   if (layout == EPI3_LAYOUT_SPLIT) {
@@ -240,7 +240,7 @@ __device__ void triplet_table(const uint32_t *planes, const int32_t *pairs,
     pair_args(pairs, Mp, i, j, k, aij, aik, ajk, mi, mj, mk);
     complete_table(n, aij, aik, ajk, mi, mj, mk, N0 + N1, tot);
     corners(planes, Mp, 0, W0, i, j, k, mask, n);
-    pair_args(case_pairs, Mp, i, j, k, aij, aik, ajk, mi, mj, mk);
+    pair_args(case_pairs, Mp, i, j, k, aij, aik, ajk, mi, mj, mk, case_stride);
     complete_table(n, aij, aik, ajk, mi, mj, mk, N1, tab[1]);
     for (int x = 0; x < 27; ++x) tab[0][x] = tot[x] - tab[1][x];
   }
@@ -269,8 +269,13 @@ __global__ void __launch_bounds__(256) rescore_kernel(const SelJob *__restrict__
     int i, j, k;
     decode_rank(J.M, rank, i, j, k);
     int tab[2][27];
-    triplet_table(J.planes, J.pairs, J.case_pairs, J.case_mask, J.layout, J.Mp, J.W0, J.W1, J.N0,
-                  J.N1, i, j, k, tab);
+    int N0 = J.N0, N1 = J.N1;
+    if (J.n1_dev) {
+      N1 = *J.n1_dev;
+      N0 = J.N0 + J.N1 - N1;
+    }
+    triplet_table(J.planes, J.pairs, J.case_pairs, J.case_stride, J.case_mask, J.layout, J.Mp,
+                  J.W0, J.W1, N0, N1, i, j, k, tab);
     if (lane == 0) {
       CandRec &R = J.rec[c];
       const double k2 = k2_fp64(tab, J.lf64);
@@ -392,8 +397,8 @@ __global__ void __launch_bounds__(256) score_triplets_kernel(
       continue;
     }
     int tab[2][27];
-    triplet_table(planes, pairs, nullptr, nullptr, EPI3_LAYOUT_SPLIT, Mp, W0, W1, N0, N1, i, j, k,
-                  tab);
+    triplet_table(planes, pairs, nullptr, 1, nullptr, EPI3_LAYOUT_SPLIT, Mp, W0, W1, N0, N1, i, j,
+                  k, tab);
     if (lane == 0) {
       float f = 0.f;
       for (int x = 0; x < 27; ++x) {

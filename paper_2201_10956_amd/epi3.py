@@ -285,3 +285,83 @@ def score_triplets(ds: Dataset, ijk, stream=None):
     _check(rc, "epi3_score_triplets")
     torch.cuda.current_stream().synchronize()
     return cc[:n], kf[:n], kd[:n]
+
+
+def pack_masks(phenos) -> np.ndarray:
+    """Host uint8 [Q][N] case indicators -> uint32 [Q][ceil(N/32)] bit masks
+    (bit s % 32 of word s / 32 is sample s)."""
+    ph = np.ascontiguousarray(np.asarray(phenos, dtype=np.uint8))
+    if ph.ndim == 1:
+        ph = ph[None]
+    Q, N = ph.shape
+    W = (N + 31) // 32
+    padded = np.zeros((Q, W * 32), dtype=np.uint8)
+    padded[:, :N] = ph
+    return np.packbits(padded, axis=1, bitorder="little").view("<u4").reshape(Q, W)
+
+
+class BatchScanner:
+    """One batched launch over several jobs.
+
+    split: `datasets` is a list of SPLIT Datasets (each with its own phenotype).
+    masked: `datasets` is one MASKED Dataset and `masks` a device uint32 tensor
+    [Q][W] of case masks (see pack_masks); job q scans phenotype q."""
+
+    def __init__(self, datasets, k, masks=None, variant: str = "auto", cand_cap: int = 0):
+        torch = _torch()
+        self.variant, self.cand_cap = _VARIANTS[variant], int(cand_cap)
+        if masks is None:
+            self.ds_list = list(datasets)
+            ks = [int(k)] * len(self.ds_list) if np.isscalar(k) else [int(x) for x in k]
+            self.jobs = (CJob * len(self.ds_list))()
+            for x, d in enumerate(self.ds_list):
+                self.jobs[x].d = ctypes.pointer(d.c)
+                self.jobs[x].case_mask = None
+                self.jobs[x].k = ks[x]
+            device = self.ds_list[0].buf.device
+        else:
+            ds = datasets
+            self.ds_list = [ds]
+            assert masks.dtype == torch.int32 or masks.dtype == torch.uint32 or masks.dtype == torch.int64
+            self.masks = masks.contiguous()
+            Q = int(self.masks.shape[0])
+            ks = [int(k)] * Q if np.isscalar(k) else [int(x) for x in k]
+            self.jobs = (CJob * Q)()
+            row = self.masks.stride(0) * self.masks.element_size()
+            for q in range(Q):
+                self.jobs[q].d = ctypes.pointer(ds.c)
+                self.jobs[q].case_mask = ctypes.c_void_p(self.masks.data_ptr() + q * row)
+                self.jobs[q].k = ks[q]
+            device = ds.buf.device
+        self.ks = ks
+        self.device = device
+        self._alloc()
+
+    def _alloc(self):
+        nbytes = _lib.epi3_batched_workspace_bytes(self.jobs, len(self.jobs), self.cand_cap)
+        _check(int(nbytes) if nbytes < 0 else OK, "epi3_batched_workspace_bytes")
+        self.ws = _buffer(nbytes, self.device)
+        self.hits = (CHit * sum(self.ks))()
+        self.n_out = (ctypes.c_int32 * len(self.jobs))()
+
+    def run(self, stream=None, retry: bool = True):
+        rc = _lib.epi3_scan_batched(self.jobs, len(self.jobs), self.variant, self.cand_cap,
+                                    ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                    ctypes.cast(self.hits, ctypes.c_void_p),
+                                    ctypes.cast(self.n_out, ctypes.c_void_p), _stream(stream))
+        if rc == E_CAPACITY and retry:
+            need = max(-int(v) for v in self.n_out)
+            self.cand_cap = max(self.cand_cap, need)
+            self._alloc()
+            return self.run(stream, retry=False)
+        _check(rc, "epi3_scan_batched")
+        out, off = [], 0
+        allh = np.frombuffer(self.hits, dtype=HIT_DTYPE, count=sum(self.ks))
+        for x, kk in enumerate(self.ks):
+            out.append(allh[off: off + int(self.n_out[x])].copy())
+            off += kk
+        return out
+
+
+def release() -> None:
+    _lib.epi3_release()

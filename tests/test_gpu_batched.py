@@ -1,0 +1,125 @@
+"""GPU parity of the batched scans (many data sets / many phenotypes in one
+graph-captured persistent launch) against the oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import CONFIGS, SplitMix64, make_config, make_dataset, make_permutations, make_uneven
+from tests.gpu_util import assert_hits_equal_oracle, hits_ijk, require_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def env():
+    return require_gpu()
+
+
+def _masks(epi3, perms):
+    import torch
+    return torch.from_numpy(epi3.pack_masks(perms).view(np.int32)).to("cuda")
+
+
+def test_uneven_datasets_one_launch(env):
+    torch, epi3 = env
+    ds_host = make_uneven(6, seed=77, scale=0.06)   # 7..61 SNPs x 61..983 samples
+    ds = [epi3.encode(to_dev(d.geno), d.pheno) for d in ds_host]
+    ks = [5, 1, 17, 3, 9, 30]
+    bs = epi3.BatchScanner(ds, ks, variant="valu")
+    res = bs.run()
+    for d, h, k in zip(ds_host, res, ks):
+        ijk, k2, cc = oracle.scan_topk(d.geno, d.pheno, k)
+        assert_hits_equal_oracle(h, ijk, k2, cc)
+
+
+def test_uneven_graph_replays_match_eager(env):
+    torch, epi3 = env
+    ds_host = make_uneven(4, seed=78, scale=0.08)
+    ds = [epi3.encode(to_dev(d.geno), d.pheno) for d in ds_host]
+    bs = epi3.BatchScanner(ds, 7, variant="valu")
+    eager = [epi3.scan_topk(d, 7, "valu") for d in ds]
+    for rep in range(3):
+        res = bs.run()
+        for a, b in zip(res, eager):
+            assert a.tobytes() == b.tobytes(), rep
+        # unrelated eager work between replays
+        x = torch.randn(1 << 20, device="cuda")
+        torch.cuda.synchronize()
+        assert float(x.abs().sum()) > 0
+
+
+@pytest.mark.parametrize("M,N,Q", [(9, 70, 3), (40, 300, 5), (66, 257, 64), (20, 200, 70)])
+def test_permutations_match_oracle(env, M, N, Q):
+    torch, epi3 = env
+    d = make_dataset(M, N, 0.4, 0.05, seed=500 + M)
+    perms = make_permutations(d.pheno, Q, seed=600 + N)
+    ds = epi3.encode(to_dev(d.geno), d.pheno, layout="masked")
+    bs = epi3.BatchScanner(ds, 6, masks=_masks(epi3, perms), variant="mfma")
+    res = bs.run()
+    assert len(res) == Q
+    for q in range(Q):
+        ijk, k2, cc = oracle.scan_topk(d.geno, perms[q], 6)
+        assert_hits_equal_oracle(res[q], ijk, k2, cc)
+
+
+def test_permutations_equal_plain_scans(env):
+    """Batched phenotypes give the same hits as one plain scan per phenotype."""
+    torch, epi3 = env
+    d = make_dataset(70, 1000, 0.3, 0.05, seed=9)
+    perms = make_permutations(d.pheno, 8, seed=10)
+    g = to_dev(d.geno)
+    ds = epi3.encode(g, d.pheno, layout="masked")
+    res = epi3.BatchScanner(ds, 12, masks=_masks(epi3, perms), variant="mfma").run()
+    for q in range(8):
+        plain = epi3.scan_topk(epi3.encode(g, perms[q]), 12, "valu")
+        assert res[q].tobytes() == plain.tobytes()
+
+
+def test_permutation_edge_phenotypes(env):
+    """All controls, all cases, a single case."""
+    torch, epi3 = env
+    d = make_dataset(12, 130, 0.5, 0.05, seed=12)
+    perms = np.zeros((3, 130), dtype=np.uint8)
+    perms[1, :] = 1
+    perms[2, 77] = 1
+    ds = epi3.encode(to_dev(d.geno), d.pheno, layout="masked")
+    res = epi3.BatchScanner(ds, 4, masks=_masks(epi3, perms), variant="mfma").run()
+    for q in range(3):
+        ijk, k2, cc = oracle.scan_topk(d.geno, perms[q], 4)
+        assert_hits_equal_oracle(res[q], ijk, k2, cc)
+
+
+def test_batched_rejects_mixed_layouts(env):
+    torch, epi3 = env
+    d = make_dataset(10, 100, 0.5, 0.05, seed=3)
+    a = epi3.encode(to_dev(d.geno), d.pheno)
+    b = epi3.encode(to_dev(d.geno), d.pheno, layout="masked")
+    with pytest.raises(epi3.Epi3Error):
+        epi3.BatchScanner([a, b], 3, variant="valu")
+
+
+def test_cfg4_permutations_full_size(env):
+    """1024 SNPs x 8192 samples x 64 phenotype permutations in one launch: each
+    phenotype's top-10 equals the stored oracle result where one exists, else
+    each hit is re-checked one by one against the oracle."""
+    torch, epi3 = env
+    c = CONFIGS[4]
+    d, perms = make_config(4)
+    ds = epi3.encode(to_dev(d.geno), d.pheno, layout="masked")
+    res = epi3.BatchScanner(ds, c["k"], masks=_masks(epi3, perms), variant="mfma").run()
+    assert len(res) == c["n_perm"]
+    for q in range(c["n_perm"]):
+        h = res[q]
+        assert len(h) == c["k"]
+        fx = os.path.join(GOLDEN, f"oracle_cfg4_perm{q:02d}_top{c['k']}.npz")
+        if os.path.exists(fx):
+            z = np.load(fx)
+            assert_hits_equal_oracle(h, z["ijk"], z["k2"], z["counts"])
+        else:
+            rc, rk = oracle.score_list(d.geno, perms[q], hits_ijk(h))
+            np.testing.assert_array_equal(h["k2"], rk)
+            np.testing.assert_array_equal(h["counts"].astype(np.int64), rc)
+            assert np.all(np.diff(h["k2"]) >= 0)
