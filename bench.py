@@ -29,12 +29,19 @@ METRIC = "tera sample-triplets/s; batched-permutation vs plain speedup at exact 
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12      # INT32 lane-ops/s: CUs x lanes x clock
 VALU_OPS_PER_ST = 16.0 / 32.0                  # 8 AND + 8 v_bcnt per triplet per 32 samples
 
+MFMA_I8_PEAK_TOPS = 5000.0                     # dense int8 matrix-core ops/s (MI355X)
+MFMA_OPS_PER_STQ = 16.0                        # 8 corner cells x (multiply + add) per sample-triplet-phenotype
+
 WORKLOADS = {
-    "plain2": dict(cfg=2, desc="plain scan, 512 SNPs x 4096 samples (50% cases), top-100"),
-    "plain3": dict(cfg=3, desc="plain scan, 2048 SNPs x 16384 samples (50% cases), top-1000"),
-    "plain1": dict(cfg=1, desc="plain scan, 64 SNPs x 1024 samples (512 cases), top-10"),
+    "plain1": dict(cfg=1, kind="plain", desc="plain scan, 64 SNPs x 1024 samples (512 cases), top-10"),
+    "plain2": dict(cfg=2, kind="plain", desc="plain scan, 512 SNPs x 4096 samples (50% cases), top-100"),
+    "plain3": dict(cfg=3, kind="plain", desc="plain scan, 2048 SNPs x 16384 samples (50% cases), top-1000"),
+    "perm4": dict(cfg=4, kind="perm", desc="batched permutations: 1024 SNPs x 8192 samples (3277 cases), "
+                  "64 phenotype permutations in one launch, top-10 each"),
+    "uneven5": dict(cfg=5, kind="uneven", desc="batched uneven data sets: 32 data sets, SNPs ~ U[128,1024], "
+                    "samples ~ U[1024,16384], one launch, top-10 each"),
 }
-DEFAULT_WORKLOAD = "plain2"
+DEFAULT_WORKLOAD = "perm4"
 
 
 def recorded_traffic(key: str):
@@ -101,8 +108,7 @@ def run_plain(args, wl):
     sc = epi3.Scanner(ds, k, variant)
 
     def step():
-        ds2 = epi3.encode(geno, d.pheno)
-        sc.ds = ds2
+        epi3.encode(geno, d.pheno, into=ds)
         return sc.run()
 
     for _ in range(args.warmup):
@@ -148,6 +154,155 @@ def run_plain(args, wl):
     return out
 
 
+def _timed_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, out
+
+
+def _kernel_times(fn, reps=2):
+    """Per-launch ms of the count stage and of the selection, from the library's
+    HIP events on the launch stream (measurement mode)."""
+    import torch
+    from paper_2201_10956_amd import epi3
+    torch.cuda.synchronize()
+    epi3.timing_reset()
+    epi3.timing_enable(True)
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    epi3.timing_enable(False)
+    c_ms, c_n = epi3.timing_query(0)
+    s_ms, s_n = epi3.timing_query(1)
+    return c_ms / max(c_n, 1), c_n / reps, s_ms / max(s_n, 1)
+
+
+def _base(args, wl, value, ms_step, dtype, config):
+    return {"metric": METRIC, "value": round(value, 4), "unit": "T sample-triplets/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic (seeded HWE genotypes, planted triplet)", "config": config}
+
+
+def run_perm(args, wl):
+    import torch
+    from paper_2201_10956_amd import epi3
+    from synth import CONFIGS, make_config
+    from math import comb
+
+    c = CONFIGS[wl["cfg"]]
+    d, perms = make_config(wl["cfg"])
+    M, N, k, Q = d.n_snps, d.n_samples, c["k"], c["n_perm"]
+    geno = torch.from_numpy(d.geno).to("cuda")
+    masks = torch.from_numpy(epi3.pack_masks(perms).view(np.int32)).to("cuda")
+    ds = epi3.encode(geno, d.pheno, layout="masked")
+    bs = epi3.BatchScanner(ds, k, masks=masks, variant="mfma")
+
+    def step():  # encode (planes, bytes, pairwise tables) + one batched launch
+        epi3.encode(geno, d.pheno, layout="masked", into=ds)
+        return bs.run()
+
+    dt, res = _timed_steps(step, args.steps, args.warmup)
+    T = comb(M, 3)
+    work = T * N * Q
+    value = work / dt / 1e12
+    k_ms, k_n, sel_ms = _kernel_times(bs.run)
+    t_kernel = k_ms / 1e3
+    achieved = MFMA_OPS_PER_STQ * T * N * Q / t_kernel / 1e12
+
+    # plain reference: one encode + VALU scan + top-k per phenotype
+    pds = epi3.encode(geno, perms[0])
+    sc = epi3.Scanner(pds, k, "valu")
+
+    def plain_all():
+        out = []
+        for q in range(Q):
+            sc.ds = epi3.encode(geno, perms[q], into=pds)
+            out.append(sc.run())
+        return out
+
+    p_dt, plain_res = _timed_steps(plain_all, 1, 1)
+    same = all(a.tobytes() == b.tobytes() for a, b in zip(res, plain_res))
+    plain_value = work / p_dt / 1e12
+    out = _base(args, wl, value, dt * 1e3, "i8", {
+        "workload": wl["desc"], "snps": M, "samples": N, "phenotypes": Q, "top_k": k,
+        "triplets": T, "variant": "mfma", "counted": "sample-triplets per phenotype, summed"})
+    out["speedup_vs_plain"] = round(value / plain_value, 3)
+    out["plain"] = {"value": round(plain_value, 4), "unit": "T sample-triplets/s",
+                    "ms_for_all_phenotypes": round(p_dt * 1e3, 3),
+                    "how": "64 x (encode split planes + VALU count + top-k), same data",
+                    "hits_identical_to_batched": bool(same)}
+    out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2), "peak": MFMA_I8_PEAK_TOPS,
+                       "unit": "TOP/s (int8)", "frac": round(achieved / MFMA_I8_PEAK_TOPS, 4),
+                       "traffic": recorded_traffic(f"count_mfma_perm_kernel|{args.workload}"),
+                       "traffic_unit": "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
+                       "kernel": "count_mfma_perm_kernel", "kernel_ms": round(k_ms, 4),
+                       "launches_per_step": k_n,
+                       "ops_per_launch": MFMA_OPS_PER_STQ * T * N * Q}
+    out["breakdown_ms"] = {"count_kernel": round(k_ms, 4), "selection": round(sel_ms, 4)}
+    out["min_k2_per_phenotype"] = [round(float(h["k2"][0]), 6) for h in res[:4]] + ["..."]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(type(d)(d.geno, perms[0], d.planted, d.maf, d.seed), k,
+                                           args.cpu_budget)
+        out["cpu_baseline"]["sample"] += ", phenotype permutation 0"
+    return out
+
+
+def run_uneven(args, wl):
+    import torch
+    from paper_2201_10956_amd import epi3
+    from synth import CONFIGS, make_config
+    from math import comb
+
+    c = CONFIGS[wl["cfg"]]
+    dsets = make_config(wl["cfg"])
+    k = c["k"]
+    genos = [torch.from_numpy(d.geno).to("cuda") for d in dsets]
+    enc = [epi3.encode(g, d.pheno) for g, d in zip(genos, dsets)]
+    bs = epi3.BatchScanner(enc, k, variant="valu")
+
+    def step():
+        for x, (g, d) in enumerate(zip(genos, dsets)):
+            epi3.encode(g, d.pheno, into=enc[x])
+        return bs.run()
+
+    dt, res = _timed_steps(step, args.steps, args.warmup)
+    work = sum(comb(d.n_snps, 3) * d.n_samples for d in dsets)
+    value = work / dt / 1e12
+    k_ms, k_n, sel_ms = _kernel_times(bs.run)
+    achieved = work * VALU_OPS_PER_ST / (k_ms / 1e3) / 1e12
+
+    def seq():
+        return [epi3.scan_topk(e, k, "valu") for e in enc]
+
+    s_dt, seq_res = _timed_steps(seq, 1, 1)
+    same = all(a.tobytes() == b.tobytes() for a, b in zip(res, seq_res))
+    out = _base(args, wl, value, dt * 1e3, "u32", {
+        "workload": wl["desc"], "datasets": len(dsets), "top_k": k,
+        "snps": [d.n_snps for d in dsets], "samples": [d.n_samples for d in dsets],
+        "sample_triplets": work, "variant": "valu"})
+    out["sequential"] = {"value": round(work / s_dt / 1e12, 4), "ms": round(s_dt * 1e3, 3),
+                         "how": "one plain scan per data set", "hits_identical": bool(same)}
+    out["roofline"] = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
+                       "unit": "T int32-lane-ops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                       "traffic": recorded_traffic(f"count_valu_kernel|{args.workload}"),
+                       "kernel": "count_valu_kernel", "kernel_ms": round(k_ms, 4),
+                       "ops_per_launch": work * VALU_OPS_PER_ST}
+    out["breakdown_ms"] = {"count_kernel": round(k_ms, 4), "selection": round(sel_ms, 4)}
+    if not args.no_cpu_baseline:
+        big = max(dsets, key=lambda d: d.n_samples)
+        out["cpu_baseline"] = cpu_baseline(big, k, args.cpu_budget)
+    return out
+
+
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 3) -> None:
     """A plain device-to-device copy of known size, for scaling the HBM byte
     counters (FETCH_SIZE / WRITE_SIZE) read by the profiler."""
@@ -179,7 +334,8 @@ def main():
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
     wl = WORKLOADS[args.workload]
-    out = run_plain(args, wl)
+    run = {"plain": run_plain, "perm": run_perm, "uneven": run_uneven}[wl["kind"]]
+    out = run(args, wl)
     print(json.dumps(out), flush=True)
 
 

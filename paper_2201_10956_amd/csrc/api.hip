@@ -595,7 +595,14 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, hipSt
     HIP_OK(launch_write_jobs(J.data(), n, W.jobs, s));
     HIP_OK(launch_tile_prefix(W.jobs, n, P, s));
     HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
-    if (begin > 0) HIP_OK(launch_count_valu(W.jobs, n, begin, W.queue, lf32, lf_len, P, false, s));
+    if (begin > 0) {
+      const int rc = timed(0, s, [&]() {
+        return launch_count_valu(W.jobs, n, begin, W.queue, lf32, lf_len, P, false, s) == hipSuccess
+                   ? EPI3_OK
+                   : EPI3_E_HIP;
+      });
+      if (rc != EPI3_OK) return rc;
+    }
   } else {
     const epi3_dataset &d = *jobs[0].d;
     std::vector<const uint32_t *> masks((size_t)W.groups * kPermGroup, nullptr);
@@ -630,13 +637,26 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, hipSt
                                const_cast<int32_t *>(pj.case_pairs), s));
       if (g == 0) HIP_OK(launch_perm_prefix(W.pjobs, s));
       HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
-      if (tiles > 0)
-        HIP_OK(launch_count_mfma_perm(W.pjobs + g, tiles, W.st + (int64_t)g * kPermGroup, W.queue,
-                                      d.lf32, d.n_samples + 2, s));
+      if (tiles > 0) {
+        const int rc = timed(0, s, [&]() {
+          return launch_count_mfma_perm(W.pjobs + g, tiles, W.st + (int64_t)g * kPermGroup,
+                                        W.queue, d.lf32, d.n_samples + 2, s) == hipSuccess
+                     ? EPI3_OK
+                     : EPI3_E_HIP;
+        });
+        if (rc != EPI3_OK) return rc;
+      }
     }
   }
-  HIP_OK(launch_select(W.sel, n, max_T, max_cap, max_k, s));
-  return EPI3_OK;
+  return timed(1, s, [&]() {
+    return launch_select(W.sel, n, max_T, max_cap, max_k, s) == hipSuccess ? EPI3_OK : EPI3_E_HIP;
+  });
+}
+
+bool timing_on() {
+  Timing &t = timing();
+  std::lock_guard<std::mutex> g(t.mu);
+  return t.on;
 }
 
 // Graphs cached per job signature.
@@ -694,7 +714,11 @@ int epi3_scan_batched(const epi3_job *jobs, int32_t n_jobs, int32_t variant, int
 
   GraphCache &G = graphs();
   hipGraphExec_t exec = nullptr;
-  {
+  if (timing_on()) {
+    // measurement mode: run the same sequence eagerly so each kernel is timed
+    rc = timed(2, s, [&]() { return enqueue_batched(jobs, n_jobs, W, s); });
+    if (rc != EPI3_OK) return rc;
+  } else {
     std::lock_guard<std::mutex> lk(G.mu);
     const auto sig = signature(jobs, n_jobs, variant, cand_cap, ws_dev, ws_bytes);
     auto it = G.exec.find(sig);
@@ -715,9 +739,8 @@ int epi3_scan_batched(const epi3_job *jobs, int32_t n_jobs, int32_t variant, int
       if (ei != hipSuccess) return EPI3_E_HIP;
       G.exec[sig] = exec;
     }
+    if (hipGraphLaunch(exec, s) != hipSuccess) return EPI3_E_HIP;
   }
-  rc = timed(2, s, [&]() { return hipGraphLaunch(exec, s) == hipSuccess ? EPI3_OK : EPI3_E_HIP; });
-  if (rc != EPI3_OK) return rc;
 
   std::vector<SelState> st(n_jobs);
   HIP_OK(hipMemcpyAsync(st.data(), W.st, sizeof(SelState) * n_jobs, hipMemcpyDeviceToHost, s));

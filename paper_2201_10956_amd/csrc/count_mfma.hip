@@ -29,7 +29,7 @@ constexpr int kPermT = 4;    // row tiles per wave tile
 
 __host__ __device__ __forceinline__ int64_t perm_tiles_of_j(int64_t M, int64_t j) {
   if (j < 1 || j > M - 2) return 0;
-  return j * ((M - 1 - j + kPermKB - 1) / kPermKB);
+  return ((j + 3) / 4) * ((M - 1 - j + kPermKB - 1) / kPermKB);
 }
 
 __device__ __forceinline__ int64_t rfl64p(int64_t v) {
@@ -146,33 +146,61 @@ __device__ __forceinline__ void load_pair(const int32_t *p, int64_t idx, int v[4
   v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
 }
 
-// One wave tile: pivot pair (i, j), 16 consecutive k > j, 64 phenotypes.
+// Staging geometry: samples are processed in chunks of kKC staged in LDS,
+// each row padded to an odd number of 16-byte units against bank conflicts.
+constexpr int kKC = 128;
+constexpr int kRow = kKC + 16;
+constexpr int kRowsPH = 64;                  // phenotype rows (B operand)
+constexpr int kRowsXK = 2 * kPermKB;         // (k, c) rows shared by the 4 waves
+constexpr int kRowsP = 16;                   // pair rows X_i[a] & X_j[b]: 4 waves x 4 (a, b)
+constexpr int kRowsAll = kRowsPH + kRowsXK + kRowsP;
+constexpr int kStageBytes = kRowsAll * kRow; // one buffer
+constexpr int kChunks16 = kRowsAll * (kKC / 16);
+// epilogue data placed in the staging buffers (bytes)
+constexpr int kEpiBytes = 16 * 4 * 64 + 8 * 4 * 64 + 8 * 64 + 4 * 64 + 16 * (4 * 16 + 16 + 16 + 4 + 4 + 4) +
+                          16 * 4 * 4 * 64 + 16 * 4 * 64 + 8 * 4 * 64;
+static_assert(kEpiBytes <= 2 * kStageBytes, "epilogue data must fit the staging buffers");
+
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T *;
+
+// Workgroup tile: pivot j, four pivots i = 4 ib + wave (one per wave), 16
+// consecutive k > j, 64 phenotypes.  Phenotype bytes, the k planes and the
+// pair words are staged per chunk of kKC samples in double-buffered LDS; each
+// wave then runs 8 MFMAs per 32 samples (4 row tiles of 4 triplets x 8
+// corner cells, 2 column tiles of 32 phenotypes).
 __global__ void __launch_bounds__(256) count_mfma_perm_kernel(const PermJob *__restrict__ pjp,
                                                               SelState *__restrict__ st,
                                                               unsigned long long *__restrict__ queue,
                                                               const float *__restrict__ lf32,
                                                               int lf_len) {
-  extern __shared__ float smem[];
-  float *sL = smem;
-  uint32_t *sTot = reinterpret_cast<uint32_t *>(smem + ((lf_len + 3) & ~3));
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  uint8_t *stage = smem;                                          // 2 buffers
+  uint32_t *sTot = reinterpret_cast<uint32_t *>(smem + 2 * kStageBytes);
+  int64_t *sTile = reinterpret_cast<int64_t *>(sTot + 4 * kPermT * 32);
+  float *sL = reinterpret_cast<float *>(sTile + 2);
   for (int x = threadIdx.x; x < lf_len; x += blockDim.x) sL[x] = lf32[x];
-  __syncthreads();
 
   const PermJob pj = *pjp;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   uint32_t *myTot = sTot + wave * (kPermT * 32);
   const int r = lane & 31, g = lane >> 5;
   const int ta = r >> 3, ra = (r >> 2) & 1, rb = (r >> 1) & 1, rc = r & 1;
   const int M = pj.M, Mp = pj.Mp, S = pj.S, Q = pj.Q, Qp = pj.Qp;
   const int64_t T = pj.T;
+  gptr<uint8_t> gb = (gptr<uint8_t>)pj.bytes;
+  gptr<uint8_t> gph = (gptr<uint8_t>)pj.ph;
   cptr<int64_t> pre = as_const(pj.jprefix);
+  const int nch = S / kKC;  // S is a multiple of 256
   int j = -1;
   int64_t jlo = 0, jhi = 0;
 
   for (;;) {
-    unsigned long long got = 0;
-    if (lane == 0) got = atomicAdd(queue, 1ull);
-    const int64_t t = rfl64p((int64_t)got);
+    __syncthreads();  // previous tile's readers of sTile / stage are done
+    if (tid == 0) sTile[0] = (int64_t)atomicAdd(queue, 1ull);
+    __syncthreads();
+    const int64_t t = rfl64p(sTile[0]);
     if (t >= pj.n_tiles) break;
     if (j < 0 || t < jlo || t >= jhi) {
       int lo = 0, hi = M - 1;
@@ -186,10 +214,49 @@ __global__ void __launch_bounds__(256) count_mfma_perm_kernel(const PermJob *__r
     }
     const int nkb = (M - 1 - j + kPermKB - 1) / kPermKB;
     const int rr = (int)(t - jlo);
-    const int i = rr / nkb, kb = rr - i * nkb;
+    const int ib = rr / nkb, kb = rr - ib * nkb;
+    const int i = 4 * ib + wave;  // may be >= j (then the wave's results are dropped)
     const int kbase = j + 1 + kb * kPermKB;
 
-    // ---- main loop over samples: 32 per step ----
+    // ---- staging plan: this thread's 16-byte chunks of one LDS buffer ----
+    // rows [0, 64): phenotype q; [64, 96): (k, c) = k planes; [96, 112): pair rows.
+    auto chunk_src = [&](int c16, int ch, v4i &v) {
+      const int row = c16 >> 3, col = (c16 & 7) * 16;
+      const int64_t s0 = (int64_t)ch * kKC + col;
+      if (row < kRowsPH) {
+        v = *reinterpret_cast<gptr<v4i>>(gph + (int64_t)row * S + s0);
+      } else if (row < kRowsPH + kRowsXK) {
+        const int x = row - kRowsPH;
+        v = *reinterpret_cast<gptr<v4i>>(gb + ((int64_t)(kbase + (x >> 1)) * 2 + (x & 1)) * S + s0);
+      } else {
+        const int x = row - kRowsPH - kRowsXK;  // wave w = x >> 2, (a, b) = x & 3
+        const int ii = 4 * ib + (x >> 2);
+        const v4i va =
+            *reinterpret_cast<gptr<v4i>>(gb + ((int64_t)ii * 2 + ((x >> 1) & 1)) * S + s0);
+        const v4i vb = *reinterpret_cast<gptr<v4i>>(gb + ((int64_t)j * 2 + (x & 1)) * S + s0);
+        v = va & vb;
+      }
+    };
+    constexpr int kPer = (kChunks16 + 255) / 256;  // chunks per thread (4)
+    v4i pf[kPer];
+    auto fetch = [&](int ch) {
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int c16 = tid + 256 * u;
+        if (c16 < kChunks16) chunk_src(c16, ch, pf[u]);
+      }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int c16 = tid + 256 * u;
+        if (c16 < kChunks16) {
+          const int row = c16 >> 3, col = (c16 & 7) * 16;
+          *reinterpret_cast<v4i *>(stage + buf * kStageBytes + row * kRow + col) = pf[u];
+        }
+      }
+    };
+
     v16i acc[kPermT][2];
     uint32_t tot[kPermT];
 #pragma unroll
@@ -198,118 +265,191 @@ __global__ void __launch_bounds__(256) count_mfma_perm_kernel(const PermJob *__r
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[tt][0][v] = acc[tt][1][v] = 0;
     }
-    const uint8_t *xi = pj.bytes + ((int64_t)i * 2 + ra) * S + 16 * g;
-    const uint8_t *xj = pj.bytes + ((int64_t)j * 2 + rb) * S + 16 * g;
-    const uint8_t *ph0 = pj.ph + (int64_t)r * S + 16 * g;
-    const uint8_t *ph1 = pj.ph + (int64_t)(32 + r) * S + 16 * g;
-    const uint8_t *xk[kPermT];
+    fetch(0);
+    store(0);
+    __syncthreads();
+    const int prow = kRowsPH + kRowsXK + wave * 4 + (ra * 2 + rb);
+    for (int ch = 0; ch < nch; ++ch) {
+      if (ch + 1 < nch) fetch(ch + 1);
+      const uint8_t *buf = stage + (ch & 1) * kStageBytes;
 #pragma unroll
-    for (int tt = 0; tt < kPermT; ++tt)
-      xk[tt] = pj.bytes + ((int64_t)(kbase + 4 * tt + ta) * 2 + rc) * S + 16 * g;
-    for (int s0 = 0; s0 < S; s0 += 32) {
-      const v4i vi = *reinterpret_cast<const v4i *>(xi + s0);
-      const v4i vj = *reinterpret_cast<const v4i *>(xj + s0);
-      const v4i b0 = *reinterpret_cast<const v4i *>(ph0 + s0);
-      const v4i b1 = *reinterpret_cast<const v4i *>(ph1 + s0);
-      const v4i p = vi & vj;
+      for (int stp = 0; stp < kKC / 32; ++stp) {
+        const int off = stp * 32 + 16 * g;
+        const v4i p = *reinterpret_cast<const v4i *>(buf + prow * kRow + off);
+        const v4i b0 = *reinterpret_cast<const v4i *>(buf + r * kRow + off);
+        const v4i b1 = *reinterpret_cast<const v4i *>(buf + (32 + r) * kRow + off);
 #pragma unroll
-      for (int tt = 0; tt < kPermT; ++tt) {
-        const v4i vk = *reinterpret_cast<const v4i *>(xk[tt] + s0);
-        const v4i a = p & vk;
-        tot[tt] += popc4(a);
-        acc[tt][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b0, acc[tt][0], 0, 0, 0);
-        acc[tt][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b1, acc[tt][1], 0, 0, 0);
+        for (int tt = 0; tt < kPermT; ++tt) {
+          const int xrow = kRowsPH + (4 * tt + ta) * 2 + rc;
+          const v4i a = p & *reinterpret_cast<const v4i *>(buf + xrow * kRow + off);
+          tot[tt] += popc4(a);
+          acc[tt][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b0, acc[tt][0], 0, 0, 0);
+          acc[tt][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b1, acc[tt][1], 0, 0, 0);
+        }
       }
+      if (ch + 1 < nch) store((ch + 1) & 1);
+      __syncthreads();
     }
+
     // totals of row r (both sample halves) to LDS
 #pragma unroll
     for (int tt = 0; tt < kPermT; ++tt) {
       const uint32_t full = tot[tt] + __shfl_xor(tot[tt], 32);
       if (g == 0) myTot[tt * 32 + r] = full;
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
 
-    // ---- epilogue: lane (q, h) finishes triplets 2h, 2h + 1 of every row tile ----
-    const int h = g;
-    const int64_t MpMp = (int64_t)Mp * Mp;
-    int tij[4], tii[4], tjj[4];
-    load_pair(pj.tot_pairs, (int64_t)i * Mp + j, tij);
-    load_pair(pj.tot_pairs, (int64_t)i * Mp + i, tii);
-    load_pair(pj.tot_pairs, (int64_t)j * Mp + j, tjj);
-    (void)MpMp;
-#pragma unroll
-    for (int qb = 0; qb < 2; ++qb) {
-      const int q = qb * 32 + r;
-      const bool qvalid = q < Q;
+    // ---- epilogue data staged in the (now idle) staging buffers ----
+    // fixed per tile: case pairs (i, j), (i, i), (j, j) of every phenotype, the
+    // phenotypes' case counts and the all-sample pairs of the tile; then per
+    // row tile: case pairs (i, k), (j, k), (k, k).  One batched round of loads
+    // per row tile instead of a dependent chain per triplet and phenotype.
+    int4 *eFix = reinterpret_cast<int4 *>(stage);
+    int4 *ePij = eFix;                      // [4 waves][64 q]
+    int2 *ePii = reinterpret_cast<int2 *>(ePij + 4 * 64);   // [4][64]
+    int2 *ePjj = ePii + 4 * 64;             // [64]
+    int *eN1 = reinterpret_cast<int *>(ePjj + 64);          // [64]
+    int4 *eTik = reinterpret_cast<int4 *>(eN1 + 64);         // [4 waves][16 k]
+    int4 *eTjk = eTik + 4 * kPermKB;        // [16]
+    int4 *eTkk = eTjk + kPermKB;            // [16]
+    int4 *eTij = eTkk + kPermKB;            // [4]
+    int4 *eTii = eTij + 4;                  // [4]
+    int4 *eTjj = eTii + 4;                  // [1]
+    int4 *ePik = eTjj + 4;                  // per row tile: [4 waves][4 tg][64 q]
+    int4 *ePjk = ePik + 4 * 4 * 64;         // [4 tg][64 q]
+    int2 *ePkk = reinterpret_cast<int2 *>(ePjk + 4 * 64);   // [4 tg][64 q]
+    const int ib4 = 4 * ib;
+    {
+      const int4 *cp = reinterpret_cast<const int4 *>(pj.case_pairs);
+      const int4 *tp = reinterpret_cast<const int4 *>(pj.tot_pairs);
+      // case pairs (i, j) and (i, i): 256 each; (j, j), n1: 64 each
+      const int w = tid >> 6, q = tid & 63;
       const int qq = q < Qp ? q : Qp - 1;
-      const int n1 = pj.n1[qq];
-      int cij[4], cii[4], cjj[4];
-      load_pair(pj.case_pairs, ((int64_t)i * Mp + j) * Qp + qq, cij);
-      load_pair(pj.case_pairs, ((int64_t)i * Mp + i) * Qp + qq, cii);
-      load_pair(pj.case_pairs, ((int64_t)j * Mp + j) * Qp + qq, cjj);
-      uint32_t kmin = 0xffffffffu, kmax = 0u;
+      const int ii = ib4 + w;
+      const int4 a = cp[((int64_t)ii * Mp + j) * Qp + qq];
+      const int4 b = cp[((int64_t)ii * Mp + ii) * Qp + qq];
+      int4 c = make_int4(0, 0, 0, 0);
+      int n1v = 0;
+      if (w == 0) c = cp[((int64_t)j * Mp + j) * Qp + qq];
+      if (w == 1) n1v = pj.n1[qq];
+      int4 d = make_int4(0, 0, 0, 0);
+      // all-sample pairs: tik [4][16] (threads 0..63), tjk, tkk (64..95), tij, tii, tjj
+      if (tid < 64) d = tp[(int64_t)(ib4 + (tid >> 4)) * Mp + kbase + (tid & 15)];
+      else if (tid < 80) d = tp[(int64_t)j * Mp + kbase + (tid - 64)];
+      else if (tid < 96) d = tp[(int64_t)(kbase + tid - 80) * Mp + kbase + (tid - 80)];
+      else if (tid < 100) d = tp[(int64_t)(ib4 + tid - 96) * Mp + j];
+      else if (tid < 104) d = tp[(int64_t)(ib4 + tid - 100) * Mp + (ib4 + tid - 100)];
+      else if (tid < 105) d = tp[(int64_t)j * Mp + j];
+      ePij[tid] = a;
+      ePii[tid] = make_int2(b.x, b.w);
+      if (w == 0) ePjj[q] = make_int2(c.x, c.w);
+      if (w == 1) eN1[q] = n1v;
+      if (tid < 64) eTik[tid] = d;
+      else if (tid < 80) eTjk[tid - 64] = d;
+      else if (tid < 96) eTkk[tid - 80] = d;
+      else if (tid < 100) eTij[tid - 96] = d;
+      else if (tid < 104) eTii[tid - 100] = d;
+      else if (tid < 105) eTjj[0] = d;
+    }
+    const int h = g;
+    const int iw = wave;  // this wave's pivot i = ib4 + iw
+    const bool wave_valid = i < j;
+    uint32_t kmin[2] = {0xffffffffu, 0xffffffffu}, kmax[2] = {0u, 0u};
+    const int64_t base_ij = wave_valid ? lex_base(M, i, j) : 0;
 #pragma unroll
-      for (int tt = 0; tt < kPermT; ++tt) {
-        int send[8], recv[8];
+    for (int tt = 0; tt < kPermT; ++tt) {
+      __syncthreads();  // previous row tile's readers are done
+      {
+        const int4 *cp = reinterpret_cast<const int4 *>(pj.case_pairs);
+        const int q = tid & 63;
+        const int qq = q < Qp ? q : Qp - 1;
+        int4 v[4];
 #pragma unroll
-        for (int x = 0; x < 8; ++x) send[x] = h ? acc[tt][qb][x] : acc[tt][qb][8 + x];
+        for (int u = 0; u < 4; ++u) {  // (i, k): [4 waves][4 tg] x 64 q = 1024
+          const int x = (tid >> 6) + 4 * u;  // 0..15 = w * 4 + tg
+          const int ii = ib4 + (x >> 2), kk = kbase + 4 * tt + (x & 3);
+          v[u] = cp[((int64_t)ii * Mp + kk) * Qp + qq];
+        }
+        const int tg = tid >> 6, kk = kbase + 4 * tt + tg;
+        const int4 vjk = cp[((int64_t)j * Mp + kk) * Qp + qq];
+        const int4 vkk = cp[((int64_t)kk * Mp + kk) * Qp + qq];
 #pragma unroll
-        for (int x = 0; x < 8; ++x) recv[x] = __shfl_xor(send[x], 32);
+        for (int u = 0; u < 4; ++u) ePik[((tid >> 6) + 4 * u) * 64 + q] = v[u];
+        ePjk[tg * 64 + q] = vjk;
+        ePkk[tg * 64 + q] = make_int2(vkk.x, vkk.w);
+      }
+      __syncthreads();
+      if (!wave_valid) continue;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int tg = 2 * h + u;                 // triplet within the row tile
-          const int k = kbase + 4 * tt + tg;
-          uint32_t cn[8], tn[8];
+      for (int u = 0; u < 2; ++u) {
+        const int tg = 2 * h + u;  // triplet within the row tile
+        const int kl = 4 * tt + tg;
+        const int k = kbase + kl;
+        // totals table of this triplet (the same for every phenotype)
+        uint32_t tn[8];
+#pragma unroll
+        for (int x = 0; x < 8; ++x) tn[x] = myTot[tt * 32 + 8 * tg + x];
+        int ttab[27];
+        {
+          const int4 a = eTij[iw], b = eTik[iw * kPermKB + kl], c = eTjk[kl];
+          const int4 ii4 = eTii[iw], jj4 = eTjj[0], kk4 = eTkk[kl];
+          const int tij[4] = {a.x, a.y, a.z, a.w}, tik[4] = {b.x, b.y, b.z, b.w};
+          const int tjk[4] = {c.x, c.y, c.z, c.w};
+          const int mi[2] = {ii4.x, ii4.w}, mj[2] = {jj4.x, jj4.w}, mk[2] = {kk4.x, kk4.w};
+          complete_table(tn, tij, tik, tjk, mi, mj, mk, pj.N, ttab);
+        }
+        float tl[27];  // L[r + 1] of each row: Eq. 1's first inner sum, shared by all phenotypes
+#pragma unroll
+        for (int x = 0; x < 27; ++x) tl[x] = sL[ttab[x] + 1];
+#pragma unroll
+        for (int qb = 0; qb < 2; ++qb) {
+          const int q = qb * 32 + r;
+          int send[4], recv[4];
+          // lane h holds corner cells a = h of triplets; partner holds a = 1 - h
+#pragma unroll
+          for (int x = 0; x < 4; ++x)
+            send[x] = h ? acc[tt][qb][4 * u + x] : acc[tt][qb][8 + 4 * u + x];
+#pragma unroll
+          for (int x = 0; x < 4; ++x) recv[x] = __shfl_xor(send[x], 32);
+          uint32_t cn[8];
 #pragma unroll
           for (int bc = 0; bc < 4; ++bc) {
             const int own = h ? acc[tt][qb][8 + 4 * u + bc] : acc[tt][qb][4 * u + bc];
-            const int oth = recv[4 * u + bc];
-            cn[bc] = (uint32_t)(h ? oth : own);      // a = 0
-            cn[4 + bc] = (uint32_t)(h ? own : oth);  // a = 1
+            cn[bc] = (uint32_t)(h ? recv[bc] : own);      // a = 0
+            cn[4 + bc] = (uint32_t)(h ? own : recv[bc]);  // a = 1
           }
-#pragma unroll
-          for (int x = 0; x < 8; ++x) tn[x] = myTot[tt * 32 + 8 * tg + x];
-          int tik[4], tjk[4], tkk[4], cik[4], cjk[4], ckk[4];
-          load_pair(pj.tot_pairs, (int64_t)i * Mp + k, tik);
-          load_pair(pj.tot_pairs, (int64_t)j * Mp + k, tjk);
-          load_pair(pj.tot_pairs, (int64_t)k * Mp + k, tkk);
-          load_pair(pj.case_pairs, ((int64_t)i * Mp + k) * Qp + qq, cik);
-          load_pair(pj.case_pairs, ((int64_t)j * Mp + k) * Qp + qq, cjk);
-          load_pair(pj.case_pairs, ((int64_t)k * Mp + k) * Qp + qq, ckk);
-          int ttab[27], ctab[27];
+          int ctab[27];
           {
-            const int mi[2] = {tii[0], tii[3]}, mj[2] = {tjj[0], tjj[3]}, mk[2] = {tkk[0], tkk[3]};
-            complete_table(tn, tij, tik, tjk, mi, mj, mk, pj.N, ttab);
+            const int4 a = ePij[iw * 64 + q], b = ePik[(iw * 4 + tg) * 64 + q], c = ePjk[tg * 64 + q];
+            const int2 ii2 = ePii[iw * 64 + q], jj2 = ePjj[q], kk2 = ePkk[tg * 64 + q];
+            const int cij[4] = {a.x, a.y, a.z, a.w}, cik[4] = {b.x, b.y, b.z, b.w};
+            const int cjk[4] = {c.x, c.y, c.z, c.w};
+            const int mi[2] = {ii2.x, ii2.y}, mj[2] = {jj2.x, jj2.y}, mk[2] = {kk2.x, kk2.y};
+            complete_table(cn, cij, cik, cjk, mi, mj, mk, eN1[q], ctab);
           }
-          {
-            const int mi[2] = {cii[0], cii[3]}, mj[2] = {cjj[0], cjj[3]}, mk[2] = {ckk[0], ckk[3]};
-            complete_table(cn, cij, cik, cjk, mi, mj, mk, n1, ctab);
-          }
-          float k2 = 0.f;
+          float k2 = 0.f;  // rows in order, each L[r + 1] - (L[r_0] + L[r_1]) as in the plain kernel
 #pragma unroll
-          for (int x = 0; x < 27; ++x) {
-            const int r1 = ctab[x], r0 = ttab[x] - ctab[x];
-            k2 += sL[ttab[x] + 1] - (sL[r0] + sL[r1]);
-          }
-          if (qvalid && k < M) {
-            pj.score[(int64_t)q * T + lex_base(M, i, j) + k] = k2;
+          for (int x = 0; x < 27; ++x) k2 += tl[x] - (sL[ttab[x] - ctab[x]] + sL[ctab[x]]);
+          if (q < Q && k < M) {
+            pj.score[(int64_t)q * T + base_ij + k] = k2;
             const uint32_t key = f2key(k2);
-            kmin = key < kmin ? key : kmin;
-            kmax = key > kmax ? key : kmax;
+            kmin[qb] = key < kmin[qb] ? key : kmin[qb];
+            kmax[qb] = key > kmax[qb] ? key : kmax[qb];
           }
         }
       }
-      // per-phenotype key range: lanes q and q + 32 hold the same q
-      const uint32_t omin = __shfl_xor(kmin, 32), omax = __shfl_xor(kmax, 32);
-      kmin = omin < kmin ? omin : kmin;
-      kmax = omax > kmax ? omax : kmax;
-      if (h == 0 && qvalid && kmax != 0u) {
-        atomicMin(&st[q].kmin, kmin);
-        atomicMax(&st[q].kmax, kmax);
+    }
+    // per-phenotype key range: lanes q and q + 32 hold the same q
+#pragma unroll
+    for (int qb = 0; qb < 2; ++qb) {
+      const int q = qb * 32 + r;
+      const uint32_t omin = __shfl_xor(kmin[qb], 32), omax = __shfl_xor(kmax[qb], 32);
+      const uint32_t mn = omin < kmin[qb] ? omin : kmin[qb];
+      const uint32_t mx = omax > kmax[qb] ? omax : kmax[qb];
+      if (h == 0 && q < Q && mx != 0u) {
+        atomicMin(&st[q].kmin, mn);
+        atomicMax(&st[q].kmax, mx);
       }
     }
-    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -371,7 +511,8 @@ hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t n_tiles, SelSta
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  const size_t lds = (size_t)((lf_len + 3) & ~3) * sizeof(float) + 4 * kPermT * 32 * sizeof(uint32_t);
+  const size_t lds = 2 * (size_t)kStageBytes + 4 * kPermT * 32 * sizeof(uint32_t) +
+                     2 * sizeof(int64_t) + (size_t)lf_len * sizeof(float);
   e = hipFuncSetAttribute(reinterpret_cast<const void *>(&count_mfma_perm_kernel),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -380,8 +521,7 @@ hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t n_tiles, SelSta
   if (e != hipSuccess) return e;
   if (per_cu <= 0) per_cu = 1;
   int64_t blocks = (int64_t)n_cu * per_cu;
-  const int64_t need = (n_tiles + 3) / 4;
-  if (blocks > need) blocks = need > 0 ? need : 1;
+  if (blocks > n_tiles) blocks = n_tiles > 0 ? n_tiles : 1;
   hipLaunchKernelGGL(count_mfma_perm_kernel, dim3((unsigned)blocks), dim3(256), lds, s, pj_dev, st,
                      queue, lf32, lf_len);
   return hipGetLastError();

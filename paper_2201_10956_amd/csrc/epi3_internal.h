@@ -4,7 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/epi3.h"
+#include "epi3.h"
 
 namespace epi3 {
 

@@ -166,8 +166,10 @@ class Dataset:
         return self.c.n_samples
 
 
-def encode(geno, pheno, layout: str = "split", stream=None) -> Dataset:
-    """geno: torch uint8 [M][N] on the GPU (rows may be strided); pheno: host uint8 [N]."""
+def encode(geno, pheno, layout: str = "split", stream=None, into: Optional[Dataset] = None) -> Dataset:
+    """geno: torch uint8 [M][N] on the GPU (rows may be strided); pheno: host uint8 [N].
+    With `into`, the encoding reuses that Dataset's device buffer and struct (same
+    addresses, so cached batched graphs stay valid)."""
     torch = _torch()
     assert geno.dtype == torch.uint8 and geno.dim() == 2 and geno.is_cuda
     assert geno.stride(1) == 1
@@ -177,13 +179,18 @@ def encode(geno, pheno, layout: str = "split", stream=None) -> Dataset:
     n1 = int(ph.sum()) if ph.size else 0
     nbytes = _lib.epi3_encode_bytes(M, n1, N - n1, lay)
     _check(int(nbytes) if nbytes < 0 else OK, "epi3_encode_bytes")
-    buf = _buffer(nbytes, geno.device)
-    c = CDataset()
+    if into is not None and into.buf.numel() >= nbytes:
+        buf, c = into.buf, into.c
+    else:
+        buf, c = _buffer(nbytes, geno.device), CDataset()
     rc = _lib.epi3_encode(ctypes.c_void_p(geno.data_ptr()), geno.stride(0),
                           ph.ctypes.data_as(ctypes.c_void_p), M, N, lay,
                           ctypes.c_void_p(buf.data_ptr()), buf.numel(), _stream(stream),
                           ctypes.byref(c))
     _check(rc, "epi3_encode")
+    if into is not None and c is into.c:
+        into.geno = geno
+        return into
     return Dataset(c=c, buf=buf, geno=geno)
 
 

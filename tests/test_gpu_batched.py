@@ -123,3 +123,23 @@ def test_cfg4_permutations_full_size(env):
             np.testing.assert_array_equal(h["k2"], rk)
             np.testing.assert_array_equal(h["counts"].astype(np.int64), rc)
             assert np.all(np.diff(h["k2"]) >= 0)
+
+
+def test_cfg5_uneven_full_size(env):
+    """32 data sets (128-1024 SNPs x 1024-16384 samples) in one launch: every
+    data set's top-10 equals the stored oracle result."""
+    torch, epi3 = env
+    from synth import manifest_sha256
+    c = CONFIGS[5]
+    dsets = make_config(5)
+    enc = [epi3.encode(to_dev(d.geno), d.pheno) for d in dsets]
+    res = epi3.BatchScanner(enc, c["k"], variant="valu").run()
+    fx = os.path.join(GOLDEN, f"oracle_cfg5_top{c['k']}.npz")
+    z = np.load(fx) if os.path.exists(fx) else None
+    for x, (d, h) in enumerate(zip(dsets, res)):
+        if z is not None:
+            assert str(z[f"sha{x}"]) == manifest_sha256([d.geno, d.pheno])
+            assert_hits_equal_oracle(h, z[f"ijk{x}"], z[f"k2{x}"], z[f"counts{x}"])
+        else:
+            rc, rk = oracle.score_list(d.geno, d.pheno, hits_ijk(h))
+            np.testing.assert_array_equal(h["k2"], rk)
