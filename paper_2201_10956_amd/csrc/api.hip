@@ -206,7 +206,7 @@ struct Timing {
   std::mutex mu;
   bool on = false;
   std::vector<hipEvent_t> pool;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[3];  // 0: count, 1: selection, 2: batched graph
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[4];  // 0: count, 1: selection, 2: batched, 3: finish
 };
 Timing &timing() {
   static Timing t;
@@ -439,6 +439,7 @@ int epi3_score_triplets(const epi3_dataset *d, const uint32_t *ijk_dev, int64_t 
 namespace {
 
 constexpr int kPermGroup = 64;  // phenotypes per matrix-core launch
+constexpr int64_t kPermPassBytes = 8ll << 30;  // scratch for one pass of counted tiles
 
 // Workspace of a batched scan.
 struct BatchLayout {
@@ -454,6 +455,8 @@ struct BatchLayout {
   int32_t *n1 = nullptr;          // MASKED: [groups][64]
   int32_t *case_pairs = nullptr;  // MASKED: [groups][Mp][Mp][64][4]
   int64_t *perm_prefix = nullptr; // MASKED: [M + 1]
+  uint8_t *perm_scratch = nullptr;// MASKED: counts of one pass of tiles
+  int64_t pass_tiles = 0;
   epi3_hit *hits = nullptr;       // [sum k]
   std::vector<int64_t *> jprefix; // SPLIT, per job
   std::vector<float *> score;
@@ -508,6 +511,10 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
     L.n1 = c.take<int32_t>((int64_t)L.groups * kPermGroup);
     L.case_pairs = c.take<int32_t>((int64_t)L.groups * d.snp_stride * d.snp_stride * kPermGroup * 4);
     L.perm_prefix = c.take<int64_t>((int64_t)d.n_snps + 1);
+    // counts of up to kPermPassBytes worth of tiles per pass
+    const int64_t tiles = host_perm_tiles(d.n_snps);
+    L.pass_tiles = std::max<int64_t>(1, std::min<int64_t>(tiles, kPermPassBytes / kPermTileScratch));
+    L.perm_scratch = c.take<uint8_t>(L.pass_tiles * kPermTileScratch);
   }
   L.jprefix.resize(n);
   L.score.resize(n);
@@ -620,6 +627,8 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, hipSt
       pj.n1 = W.n1 + (int64_t)g * kPermGroup;
       pj.score = W.score[g * kPermGroup];
       pj.jprefix = W.perm_prefix;
+      pj.corners = reinterpret_cast<uint4 *>(W.perm_scratch);
+      pj.totals = reinterpret_cast<uint4 *>(W.perm_scratch + W.pass_tiles * 64 * 64 * 16);
       pj.n_tiles = tiles;
       pj.T = epi3_n_triplets(d.n_snps);
       pj.M = d.n_snps;
@@ -636,11 +645,17 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, hipSt
                                W.masks + (int64_t)g * kPermGroup, Q, kPermGroup,
                                const_cast<int32_t *>(pj.case_pairs), s));
       if (g == 0) HIP_OK(launch_perm_prefix(W.pjobs, s));
-      HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
-      if (tiles > 0) {
-        const int rc = timed(0, s, [&]() {
-          return launch_count_mfma_perm(W.pjobs + g, tiles, W.st + (int64_t)g * kPermGroup,
-                                        W.queue, d.lf32, d.n_samples + 2, s) == hipSuccess
+      for (int64_t t0 = 0; t0 < tiles; t0 += W.pass_tiles) {
+        const int64_t t1 = std::min(tiles, t0 + W.pass_tiles);
+        HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
+        int rc = timed(0, s, [&]() {
+          return launch_count_mfma_perm(W.pjobs + g, t0, t1, W.queue, s) == hipSuccess ? EPI3_OK
+                                                                                      : EPI3_E_HIP;
+        });
+        if (rc != EPI3_OK) return rc;
+        rc = timed(3, s, [&]() {
+          return launch_finish_perm(W.pjobs + g, t0, t1, W.st + (int64_t)g * kPermGroup, d.lf32,
+                                    d.n_samples + 2, s) == hipSuccess
                      ? EPI3_OK
                      : EPI3_E_HIP;
         });
@@ -781,7 +796,7 @@ void epi3_timing_enable(int enable) {
 }
 
 int epi3_timing_query(int32_t which, double *ms, int64_t *launches) {
-  if (which < 0 || which > 2 || !ms || !launches) return EPI3_E_INVALID;
+  if (which < 0 || which > 3 || !ms || !launches) return EPI3_E_INVALID;
   Timing &t = timing();
   std::lock_guard<std::mutex> g(t.mu);
   double sum = 0.0;

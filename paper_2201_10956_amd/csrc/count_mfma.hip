@@ -155,11 +155,7 @@ constexpr int kRowsXK = 2 * kPermKB;         // (k, c) rows shared by the 4 wave
 constexpr int kRowsP = 16;                   // pair rows X_i[a] & X_j[b]: 4 waves x 4 (a, b)
 constexpr int kRowsAll = kRowsPH + kRowsXK + kRowsP;
 constexpr int kStageBytes = kRowsAll * kRow; // one buffer
-constexpr int kChunks16 = kRowsAll * (kKC / 16);
-// epilogue data placed in the staging buffers (bytes)
-constexpr int kEpiBytes = 16 * 4 * 64 + 8 * 4 * 64 + 8 * 64 + 4 * 64 + 16 * (4 * 16 + 16 + 16 + 4 + 4 + 4) +
-                          16 * 4 * 4 * 64 + 16 * 4 * 64 + 8 * 4 * 64;
-static_assert(kEpiBytes <= 2 * kStageBytes, "epilogue data must fit the staging buffers");
+
 
 template <typename T>
 using gptr = const __attribute__((address_space(1))) T *;
@@ -169,26 +165,18 @@ using gptr = const __attribute__((address_space(1))) T *;
 // pair words are staged per chunk of kKC samples in double-buffered LDS; each
 // wave then runs 8 MFMAs per 32 samples (4 row tiles of 4 triplets x 8
 // corner cells, 2 column tiles of 32 phenotypes).
-__global__ void __launch_bounds__(256) count_mfma_perm_kernel(const PermJob *__restrict__ pjp,
-                                                              SelState *__restrict__ st,
-                                                              unsigned long long *__restrict__ queue,
-                                                              const float *__restrict__ lf32,
-                                                              int lf_len) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  uint8_t *stage = smem;                                          // 2 buffers
-  uint32_t *sTot = reinterpret_cast<uint32_t *>(smem + 2 * kStageBytes);
-  int64_t *sTile = reinterpret_cast<int64_t *>(sTot + 4 * kPermT * 32);
-  float *sL = reinterpret_cast<float *>(sTile + 2);
-  for (int x = threadIdx.x; x < lf_len; x += blockDim.x) sL[x] = lf32[x];
+__global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
+    const PermJob *__restrict__ pjp, int64_t tile_begin, int64_t tile_end,
+    unsigned long long *__restrict__ queue) {
+  __shared__ __attribute__((aligned(16))) unsigned char stage[2 * kStageBytes];
+  __shared__ int64_t sTile[2];
 
   const PermJob pj = *pjp;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  uint32_t *myTot = sTot + wave * (kPermT * 32);
   const int r = lane & 31, g = lane >> 5;
   const int ta = r >> 3, ra = (r >> 2) & 1, rb = (r >> 1) & 1, rc = r & 1;
-  const int M = pj.M, Mp = pj.Mp, S = pj.S, Q = pj.Q, Qp = pj.Qp;
-  const int64_t T = pj.T;
+  const int M = pj.M, S = pj.S;
   gptr<uint8_t> gb = (gptr<uint8_t>)pj.bytes;
   gptr<uint8_t> gph = (gptr<uint8_t>)pj.ph;
   cptr<int64_t> pre = as_const(pj.jprefix);
@@ -198,10 +186,11 @@ __global__ void __launch_bounds__(256) count_mfma_perm_kernel(const PermJob *__r
 
   for (;;) {
     __syncthreads();  // previous tile's readers of sTile / stage are done
-    if (tid == 0) sTile[0] = (int64_t)atomicAdd(queue, 1ull);
+    if (tid == 0) sTile[0] = tile_begin + (int64_t)atomicAdd(queue, 1ull);
     __syncthreads();
     const int64_t t = rfl64p(sTile[0]);
-    if (t >= pj.n_tiles) break;
+    if (t >= tile_end) break;
+    const int64_t slot = t - tile_begin;
     if (j < 0 || t < jlo || t >= jhi) {
       int lo = 0, hi = M - 1;
       while (lo < hi) {
@@ -220,41 +209,43 @@ __global__ void __launch_bounds__(256) count_mfma_perm_kernel(const PermJob *__r
 
     // ---- staging plan: this thread's 16-byte chunks of one LDS buffer ----
     // rows [0, 64): phenotype q; [64, 96): (k, c) = k planes; [96, 112): pair rows.
-    auto chunk_src = [&](int c16, int ch, v4i &v) {
-      const int row = c16 >> 3, col = (c16 & 7) * 16;
-      const int64_t s0 = (int64_t)ch * kKC + col;
-      if (row < kRowsPH) {
-        v = *reinterpret_cast<gptr<v4i>>(gph + (int64_t)row * S + s0);
-      } else if (row < kRowsPH + kRowsXK) {
-        const int x = row - kRowsPH;
-        v = *reinterpret_cast<gptr<v4i>>(gb + ((int64_t)(kbase + (x >> 1)) * 2 + (x & 1)) * S + s0);
-      } else {
-        const int x = row - kRowsPH - kRowsXK;  // wave w = x >> 2, (a, b) = x & 3
-        const int ii = 4 * ib + (x >> 2);
-        const v4i va =
-            *reinterpret_cast<gptr<v4i>>(gb + ((int64_t)ii * 2 + ((x >> 1) & 1)) * S + s0);
-        const v4i vb = *reinterpret_cast<gptr<v4i>>(gb + ((int64_t)j * 2 + (x & 1)) * S + s0);
-        v = va & vb;
-      }
-    };
-    constexpr int kPer = (kChunks16 + 255) / 256;  // chunks per thread (4)
-    v4i pf[kPer];
+    // Each chunk is loaded into registers one chunk ahead.  Thread chunks
+    // c16 = tid + 256 u: u = 0..2 cover the phenotype and k rows (row < 96),
+    // u = 3 covers the 16 pair rows (tid < 128), which keep both source words
+    // and are ANDed only when stored, so no load is waited for before the
+    // current chunk's matrix products are issued.
+    static_assert(kRowsPH + kRowsXK == 96 && kRowsP == 16 && kKC / 16 == 8, "staging plan");
+    v4i pf[3], pa, pb;
     auto fetch = [&](int ch) {
 #pragma unroll
-      for (int u = 0; u < kPer; ++u) {
+      for (int u = 0; u < 3; ++u) {
         const int c16 = tid + 256 * u;
-        if (c16 < kChunks16) chunk_src(c16, ch, pf[u]);
+        const int row = c16 >> 3, col = (c16 & 7) * 16;
+        const int64_t s0 = (int64_t)ch * kKC + col;
+        if (row < kRowsPH) {
+          pf[u] = *reinterpret_cast<gptr<v4i>>(gph + (int64_t)row * S + s0);
+        } else {
+          const int x = row - kRowsPH;
+          pf[u] = *reinterpret_cast<gptr<v4i>>(gb + ((int64_t)(kbase + (x >> 1)) * 2 + (x & 1)) * S + s0);
+        }
+      }
+      if (tid < 128) {
+        const int x = tid >> 3, col = (tid & 7) * 16;  // pair row x: wave x >> 2, (a, b) = x & 3
+        const int64_t s0 = (int64_t)ch * kKC + col;
+        const int ii = 4 * ib + (x >> 2);
+        pa = *reinterpret_cast<gptr<v4i>>(gb + ((int64_t)ii * 2 + ((x >> 1) & 1)) * S + s0);
+        pb = *reinterpret_cast<gptr<v4i>>(gb + ((int64_t)j * 2 + (x & 1)) * S + s0);
       }
     };
     auto store = [&](int buf) {
+      uint8_t *dst = stage + buf * kStageBytes;
 #pragma unroll
-      for (int u = 0; u < kPer; ++u) {
+      for (int u = 0; u < 3; ++u) {
         const int c16 = tid + 256 * u;
-        if (c16 < kChunks16) {
-          const int row = c16 >> 3, col = (c16 & 7) * 16;
-          *reinterpret_cast<v4i *>(stage + buf * kStageBytes + row * kRow + col) = pf[u];
-        }
+        *reinterpret_cast<v4i *>(dst + (c16 >> 3) * kRow + (c16 & 7) * 16) = pf[u];
       }
+      if (tid < 128)
+        *reinterpret_cast<v4i *>(dst + (96 + (tid >> 3)) * kRow + (tid & 7) * 16) = pa & pb;
     };
 
     v16i acc[kPermT][2];
@@ -291,165 +282,127 @@ __global__ void __launch_bounds__(256) count_mfma_perm_kernel(const PermJob *__r
       __syncthreads();
     }
 
-    // totals of row r (both sample halves) to LDS
+    if (i >= j) continue;  // padding pivot of the last i-block: nothing to write
+
+    // ---- counts out: all-sample corner cells per triplet, case corner cells
+    // per (triplet, phenotype); the finish kernel completes tables and scores.
+    uint4 *cor = pj.corners + (slot * 4 + wave) * (int64_t)kPermKB * 64;
+    uint16_t *tot16 = reinterpret_cast<uint16_t *>(pj.totals + (slot * 4 + wave) * (int64_t)kPermKB);
 #pragma unroll
     for (int tt = 0; tt < kPermT; ++tt) {
       const uint32_t full = tot[tt] + __shfl_xor(tot[tt], 32);
-      if (g == 0) myTot[tt * 32 + r] = full;
+      if (g == 0) tot16[(4 * tt + ta) * 8 + (r & 7)] = (uint16_t)full;
     }
+    // lane (q, h) holds, for each of the 4 triplets of a row tile, the 4 case
+    // cells with genotype a = h at SNP i: registers 4 t + (2 b + c).  Each lane
+    // writes them as 4 x uint16; halves h = 0, 1 of one (triplet, phenotype)
+    // are adjacent, so the 16 bytes hold cells 4 a + 2 b + c in order.
+    uint2 *cor2 = reinterpret_cast<uint2 *>(cor);
+#pragma unroll
+    for (int tt = 0; tt < kPermT; ++tt)
+#pragma unroll
+      for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+        for (int t4 = 0; t4 < 4; ++t4) {
+          const uint32_t c0 = (uint32_t)acc[tt][qb][4 * t4 + 0], c1 = (uint32_t)acc[tt][qb][4 * t4 + 1];
+          const uint32_t c2 = (uint32_t)acc[tt][qb][4 * t4 + 2], c3 = (uint32_t)acc[tt][qb][4 * t4 + 3];
+          cor2[((4 * tt + t4) * 64 + qb * 32 + r) * 2 + g] = make_uint2(c0 | (c1 << 16), c2 | (c3 << 16));
+        }
+  }
+}
 
-    // ---- epilogue data staged in the (now idle) staging buffers ----
-    // fixed per tile: case pairs (i, j), (i, i), (j, j) of every phenotype, the
-    // phenotypes' case counts and the all-sample pairs of the tile; then per
-    // row tile: case pairs (i, k), (j, k), (k, k).  One batched round of loads
-    // per row tile instead of a dependent chain per triplet and phenotype.
-    int4 *eFix = reinterpret_cast<int4 *>(stage);
-    int4 *ePij = eFix;                      // [4 waves][64 q]
-    int2 *ePii = reinterpret_cast<int2 *>(ePij + 4 * 64);   // [4][64]
-    int2 *ePjj = ePii + 4 * 64;             // [64]
-    int *eN1 = reinterpret_cast<int *>(ePjj + 64);          // [64]
-    int4 *eTik = reinterpret_cast<int4 *>(eN1 + 64);         // [4 waves][16 k]
-    int4 *eTjk = eTik + 4 * kPermKB;        // [16]
-    int4 *eTkk = eTjk + kPermKB;            // [16]
-    int4 *eTij = eTkk + kPermKB;            // [4]
-    int4 *eTii = eTij + 4;                  // [4]
-    int4 *eTjj = eTii + 4;                  // [1]
-    int4 *ePik = eTjj + 4;                  // per row tile: [4 waves][4 tg][64 q]
-    int4 *ePjk = ePik + 4 * 4 * 64;         // [4 tg][64 q]
-    int2 *ePkk = reinterpret_cast<int2 *>(ePjk + 4 * 64);   // [4 tg][64 q]
-    const int ib4 = 4 * ib;
+// Completes the tables of one pass of tiles and scores them.  Workgroup per
+// tile (persistent, round robin); wave w = pivot i = 4 ib + w; lane = (16 k x
+// 4 phenotypes), looping over 16 groups of 4 phenotypes.
+__global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restrict__ pjp,
+                                                          int64_t tile_begin, int64_t tile_end,
+                                                          SelState *__restrict__ st,
+                                                          const float *__restrict__ lf32,
+                                                          int lf_len) {
+  extern __shared__ float sL[];
+  __shared__ uint32_t sRange[64][2];
+  for (int x = threadIdx.x; x < lf_len; x += blockDim.x) sL[x] = lf32[x];
+  if (threadIdx.x < 64) {
+    sRange[threadIdx.x][0] = 0xffffffffu;
+    sRange[threadIdx.x][1] = 0u;
+  }
+  __syncthreads();
+  const PermJob pj = *pjp;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kl = lane & 15, qs = lane >> 4;
+  const int M = pj.M, Mp = pj.Mp, Q = pj.Q, Qp = pj.Qp;
+  const int64_t T = pj.T;
+  cptr<int64_t> pre = as_const(pj.jprefix);
+  const int4 *tp = reinterpret_cast<const int4 *>(pj.tot_pairs);
+  const int4 *cp = reinterpret_cast<const int4 *>(pj.case_pairs);
+  int j = -1;
+  int64_t jlo = 0, jhi = 0;
+  for (int64_t t = tile_begin + blockIdx.x; t < tile_end; t += gridDim.x) {
+    if (j < 0 || t < jlo || t >= jhi) {
+      int lo = 0, hi = M - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= t) lo = mid; else hi = mid - 1;
+      }
+      j = lo;
+      jlo = pre[j];
+      jhi = pre[j + 1];
+    }
+    const int nkb = (M - 1 - j + kPermKB - 1) / kPermKB;
+    const int rr = (int)(t - jlo);
+    const int ib = rr / nkb, kb = rr - ib * nkb;
+    const int i = 4 * ib + wave;
+    const int k = j + 1 + kb * kPermKB + kl;
+    if (i >= j) continue;  // wave-uniform
+    const int64_t slot = t - tile_begin;
+    const uint4 *cor = pj.corners + (slot * 4 + wave) * (int64_t)kPermKB * 64;
+    const uint4 tq = pj.totals[(slot * 4 + wave) * (int64_t)kPermKB + kl];
+    // all-sample table of triplet (i, j, k), shared by every phenotype
+    int ttab[27];
     {
-      const int4 *cp = reinterpret_cast<const int4 *>(pj.case_pairs);
-      const int4 *tp = reinterpret_cast<const int4 *>(pj.tot_pairs);
-      // case pairs (i, j) and (i, i): 256 each; (j, j), n1: 64 each
-      const int w = tid >> 6, q = tid & 63;
-      const int qq = q < Qp ? q : Qp - 1;
-      const int ii = ib4 + w;
-      const int4 a = cp[((int64_t)ii * Mp + j) * Qp + qq];
-      const int4 b = cp[((int64_t)ii * Mp + ii) * Qp + qq];
-      int4 c = make_int4(0, 0, 0, 0);
-      int n1v = 0;
-      if (w == 0) c = cp[((int64_t)j * Mp + j) * Qp + qq];
-      if (w == 1) n1v = pj.n1[qq];
-      int4 d = make_int4(0, 0, 0, 0);
-      // all-sample pairs: tik [4][16] (threads 0..63), tjk, tkk (64..95), tij, tii, tjj
-      if (tid < 64) d = tp[(int64_t)(ib4 + (tid >> 4)) * Mp + kbase + (tid & 15)];
-      else if (tid < 80) d = tp[(int64_t)j * Mp + kbase + (tid - 64)];
-      else if (tid < 96) d = tp[(int64_t)(kbase + tid - 80) * Mp + kbase + (tid - 80)];
-      else if (tid < 100) d = tp[(int64_t)(ib4 + tid - 96) * Mp + j];
-      else if (tid < 104) d = tp[(int64_t)(ib4 + tid - 100) * Mp + (ib4 + tid - 100)];
-      else if (tid < 105) d = tp[(int64_t)j * Mp + j];
-      ePij[tid] = a;
-      ePii[tid] = make_int2(b.x, b.w);
-      if (w == 0) ePjj[q] = make_int2(c.x, c.w);
-      if (w == 1) eN1[q] = n1v;
-      if (tid < 64) eTik[tid] = d;
-      else if (tid < 80) eTjk[tid - 64] = d;
-      else if (tid < 96) eTkk[tid - 80] = d;
-      else if (tid < 100) eTij[tid - 96] = d;
-      else if (tid < 104) eTii[tid - 100] = d;
-      else if (tid < 105) eTjj[0] = d;
+      const uint32_t tn[8] = {tq.x & 0xffffu, tq.x >> 16, tq.y & 0xffffu, tq.y >> 16,
+                              tq.z & 0xffffu, tq.z >> 16, tq.w & 0xffffu, tq.w >> 16};
+      const int4 a = tp[(int64_t)i * Mp + j], b = tp[(int64_t)i * Mp + k], c = tp[(int64_t)j * Mp + k];
+      const int4 ii4 = tp[(int64_t)i * Mp + i], jj4 = tp[(int64_t)j * Mp + j], kk4 = tp[(int64_t)k * Mp + k];
+      const int tij[4] = {a.x, a.y, a.z, a.w}, tik[4] = {b.x, b.y, b.z, b.w};
+      const int tjk[4] = {c.x, c.y, c.z, c.w};
+      const int mi[2] = {ii4.x, ii4.w}, mj[2] = {jj4.x, jj4.w}, mk[2] = {kk4.x, kk4.w};
+      complete_table(tn, tij, tik, tjk, mi, mj, mk, pj.N, ttab);
     }
-    const int h = g;
-    const int iw = wave;  // this wave's pivot i = ib4 + iw
-    const bool wave_valid = i < j;
-    uint32_t kmin[2] = {0xffffffffu, 0xffffffffu}, kmax[2] = {0u, 0u};
-    const int64_t base_ij = wave_valid ? lex_base(M, i, j) : 0;
+    float tl[27];  // L[r + 1] per row (Eq. 1's first inner sum)
 #pragma unroll
-    for (int tt = 0; tt < kPermT; ++tt) {
-      __syncthreads();  // previous row tile's readers are done
+    for (int x = 0; x < 27; ++x) tl[x] = sL[ttab[x] + 1];
+    const int64_t rank = lex_base(M, i, j) + k;
+    for (int qg = 0; qg < 16; ++qg) {
+      const int q = 4 * qg + qs;
+      if (q >= Q || k >= M) continue;
+      const uint4 cq = cor[kl * 64 + q];
+      const uint32_t cn[8] = {cq.x & 0xffffu, cq.x >> 16, cq.y & 0xffffu, cq.y >> 16,
+                              cq.z & 0xffffu, cq.z >> 16, cq.w & 0xffffu, cq.w >> 16};
+      int ctab[27];
       {
-        const int4 *cp = reinterpret_cast<const int4 *>(pj.case_pairs);
-        const int q = tid & 63;
-        const int qq = q < Qp ? q : Qp - 1;
-        int4 v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {  // (i, k): [4 waves][4 tg] x 64 q = 1024
-          const int x = (tid >> 6) + 4 * u;  // 0..15 = w * 4 + tg
-          const int ii = ib4 + (x >> 2), kk = kbase + 4 * tt + (x & 3);
-          v[u] = cp[((int64_t)ii * Mp + kk) * Qp + qq];
-        }
-        const int tg = tid >> 6, kk = kbase + 4 * tt + tg;
-        const int4 vjk = cp[((int64_t)j * Mp + kk) * Qp + qq];
-        const int4 vkk = cp[((int64_t)kk * Mp + kk) * Qp + qq];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) ePik[((tid >> 6) + 4 * u) * 64 + q] = v[u];
-        ePjk[tg * 64 + q] = vjk;
-        ePkk[tg * 64 + q] = make_int2(vkk.x, vkk.w);
+        const int4 a = cp[((int64_t)i * Mp + j) * Qp + q], b = cp[((int64_t)i * Mp + k) * Qp + q];
+        const int4 c = cp[((int64_t)j * Mp + k) * Qp + q];
+        const int4 ii4 = cp[((int64_t)i * Mp + i) * Qp + q], jj4 = cp[((int64_t)j * Mp + j) * Qp + q];
+        const int4 kk4 = cp[((int64_t)k * Mp + k) * Qp + q];
+        const int cij[4] = {a.x, a.y, a.z, a.w}, cik[4] = {b.x, b.y, b.z, b.w};
+        const int cjk[4] = {c.x, c.y, c.z, c.w};
+        const int mi[2] = {ii4.x, ii4.w}, mj[2] = {jj4.x, jj4.w}, mk[2] = {kk4.x, kk4.w};
+        complete_table(cn, cij, cik, cjk, mi, mj, mk, pj.n1[q], ctab);
       }
-      __syncthreads();
-      if (!wave_valid) continue;
+      float k2 = 0.f;  // rows in order: L[r + 1] - (L[r_0] + L[r_1]), r_1 = cases
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int tg = 2 * h + u;  // triplet within the row tile
-        const int kl = 4 * tt + tg;
-        const int k = kbase + kl;
-        // totals table of this triplet (the same for every phenotype)
-        uint32_t tn[8];
-#pragma unroll
-        for (int x = 0; x < 8; ++x) tn[x] = myTot[tt * 32 + 8 * tg + x];
-        int ttab[27];
-        {
-          const int4 a = eTij[iw], b = eTik[iw * kPermKB + kl], c = eTjk[kl];
-          const int4 ii4 = eTii[iw], jj4 = eTjj[0], kk4 = eTkk[kl];
-          const int tij[4] = {a.x, a.y, a.z, a.w}, tik[4] = {b.x, b.y, b.z, b.w};
-          const int tjk[4] = {c.x, c.y, c.z, c.w};
-          const int mi[2] = {ii4.x, ii4.w}, mj[2] = {jj4.x, jj4.w}, mk[2] = {kk4.x, kk4.w};
-          complete_table(tn, tij, tik, tjk, mi, mj, mk, pj.N, ttab);
-        }
-        float tl[27];  // L[r + 1] of each row: Eq. 1's first inner sum, shared by all phenotypes
-#pragma unroll
-        for (int x = 0; x < 27; ++x) tl[x] = sL[ttab[x] + 1];
-#pragma unroll
-        for (int qb = 0; qb < 2; ++qb) {
-          const int q = qb * 32 + r;
-          int send[4], recv[4];
-          // lane h holds corner cells a = h of triplets; partner holds a = 1 - h
-#pragma unroll
-          for (int x = 0; x < 4; ++x)
-            send[x] = h ? acc[tt][qb][4 * u + x] : acc[tt][qb][8 + 4 * u + x];
-#pragma unroll
-          for (int x = 0; x < 4; ++x) recv[x] = __shfl_xor(send[x], 32);
-          uint32_t cn[8];
-#pragma unroll
-          for (int bc = 0; bc < 4; ++bc) {
-            const int own = h ? acc[tt][qb][8 + 4 * u + bc] : acc[tt][qb][4 * u + bc];
-            cn[bc] = (uint32_t)(h ? recv[bc] : own);      // a = 0
-            cn[4 + bc] = (uint32_t)(h ? own : recv[bc]);  // a = 1
-          }
-          int ctab[27];
-          {
-            const int4 a = ePij[iw * 64 + q], b = ePik[(iw * 4 + tg) * 64 + q], c = ePjk[tg * 64 + q];
-            const int2 ii2 = ePii[iw * 64 + q], jj2 = ePjj[q], kk2 = ePkk[tg * 64 + q];
-            const int cij[4] = {a.x, a.y, a.z, a.w}, cik[4] = {b.x, b.y, b.z, b.w};
-            const int cjk[4] = {c.x, c.y, c.z, c.w};
-            const int mi[2] = {ii2.x, ii2.y}, mj[2] = {jj2.x, jj2.y}, mk[2] = {kk2.x, kk2.y};
-            complete_table(cn, cij, cik, cjk, mi, mj, mk, eN1[q], ctab);
-          }
-          float k2 = 0.f;  // rows in order, each L[r + 1] - (L[r_0] + L[r_1]) as in the plain kernel
-#pragma unroll
-          for (int x = 0; x < 27; ++x) k2 += tl[x] - (sL[ttab[x] - ctab[x]] + sL[ctab[x]]);
-          if (q < Q && k < M) {
-            pj.score[(int64_t)q * T + base_ij + k] = k2;
-            const uint32_t key = f2key(k2);
-            kmin[qb] = key < kmin[qb] ? key : kmin[qb];
-            kmax[qb] = key > kmax[qb] ? key : kmax[qb];
-          }
-        }
-      }
+      for (int x = 0; x < 27; ++x) k2 += tl[x] - (sL[ttab[x] - ctab[x]] + sL[ctab[x]]);
+      pj.score[(int64_t)q * T + rank] = k2;
+      const uint32_t key = f2key(k2);
+      atomicMin(&sRange[q][0], key);
+      atomicMax(&sRange[q][1], key);
     }
-    // per-phenotype key range: lanes q and q + 32 hold the same q
-#pragma unroll
-    for (int qb = 0; qb < 2; ++qb) {
-      const int q = qb * 32 + r;
-      const uint32_t omin = __shfl_xor(kmin[qb], 32), omax = __shfl_xor(kmax[qb], 32);
-      const uint32_t mn = omin < kmin[qb] ? omin : kmin[qb];
-      const uint32_t mx = omax > kmax[qb] ? omax : kmax[qb];
-      if (h == 0 && q < Q && mx != 0u) {
-        atomicMin(&st[q].kmin, mn);
-        atomicMax(&st[q].kmax, mx);
-      }
-    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 64 && threadIdx.x < Q && sRange[threadIdx.x][1] != 0u) {
+    atomicMin(&st[threadIdx.x].kmin, sRange[threadIdx.x][0]);
+    atomicMax(&st[threadIdx.x].kmax, sRange[threadIdx.x][1]);
   }
 }
 
@@ -503,27 +456,47 @@ int64_t host_perm_tiles(int64_t M) {
   return n;
 }
 
-hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t n_tiles, SelState *st,
-                                  unsigned long long *queue, const float *lf32, int32_t lf_len,
-                                  hipStream_t s) {
+hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,
+                                  unsigned long long *queue, hipStream_t s) {
+  const int64_t n = tile_end - tile_begin;
+  if (n <= 0) return hipSuccess;
   int dev = 0, n_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  const size_t lds = 2 * (size_t)kStageBytes + 4 * kPermT * 32 * sizeof(uint32_t) +
-                     2 * sizeof(int64_t) + (size_t)lf_len * sizeof(float);
-  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&count_mfma_perm_kernel),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, count_mfma_perm_kernel, 256, lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, count_mfma_perm_kernel, 256, 0);
   if (e != hipSuccess) return e;
   if (per_cu <= 0) per_cu = 1;
   int64_t blocks = (int64_t)n_cu * per_cu;
-  if (blocks > n_tiles) blocks = n_tiles > 0 ? n_tiles : 1;
-  hipLaunchKernelGGL(count_mfma_perm_kernel, dim3((unsigned)blocks), dim3(256), lds, s, pj_dev, st,
-                     queue, lf32, lf_len);
+  if (blocks > n) blocks = n;
+  hipLaunchKernelGGL(count_mfma_perm_kernel, dim3((unsigned)blocks), dim3(256), 0, s, pj_dev,
+                     tile_begin, tile_end, queue);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,
+                              SelState *st, const float *lf32, int32_t lf_len, hipStream_t s) {
+  const int64_t n = tile_end - tile_begin;
+  if (n <= 0) return hipSuccess;
+  int dev = 0, n_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const size_t lds = (size_t)lf_len * sizeof(float);
+  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&finish_perm_kernel),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, finish_perm_kernel, 256, lds);
+  if (e != hipSuccess) return e;
+  if (per_cu <= 0) per_cu = 1;
+  int64_t blocks = (int64_t)n_cu * per_cu;
+  if (blocks > n) blocks = n;
+  hipLaunchKernelGGL(finish_perm_kernel, dim3((unsigned)blocks), dim3(256), lds, s, pj_dev,
+                     tile_begin, tile_end, st, lf32, lf_len);
   return hipGetLastError();
 }
 

@@ -99,6 +99,8 @@ struct PermJob {
   const int32_t *n1;          // [Qp] cases per phenotype
   float *score;               // [Q][T]
   const int64_t *jprefix;     // [M + 1]
+  uint4 *corners;             // scratch: [pass tile][4 pivots i][16 k][64 q] 8 x uint16 case cells
+  uint4 *totals;              // scratch: [pass tile][4 pivots i][16 k] 8 x uint16 all-sample cells
   int64_t n_tiles, T;
   int32_t M, Mp, S, N, Q, Qp;
 };
@@ -201,9 +203,11 @@ hipError_t launch_case_pairs(const uint32_t *planes, int32_t Mp, int32_t W,
                              const uint32_t *const *masks_dev, int32_t Q, int32_t Qp, int32_t *out,
                              hipStream_t s);
 int64_t host_perm_tiles(int64_t M);
-hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t n_tiles, SelState *st,
-                                  unsigned long long *queue, const float *lf32, int32_t lf_len,
-                                  hipStream_t s);
+hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,
+                                  unsigned long long *queue, hipStream_t s);
+hipError_t launch_finish_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,
+                              SelState *st, const float *lf32, int32_t lf_len, hipStream_t s);
+constexpr int64_t kPermTileScratch = 64 * 64 * 16 + 64 * 16;  // bytes per tile (corners + totals)
 hipError_t launch_write_permjob(const PermJob &h, PermJob *dst_dev, hipStream_t s);
 hipError_t launch_write_ptrs(const uint32_t *const *h, int32_t n, const uint32_t **dst_dev,
                              hipStream_t s);
