@@ -30,6 +30,7 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12      # INT32 lane-ops/s: CUs x lanes x 
 VALU_OPS_PER_ST = 16.0 / 32.0                  # 8 AND + 8 v_bcnt per triplet per 32 samples
 
 MFMA_I8_PEAK_TOPS = 5000.0                     # dense int8 matrix-core ops/s (MI355X)
+MFMA_FP4_PEAK_TFLOPS = 10100.0                 # dense FP4 matrix-core flop/s (MI355X)
 MFMA_OPS_PER_STQ = 16.0                        # 8 corner cells x (multiply + add) per sample-triplet-phenotype
 
 WORKLOADS = {
@@ -103,7 +104,7 @@ def run_plain(args, wl):
     d = make_config(wl["cfg"])
     M, N, k = d.n_snps, d.n_samples, c["k"]
     geno = torch.from_numpy(d.geno).to("cuda")          # resident before timing
-    variant = args.variant
+    variant = "valu" if args.variant in ("auto", "mfma_fp4") else args.variant
     ds = epi3.encode(geno, d.pheno)
     sc = epi3.Scanner(ds, k, variant)
 
@@ -206,7 +207,8 @@ def run_perm(args, wl):
     geno = torch.from_numpy(d.geno).to("cuda")
     masks = torch.from_numpy(epi3.pack_masks(perms).view(np.int32)).to("cuda")
     ds = epi3.encode(geno, d.pheno, layout="masked")
-    bs = epi3.BatchScanner(ds, k, masks=masks, variant="mfma")
+    variant = "mfma" if args.variant == "mfma" else "mfma_fp4"
+    bs = epi3.BatchScanner(ds, k, masks=masks, variant=variant)
 
     def step():  # encode (planes, bytes, pairwise tables) + one batched launch
         epi3.encode(geno, d.pheno, layout="masked", into=ds)
@@ -234,22 +236,25 @@ def run_perm(args, wl):
     p_dt, plain_res = _timed_steps(plain_all, 1, 1)
     same = all(a.tobytes() == b.tobytes() for a, b in zip(res, plain_res))
     plain_value = work / p_dt / 1e12
-    out = _base(args, wl, value, dt * 1e3, "i8", {
+    out = _base(args, wl, value, dt * 1e3, "fp4" if variant == "mfma_fp4" else "i8", {
         "workload": wl["desc"], "snps": M, "samples": N, "phenotypes": Q, "top_k": k,
-        "triplets": T, "variant": "mfma", "counted": "sample-triplets per phenotype, summed"})
+        "triplets": T, "variant": variant, "counted": "sample-triplets per phenotype, summed"})
     out["speedup_vs_plain"] = round(value / plain_value, 3)
     out["plain"] = {"value": round(plain_value, 4), "unit": "T sample-triplets/s",
                     "ms_for_all_phenotypes": round(p_dt * 1e3, 3),
                     "how": "64 x (encode split planes + VALU count + top-k), same data",
                     "hits_identical_to_batched": bool(same)}
-    out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2), "peak": MFMA_I8_PEAK_TOPS,
-                       "unit": "TOP/s (int8)", "frac": round(achieved / MFMA_I8_PEAK_TOPS, 4),
+    peak = MFMA_FP4_PEAK_TFLOPS if variant == "mfma_fp4" else MFMA_I8_PEAK_TOPS
+    out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
+                       "unit": "TFLOP/s (fp4)" if variant == "mfma_fp4" else "TOP/s (int8)",
+                       "frac": round(achieved / peak, 4),
                        "traffic": recorded_traffic(f"count_mfma_perm_kernel|{args.workload}"),
                        "traffic_unit": "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
                        "kernel": "count_mfma_perm_kernel", "kernel_ms": round(k_ms / max(k_n, 1), 4),
                        "launches_per_step": k_n,
                        "ops_per_launch": MFMA_OPS_PER_STQ * T * N * Q / max(k_n, 1),
-                       "measured_peak_note": "register-only v_mfma_i32_32x32x32_i8 chains sustain 4.6 POP/s"}
+                       "measured_peak_note": "register-only chains sustain 4.6 POP/s (int8 32x32x32) "
+                                             "and 9.0 PFLOP/s (fp4 32x32x64)"}
     out["breakdown_ms"] = {"count_kernels": round(k_ms, 3), "finish_kernels": round(fin_ms, 3),
                            "selection": round(sel_ms, 3)}
     out["min_k2_per_phenotype"] = [round(float(h["k2"][0]), 6) for h in res[:4]] + ["..."]
@@ -326,7 +331,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
-    ap.add_argument("--variant", default="valu", choices=["auto", "valu", "mfma"])
+    ap.add_argument("--variant", default="auto", choices=["auto", "valu", "mfma", "mfma_fp4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true")

@@ -71,7 +71,9 @@ enum {
 enum {
     EPI3_VARIANT_AUTO = 0,  /* library choice (MFMA where available) */
     EPI3_VARIANT_VALU = 1,  /* AND + v_bcnt popcount on the vector ALU */
-    EPI3_VARIANT_MFMA = 2   /* 0/1 byte matrices on int8 matrix cores */
+    EPI3_VARIANT_MFMA = 2,  /* 0/1 byte matrices on int8 matrix cores, int32 accumulation */
+    EPI3_VARIANT_MFMA_FP4 = 3 /* 0/1 values as FP4 (E2M1) on the matrix cores, FP32 accumulation
+                                 (exact: every count is an integer below 2^24) */
 };
 
 /* An encoded data set.  Plain data; every pointer points into the caller's
@@ -88,6 +90,8 @@ typedef struct {
     int32_t reserved;
     void *planes;         /* device: bit planes  [word][snp_stride][2] uint32 */
     void *bytes;          /* device: byte planes [snp_stride][2][byte_stride] (MASKED), else NULL */
+    void *nibbles;        /* device: the same as E2M1 nibbles, 0x2 = 1.0, two samples per byte
+                             (low nibble first) [snp_stride][2][byte_stride / 2] (MASKED), else NULL */
     int32_t *pairs;       /* device: pairwise tables [class][snp_stride][snp_stride][4] */
     double *lf64;         /* device: log factorials L[0..N+1] in FP64 */
     float *lf32;          /* device: the same rounded to FP32 */

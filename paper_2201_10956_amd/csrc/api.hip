@@ -41,6 +41,7 @@ struct EncodeLayout {
   int32_t Mp, W0, W1, Wtot, classes, S;
   uint32_t *planes;
   uint8_t *bytes;
+  uint8_t *nibbles;
   int32_t *pairs;
   double *lf64;
   float *lf32;
@@ -69,6 +70,7 @@ EncodeLayout encode_layout(void *buf, int32_t M, int32_t n1, int32_t n0, int32_t
   L.status = c.take<int32_t>(64);
   L.planes = c.take<uint32_t>((int64_t)L.Wtot * L.Mp * 2);
   L.bytes = c.take<uint8_t>((int64_t)L.Mp * 2 * L.S);
+  L.nibbles = c.take<uint8_t>((int64_t)L.Mp * 2 * (L.S / 2));
   L.pairs = c.take<int32_t>((int64_t)L.classes * L.Mp * L.Mp * 4);
   L.lf64 = c.take<double>((int64_t)N + 2);
   L.lf32 = c.take<float>((int64_t)N + 2);
@@ -309,8 +311,10 @@ int epi3_encode(const uint8_t *geno_dev, int64_t ld, const uint8_t *pheno_host, 
   HIP_OK(hipMemcpyAsync(L.lf32, L32.data(), L32.size() * sizeof(float), hipMemcpyHostToDevice, s));
   HIP_OK(launch_encode(geno_dev, ld, L.list, n_snps, L.Mp, layout == EPI3_LAYOUT_SPLIT ? L.W0 : L.Wtot,
                        layout == EPI3_LAYOUT_SPLIT ? L.W1 : 0, L.planes, L.status, s));
-  if (layout == EPI3_LAYOUT_MASKED)
+  if (layout == EPI3_LAYOUT_MASKED) {
     HIP_OK(launch_encode_bytes(geno_dev, ld, n_snps, n_samples, L.Mp, L.S, L.bytes, s));
+    HIP_OK(launch_encode_nibbles(geno_dev, ld, n_snps, n_samples, L.Mp, L.S, L.nibbles, s));
+  }
   HIP_OK(launch_pairs(L.planes, L.Mp, n_snps, L.W0, layout == EPI3_LAYOUT_SPLIT ? L.W1 : 0,
                       L.classes, nullptr, L.pairs, s));
   HIP_OK(hipStreamSynchronize(s));  // host vectors above must outlive the copies
@@ -327,6 +331,7 @@ int epi3_encode(const uint8_t *geno_dev, int64_t ld, const uint8_t *pheno_host, 
   out->byte_stride = L.S;
   out->planes = L.planes;
   out->bytes = layout == EPI3_LAYOUT_MASKED ? L.bytes : nullptr;
+  out->nibbles = layout == EPI3_LAYOUT_MASKED ? L.nibbles : nullptr;
   out->pairs = L.pairs;
   out->lf64 = L.lf64;
   out->lf32 = L.lf32;
@@ -545,7 +550,9 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
 }
 
 // Enqueues the whole batched scan (no host synchronisation inside).
-int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, hipStream_t s) {
+int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32_t variant,
+                    hipStream_t s) {
+  const bool fp4 = variant != EPI3_VARIANT_MFMA;  // MASKED: AUTO and MFMA_FP4 use FP4
   // selection state first: the count kernels write each job's key range into it
   std::vector<SelJob> sj(n);
   for (int x = 0; x < n; ++x) {
@@ -620,8 +627,8 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, hipSt
     for (int g = 0; g < W.groups; ++g) {
       const int Q = std::min(kPermGroup, n - g * kPermGroup);
       PermJob pj{};
-      pj.bytes = static_cast<const uint8_t *>(d.bytes);
-      pj.ph = W.ph + (int64_t)g * kPermGroup * d.byte_stride;
+      pj.bytes = static_cast<const uint8_t *>(fp4 ? d.nibbles : d.bytes);
+      pj.ph = W.ph + (int64_t)g * kPermGroup * d.byte_stride;  // FP4 rows use the first half
       pj.tot_pairs = d.pairs;
       pj.case_pairs = W.case_pairs + (int64_t)g * d.snp_stride * d.snp_stride * kPermGroup * 4;
       pj.n1 = W.n1 + (int64_t)g * kPermGroup;
@@ -633,14 +640,14 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, hipSt
       pj.T = epi3_n_triplets(d.n_snps);
       pj.M = d.n_snps;
       pj.Mp = d.snp_stride;
-      pj.S = d.byte_stride;
+      pj.S = fp4 ? d.byte_stride / 2 : d.byte_stride;
       pj.N = d.n_samples;
       pj.Q = Q;
       pj.Qp = kPermGroup;
       HIP_OK(launch_write_permjob(pj, W.pjobs + g, s));
       HIP_OK(launch_mask_bytes(W.masks + (int64_t)g * kPermGroup, Q, kPermGroup, d.n_samples,
                                d.byte_stride, const_cast<uint8_t *>(pj.ph),
-                               const_cast<int32_t *>(pj.n1), s));
+                               const_cast<int32_t *>(pj.n1), fp4, s));
       HIP_OK(launch_case_pairs(static_cast<const uint32_t *>(d.planes), d.snp_stride, d.words[0],
                                W.masks + (int64_t)g * kPermGroup, Q, kPermGroup,
                                const_cast<int32_t *>(pj.case_pairs), s));
@@ -649,8 +656,9 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, hipSt
         const int64_t t1 = std::min(tiles, t0 + W.pass_tiles);
         HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
         int rc = timed(0, s, [&]() {
-          return launch_count_mfma_perm(W.pjobs + g, t0, t1, W.queue, s) == hipSuccess ? EPI3_OK
-                                                                                      : EPI3_E_HIP;
+          return launch_count_mfma_perm(W.pjobs + g, t0, t1, W.queue, fp4, s) == hipSuccess
+                     ? EPI3_OK
+                     : EPI3_E_HIP;
         });
         if (rc != EPI3_OK) return rc;
         rc = timed(3, s, [&]() {
@@ -723,6 +731,8 @@ int epi3_scan_batched(const epi3_job *jobs, int32_t n_jobs, int32_t variant, int
   const int layout = jobs[0].d->layout;
   if (layout == EPI3_LAYOUT_SPLIT && variant == EPI3_VARIANT_MFMA) return EPI3_E_UNSUPPORTED;
   if (layout == EPI3_LAYOUT_MASKED && variant == EPI3_VARIANT_VALU) return EPI3_E_UNSUPPORTED;
+  if (layout == EPI3_LAYOUT_SPLIT && variant == EPI3_VARIANT_MFMA_FP4) return EPI3_E_UNSUPPORTED;
+  if (variant < EPI3_VARIANT_AUTO || variant > EPI3_VARIANT_MFMA_FP4) return EPI3_E_INVALID;
   BatchLayout W = batch_layout(ws_dev, jobs, n_jobs, cand_cap);
   if (ws_bytes < W.total) return EPI3_E_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -731,7 +741,7 @@ int epi3_scan_batched(const epi3_job *jobs, int32_t n_jobs, int32_t variant, int
   hipGraphExec_t exec = nullptr;
   if (timing_on()) {
     // measurement mode: run the same sequence eagerly so each kernel is timed
-    rc = timed(2, s, [&]() { return enqueue_batched(jobs, n_jobs, W, s); });
+    rc = timed(2, s, [&]() { return enqueue_batched(jobs, n_jobs, W, variant, s); });
     if (rc != EPI3_OK) return rc;
   } else {
     std::lock_guard<std::mutex> lk(G.mu);
@@ -742,7 +752,7 @@ int epi3_scan_batched(const epi3_job *jobs, int32_t n_jobs, int32_t variant, int
     } else {
       if (!G.capture) HIP_OK(hipStreamCreateWithFlags(&G.capture, hipStreamNonBlocking));
       HIP_OK(hipStreamBeginCapture(G.capture, hipStreamCaptureModeRelaxed));
-      rc = enqueue_batched(jobs, n_jobs, W, G.capture);
+      rc = enqueue_batched(jobs, n_jobs, W, variant, G.capture);
       hipGraph_t graph = nullptr;
       const hipError_t e = hipStreamEndCapture(G.capture, &graph);
       if (rc != EPI3_OK || e != hipSuccess) {

@@ -71,22 +71,25 @@ __global__ void __launch_bounds__(1024) perm_prefix_kernel(PermJob *pj) {
 
 // PH[q][s] = 1 if sample s is a case of phenotype q (0 for q >= Q or s >= N);
 // n1[q] = number of cases.  One block per q.
+// With FP4, the row holds E2M1 nibbles (1.0 = 0x2, two samples per byte, low
+// nibble first) and is S / 2 bytes long.
 __global__ void __launch_bounds__(256) mask_bytes_kernel(const uint32_t *const *masks, int32_t Q,
                                                          int32_t N, int32_t S, uint8_t *ph,
-                                                         int32_t *n1) {
+                                                         int32_t *n1, int fp4) {
   const int q = blockIdx.x;
   __shared__ int red[256];
   int cnt = 0;
-  uint32_t *row = reinterpret_cast<uint32_t *>(ph + (int64_t)q * S);
-  for (int d = threadIdx.x; d < S / 4; d += blockDim.x) {
+  const int per = fp4 ? 8 : 4;           // samples per dword
+  const int rowb = fp4 ? S / 2 : S;      // bytes per row
+  uint32_t *row = reinterpret_cast<uint32_t *>(ph + (int64_t)q * rowb);
+  for (int d = threadIdx.x; d < rowb / 4; d += blockDim.x) {
     uint32_t v = 0;
     if (q < Q) {
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int s = 4 * d + b;
+      for (int b = 0; b < per; ++b) {
+        const int s = per * d + b;
         if (s < N) {
           const uint32_t bit = (masks[q][s >> 5] >> (s & 31)) & 1u;
-          v |= bit << (8 * b);
+          v |= fp4 ? (bit << (4 * b + 1)) : (bit << (8 * b));
           cnt += (int)bit;
         }
       }
@@ -165,9 +168,37 @@ using gptr = const __attribute__((address_space(1))) T *;
 // pair words are staged per chunk of kKC samples in double-buffered LDS; each
 // wave then runs 8 MFMAs per 32 samples (4 row tiles of 4 triplets x 8
 // corner cells, 2 column tiles of 32 phenotypes).
+// FP4: operands are E2M1 nibbles (each staged byte holds two samples, so a
+// 32-byte step covers 64 samples) on v_mfma_scale_f32_32x32x64_f8f6f4 with
+// unit scales; accumulation in FP32 is exact for counts below 2^24.
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+template <bool FP4>
+struct PermAcc {
+  typedef v16i type;
+  static __device__ __forceinline__ type mma(v4i a, v4i b, type c) {
+    return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ uint32_t get(const type &c, int v) { return (uint32_t)c[v]; }
+};
+template <>
+struct PermAcc<true> {
+  typedef v16f type;
+  static __device__ __forceinline__ type mma(v4i a, v4i b, type c) {
+    const v8i a8 = {a.x, a.y, a.z, a.w, 0, 0, 0, 0};
+    const v8i b8 = {b.x, b.y, b.z, b.w, 0, 0, 0, 0};
+    // cbsz = blgp = 4: both operands FP4 (E2M1); scale exponents 127 = 2^0
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, c, 4, 4, 0, 127, 0, 127);
+  }
+  static __device__ __forceinline__ uint32_t get(const type &c, int v) { return (uint32_t)c[v]; }
+};
+
+template <bool FP4>
 __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
     const PermJob *__restrict__ pjp, int64_t tile_begin, int64_t tile_end,
     unsigned long long *__restrict__ queue) {
+  typedef PermAcc<FP4> Acc;
   __shared__ __attribute__((aligned(16))) unsigned char stage[2 * kStageBytes];
   __shared__ int64_t sTile[2];
 
@@ -180,7 +211,7 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
   gptr<uint8_t> gb = (gptr<uint8_t>)pj.bytes;
   gptr<uint8_t> gph = (gptr<uint8_t>)pj.ph;
   cptr<int64_t> pre = as_const(pj.jprefix);
-  const int nch = S / kKC;  // S is a multiple of 256
+  const int nch = S / kKC;  // bytes per row: a multiple of 128
   int j = -1;
   int64_t jlo = 0, jhi = 0;
 
@@ -248,7 +279,7 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
         *reinterpret_cast<v4i *>(dst + (96 + (tid >> 3)) * kRow + (tid & 7) * 16) = pa & pb;
     };
 
-    v16i acc[kPermT][2];
+    typename Acc::type acc[kPermT][2];
     uint32_t tot[kPermT];
 #pragma unroll
     for (int tt = 0; tt < kPermT; ++tt) {
@@ -263,7 +294,7 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
     for (int ch = 0; ch < nch; ++ch) {
       if (ch + 1 < nch) fetch(ch + 1);
       const uint8_t *buf = stage + (ch & 1) * kStageBytes;
-#pragma unroll
+#pragma unroll 1  // one step at a time keeps the operands of a single step live (no spills)
       for (int stp = 0; stp < kKC / 32; ++stp) {
         const int off = stp * 32 + 16 * g;
         const v4i p = *reinterpret_cast<const v4i *>(buf + prow * kRow + off);
@@ -274,8 +305,8 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
           const int xrow = kRowsPH + (4 * tt + ta) * 2 + rc;
           const v4i a = p & *reinterpret_cast<const v4i *>(buf + xrow * kRow + off);
           tot[tt] += popc4(a);
-          acc[tt][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b0, acc[tt][0], 0, 0, 0);
-          acc[tt][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b1, acc[tt][1], 0, 0, 0);
+          acc[tt][0] = Acc::mma(a, b0, acc[tt][0]);
+          acc[tt][1] = Acc::mma(a, b1, acc[tt][1]);
         }
       }
       if (ch + 1 < nch) store((ch + 1) & 1);
@@ -304,8 +335,8 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
       for (int qb = 0; qb < 2; ++qb)
 #pragma unroll
         for (int t4 = 0; t4 < 4; ++t4) {
-          const uint32_t c0 = (uint32_t)acc[tt][qb][4 * t4 + 0], c1 = (uint32_t)acc[tt][qb][4 * t4 + 1];
-          const uint32_t c2 = (uint32_t)acc[tt][qb][4 * t4 + 2], c3 = (uint32_t)acc[tt][qb][4 * t4 + 3];
+          const uint32_t c0 = Acc::get(acc[tt][qb], 4 * t4 + 0), c1 = Acc::get(acc[tt][qb], 4 * t4 + 1);
+          const uint32_t c2 = Acc::get(acc[tt][qb], 4 * t4 + 2), c3 = Acc::get(acc[tt][qb], 4 * t4 + 3);
           cor2[((4 * tt + t4) * 64 + qb * 32 + r) * 2 + g] = make_uint2(c0 | (c1 << 16), c2 | (c3 << 16));
         }
   }
@@ -412,8 +443,9 @@ hipError_t launch_perm_prefix(PermJob *pj_dev, hipStream_t s) {
 }
 
 hipError_t launch_mask_bytes(const uint32_t *const *masks_dev, int32_t Q, int32_t Qp, int32_t N,
-                             int32_t S, uint8_t *ph, int32_t *n1, hipStream_t s) {
-  hipLaunchKernelGGL(mask_bytes_kernel, dim3(Qp), dim3(256), 0, s, masks_dev, Q, N, S, ph, n1);
+                             int32_t S, uint8_t *ph, int32_t *n1, bool fp4, hipStream_t s) {
+  hipLaunchKernelGGL(mask_bytes_kernel, dim3(Qp), dim3(256), 0, s, masks_dev, Q, N, S, ph, n1,
+                     fp4 ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -456,8 +488,9 @@ int64_t host_perm_tiles(int64_t M) {
   return n;
 }
 
-hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,
-                                  unsigned long long *queue, hipStream_t s) {
+template <bool FP4>
+static hipError_t launch_count_t(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,
+                                 unsigned long long *queue, hipStream_t s) {
   const int64_t n = tile_end - tile_begin;
   if (n <= 0) return hipSuccess;
   int dev = 0, n_cu = 0;
@@ -466,14 +499,20 @@ hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t tile_begin, int
   e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, count_mfma_perm_kernel, 256, 0);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, count_mfma_perm_kernel<FP4>, 256, 0);
   if (e != hipSuccess) return e;
   if (per_cu <= 0) per_cu = 1;
   int64_t blocks = (int64_t)n_cu * per_cu;
   if (blocks > n) blocks = n;
-  hipLaunchKernelGGL(count_mfma_perm_kernel, dim3((unsigned)blocks), dim3(256), 0, s, pj_dev,
+  hipLaunchKernelGGL(count_mfma_perm_kernel<FP4>, dim3((unsigned)blocks), dim3(256), 0, s, pj_dev,
                      tile_begin, tile_end, queue);
   return hipGetLastError();
+}
+
+hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,
+                                  unsigned long long *queue, bool fp4, hipStream_t s) {
+  return fp4 ? launch_count_t<true>(pj_dev, tile_begin, tile_end, queue, s)
+             : launch_count_t<false>(pj_dev, tile_begin, tile_end, queue, s);
 }
 
 hipError_t launch_finish_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,

@@ -71,6 +71,34 @@ __global__ void __launch_bounds__(256) encode_bytes_kernel(const uint8_t *__rest
   }
 }
 
+// nib[m][p][s / 2]: E2M1 value 1.0 (nibble 0x2) if sample s of SNP m has
+// genotype p, else 0.0; samples 2d and 2d + 1 share byte d (low nibble first).
+__global__ void __launch_bounds__(256) encode_nibbles_kernel(const uint8_t *__restrict__ geno,
+                                                             int64_t ld, int32_t M, int32_t N,
+                                                             int32_t Mp, int32_t S,
+                                                             uint32_t *__restrict__ nib) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;  // dword of a row: 8 samples
+  const int S8 = S >> 3;
+  if (q >= S8) return;
+  for (int m = blockIdx.y; m < Mp; m += gridDim.y) {
+    uint32_t v0 = 0, v1 = 0;
+    if (m < M) {
+      const uint8_t *row = geno + (int64_t)m * ld;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int s = 8 * q + b;
+        if (s < N) {
+          const uint32_t g = row[s];
+          v0 |= (uint32_t)(g == 0u) << (4 * b + 1);
+          v1 |= (uint32_t)(g == 1u) << (4 * b + 1);
+        }
+      }
+    }
+    nib[((int64_t)m * 2 + 0) * S8 + q] = v0;
+    nib[((int64_t)m * 2 + 1) * S8 + q] = v1;
+  }
+}
+
 // Pairwise tables: pairs[c][x][y] = (n(0,0), n(0,1), n(1,0), n(1,1)) with
 // n(a,b) = number of class-c samples where SNP x has genotype a and SNP y has
 // genotype b.  The diagonal holds the per-SNP counts (n_x(0), 0, 0, n_x(1)).
@@ -133,6 +161,15 @@ hipError_t launch_encode_bytes(const uint8_t *geno, int64_t ld, int32_t M, int32
   dim3 grid((S4 + 255) / 256, Mp < 65535 ? Mp : 65535);
   hipLaunchKernelGGL(encode_bytes_kernel, grid, dim3(256), 0, s, geno, ld, M, N, Mp, S,
                      reinterpret_cast<uint32_t *>(bytes));
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_nibbles(const uint8_t *geno, int64_t ld, int32_t M, int32_t N, int32_t Mp,
+                                 int32_t S, uint8_t *nib, hipStream_t s) {
+  const int S8 = S / 8;
+  dim3 grid((S8 + 255) / 256, Mp < 65535 ? Mp : 65535);
+  hipLaunchKernelGGL(encode_nibbles_kernel, grid, dim3(256), 0, s, geno, ld, M, N, Mp, S,
+                     reinterpret_cast<uint32_t *>(nib));
   return hipGetLastError();
 }
 

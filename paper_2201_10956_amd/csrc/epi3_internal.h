@@ -92,8 +92,8 @@ struct CandRec {
 // Phenotype batch for the matrix-core kernel: one MASKED data set and up to
 // 64 phenotypes (case masks).
 struct PermJob {
-  const uint8_t *bytes;       // [Mp][2][S] 0/1 genotype bytes
-  const uint8_t *ph;          // [64][S] 0/1 case bytes per phenotype
+  const uint8_t *bytes;       // [Mp][2][S] 0/1 genotype values (bytes, or E2M1 nibbles)
+  const uint8_t *ph;          // [64][S] 0/1 case values per phenotype (same format)
   const int32_t *tot_pairs;   // [Mp][Mp][4] pairwise tables over all samples
   const int32_t *case_pairs;  // [Mp][Mp][Qp][4] pairwise tables over each phenotype's cases
   const int32_t *n1;          // [Qp] cases per phenotype
@@ -102,7 +102,7 @@ struct PermJob {
   uint4 *corners;             // scratch: [pass tile][4 pivots i][16 k][64 q] 8 x uint16 case cells
   uint4 *totals;              // scratch: [pass tile][4 pivots i][16 k] 8 x uint16 all-sample cells
   int64_t n_tiles, T;
-  int32_t M, Mp, S, N, Q, Qp;
+  int32_t M, Mp, S, N, Q, Qp;  // S: bytes per staged row (samples for bytes, samples / 2 for nibbles)
 };
 
 // Selection job: one score plane plus its candidate buffers.
@@ -180,6 +180,8 @@ hipError_t launch_encode(const uint8_t *geno, int64_t ld, const int32_t *sample_
                          int32_t *status, hipStream_t s);
 hipError_t launch_encode_bytes(const uint8_t *geno, int64_t ld, int32_t M, int32_t N, int32_t Mp,
                                int32_t S, uint8_t *bytes, hipStream_t s);
+hipError_t launch_encode_nibbles(const uint8_t *geno, int64_t ld, int32_t M, int32_t N, int32_t Mp,
+                                 int32_t S, uint8_t *nib, hipStream_t s);
 hipError_t launch_pairs(const uint32_t *planes, int32_t Mp, int32_t M, int32_t W0, int32_t W1,
                         int32_t n_classes, const uint32_t *mask, int32_t *pairs, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
@@ -198,13 +200,13 @@ hipError_t launch_score_triplets(const epi3_dataset &d, const uint32_t *ijk, int
 
 hipError_t launch_perm_prefix(PermJob *pj_dev, hipStream_t s);
 hipError_t launch_mask_bytes(const uint32_t *const *masks_dev, int32_t Q, int32_t Qp, int32_t N,
-                             int32_t S, uint8_t *ph, int32_t *n1, hipStream_t s);
+                             int32_t S, uint8_t *ph, int32_t *n1, bool fp4, hipStream_t s);
 hipError_t launch_case_pairs(const uint32_t *planes, int32_t Mp, int32_t W,
                              const uint32_t *const *masks_dev, int32_t Q, int32_t Qp, int32_t *out,
                              hipStream_t s);
 int64_t host_perm_tiles(int64_t M);
 hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,
-                                  unsigned long long *queue, hipStream_t s);
+                                  unsigned long long *queue, bool fp4, hipStream_t s);
 hipError_t launch_finish_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,
                               SelState *st, const float *lf32, int32_t lf_len, hipStream_t s);
 constexpr int64_t kPermTileScratch = 64 * 64 * 16 + 64 * 16;  // bytes per tile (corners + totals)

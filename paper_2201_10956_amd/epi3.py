@@ -17,8 +17,9 @@ LIB_PATH = os.path.join(_HERE, "libepi3.so")
 OK, E_INVALID, E_GENOTYPE, E_PHENOTYPE, E_WORKSPACE, E_CAPACITY, E_HIP, E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7
 LAYOUT_SPLIT, LAYOUT_MASKED = 0, 1
-VARIANT_AUTO, VARIANT_VALU, VARIANT_MFMA = 0, 1, 2
-_VARIANTS = {"auto": VARIANT_AUTO, "valu": VARIANT_VALU, "mfma": VARIANT_MFMA}
+VARIANT_AUTO, VARIANT_VALU, VARIANT_MFMA, VARIANT_MFMA_FP4 = 0, 1, 2, 3
+_VARIANTS = {"auto": VARIANT_AUTO, "valu": VARIANT_VALU, "mfma": VARIANT_MFMA,
+             "mfma_fp4": VARIANT_MFMA_FP4}
 _ERRORS = {E_INVALID: "invalid argument", E_GENOTYPE: "genotype byte outside {0,1,2}",
            E_PHENOTYPE: "phenotype byte outside {0,1}", E_WORKSPACE: "workspace too small",
            E_CAPACITY: "candidate capacity exceeded", E_HIP: "HIP runtime error",
@@ -37,7 +38,7 @@ class CDataset(ctypes.Structure):
                 ("words", ctypes.c_int32 * 2), ("layout", ctypes.c_int32),
                 ("snp_stride", ctypes.c_int32), ("byte_stride", ctypes.c_int32),
                 ("reserved", ctypes.c_int32),
-                ("planes", ctypes.c_void_p), ("bytes", ctypes.c_void_p),
+                ("planes", ctypes.c_void_p), ("bytes", ctypes.c_void_p), ("nibbles", ctypes.c_void_p),
                 ("pairs", ctypes.c_void_p), ("lf64", ctypes.c_void_p),
                 ("lf32", ctypes.c_void_p), ("status", ctypes.c_void_p)]
 
@@ -56,7 +57,7 @@ class CJob(ctypes.Structure):
 HIT_DTYPE = np.dtype([("i", "<u4"), ("j", "<u4"), ("k", "<u4"), ("k2_f32", "<f4"),
                       ("k2", "<f8"), ("counts", "<u4", (2, 27))])
 assert HIT_DTYPE.itemsize == ctypes.sizeof(CHit) == 240
-assert ctypes.sizeof(CDataset) == 88 and ctypes.sizeof(CJob) == 24
+assert ctypes.sizeof(CDataset) == 96 and ctypes.sizeof(CJob) == 24
 
 
 def _load():

@@ -51,13 +51,15 @@ def test_uneven_graph_replays_match_eager(env):
         assert float(x.abs().sum()) > 0
 
 
-@pytest.mark.parametrize("M,N,Q", [(9, 70, 3), (40, 300, 5), (66, 257, 64), (20, 200, 70)])
-def test_permutations_match_oracle(env, M, N, Q):
+@pytest.mark.parametrize("variant", ["mfma", "mfma_fp4"])
+@pytest.mark.parametrize("M,N,Q", [(9, 70, 3), (40, 300, 5), (66, 257, 64), (20, 200, 70),
+                                   (35, 1111, 17)])
+def test_permutations_match_oracle(env, M, N, Q, variant):
     torch, epi3 = env
     d = make_dataset(M, N, 0.4, 0.05, seed=500 + M)
     perms = make_permutations(d.pheno, Q, seed=600 + N)
     ds = epi3.encode(to_dev(d.geno), d.pheno, layout="masked")
-    bs = epi3.BatchScanner(ds, 6, masks=_masks(epi3, perms), variant="mfma")
+    bs = epi3.BatchScanner(ds, 6, masks=_masks(epi3, perms), variant=variant)
     res = bs.run()
     assert len(res) == Q
     for q in range(Q):
@@ -65,20 +67,22 @@ def test_permutations_match_oracle(env, M, N, Q):
         assert_hits_equal_oracle(res[q], ijk, k2, cc)
 
 
-def test_permutations_equal_plain_scans(env):
+@pytest.mark.parametrize("variant", ["mfma", "mfma_fp4"])
+def test_permutations_equal_plain_scans(env, variant):
     """Batched phenotypes give the same hits as one plain scan per phenotype."""
     torch, epi3 = env
     d = make_dataset(70, 1000, 0.3, 0.05, seed=9)
     perms = make_permutations(d.pheno, 8, seed=10)
     g = to_dev(d.geno)
     ds = epi3.encode(g, d.pheno, layout="masked")
-    res = epi3.BatchScanner(ds, 12, masks=_masks(epi3, perms), variant="mfma").run()
+    res = epi3.BatchScanner(ds, 12, masks=_masks(epi3, perms), variant=variant).run()
     for q in range(8):
         plain = epi3.scan_topk(epi3.encode(g, perms[q]), 12, "valu")
         assert res[q].tobytes() == plain.tobytes()
 
 
-def test_permutation_edge_phenotypes(env):
+@pytest.mark.parametrize("variant", ["mfma", "mfma_fp4"])
+def test_permutation_edge_phenotypes(env, variant):
     """All controls, all cases, a single case."""
     torch, epi3 = env
     d = make_dataset(12, 130, 0.5, 0.05, seed=12)
@@ -86,7 +90,7 @@ def test_permutation_edge_phenotypes(env):
     perms[1, :] = 1
     perms[2, 77] = 1
     ds = epi3.encode(to_dev(d.geno), d.pheno, layout="masked")
-    res = epi3.BatchScanner(ds, 4, masks=_masks(epi3, perms), variant="mfma").run()
+    res = epi3.BatchScanner(ds, 4, masks=_masks(epi3, perms), variant=variant).run()
     for q in range(3):
         ijk, k2, cc = oracle.scan_topk(d.geno, perms[q], 4)
         assert_hits_equal_oracle(res[q], ijk, k2, cc)
@@ -109,7 +113,7 @@ def test_cfg4_permutations_full_size(env):
     c = CONFIGS[4]
     d, perms = make_config(4)
     ds = epi3.encode(to_dev(d.geno), d.pheno, layout="masked")
-    res = epi3.BatchScanner(ds, c["k"], masks=_masks(epi3, perms), variant="mfma").run()
+    res = epi3.BatchScanner(ds, c["k"], masks=_masks(epi3, perms), variant="auto").run()
     assert len(res) == c["n_perm"]
     for q in range(c["n_perm"]):
         h = res[q]
@@ -143,3 +147,15 @@ def test_cfg5_uneven_full_size(env):
         else:
             rc, rk = oracle.score_list(d.geno, d.pheno, hits_ijk(h))
             np.testing.assert_array_equal(h["k2"], rk)
+
+
+def test_fp4_and_int8_permutation_batches_agree(env):
+    torch, epi3 = env
+    d = make_dataset(130, 3000, 0.45, 0.05, seed=21)
+    perms = make_permutations(d.pheno, 40, seed=22)
+    ds = epi3.encode(to_dev(d.geno), d.pheno, layout="masked")
+    m = _masks(epi3, perms)
+    a = epi3.BatchScanner(ds, 25, masks=m, variant="mfma").run()
+    b = epi3.BatchScanner(ds, 25, masks=m, variant="mfma_fp4").run()
+    for x, y in zip(a, b):
+        assert x.tobytes() == y.tobytes()
