@@ -444,13 +444,14 @@ int epi3_score_triplets(const epi3_dataset *d, const uint32_t *ijk_dev, int64_t 
 namespace {
 
 constexpr int kPermGroup = 64;  // phenotypes per matrix-core launch
-constexpr int64_t kPermPassBytes = 8ll << 30;  // scratch for one pass of counted tiles
+constexpr int64_t kPermPassBytes = 4ll << 30;  // scratch for one pass of counted tiles
 
 // Workspace of a batched scan.
 struct BatchLayout {
   int n = 0, layout = 0, groups = 0;
   Job *jobs = nullptr;            // SPLIT
   PermJob *pjobs = nullptr;       // MASKED, one per group of 64 phenotypes
+  PermJob *pjobs_alt = nullptr;   // the same with the second scratch buffer
   SelJob *sel = nullptr;
   SelState *st = nullptr;
   uint32_t *hist = nullptr;
@@ -511,6 +512,7 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
     const epi3_dataset &d = *jobs[0].d;
     L.groups = (n + kPermGroup - 1) / kPermGroup;
     L.pjobs = c.take<PermJob>(L.groups);
+    L.pjobs_alt = c.take<PermJob>(L.groups);
     L.masks = c.take<const uint32_t *>((int64_t)L.groups * kPermGroup);
     L.ph = c.take<uint8_t>((int64_t)L.groups * kPermGroup * d.byte_stride);
     L.n1 = c.take<int32_t>((int64_t)L.groups * kPermGroup);
@@ -519,7 +521,8 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
     // counts of up to kPermPassBytes worth of tiles per pass
     const int64_t tiles = host_perm_tiles(d.n_snps);
     L.pass_tiles = std::max<int64_t>(1, std::min<int64_t>(tiles, kPermPassBytes / kPermTileScratch));
-    L.perm_scratch = c.take<uint8_t>(L.pass_tiles * kPermTileScratch);
+    // two buffers: the count kernel of pass p + 1 runs while pass p is scored
+    L.perm_scratch = c.take<uint8_t>(2 * L.pass_tiles * kPermTileScratch);
   }
   L.jprefix.resize(n);
   L.score.resize(n);
@@ -547,6 +550,30 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
   }
   L.total = c.size();
   return L;
+}
+
+// Second stream and events for the count / finish overlap (created once).
+struct Aux {
+  std::mutex mu;
+  hipStream_t s2 = nullptr;
+  std::vector<hipEvent_t> ev;
+};
+Aux &aux() {
+  static Aux a;
+  return a;
+}
+int aux_get(hipStream_t *s2, hipEvent_t *ev, int n_ev) {
+  Aux &a = aux();
+  std::lock_guard<std::mutex> g(a.mu);
+  if (!a.s2 && hipStreamCreateWithFlags(&a.s2, hipStreamNonBlocking) != hipSuccess) return EPI3_E_HIP;
+  while ((int)a.ev.size() < n_ev) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return EPI3_E_HIP;
+    a.ev.push_back(e);
+  }
+  *s2 = a.s2;
+  for (int x = 0; x < n_ev; ++x) ev[x] = a.ev[x];
+  return EPI3_OK;
 }
 
 // Enqueues the whole batched scan (no host synchronisation inside).
@@ -651,24 +678,49 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
       HIP_OK(launch_case_pairs(static_cast<const uint32_t *>(d.planes), d.snp_stride, d.words[0],
                                W.masks + (int64_t)g * kPermGroup, Q, kPermGroup,
                                const_cast<int32_t *>(pj.case_pairs), s));
-      if (g == 0) HIP_OK(launch_perm_prefix(W.pjobs, s));
-      for (int64_t t0 = 0; t0 < tiles; t0 += W.pass_tiles) {
+      if (g == 0) HIP_OK(launch_perm_prefix(W.pjobs + 0, s));
+      // Pass p counts into scratch buffer p % 2 on `s`; its finish kernel runs on
+      // the second stream while `s` counts pass p + 1.  Count p + 2 waits for
+      // finish p (same buffer).  Events order the two streams (also when captured).
+      hipStream_t s2 = nullptr;
+      hipEvent_t ev[5];
+      int rc = aux_get(&s2, ev, 5);
+      if (rc != EPI3_OK) return rc;
+      hipEvent_t ev_start = ev[0], ev_cnt[2] = {ev[1], ev[2]}, ev_fin[2] = {ev[3], ev[4]};
+      HIP_OK(hipEventRecord(ev_start, s));
+      HIP_OK(hipStreamWaitEvent(s2, ev_start, 0));
+      PermJob pjb[2] = {pj, pj};
+      pjb[1].corners = reinterpret_cast<uint4 *>(W.perm_scratch + W.pass_tiles * kPermTileScratch);
+      pjb[1].totals = reinterpret_cast<uint4 *>(W.perm_scratch + W.pass_tiles * kPermTileScratch +
+                                                W.pass_tiles * 64 * 64 * 16);
+      HIP_OK(launch_write_permjob(pjb[1], W.pjobs_alt + g, s));
+      const PermJob *pdev[2] = {W.pjobs + g, W.pjobs_alt + g};
+      int p = 0;
+      for (int64_t t0 = 0; t0 < tiles; t0 += W.pass_tiles, ++p) {
         const int64_t t1 = std::min(tiles, t0 + W.pass_tiles);
+        const int b = p & 1;
+        if (p >= 2) HIP_OK(hipStreamWaitEvent(s, ev_fin[b], 0));
         HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
-        int rc = timed(0, s, [&]() {
-          return launch_count_mfma_perm(W.pjobs + g, t0, t1, W.queue, fp4, s) == hipSuccess
+        rc = timed(0, s, [&]() {
+          return launch_count_mfma_perm(pdev[b], t0, t1, W.queue, fp4, s) == hipSuccess
                      ? EPI3_OK
                      : EPI3_E_HIP;
         });
         if (rc != EPI3_OK) return rc;
-        rc = timed(3, s, [&]() {
-          return launch_finish_perm(W.pjobs + g, t0, t1, W.st + (int64_t)g * kPermGroup, d.lf32,
-                                    d.n_samples + 2, s) == hipSuccess
+        HIP_OK(hipEventRecord(ev_cnt[b], s));
+        HIP_OK(hipStreamWaitEvent(s2, ev_cnt[b], 0));
+        rc = timed(3, s2, [&]() {
+          return launch_finish_perm(pdev[b], t0, t1, W.st + (int64_t)g * kPermGroup, d.lf32,
+                                    d.n_samples + 2, s2) == hipSuccess
                      ? EPI3_OK
                      : EPI3_E_HIP;
         });
         if (rc != EPI3_OK) return rc;
+        HIP_OK(hipEventRecord(ev_fin[b], s2));
       }
+      // join: everything on the second stream precedes what follows on `s`
+      HIP_OK(hipEventRecord(ev_fin[0], s2));
+      HIP_OK(hipStreamWaitEvent(s, ev_fin[0], 0));
     }
   }
   return timed(1, s, [&]() {
@@ -789,6 +841,14 @@ int epi3_scan_batched(const epi3_job *jobs, int32_t n_jobs, int32_t variant, int
 }
 
 void epi3_release(void) {
+  {
+    Aux &a = aux();
+    std::lock_guard<std::mutex> lk(a.mu);
+    for (auto e : a.ev) (void)hipEventDestroy(e);
+    a.ev.clear();
+    if (a.s2) (void)hipStreamDestroy(a.s2);
+    a.s2 = nullptr;
+  }
   GraphCache &G = graphs();
   std::lock_guard<std::mutex> lk(G.mu);
   for (auto &kv : G.exec) (void)hipGraphExecDestroy(kv.second);
