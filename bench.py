@@ -104,52 +104,51 @@ def run_plain(args, wl):
     d = make_config(wl["cfg"])
     M, N, k = d.n_snps, d.n_samples, c["k"]
     geno = torch.from_numpy(d.geno).to("cuda")          # resident before timing
-    variant = "valu" if args.variant in ("auto", "mfma_fp4") else args.variant
     ds = epi3.encode(geno, d.pheno)
+    variant = epi3.tile_for(ds, "auto") if args.variant == "auto" else args.variant
+    if args.tile:
+        epi3.tile_rule(variant, 0, 0, args.tile)
+    tile = epi3.tile_for(ds, variant)
     sc = epi3.Scanner(ds, k, variant)
 
     def step():
         epi3.encode(geno, d.pheno, into=ds)
         return sc.run()
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    epi3.timing_reset()
-    epi3.timing_enable(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        hits = step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    epi3.timing_enable(False)
-    cnt_ms, cnt_n = epi3.timing_query(0)
-    sel_ms, sel_n = epi3.timing_query(1)
+    dt, hits = _timed_steps(step, args.steps, args.warmup)
+    cnt_ms, cnt_n, sel_ms, fin_ms = _kernel_times(step)
     T = epi3.n_triplets(M)
     work = T * N
-    ms_step = dt * 1e3 / args.steps
-    value = work / (ms_step / 1e3) / 1e12
-    t_kernel = cnt_ms / max(cnt_n, 1) / 1e3
-    achieved = work * VALU_OPS_PER_ST / t_kernel / 1e12
-    out = {
-        "metric": METRIC, "value": round(value, 4), "unit": "T sample-triplets/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u32", "data": "synthetic (seeded HWE genotypes, planted triplet)",
-        "config": {"workload": wl["desc"], "snps": M, "samples": N, "cases": int(d.pheno.sum()),
-                   "top_k": k, "triplets": T, "variant": variant},
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
-                     "unit": "T int32-lane-ops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                     "traffic": recorded_traffic(f"count_valu_kernel|{args.workload}"),
-                     "traffic_unit": "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
-                     "kernel": "count_valu_kernel",
-                     "kernel_ms": round(t_kernel * 1e3, 4),
-                     "ops_per_launch": work * VALU_OPS_PER_ST},
-        "breakdown_ms": {"count_kernel": round(cnt_ms / max(cnt_n, 1), 4),
-                         "selection": round(sel_ms / max(sel_n, 1), 4)},
-        "best": {"ijk": [int(hits["i"][0]), int(hits["j"][0]), int(hits["k"][0])],
-                 "k2": float(hits["k2"][0])},
-    }
+    ms_step = dt * 1e3
+    value = work / dt / 1e12
+    out = _base(args, wl, value, ms_step, {"valu": "u32", "mfma": "i8", "mfma_fp4": "fp4"}[variant], {
+        "workload": wl["desc"], "snps": M, "samples": N, "cases": int(d.pheno.sum()),
+        "top_k": k, "triplets": T, "variant": variant, "tile": tile})
+    if variant == "valu":
+        achieved = work * VALU_OPS_PER_ST / (cnt_ms / 1e3) / 1e12
+        out["roofline"] = {
+            "bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
+            "unit": "T int32-lane-ops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+            "traffic": recorded_traffic(f"count_valu_kernel|{args.workload}"),
+            "traffic_unit": "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
+            "kernel": "count_valu_kernel", "kernel_ms": round(cnt_ms / max(cnt_n, 1), 4),
+            "ops_per_launch": work * VALU_OPS_PER_ST / max(cnt_n, 1)}
+    else:
+        peak = MFMA_FP4_PEAK_TFLOPS if variant == "mfma_fp4" else MFMA_I8_PEAK_TOPS
+        achieved = MFMA_OPS_PER_STQ * work / (cnt_ms / 1e3) / 1e12
+        out["roofline"] = {
+            "bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
+            "unit": "TFLOP/s (fp4)" if variant == "mfma_fp4" else "TOP/s (int8)",
+            "frac": round(achieved / peak, 4),
+            "traffic": recorded_traffic(f"count_mfma_plain_kernel|{args.workload}"),
+            "traffic_unit": "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
+            "kernel": "count_mfma_plain_kernel", "kernel_ms": round(cnt_ms / max(cnt_n, 1), 4),
+            "launches_per_step": cnt_n,
+            "ops_per_launch": MFMA_OPS_PER_STQ * work / max(cnt_n, 1)}
+    out["breakdown_ms"] = {"count_kernels": round(cnt_ms, 4), "finish_kernels": round(fin_ms, 4),
+                           "selection": round(sel_ms, 4)}
+    out["best"] = {"ijk": [int(hits["i"][0]), int(hits["j"][0]), int(hits["k"][0])],
+                   "k2": float(hits["k2"][0])}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d, k, args.cpu_budget)
     return out
@@ -332,6 +331,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--variant", default="auto", choices=["auto", "valu", "mfma", "mfma_fp4"])
+    ap.add_argument("--tile", type=int, default=0,
+                    help="force the count kernel's tile (plain workloads; 0: tuned table)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true")

@@ -69,7 +69,7 @@ enum {
 
 /* Count-stage kernels. */
 enum {
-    EPI3_VARIANT_AUTO = 0,  /* library choice (MFMA where available) */
+    EPI3_VARIANT_AUTO = 0,  /* library choice (see epi3_tile_rule) */
     EPI3_VARIANT_VALU = 1,  /* AND + v_bcnt popcount on the vector ALU */
     EPI3_VARIANT_MFMA = 2,  /* 0/1 byte matrices on int8 matrix cores, int32 accumulation */
     EPI3_VARIANT_MFMA_FP4 = 3 /* 0/1 values as FP4 (E2M1) on the matrix cores, FP32 accumulation
@@ -86,12 +86,13 @@ typedef struct {
     int32_t words[2];     /* 32-sample words of controls, cases (MASKED: all samples in both) */
     int32_t layout;       /* EPI3_LAYOUT_* */
     int32_t snp_stride;   /* padded SNP count of the plane arrays */
-    int32_t byte_stride;  /* padded sample count of the byte planes (MASKED), else 0 */
+    int32_t byte_stride;  /* padded sample count of the value planes (per class for SPLIT) */
     int32_t reserved;
     void *planes;         /* device: bit planes  [word][snp_stride][2] uint32 */
-    void *bytes;          /* device: byte planes [snp_stride][2][byte_stride] (MASKED), else NULL */
+    void *bytes;          /* device: 0/1 value planes [class][snp_stride][2][byte_stride] bytes
+                             (MASKED: one class of all samples; SPLIT: controls, cases) */
     void *nibbles;        /* device: the same as E2M1 nibbles, 0x2 = 1.0, two samples per byte
-                             (low nibble first) [snp_stride][2][byte_stride / 2] (MASKED), else NULL */
+                             (low nibble first) [class][snp_stride][2][byte_stride / 2] */
     int32_t *pairs;       /* device: pairwise tables [class][snp_stride][snp_stride][4] */
     double *lf64;         /* device: log factorials L[0..N+1] in FP64 */
     float *lf32;          /* device: the same rounded to FP32 */
@@ -147,12 +148,18 @@ int epi3_encode(const uint8_t *geno_dev, int64_t ld, const uint8_t *pheno_host,
  * samples), then the k lowest.
  * ------------------------------------------------------------------------ */
 
-/* Workspace bytes for epi3_scan + epi3_topk.  cand_cap <= 0 picks a default
- * capacity for FP32-screen candidates. */
-int64_t epi3_workspace_bytes(const epi3_dataset *d, int32_t k, int64_t cand_cap);
+/* Workspace bytes for epi3_scan + epi3_topk with count kernel `variant`.
+ * cand_cap <= 0 picks a default capacity for FP32-screen candidates.  The
+ * matrix-core variants add a scratch buffer for counted corner cells at the
+ * end of the workspace; every other part sits at the same offset for all
+ * variants. */
+int64_t epi3_workspace_bytes(const epi3_dataset *d, int32_t k, int32_t variant, int64_t cand_cap);
 
 /* Count + score every triplet and select candidates; asynchronous.
- * variant: EPI3_VARIANT_*.  ws_dev: device workspace (256-byte aligned). */
+ * variant: EPI3_VARIANT_*.  EPI3_VARIANT_MFMA and _MFMA_FP4 need class sizes
+ * of at most 65535 samples (EPI3_E_UNSUPPORTED otherwise).
+ * ws_dev: device workspace of epi3_workspace_bytes(d, k, variant, cand_cap)
+ * bytes (256-byte aligned). */
 int epi3_scan(const epi3_dataset *d, int32_t k, int32_t variant, int64_t cand_cap,
               void *ws_dev, int64_t ws_bytes, void *stream);
 
@@ -185,6 +192,15 @@ int epi3_scan_batched(const epi3_job *jobs, int32_t n_jobs, int32_t variant, int
                       void *ws_dev, int64_t ws_bytes, epi3_hit *hits_host,
                       int32_t *n_out_host, void *stream);
 
+/* Family-wise permutation p-value of an observed best score (not in the
+ * paper): p = (1 + #{q : perm_min_k2[q] <= observed_k2}) / (n_perm + 1), where
+ * perm_min_k2[q] is the lowest K2 of phenotype permutation q (hit 0 of job q of
+ * a MASKED batched scan) and observed_k2 the lowest K2 of the real phenotype.
+ * Lower K2 is stronger evidence, so a permutation counts when its best is at
+ * least as low.  Host arrays; EPI3_E_INVALID for n_perm < 1 or NULL pointers
+ * or a NaN score. */
+int epi3_perm_pvalue(double observed_k2, const double *perm_min_k2, int32_t n_perm, double *p_out);
+
 /* ---------------------------------------------------------------------------
  * Test hooks.
  * ------------------------------------------------------------------------ */
@@ -192,7 +208,7 @@ int epi3_scan_batched(const epi3_job *jobs, int32_t n_jobs, int32_t variant, int
 /* Run the count kernel of `variant` over every triplet of a SPLIT data set and
  * write each triplet's table and FP32 K2 in lexicographic (i, j, k) order:
  * counts_dev [C(M,3)][2][27] uint32 (may be NULL), k2_dev [C(M,3)] float.
- * ws_dev: a workspace of epi3_workspace_bytes(d, 1, 0) bytes.  Asynchronous. */
+ * ws_dev: a workspace of epi3_workspace_bytes(d, 1, variant, 0) bytes.  Asynchronous. */
 int epi3_scan_tables(const epi3_dataset *d, int32_t variant, uint32_t *counts_dev,
                      float *k2_dev, void *ws_dev, int64_t ws_bytes, void *stream);
 
@@ -222,6 +238,29 @@ void epi3_release(void);
 void epi3_timing_enable(int enable);
 int epi3_timing_query(int32_t which, double *ms, int64_t *launches);
 void epi3_timing_reset(void);
+
+/* ---------------------------------------------------------------------------
+ * Tile shapes (autotuning).  Not in the paper, whose kernels fix one tile.
+ * A rule applies to data sets with n_snps >= min_snps and n_samples >=
+ * min_samples; among the rules of a variant that apply, the one with the
+ * largest (min_snps, min_samples) wins, else the built-in default.
+ *   EPI3_VARIANT_VALU: tile = pivot pairs per lane tile, 4 or 8.
+ *   EPI3_VARIANT_MFMA, EPI3_VARIANT_MFMA_FP4 (plain scans): tile = JB, the
+ *     pivots j per workgroup tile of 16 i x JB j x 256 / JB k: 2, 4 or 8.
+ *   EPI3_VARIANT_AUTO: tile = the variant that AUTO selects for plain scans
+ *     (EPI3_VARIANT_VALU, _MFMA or _MFMA_FP4; a matrix-core choice falls back
+ *     to VALU for data sets it does not support).
+ * Rules are process-wide; change them only between scans and size each
+ * workspace after the change (the matrix-core scratch depends on the tile).
+ * Returns EPI3_E_INVALID for an unknown variant or tile.
+ * ------------------------------------------------------------------------ */
+int epi3_tile_rule(int32_t variant, int32_t min_snps, int32_t min_samples, int32_t tile);
+void epi3_tile_rules_clear(void);
+/* The tile (or, for AUTO, the variant) a scan of d with `variant` uses. */
+int32_t epi3_tile_for(const epi3_dataset *d, int32_t variant);
+/* Scratch bytes per pass buffer of the matrix-core paths (0: default 1 GiB
+ * for plain scans, 4 GiB for phenotype batches).  Same rules as above. */
+int epi3_set_pass_bytes(int64_t bytes);
 
 /* Library version string. */
 const char *epi3_version(void);

@@ -59,7 +59,7 @@ EncodeLayout encode_layout(void *buf, int32_t M, int32_t n1, int32_t n0, int32_t
     L.W1 = words_of(n1);
     L.Wtot = L.W0 + L.W1;
     L.classes = 2;
-    L.S = 0;
+    L.S = byte_stride(n0 > n1 ? n0 : n1);
   } else {
     L.W0 = L.W1 = words_of(N);
     L.Wtot = L.W0;
@@ -69,8 +69,8 @@ EncodeLayout encode_layout(void *buf, int32_t M, int32_t n1, int32_t n0, int32_t
   Carver c(buf);
   L.status = c.take<int32_t>(64);
   L.planes = c.take<uint32_t>((int64_t)L.Wtot * L.Mp * 2);
-  L.bytes = c.take<uint8_t>((int64_t)L.Mp * 2 * L.S);
-  L.nibbles = c.take<uint8_t>((int64_t)L.Mp * 2 * (L.S / 2));
+  L.bytes = c.take<uint8_t>((int64_t)L.classes * L.Mp * 2 * L.S);
+  L.nibbles = c.take<uint8_t>((int64_t)L.classes * L.Mp * 2 * (L.S / 2));
   L.pairs = c.take<int32_t>((int64_t)L.classes * L.Mp * L.Mp * 4);
   L.lf64 = c.take<double>((int64_t)N + 2);
   L.lf32 = c.take<float>((int64_t)N + 2);
@@ -110,6 +110,9 @@ struct ScanLayout {
   int64_t *cand;
   CandRec *rec;
   epi3_hit *hits;
+  PlainJob *pjob;         // [2]: one per scratch buffer
+  uint8_t *scratch;       // matrix-core variants: two buffers of pass_tiles tiles
+  int64_t pass_tiles;
   int64_t cap;
   int64_t total;
 };
@@ -120,7 +123,59 @@ int64_t default_cap(int64_t T, int32_t k, int64_t cand_cap) {
   return std::max<int64_t>(cap, 1);
 }
 
-ScanLayout scan_layout(void *ws, const epi3_dataset &d, int32_t k, int64_t cand_cap) {
+constexpr int64_t kPlainPassBytes = 1ll << 30;  // per scratch buffer of the plain matrix-core path
+
+// Tile rules registered by epi3_tile_rule (process-wide).
+struct TileRule {
+  int32_t variant, min_snps, min_samples, tile;
+};
+struct Tiles {
+  std::mutex mu;
+  std::vector<TileRule> rules;
+  int64_t pass_bytes = 0;
+};
+Tiles &tiles() {
+  static Tiles t;
+  return t;
+}
+// The applicable rule's tile for (variant, M, N), or `dflt`.
+int rule_tile(int32_t variant, int32_t M, int32_t N, int dflt) {
+  Tiles &t = tiles();
+  std::lock_guard<std::mutex> g(t.mu);
+  const TileRule *best = nullptr;
+  for (const TileRule &r : t.rules) {
+    if (r.variant != variant || r.min_snps > M || r.min_samples > N) continue;
+    if (!best || r.min_snps > best->min_snps ||
+        (r.min_snps == best->min_snps && r.min_samples >= best->min_samples))
+      best = &r;
+  }
+  return best ? best->tile : dflt;
+}
+int64_t pass_bytes(int64_t dflt) {
+  Tiles &t = tiles();
+  std::lock_guard<std::mutex> g(t.mu);
+  return t.pass_bytes > 0 ? t.pass_bytes : dflt;
+}
+
+bool mfma_supported(const epi3_dataset &d) {
+  return d.bytes && d.nibbles && d.n_cases <= 65535 && d.n_controls <= 65535;
+}
+
+// Count-kernel choice for a SPLIT data set (a variant, or a negative status).
+int plain_variant(const epi3_dataset &d, int32_t variant) {
+  if (variant < EPI3_VARIANT_AUTO || variant > EPI3_VARIANT_MFMA_FP4) return EPI3_E_INVALID;
+  if (variant == EPI3_VARIANT_AUTO) {
+    const int v = rule_tile(EPI3_VARIANT_AUTO, d.n_snps, d.n_samples, EPI3_VARIANT_VALU);
+    return v != EPI3_VARIANT_VALU && mfma_supported(d) ? v : EPI3_VARIANT_VALU;
+  }
+  if (variant != EPI3_VARIANT_VALU && !mfma_supported(d)) return EPI3_E_UNSUPPORTED;
+  return variant;
+}
+
+int pick_JB(const epi3_dataset &d, int32_t v) { return rule_tile(v, d.n_snps, d.n_samples, 4); }
+
+ScanLayout scan_layout(void *ws, const epi3_dataset &d, int32_t k, int64_t cand_cap,
+                       int32_t variant) {
   ScanLayout L{};
   const int64_t T = epi3_n_triplets(d.n_snps);
   L.cap = default_cap(T, k, cand_cap);
@@ -135,6 +190,14 @@ ScanLayout scan_layout(void *ws, const epi3_dataset &d, int32_t k, int64_t cand_
   L.cand = c.take<int64_t>(L.cap);
   L.rec = c.take<CandRec>(L.cap);
   L.hits = c.take<epi3_hit>(std::max<int32_t>(k, 1));
+  L.pjob = c.take<PlainJob>(2);
+  const int v = plain_variant(d, variant);
+  if (T > 0 && (v == EPI3_VARIANT_MFMA || v == EPI3_VARIANT_MFMA_FP4)) {
+    const int64_t tiles = host_plain_tiles(d.n_snps, pick_JB(d, v));
+    L.pass_tiles = std::max<int64_t>(
+        1, std::min<int64_t>(tiles, pass_bytes(kPlainPassBytes) / kPlainTileScratch));
+    L.scratch = c.take<uint8_t>(2 * L.pass_tiles * kPlainTileScratch);
+  }
   L.total = c.size();
   return L;
 }
@@ -167,6 +230,7 @@ Job make_job(const epi3_dataset &d, float *score, uint32_t *counts, int64_t *jpr
   J.W1 = d.words[1];
   J.N0 = d.n_controls;
   J.N1 = d.n_cases;
+  J.P = P;
   return J;
 }
 
@@ -201,7 +265,33 @@ SelJob make_seljob(const epi3_dataset &d, const float *score, int64_t T, SelStat
   return S;
 }
 
-int pick_P(const epi3_dataset &d) { return tile_P_default(d.n_snps, d.n_samples); }
+int pick_P(const epi3_dataset &d) {
+  return rule_tile(EPI3_VARIANT_VALU, d.n_snps, d.n_samples, tile_P_default(d.n_snps, d.n_samples));
+}
+
+// Second stream and events for the count / finish overlap (created once).
+struct Aux {
+  std::mutex mu;
+  hipStream_t s2 = nullptr;
+  std::vector<hipEvent_t> ev;
+};
+Aux &aux() {
+  static Aux a;
+  return a;
+}
+int aux_get(hipStream_t *s2, hipEvent_t *ev, int n_ev) {
+  Aux &a = aux();
+  std::lock_guard<std::mutex> g(a.mu);
+  if (!a.s2 && hipStreamCreateWithFlags(&a.s2, hipStreamNonBlocking) != hipSuccess) return EPI3_E_HIP;
+  while ((int)a.ev.size() < n_ev) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return EPI3_E_HIP;
+    a.ev.push_back(e);
+  }
+  *s2 = a.s2;
+  for (int x = 0; x < n_ev; ++x) ev[x] = a.ev[x];
+  return EPI3_OK;
+}
 
 // ---- optional kernel timing: HIP events on the call's stream ----
 struct Timing {
@@ -311,10 +401,12 @@ int epi3_encode(const uint8_t *geno_dev, int64_t ld, const uint8_t *pheno_host, 
   HIP_OK(hipMemcpyAsync(L.lf32, L32.data(), L32.size() * sizeof(float), hipMemcpyHostToDevice, s));
   HIP_OK(launch_encode(geno_dev, ld, L.list, n_snps, L.Mp, layout == EPI3_LAYOUT_SPLIT ? L.W0 : L.Wtot,
                        layout == EPI3_LAYOUT_SPLIT ? L.W1 : 0, L.planes, L.status, s));
-  if (layout == EPI3_LAYOUT_MASKED) {
-    HIP_OK(launch_encode_bytes(geno_dev, ld, n_snps, n_samples, L.Mp, L.S, L.bytes, s));
-    HIP_OK(launch_encode_nibbles(geno_dev, ld, n_snps, n_samples, L.Mp, L.S, L.nibbles, s));
-  }
+  if (layout == EPI3_LAYOUT_MASKED)
+    HIP_OK(launch_encode_values(geno_dev, ld, L.list, 0, n_samples, 0, 0, 1, n_snps, L.Mp, L.S,
+                                L.bytes, L.nibbles, s));
+  else
+    HIP_OK(launch_encode_values(geno_dev, ld, L.list, 0, n0, L.W0 * 32, n1, 2, n_snps, L.Mp, L.S,
+                                L.bytes, L.nibbles, s));
   HIP_OK(launch_pairs(L.planes, L.Mp, n_snps, L.W0, layout == EPI3_LAYOUT_SPLIT ? L.W1 : 0,
                       L.classes, nullptr, L.pairs, s));
   HIP_OK(hipStreamSynchronize(s));  // host vectors above must outlive the copies
@@ -330,8 +422,8 @@ int epi3_encode(const uint8_t *geno_dev, int64_t ld, const uint8_t *pheno_host, 
   out->snp_stride = L.Mp;
   out->byte_stride = L.S;
   out->planes = L.planes;
-  out->bytes = layout == EPI3_LAYOUT_MASKED ? L.bytes : nullptr;
-  out->nibbles = layout == EPI3_LAYOUT_MASKED ? L.nibbles : nullptr;
+  out->bytes = L.bytes;
+  out->nibbles = L.nibbles;
   out->pairs = L.pairs;
   out->lf64 = L.lf64;
   out->lf32 = L.lf32;
@@ -339,21 +431,94 @@ int epi3_encode(const uint8_t *geno_dev, int64_t ld, const uint8_t *pheno_host, 
   return EPI3_OK;
 }
 
-int64_t epi3_workspace_bytes(const epi3_dataset *d, int32_t k, int64_t cand_cap) {
+int64_t epi3_workspace_bytes(const epi3_dataset *d, int32_t k, int32_t variant, int64_t cand_cap) {
   if (!valid_dataset(d) || k <= 0) return EPI3_E_INVALID;
-  return scan_layout(nullptr, *d, k, cand_cap).total;
+  const int v = plain_variant(*d, variant);
+  if (v < 0) return v;
+  return scan_layout(nullptr, *d, k, cand_cap, variant).total;
+}
+
+static int enqueue_count_mfma(const epi3_dataset &d, bool fp4, float *score, uint32_t *counts,
+                              const ScanLayout &W, hipStream_t s) {
+  const int JB = pick_JB(d, fp4 ? EPI3_VARIANT_MFMA_FP4 : EPI3_VARIANT_MFMA);
+  const int64_t tiles = host_plain_tiles(d.n_snps, JB);
+  const int32_t unit = fp4 ? 128 : 64;  // samples per 64-byte staged chunk
+  PlainJob pj{};
+  pj.vals = static_cast<const uint8_t *>(fp4 ? d.nibbles : d.bytes);
+  pj.pairs = d.pairs;
+  pj.score = score;
+  pj.counts = counts;
+  pj.keyrange = &W.st->kmin;
+  pj.jprefix = W.jprefix;
+  pj.corners = reinterpret_cast<uint4 *>(W.scratch);
+  pj.n_tiles = tiles;
+  pj.T = epi3_n_triplets(d.n_snps);
+  pj.M = d.n_snps;
+  pj.Mp = d.snp_stride;
+  pj.Sb = fp4 ? d.byte_stride / 2 : d.byte_stride;
+  pj.Sb0 = (d.n_controls + unit - 1) / unit * 64;
+  pj.Sb1 = (d.n_cases + unit - 1) / unit * 64;
+  pj.N0 = d.n_controls;
+  pj.N1 = d.n_cases;
+  pj.JB = JB;
+  if (pj.Sb0 > pj.Sb || pj.Sb1 > pj.Sb) return EPI3_E_INVALID;
+  PlainJob pjb[2] = {pj, pj};
+  pjb[1].corners = reinterpret_cast<uint4 *>(W.scratch + W.pass_tiles * kPlainTileScratch);
+  HIP_OK(launch_write_plainjob(pjb[0], W.pjob + 0, s));
+  HIP_OK(launch_write_plainjob(pjb[1], W.pjob + 1, s));
+  HIP_OK(launch_plain_prefix(W.pjob, s));
+  // Pass p counts into scratch buffer p % 2 on `s`; its finish kernel runs on
+  // the second stream while `s` counts pass p + 1.  Count p + 2 waits for
+  // finish p (same buffer).
+  hipStream_t s2 = nullptr;
+  hipEvent_t ev[5];
+  int rc = aux_get(&s2, ev, 5);
+  if (rc != EPI3_OK) return rc;
+  hipEvent_t ev_start = ev[0], ev_cnt[2] = {ev[1], ev[2]}, ev_fin[2] = {ev[3], ev[4]};
+  HIP_OK(hipEventRecord(ev_start, s));
+  HIP_OK(hipStreamWaitEvent(s2, ev_start, 0));
+  int p = 0;
+  for (int64_t t0 = 0; t0 < tiles; t0 += W.pass_tiles, ++p) {
+    const int64_t t1 = std::min(tiles, t0 + W.pass_tiles);
+    const int b = p & 1;
+    if (p >= 2) HIP_OK(hipStreamWaitEvent(s, ev_fin[b], 0));
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
+    rc = timed(0, s, [&]() {
+      return launch_count_mfma_plain(W.pjob + b, JB, fp4, t0, t1, W.queue, s) == hipSuccess
+                 ? EPI3_OK
+                 : EPI3_E_HIP;
+    });
+    if (rc != EPI3_OK) return rc;
+    HIP_OK(hipEventRecord(ev_cnt[b], s));
+    HIP_OK(hipStreamWaitEvent(s2, ev_cnt[b], 0));
+    rc = timed(3, s2, [&]() {
+      return launch_finish_plain(W.pjob + b, JB, t0, t1, d.lf32, d.n_samples + 2, s2) == hipSuccess
+                 ? EPI3_OK
+                 : EPI3_E_HIP;
+    });
+    if (rc != EPI3_OK) return rc;
+    HIP_OK(hipEventRecord(ev_fin[b], s2));
+  }
+  HIP_OK(hipEventRecord(ev_fin[0], s2));
+  HIP_OK(hipStreamWaitEvent(s, ev_fin[0], 0));
+  return EPI3_OK;
 }
 
 static int enqueue_count(const epi3_dataset &d, int32_t variant, float *score, uint32_t *counts,
                          const ScanLayout &W, hipStream_t s) {
-  if (variant == EPI3_VARIANT_MFMA) return EPI3_E_UNSUPPORTED;
+  const int v = plain_variant(d, variant);
+  if (v < 0) return v;
+  if (v == EPI3_VARIANT_MFMA || v == EPI3_VARIANT_MFMA_FP4) {
+    if (!W.scratch) return EPI3_E_WORKSPACE;
+    return enqueue_count_mfma(d, v == EPI3_VARIANT_MFMA_FP4, score, counts, W, s);
+  }
   const int P = pick_P(d);
   Job J = make_job(d, score, counts, W.jprefix, &W.st->kmin, P);
   HIP_OK(launch_write_jobs(&J, 1, W.job, s));
-  HIP_OK(launch_tile_prefix(W.job, 1, P, s));
+  HIP_OK(launch_tile_prefix(W.job, 1, s));
   HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
   return timed(0, s, [&]() {
-    return launch_count_valu(W.job, 1, J.n_tiles, W.queue, d.lf32, d.n_samples + 2, P,
+    return launch_count_valu(W.job, 1, J.n_tiles, W.queue, d.lf32, d.n_samples + 2, P, P,
                              counts != nullptr, s) == hipSuccess
                ? EPI3_OK
                : EPI3_E_HIP;
@@ -365,7 +530,9 @@ int epi3_scan(const epi3_dataset *d, int32_t k, int32_t variant, int64_t cand_ca
   if (!valid_dataset(d) || k <= 0 || !ws_dev) return EPI3_E_INVALID;
   if (d->layout != EPI3_LAYOUT_SPLIT) return EPI3_E_INVALID;
   if (reinterpret_cast<uintptr_t>(ws_dev) % kAlign) return EPI3_E_INVALID;
-  ScanLayout W = scan_layout(ws_dev, *d, k, cand_cap);
+  const int v = plain_variant(*d, variant);
+  if (v < 0) return v;
+  ScanLayout W = scan_layout(ws_dev, *d, k, cand_cap, variant);
   if (ws_bytes < W.total) return EPI3_E_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t T = epi3_n_triplets(d->n_snps);
@@ -384,7 +551,7 @@ int epi3_scan(const epi3_dataset *d, int32_t k, int32_t variant, int64_t cand_ca
 int epi3_topk(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev, epi3_hit *hits_host,
               int32_t *n_out, void *stream) {
   if (!valid_dataset(d) || k <= 0 || !ws_dev || !hits_host || !n_out) return EPI3_E_INVALID;
-  ScanLayout W = scan_layout(ws_dev, *d, k, cand_cap);
+  ScanLayout W = scan_layout(ws_dev, *d, k, cand_cap, EPI3_VARIANT_VALU);
   hipStream_t s = static_cast<hipStream_t>(stream);
   SelState st;
   int32_t status = 0;
@@ -409,7 +576,7 @@ int epi3_topk(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev, 
 int epi3_score_plane(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
                      float **plane_dev) {
   if (!valid_dataset(d) || k <= 0 || !ws_dev || !plane_dev) return EPI3_E_INVALID;
-  *plane_dev = scan_layout(ws_dev, *d, k, cand_cap).score;
+  *plane_dev = scan_layout(ws_dev, *d, k, cand_cap, EPI3_VARIANT_VALU).score;
   return EPI3_OK;
 }
 
@@ -417,17 +584,16 @@ int epi3_scan_tables(const epi3_dataset *d, int32_t variant, uint32_t *counts_de
                      void *ws_dev, int64_t ws_bytes, void *stream) {
   if (!valid_dataset(d) || !k2_dev || !ws_dev) return EPI3_E_INVALID;
   if (d->layout != EPI3_LAYOUT_SPLIT) return EPI3_E_INVALID;
-  ScanLayout W = scan_layout(ws_dev, *d, 1, 0);
+  const int v = plain_variant(*d, variant);
+  if (v < 0) return v;
+  ScanLayout W = scan_layout(ws_dev, *d, 1, 0, variant);
   if (ws_bytes < W.total) return EPI3_E_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t T = epi3_n_triplets(d->n_snps);
   if (T == 0) return EPI3_OK;
   HIP_OK(launch_fill_u32(&W.st->kmin, 0xffffffffu, 1, s));
   HIP_OK(launch_fill_u32(&W.st->kmax, 0u, 1, s));
-  // counts requested: the kernel variant that writes tables
-  return enqueue_count(*d, variant, k2_dev, counts_dev ? counts_dev : nullptr, W, s) == EPI3_OK
-             ? EPI3_OK
-             : EPI3_E_UNSUPPORTED;
+  return enqueue_count(*d, variant, k2_dev, counts_dev ? counts_dev : nullptr, W, s);
 }
 
 int epi3_score_triplets(const epi3_dataset *d, const uint32_t *ijk_dev, int64_t n,
@@ -520,7 +686,8 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
     L.perm_prefix = c.take<int64_t>((int64_t)d.n_snps + 1);
     // counts of up to kPermPassBytes worth of tiles per pass
     const int64_t tiles = host_perm_tiles(d.n_snps);
-    L.pass_tiles = std::max<int64_t>(1, std::min<int64_t>(tiles, kPermPassBytes / kPermTileScratch));
+    L.pass_tiles = std::max<int64_t>(
+        1, std::min<int64_t>(tiles, pass_bytes(kPermPassBytes) / kPermTileScratch));
     // two buffers: the count kernel of pass p + 1 runs while pass p is scored
     L.perm_scratch = c.take<uint8_t>(2 * L.pass_tiles * kPermTileScratch);
   }
@@ -550,30 +717,6 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
   }
   L.total = c.size();
   return L;
-}
-
-// Second stream and events for the count / finish overlap (created once).
-struct Aux {
-  std::mutex mu;
-  hipStream_t s2 = nullptr;
-  std::vector<hipEvent_t> ev;
-};
-Aux &aux() {
-  static Aux a;
-  return a;
-}
-int aux_get(hipStream_t *s2, hipEvent_t *ev, int n_ev) {
-  Aux &a = aux();
-  std::lock_guard<std::mutex> g(a.mu);
-  if (!a.s2 && hipStreamCreateWithFlags(&a.s2, hipStreamNonBlocking) != hipSuccess) return EPI3_E_HIP;
-  while ((int)a.ev.size() < n_ev) {
-    hipEvent_t e = nullptr;
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return EPI3_E_HIP;
-    a.ev.push_back(e);
-  }
-  *s2 = a.s2;
-  for (int x = 0; x < n_ev; ++x) ev[x] = a.ev[x];
-  return EPI3_OK;
 }
 
 // Enqueues the whole batched scan (no host synchronisation inside).
@@ -615,11 +758,12 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
       const epi3_dataset &da = *jobs[a].d, &db = *jobs[b].d;
       return da.words[0] + da.words[1] > db.words[0] + db.words[1];
     });
-    int P = 8;
+    int P_lo = 8, P_hi = 4;
     int32_t lf_len = 2;
     const float *lf32 = nullptr;
     for (int x = 0; x < n; ++x) {
-      P = std::min(P, pick_P(*jobs[x].d));
+      P_lo = std::min(P_lo, pick_P(*jobs[x].d));
+      P_hi = std::max(P_hi, pick_P(*jobs[x].d));
       if (jobs[x].d->n_samples + 2 > lf_len) {
         lf_len = jobs[x].d->n_samples + 2;
         lf32 = jobs[x].d->lf32;
@@ -629,16 +773,18 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
     int64_t begin = 0;
     for (int y = 0; y < n; ++y) {
       const int x = order[y];
-      J[y] = make_job(*jobs[x].d, W.score[x], nullptr, W.jprefix[x], &W.st[x].kmin, P);
+      J[y] = make_job(*jobs[x].d, W.score[x], nullptr, W.jprefix[x], &W.st[x].kmin,
+                      pick_P(*jobs[x].d));
       J[y].tile_begin = begin;
       begin += J[y].n_tiles;
     }
     HIP_OK(launch_write_jobs(J.data(), n, W.jobs, s));
-    HIP_OK(launch_tile_prefix(W.jobs, n, P, s));
+    HIP_OK(launch_tile_prefix(W.jobs, n, s));
     HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
     if (begin > 0) {
       const int rc = timed(0, s, [&]() {
-        return launch_count_valu(W.jobs, n, begin, W.queue, lf32, lf_len, P, false, s) == hipSuccess
+        return launch_count_valu(W.jobs, n, begin, W.queue, lf32, lf_len, P_lo, P_hi, false, s) ==
+                       hipSuccess
                    ? EPI3_OK
                    : EPI3_E_HIP;
       });
@@ -857,6 +1003,60 @@ void epi3_release(void) {
     (void)hipStreamDestroy(G.capture);
     G.capture = nullptr;
   }
+}
+
+int epi3_perm_pvalue(double observed_k2, const double *perm_min_k2, int32_t n_perm, double *p_out) {
+  if (!perm_min_k2 || !p_out || n_perm < 1 || observed_k2 != observed_k2) return EPI3_E_INVALID;
+  int64_t hits = 0;
+  for (int32_t q = 0; q < n_perm; ++q) {
+    if (perm_min_k2[q] != perm_min_k2[q]) return EPI3_E_INVALID;
+    hits += perm_min_k2[q] <= observed_k2;
+  }
+  *p_out = (double)(1 + hits) / (double)(n_perm + 1);
+  return EPI3_OK;
+}
+
+int epi3_tile_rule(int32_t variant, int32_t min_snps, int32_t min_samples, int32_t tile) {
+  if (min_snps < 0 || min_samples < 0) return EPI3_E_INVALID;
+  bool ok = false;
+  if (variant == EPI3_VARIANT_VALU) ok = tile == 4 || tile == 8;
+  if (variant == EPI3_VARIANT_MFMA || variant == EPI3_VARIANT_MFMA_FP4)
+    ok = tile == 2 || tile == 4 || tile == 8;
+  if (variant == EPI3_VARIANT_AUTO)
+    ok = tile == EPI3_VARIANT_VALU || tile == EPI3_VARIANT_MFMA || tile == EPI3_VARIANT_MFMA_FP4;
+  if (!ok) return EPI3_E_INVALID;
+  Tiles &t = tiles();
+  std::lock_guard<std::mutex> g(t.mu);
+  for (TileRule &r : t.rules) {
+    if (r.variant == variant && r.min_snps == min_snps && r.min_samples == min_samples) {
+      r.tile = tile;
+      return EPI3_OK;
+    }
+  }
+  t.rules.push_back({variant, min_snps, min_samples, tile});
+  return EPI3_OK;
+}
+
+void epi3_tile_rules_clear(void) {
+  Tiles &t = tiles();
+  std::lock_guard<std::mutex> g(t.mu);
+  t.rules.clear();
+}
+
+int32_t epi3_tile_for(const epi3_dataset *d, int32_t variant) {
+  if (!valid_dataset(d)) return EPI3_E_INVALID;
+  if (variant == EPI3_VARIANT_AUTO) return plain_variant(*d, variant);
+  if (variant == EPI3_VARIANT_VALU) return pick_P(*d);
+  if (variant == EPI3_VARIANT_MFMA || variant == EPI3_VARIANT_MFMA_FP4) return pick_JB(*d, variant);
+  return EPI3_E_INVALID;
+}
+
+int epi3_set_pass_bytes(int64_t bytes) {
+  if (bytes < 0) return EPI3_E_INVALID;
+  Tiles &t = tiles();
+  std::lock_guard<std::mutex> g(t.mu);
+  t.pass_bytes = bytes;
+  return EPI3_OK;
 }
 
 void epi3_timing_enable(int enable) {

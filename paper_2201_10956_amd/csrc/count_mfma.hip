@@ -345,14 +345,19 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
 // Completes the tables of one pass of tiles and scores them.  Workgroup per
 // tile (persistent, round robin); wave w = pivot i = 4 ib + w; lane = (16 k x
 // 4 phenotypes), looping over 16 groups of 4 phenotypes.
+template <bool LDS>
 __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restrict__ pjp,
                                                           int64_t tile_begin, int64_t tile_end,
                                                           SelState *__restrict__ st,
                                                           const float *__restrict__ lf32,
                                                           int lf_len) {
-  extern __shared__ float sL[];
+  extern __shared__ float sLds[];
   __shared__ uint32_t sRange[64][2];
-  for (int x = threadIdx.x; x < lf_len; x += blockDim.x) sL[x] = lf32[x];
+  const float *sL = lf32;
+  if (LDS) {
+    for (int x = threadIdx.x; x < lf_len; x += blockDim.x) sLds[x] = lf32[x];
+    sL = sLds;
+  }
   if (threadIdx.x < 64) {
     sRange[threadIdx.x][0] = 0xffffffffu;
     sRange[threadIdx.x][1] = 0u;
@@ -515,8 +520,10 @@ hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t tile_begin, int
              : launch_count_t<false>(pj_dev, tile_begin, tile_end, queue, s);
 }
 
-hipError_t launch_finish_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,
-                              SelState *st, const float *lf32, int32_t lf_len, hipStream_t s) {
+template <bool LDS>
+static hipError_t launch_finish_perm_l(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,
+                                       SelState *st, const float *lf32, int32_t lf_len,
+                                       hipStream_t s) {
   const int64_t n = tile_end - tile_begin;
   if (n <= 0) return hipSuccess;
   int dev = 0, n_cu = 0;
@@ -524,19 +531,26 @@ hipError_t launch_finish_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  const size_t lds = (size_t)lf_len * sizeof(float);
-  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&finish_perm_kernel),
+  const size_t lds = LDS ? (size_t)lf_len * sizeof(float) : 0;
+  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&finish_perm_kernel<LDS>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, finish_perm_kernel, 256, lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, finish_perm_kernel<LDS>, 256, lds);
   if (e != hipSuccess) return e;
   if (per_cu <= 0) per_cu = 1;
   int64_t blocks = (int64_t)n_cu * per_cu;
   if (blocks > n) blocks = n;
-  hipLaunchKernelGGL(finish_perm_kernel, dim3((unsigned)blocks), dim3(256), lds, s, pj_dev,
+  hipLaunchKernelGGL(finish_perm_kernel<LDS>, dim3((unsigned)blocks), dim3(256), lds, s, pj_dev,
                      tile_begin, tile_end, st, lf32, lf_len);
   return hipGetLastError();
+}
+
+hipError_t launch_finish_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,
+                              SelState *st, const float *lf32, int32_t lf_len, hipStream_t s) {
+  return lf_in_lds(lf_len)
+             ? launch_finish_perm_l<true>(pj_dev, tile_begin, tile_end, st, lf32, lf_len, s)
+             : launch_finish_perm_l<false>(pj_dev, tile_begin, tile_end, st, lf32, lf_len, s);
 }
 
 }  // namespace epi3

@@ -1,0 +1,464 @@
+// Count stage of the plain (two-class) scan on the matrix cores.
+//
+// For one class c, the corner cells of every triplet (i, j, k) are entries
+// of matrix products over that class's samples:
+//     C[(i, j, a, b), (k, g)] = sum_s (X_i[a][s] X_j[b][s]) X_k[g][s],
+// rows (i, j, a, b), columns (k, g), K = the class's samples, 0/1 values
+// (int8 bytes or FP4 nibbles) and exact accumulation.  This is the same
+// integer table the paper fills with AND + POPCNT (Alg. 2); the other 19
+// cells of each class follow from the pairwise tables as in the vector-ALU
+// kernel.  Counting writes the 8 corner cells of both classes of every
+// triplet of a pass of tiles to a scratch buffer; a second kernel completes
+// the tables and scores them (Eq. 1, FP32).
+//
+// Workgroup tile: 16 consecutive i, JB consecutive j, 256 / JB consecutive
+// k (4096 triplets), so one staged sample chunk serves 16 + JB + 256 / JB
+// SNPs instead of the 161 of a (32 i, one j, 128 k) slab.  Each of the 4
+// waves owns 2 i-blocks of 8 x 2 j (four 32-row A tiles: 8 i x (a, b), the
+// rows X_i[a] & X_j[b] formed in registers) and two 32-column B tiles
+// (16 k x g).  Operand rows are staged per 64-byte chunk in double-buffered
+// LDS.
+#include "epi3_internal.h"
+
+namespace epi3 {
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T *;
+
+constexpr int kPI = kPlainI;   // i per workgroup tile
+constexpr int kPKC = 64;       // bytes per staged chunk of a row
+constexpr int kPRow = kPKC + 16;
+
+__host__ __device__ __forceinline__ int plain_kt(int JB) { return 256 / JB; }
+
+// Tiles of j-block J (j in [JB J, JB J + JB)): i-blocks of 16 below the
+// block's last pivot, k-blocks of 256 / JB from JB J + 1 up to M - 1.
+__host__ __device__ __forceinline__ int64_t plain_tiles_of_jb(int64_t M, int64_t J, int JB) {
+  const int64_t j0 = J * JB;
+  int64_t jmax = j0 + JB - 1;
+  if (jmax > M - 2) jmax = M - 2;
+  if (jmax < 1 || j0 > M - 2) return 0;
+  const int KT = plain_kt(JB);
+  return ((jmax + kPI - 1) / kPI) * ((M - 1 - j0 + KT - 1) / KT);
+}
+
+__host__ __device__ __forceinline__ int64_t plain_jblocks(int64_t M, int JB) {
+  return M < 3 ? 0 : (M - 1 + JB - 1) / JB;
+}
+
+__device__ __forceinline__ int64_t rfl64q(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// jprefix[J] = tiles before j-block J; jprefix[nJ] = total.
+__global__ void __launch_bounds__(1024) plain_prefix_kernel(PlainJob *pj) {
+  const int64_t M = pj->M;
+  const int JB = pj->JB;
+  const int64_t nJ = plain_jblocks(M, JB);
+  int64_t *pre = const_cast<int64_t *>(pj->jprefix);
+  __shared__ int64_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t chunk = (nJ + 1023) / 1024;
+  const int64_t a = t * chunk, b = (a + chunk < nJ) ? a + chunk : nJ;
+  int64_t sum = 0;
+  for (int64_t J = a; J < b; ++J) sum += plain_tiles_of_jb(M, J, JB);
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int64_t v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int64_t run = part[t] - sum;
+  for (int64_t J = a; J < b; ++J) {
+    pre[J] = run;
+    run += plain_tiles_of_jb(M, J, JB);
+  }
+  if (t == 1023) pre[nJ] = part[1023];
+}
+
+template <bool FP4>
+struct PlainAcc {
+  typedef v16i type;
+  static __device__ __forceinline__ type mma(v4i a, v4i b, type c) {
+    return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ uint32_t get(const type &c, int v) { return (uint32_t)c[v]; }
+};
+template <>
+struct PlainAcc<true> {
+  typedef v16f type;
+  static __device__ __forceinline__ type mma(v4i a, v4i b, type c) {
+    const v8i a8 = {a.x, a.y, a.z, a.w, 0, 0, 0, 0};
+    const v8i b8 = {b.x, b.y, b.z, b.w, 0, 0, 0, 0};
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, c, 4, 4, 0, 127, 0, 127);
+  }
+  static __device__ __forceinline__ uint32_t get(const type &c, int v) { return (uint32_t)c[v]; }
+};
+
+// Decodes a tile index into its j-block through the prefix table.
+struct TileDecoder {
+  int J = -1;
+  int64_t jlo = 0, jhi = 0;
+  __device__ __forceinline__ void find(cptr<int64_t> pre, int nJ, int64_t t) {
+    if (J < 0 || t < jlo || t >= jhi) {
+      int lo = 0, hi = nJ - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= t) lo = mid; else hi = mid - 1;
+      }
+      J = lo;
+      jlo = pre[J];
+      jhi = pre[J + 1];
+    }
+  }
+};
+
+// (i0, j0, k0) of tile t of j-block J.
+__device__ __forceinline__ void plain_tile_origin(const TileDecoder &dec, int64_t t, int M, int JB,
+                                                  int &i0, int &j0, int &k0) {
+  const int KT = 256 / JB;
+  j0 = dec.J * JB;
+  const int nkb = (M - 1 - j0 + KT - 1) / KT;
+  const int rr = (int)(t - dec.jlo);
+  const int ib = rr / nkb, kb = rr - ib * nkb;
+  i0 = ib * kPI;
+  k0 = j0 + 1 + kb * KT;
+}
+
+template <bool FP4, int JB>
+__global__ void __launch_bounds__(256, 2) count_mfma_plain_kernel(
+    const PlainJob *__restrict__ pjp, int64_t tile_begin, int64_t tile_end,
+    unsigned long long *__restrict__ queue) {
+  typedef PlainAcc<FP4> Acc;
+  constexpr int KT = 256 / JB;
+  constexpr int kRowsI = 2 * kPI, kRowsJ = 2 * JB, kRowsK = 2 * KT;
+  constexpr int kRows = kRowsI + kRowsJ + kRowsK;
+  constexpr int kBuf = kRows * kPRow;
+  constexpr int kChunks = kRows * (kPKC / 16);
+  constexpr int kPer = (kChunks + 255) / 256;
+  constexpr int NBP = KT / 32;  // pairs of B tiles; the 4 waves are (JB / 2) x NBP
+  static_assert((JB / 2) * NBP == 4, "four waves per tile");
+  __shared__ __attribute__((aligned(16))) unsigned char stage[2 * kBuf];
+  __shared__ int64_t sTile[2];
+
+  const PlainJob pj = *pjp;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wj = wave / NBP, wb = wave - wj * NBP;
+  const int r = lane & 31, g = lane >> 5;
+  const int M = pj.M, Mp = pj.Mp, Sb = pj.Sb;
+  const int nJ = (int)plain_jblocks(M, JB);
+  gptr<uint8_t> gv = (gptr<uint8_t>)pj.vals;
+  cptr<int64_t> pre = as_const(pj.jprefix);
+  TileDecoder dec;
+  // lane roles: A row r = 4 i8 + 2 a + b; B column r = 2 k16 + g_k
+  const int ri8 = r >> 2, ra = (r >> 1) & 1, rb = r & 1;
+  const int ck16 = r >> 1, cpl = r & 1;
+
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) sTile[0] = tile_begin + (int64_t)atomicAdd(queue, 1ull);
+    __syncthreads();
+    const int64_t t = rfl64q(sTile[0]);
+    if (t >= tile_end) break;
+    const int64_t slot = t - tile_begin;
+    dec.find(pre, nJ, t);
+    int i0, j0, k0;
+    plain_tile_origin(dec, t, M, JB, i0, j0, k0);
+
+    for (int cls = 0; cls < 2; ++cls) {
+      const int nch = (cls ? pj.Sb1 : pj.Sb0) / kPKC;
+      const int64_t cbase = (int64_t)cls * pj.Mp * 2;  // first row of this class
+      // staging plan: rows [0, 32) X_i (i0 + x / 2, plane x % 2), then 2 JB
+      // rows X_j, then 2 KT rows X_k (k0 + x / 2, plane x % 2)
+      v4i pf[kPer];
+      auto fetch = [&](int ch) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+          const int c16 = tid + 256 * u;
+          if (c16 < kChunks) {
+            const int row = c16 >> 2, col = (c16 & 3) * 16;
+            int snp, pl;
+            if (row < kRowsI) { snp = i0 + (row >> 1); pl = row & 1; }
+            else if (row < kRowsI + kRowsJ) { const int x = row - kRowsI; snp = j0 + (x >> 1); pl = x & 1; }
+            else { const int x = row - kRowsI - kRowsJ; snp = k0 + (x >> 1); pl = x & 1; }
+            snp = snp < Mp ? snp : Mp - 1;  // rows past M read a zero row
+            pf[u] = *reinterpret_cast<gptr<v4i>>(gv + (cbase + (int64_t)snp * 2 + pl) * Sb +
+                                                 (int64_t)ch * kPKC + col);
+          }
+        }
+      };
+      auto store = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+          const int c16 = tid + 256 * u;
+          if (c16 < kChunks)
+            *reinterpret_cast<v4i *>(stage + buf * kBuf + (c16 >> 2) * kPRow + (c16 & 3) * 16) = pf[u];
+        }
+      };
+      typename Acc::type acc[2][2][2];  // [i-block][j of the pair][B tile]
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int z = 0; z < 2; ++z)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[x][y][z][v] = 0;
+      if (nch > 0) {
+        fetch(0);
+        store(0);
+      }
+      __syncthreads();
+      for (int ch = 0; ch < nch; ++ch) {
+        if (ch + 1 < nch) fetch(ch + 1);
+        const uint8_t *buf = stage + (ch & 1) * kBuf;
+#pragma unroll 1
+        for (int stp = 0; stp < kPKC / 32; ++stp) {
+          const int off = stp * 32 + 16 * g;
+          v4i xi[2], xj[2], b[2];
+#pragma unroll
+          for (int x = 0; x < 2; ++x) {
+            xi[x] = *reinterpret_cast<const v4i *>(buf + (2 * (8 * x + ri8) + ra) * kPRow + off);
+            xj[x] = *reinterpret_cast<const v4i *>(buf + (kRowsI + 2 * (2 * wj + x) + rb) * kPRow + off);
+            b[x] = *reinterpret_cast<const v4i *>(
+                buf + (kRowsI + kRowsJ + 2 * (16 * (2 * wb + x) + ck16) + cpl) * kPRow + off);
+          }
+#pragma unroll
+          for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+              const v4i a = xi[x] & xj[y];
+#pragma unroll
+              for (int z = 0; z < 2; ++z) acc[x][y][z] = Acc::mma(a, b[z], acc[x][y][z]);
+            }
+        }
+        if (ch + 1 < nch) store((ch + 1) & 1);
+        __syncthreads();
+      }
+      // corners out: lane (column, g) holds rows 8 u + 4 g + w, i.e. pivot
+      // i8 = 2 u + g with cells (a, b) = w, for its column (k16, plane).
+      // Record (i, j, k) of class cls is 16 bytes: plane-0 cells then plane-1
+      // cells, each 4 x uint16 in (a, b) order.
+      uint2 *cor = reinterpret_cast<uint2 *>(pj.corners) + ((slot * 2 + cls) * (int64_t)kPI * 256) * 2;
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int z = 0; z < 2; ++z)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int il = 8 * x + 2 * u + g, jl = 2 * wj + y, kl = 16 * (2 * wb + z) + ck16;
+              const uint32_t c0 = Acc::get(acc[x][y][z], 4 * u + 0), c1 = Acc::get(acc[x][y][z], 4 * u + 1);
+              const uint32_t c2 = Acc::get(acc[x][y][z], 4 * u + 2), c3 = Acc::get(acc[x][y][z], 4 * u + 3);
+              cor[(((int64_t)il * JB + jl) * KT + kl) * 2 + cpl] =
+                  make_uint2(c0 | (c1 << 16), c2 | (c3 << 16));
+            }
+    }
+  }
+}
+
+// Completes both tables of every triplet of a pass and scores it; workgroup
+// per tile (persistent, round robin), thread per triplet of the tile.
+template <int JB, bool LDS>
+__global__ void __launch_bounds__(256) finish_plain_kernel(const PlainJob *__restrict__ pjp,
+                                                           int64_t tile_begin, int64_t tile_end,
+                                                           const float *__restrict__ lf32,
+                                                           int lf_len) {
+  constexpr int KT = 256 / JB;
+  constexpr int kTile = kPI * JB * KT;  // 4096 triplets
+  extern __shared__ float sLds[];
+  __shared__ uint32_t sRange[2];
+  const float *sL = lf32;
+  if (LDS) {
+    for (int x = threadIdx.x; x < lf_len; x += blockDim.x) sLds[x] = lf32[x];
+    sL = sLds;
+  }
+  if (threadIdx.x == 0) {
+    sRange[0] = 0xffffffffu;
+    sRange[1] = 0u;
+  }
+  __syncthreads();
+  const PlainJob pj = *pjp;
+  const int M = pj.M, Mp = pj.Mp;
+  const int nJ = (int)plain_jblocks(M, JB);
+  cptr<int64_t> pre = as_const(pj.jprefix);
+  const int4 *pr = reinterpret_cast<const int4 *>(pj.pairs);
+  const int64_t MpMp = (int64_t)Mp * Mp;
+  uint32_t kmin = 0xffffffffu, kmax = 0u;
+  TileDecoder dec;
+  for (int64_t t = tile_begin + blockIdx.x; t < tile_end; t += gridDim.x) {
+    dec.find(pre, nJ, t);
+    int i0, j0, k0;
+    plain_tile_origin(dec, t, M, JB, i0, j0, k0);
+    const int64_t slot = t - tile_begin;
+    const uint4 *cor = pj.corners + slot * 2 * (int64_t)kTile;
+    for (int x = threadIdx.x; x < kTile; x += blockDim.x) {
+      const int il = x / (JB * KT), jl = (x / KT) % JB, kl = x % KT;
+      const int i = i0 + il, j = j0 + jl, k = k0 + kl;
+      if (i >= j || j >= k || k >= M) continue;
+      int tab[2][27];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const uint4 q = cor[(int64_t)c * kTile + x];
+        // record order: [plane of k][a][b] -> corner index 4 a + 2 b + plane
+        const uint32_t n[8] = {q.x & 0xffffu, q.z & 0xffffu, q.x >> 16, q.z >> 16,
+                               q.y & 0xffffu, q.w & 0xffffu, q.y >> 16, q.w >> 16};
+        const int4 a4 = pr[c * MpMp + (int64_t)i * Mp + j], b4 = pr[c * MpMp + (int64_t)i * Mp + k];
+        const int4 c4 = pr[c * MpMp + (int64_t)j * Mp + k];
+        const int4 ii = pr[c * MpMp + (int64_t)i * Mp + i], jj = pr[c * MpMp + (int64_t)j * Mp + j];
+        const int4 kk = pr[c * MpMp + (int64_t)k * Mp + k];
+        const int pij[4] = {a4.x, a4.y, a4.z, a4.w}, pik[4] = {b4.x, b4.y, b4.z, b4.w};
+        const int pjk[4] = {c4.x, c4.y, c4.z, c4.w};
+        const int mi[2] = {ii.x, ii.w}, mj[2] = {jj.x, jj.w}, mk[2] = {kk.x, kk.w};
+        complete_table(n, pij, pik, pjk, mi, mj, mk, c ? pj.N1 : pj.N0, tab[c]);
+      }
+      float k2 = 0.f;  // rows in order, each L[r + 1] - (L[r_0] + L[r_1])
+#pragma unroll
+      for (int x2 = 0; x2 < 27; ++x2) {
+        const int r0 = tab[0][x2], r1 = tab[1][x2];
+        k2 += sL[r0 + r1 + 1] - (sL[r0] + sL[r1]);
+      }
+      const int64_t rank = lex_base(M, i, j) + k;
+      pj.score[rank] = k2;
+      if (pj.counts) {
+        uint32_t *o = pj.counts + rank * 54;
+        for (int x2 = 0; x2 < 27; ++x2) {
+          o[x2] = (uint32_t)tab[0][x2];
+          o[27 + x2] = (uint32_t)tab[1][x2];
+        }
+      }
+      const uint32_t key = f2key(k2);
+      kmin = key < kmin ? key : kmin;
+      kmax = key > kmax ? key : kmax;
+    }
+  }
+  if (kmax != 0u) {
+    atomicMin(&sRange[0], kmin);
+    atomicMax(&sRange[1], kmax);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && sRange[1] != 0u) {
+    atomicMin(pj.keyrange, sRange[0]);
+    atomicMax(pj.keyrange + 1, sRange[1]);
+  }
+}
+
+__global__ void write_plainjob_kernel(PlainJob h, PlainJob *dst) { if (threadIdx.x == 0) *dst = h; }
+
+}  // namespace
+
+int64_t host_plain_tiles(int64_t M, int JB) {
+  int64_t n = 0;
+  const int64_t nJ = plain_jblocks(M, JB);
+  for (int64_t J = 0; J < nJ; ++J) n += plain_tiles_of_jb(M, J, JB);
+  return n;
+}
+
+hipError_t launch_write_plainjob(const PlainJob &h, PlainJob *dst_dev, hipStream_t s) {
+  hipLaunchKernelGGL(write_plainjob_kernel, dim3(1), dim3(64), 0, s, h, dst_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_plain_prefix(PlainJob *pj_dev, hipStream_t s) {
+  hipLaunchKernelGGL(plain_prefix_kernel, dim3(1), dim3(1024), 0, s, pj_dev);
+  return hipGetLastError();
+}
+
+static hipError_t cu_count(int *n_cu) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  return hipDeviceGetAttribute(n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+}
+
+template <bool FP4, int JB>
+static hipError_t launch_plain_count_t(const PlainJob *pj_dev, int64_t tile_begin,
+                                       int64_t tile_end, unsigned long long *queue, hipStream_t s) {
+  const int64_t n = tile_end - tile_begin;
+  if (n <= 0) return hipSuccess;
+  int n_cu = 0;
+  hipError_t e = cu_count(&n_cu);
+  if (e != hipSuccess) return e;
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, count_mfma_plain_kernel<FP4, JB>, 256, 0);
+  if (e != hipSuccess) return e;
+  if (per_cu <= 0) per_cu = 1;
+  int64_t blocks = (int64_t)n_cu * per_cu;
+  if (blocks > n) blocks = n;
+  hipLaunchKernelGGL((count_mfma_plain_kernel<FP4, JB>), dim3((unsigned)blocks), dim3(256), 0, s,
+                     pj_dev, tile_begin, tile_end, queue);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_mfma_plain(const PlainJob *pj_dev, int JB, bool fp4, int64_t tile_begin,
+                                   int64_t tile_end, unsigned long long *queue, hipStream_t s) {
+  switch (JB) {
+    case 2:
+      return fp4 ? launch_plain_count_t<true, 2>(pj_dev, tile_begin, tile_end, queue, s)
+                 : launch_plain_count_t<false, 2>(pj_dev, tile_begin, tile_end, queue, s);
+    case 4:
+      return fp4 ? launch_plain_count_t<true, 4>(pj_dev, tile_begin, tile_end, queue, s)
+                 : launch_plain_count_t<false, 4>(pj_dev, tile_begin, tile_end, queue, s);
+    case 8:
+      return fp4 ? launch_plain_count_t<true, 8>(pj_dev, tile_begin, tile_end, queue, s)
+                 : launch_plain_count_t<false, 8>(pj_dev, tile_begin, tile_end, queue, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int JB, bool LDS>
+static hipError_t launch_finish_plain_t(const PlainJob *pj_dev, int64_t tile_begin,
+                                        int64_t tile_end, const float *lf32, int32_t lf_len,
+                                        hipStream_t s) {
+  const int64_t n = tile_end - tile_begin;
+  if (n <= 0) return hipSuccess;
+  int n_cu = 0;
+  hipError_t e = cu_count(&n_cu);
+  if (e != hipSuccess) return e;
+  const size_t lds = LDS ? (size_t)lf_len * sizeof(float) : 0;
+  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&finish_plain_kernel<JB, LDS>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, finish_plain_kernel<JB, LDS>, 256, lds);
+  if (e != hipSuccess) return e;
+  if (per_cu <= 0) per_cu = 1;
+  int64_t blocks = (int64_t)n_cu * per_cu;
+  if (blocks > n) blocks = n;
+  hipLaunchKernelGGL((finish_plain_kernel<JB, LDS>), dim3((unsigned)blocks), dim3(256), lds, s,
+                     pj_dev, tile_begin, tile_end, lf32, lf_len);
+  return hipGetLastError();
+}
+
+template <int JB>
+static hipError_t launch_finish_plain_j(const PlainJob *pj_dev, int64_t tile_begin,
+                                        int64_t tile_end, const float *lf32, int32_t lf_len,
+                                        hipStream_t s) {
+  return lf_in_lds(lf_len)
+             ? launch_finish_plain_t<JB, true>(pj_dev, tile_begin, tile_end, lf32, lf_len, s)
+             : launch_finish_plain_t<JB, false>(pj_dev, tile_begin, tile_end, lf32, lf_len, s);
+}
+
+hipError_t launch_finish_plain(const PlainJob *pj_dev, int JB, int64_t tile_begin,
+                               int64_t tile_end, const float *lf32, int32_t lf_len,
+                               hipStream_t s) {
+  switch (JB) {
+    case 2: return launch_finish_plain_j<2>(pj_dev, tile_begin, tile_end, lf32, lf_len, s);
+    case 4: return launch_finish_plain_j<4>(pj_dev, tile_begin, tile_end, lf32, lf_len, s);
+    case 8: return launch_finish_plain_j<8>(pj_dev, tile_begin, tile_end, lf32, lf_len, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace epi3

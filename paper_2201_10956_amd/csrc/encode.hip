@@ -99,6 +99,44 @@ __global__ void __launch_bounds__(256) encode_nibbles_kernel(const uint8_t *__re
   }
 }
 
+// Per-class 0/1 value planes for the matrix cores, through the class sample
+// list: position p of class c is sample list[off_c + p] (p < len_c), else
+// padding.  bytes[c][m][g][p] = 1 and nib[c][m][g][p / 2] nibble = 0x2 (E2M1
+// 1.0) when that sample has genotype g in {0, 1}; padding and SNPs m >= M
+// are 0.  One thread per 8 positions.
+__global__ void __launch_bounds__(256) encode_values_kernel(
+    const uint8_t *__restrict__ geno, int64_t ld, const int32_t *__restrict__ list, int32_t off0,
+    int32_t len0, int32_t off1, int32_t len1, int32_t M, int32_t Mp, int32_t S,
+    uint32_t *__restrict__ bytes, uint32_t *__restrict__ nib) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;  // positions 8q .. 8q + 7
+  if (q >= S / 8) return;
+  const int c = blockIdx.z;
+  const int off = c ? off1 : off0, len = c ? len1 : len0;
+  for (int m = blockIdx.y; m < Mp; m += gridDim.y) {
+    uint32_t b0[2] = {0, 0}, b1[2] = {0, 0}, n0 = 0, n1 = 0;
+    if (m < M) {
+      const uint8_t *row = geno + (int64_t)m * ld;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int p = 8 * q + b;
+        if (p < len) {
+          const uint32_t g = row[list[off + p]];
+          const uint32_t is0 = g == 0u, is1 = g == 1u;
+          b0[b >> 2] |= is0 << (8 * (b & 3));
+          b1[b >> 2] |= is1 << (8 * (b & 3));
+          n0 |= is0 << (4 * b + 1);
+          n1 |= is1 << (4 * b + 1);
+        }
+      }
+    }
+    const int64_t rb = ((int64_t)c * Mp + m) * 2;  // row of (class, snp, plane 0)
+    reinterpret_cast<uint2 *>(bytes)[(rb + 0) * (S / 8) + q] = make_uint2(b0[0], b0[1]);
+    reinterpret_cast<uint2 *>(bytes)[(rb + 1) * (S / 8) + q] = make_uint2(b1[0], b1[1]);
+    nib[(rb + 0) * (S / 8) + q] = n0;
+    nib[(rb + 1) * (S / 8) + q] = n1;
+  }
+}
+
 // Pairwise tables: pairs[c][x][y] = (n(0,0), n(0,1), n(1,0), n(1,1)) with
 // n(a,b) = number of class-c samples where SNP x has genotype a and SNP y has
 // genotype b.  The diagonal holds the per-SNP counts (n_x(0), 0, 0, n_x(1)).
@@ -169,6 +207,17 @@ hipError_t launch_encode_nibbles(const uint8_t *geno, int64_t ld, int32_t M, int
   const int S8 = S / 8;
   dim3 grid((S8 + 255) / 256, Mp < 65535 ? Mp : 65535);
   hipLaunchKernelGGL(encode_nibbles_kernel, grid, dim3(256), 0, s, geno, ld, M, N, Mp, S,
+                     reinterpret_cast<uint32_t *>(nib));
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_values(const uint8_t *geno, int64_t ld, const int32_t *list, int32_t off0,
+                                int32_t len0, int32_t off1, int32_t len1, int32_t classes,
+                                int32_t M, int32_t Mp, int32_t S, uint8_t *bytes, uint8_t *nib,
+                                hipStream_t s) {
+  dim3 grid((S / 8 + 255) / 256, Mp < 65535 ? Mp : 65535, classes);
+  hipLaunchKernelGGL(encode_values_kernel, grid, dim3(256), 0, s, geno, ld, list, off0, len0, off1,
+                     len1, M, Mp, S, reinterpret_cast<uint32_t *>(bytes),
                      reinterpret_cast<uint32_t *>(nib));
   return hipGetLastError();
 }

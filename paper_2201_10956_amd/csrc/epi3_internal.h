@@ -60,6 +60,8 @@ struct Job {
   int64_t n_tiles;
   int64_t T;
   int32_t M, Mp, W0, W1, N0, N1;
+  int32_t P;               // pivots i per tile (4 or 8)
+  int32_t pad;
 };
 
 // Per-job radix-select state.
@@ -103,6 +105,20 @@ struct PermJob {
   uint4 *totals;              // scratch: [pass tile][4 pivots i][16 k] 8 x uint16 all-sample cells
   int64_t n_tiles, T;
   int32_t M, Mp, S, N, Q, Qp;  // S: bytes per staged row (samples for bytes, samples / 2 for nibbles)
+};
+
+// Plain two-class scan on the matrix cores: one SPLIT data set, counted in
+// passes of tiles whose corner cells go through a scratch buffer.
+struct PlainJob {
+  const uint8_t *vals;     // [2][Mp][2][Sb] 0/1 values per class (bytes, or E2M1 nibbles)
+  const int32_t *pairs;    // [2][Mp][Mp][4]
+  float *score;            // [T] FP32 K2 by lexicographic rank
+  uint32_t *counts;        // optional [T][2][27]
+  uint32_t *keyrange;      // [2] atomic min / max of f2key(score)
+  const int64_t *jprefix;  // [M + 1] tiles before pivot j
+  uint4 *corners;          // scratch: [pass tile][class][16 i][JB j][256 / JB k] 8 x uint16 cells
+  int64_t n_tiles, T;
+  int32_t M, Mp, Sb, Sb0, Sb1, N0, N1, JB;  // Sb: bytes per row; Sb0 / Sb1: bytes holding each class
 };
 
 // Selection job: one score plane plus its candidate buffers.
@@ -174,6 +190,11 @@ __device__ __forceinline__ void complete_table(const uint32_t n[8], const int pi
   t[26] = Nc - s;
 }
 
+// The FP32 log-factorial table sits in LDS when it fits in this many bytes
+// (two workgroups per CU); larger tables are read from global memory.
+constexpr int64_t kLdsTableBytes = 80 * 1024;
+inline bool lf_in_lds(int32_t lf_len) { return (int64_t)lf_len * 4 <= kLdsTableBytes; }
+
 // ---- host-side launchers (defined in the .hip files) ----
 hipError_t launch_encode(const uint8_t *geno, int64_t ld, const int32_t *sample_list,
                          int32_t M, int32_t Mp, int32_t W0, int32_t W1, uint32_t *planes,
@@ -182,15 +203,19 @@ hipError_t launch_encode_bytes(const uint8_t *geno, int64_t ld, int32_t M, int32
                                int32_t S, uint8_t *bytes, hipStream_t s);
 hipError_t launch_encode_nibbles(const uint8_t *geno, int64_t ld, int32_t M, int32_t N, int32_t Mp,
                                  int32_t S, uint8_t *nib, hipStream_t s);
+hipError_t launch_encode_values(const uint8_t *geno, int64_t ld, const int32_t *list, int32_t off0,
+                                int32_t len0, int32_t off1, int32_t len1, int32_t classes,
+                                int32_t M, int32_t Mp, int32_t S, uint8_t *bytes, uint8_t *nib,
+                                hipStream_t s);
 hipError_t launch_pairs(const uint32_t *planes, int32_t Mp, int32_t M, int32_t W0, int32_t W1,
                         int32_t n_classes, const uint32_t *mask, int32_t *pairs, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
-hipError_t launch_tile_prefix(Job *jobs_dev, int32_t n_jobs, int32_t P, hipStream_t s);
+hipError_t launch_tile_prefix(Job *jobs_dev, int32_t n_jobs, hipStream_t s);
 int64_t host_tiles(int64_t M, int P);
 hipError_t launch_write_jobs(const Job *jobs_host, int32_t n, Job *dst_dev, hipStream_t s);
 hipError_t launch_count_valu(const Job *jobs_dev, int32_t n_jobs, int64_t total_tiles,
                              unsigned long long *queue, const float *lf32, int32_t lf_len,
-                             int32_t P, bool counts, hipStream_t s);
+                             int32_t P_lo, int32_t P_hi, bool counts, hipStream_t s);
 hipError_t launch_select(SelJob *sel_dev, int32_t n_jobs, int64_t max_T, int64_t max_cap,
                          int32_t max_k, hipStream_t s);
 hipError_t launch_write_seljobs(const SelJob *h, int32_t n, SelJob *dst_dev, hipStream_t s);
@@ -213,6 +238,16 @@ constexpr int64_t kPermTileScratch = 64 * 64 * 16 + 64 * 16;  // bytes per tile 
 hipError_t launch_write_permjob(const PermJob &h, PermJob *dst_dev, hipStream_t s);
 hipError_t launch_write_ptrs(const uint32_t *const *h, int32_t n, const uint32_t **dst_dev,
                              hipStream_t s);
+
+int64_t host_plain_tiles(int64_t M, int JB);
+constexpr int kPlainI = 16;  // pivots i per plain matrix-core tile (x JB j x 256 / JB k)
+constexpr int64_t kPlainTileScratch = 2ll * kPlainI * 256 * 16;  // bytes per tile, both classes
+hipError_t launch_write_plainjob(const PlainJob &h, PlainJob *dst_dev, hipStream_t s);
+hipError_t launch_plain_prefix(PlainJob *pj_dev, hipStream_t s);
+hipError_t launch_count_mfma_plain(const PlainJob *pj_dev, int JB, bool fp4, int64_t tile_begin,
+                                   int64_t tile_end, unsigned long long *queue, hipStream_t s);
+hipError_t launch_finish_plain(const PlainJob *pj_dev, int JB, int64_t tile_begin,
+                               int64_t tile_end, const float *lf32, int32_t lf_len, hipStream_t s);
 
 int tile_P_default(int32_t M, int32_t N);
 

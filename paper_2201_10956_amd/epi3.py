@@ -70,7 +70,7 @@ def _load():
     sigs = {
         "epi3_encode_bytes": (i64, [i32, i32, i32, i32]),
         "epi3_encode": (ctypes.c_int, [vp, i64, vp, i32, i32, i32, vp, i64, vp, P(CDataset)]),
-        "epi3_workspace_bytes": (i64, [P(CDataset), i32, i64]),
+        "epi3_workspace_bytes": (i64, [P(CDataset), i32, i32, i64]),
         "epi3_scan": (ctypes.c_int, [P(CDataset), i32, i32, i64, vp, i64, vp]),
         "epi3_topk": (ctypes.c_int, [P(CDataset), i32, i64, vp, vp, P(i32), vp]),
         "epi3_batched_workspace_bytes": (i64, [P(CJob), i32, i64]),
@@ -85,6 +85,11 @@ def _load():
         "epi3_timing_query": (ctypes.c_int, [i32, P(ctypes.c_double), P(i64)]),
         "epi3_timing_reset": (None, []),
         "epi3_version": (ctypes.c_char_p, []),
+        "epi3_tile_rule": (ctypes.c_int, [i32, i32, i32, i32]),
+        "epi3_tile_rules_clear": (None, []),
+        "epi3_tile_for": (i32, [P(CDataset), i32]),
+        "epi3_set_pass_bytes": (ctypes.c_int, [i64]),
+        "epi3_perm_pvalue": (ctypes.c_int, [ctypes.c_double, vp, i32, P(ctypes.c_double)]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -97,7 +102,10 @@ _lib = _load()
 EXPORTS = ("epi3_encode_bytes", "epi3_encode", "epi3_workspace_bytes", "epi3_scan", "epi3_topk",
            "epi3_batched_workspace_bytes", "epi3_scan_batched", "epi3_scan_tables",
            "epi3_score_triplets", "epi3_score_plane", "epi3_k2_error_bound", "epi3_n_triplets", "epi3_release",
-           "epi3_version", "epi3_timing_enable", "epi3_timing_query", "epi3_timing_reset")
+           "epi3_version", "epi3_timing_enable", "epi3_timing_query", "epi3_timing_reset",
+           "epi3_tile_rule", "epi3_tile_rules_clear", "epi3_tile_for", "epi3_set_pass_bytes",
+           "epi3_perm_pvalue")
+TILES_PATH = os.path.join(_HERE, "tiles.json")
 
 
 def _check(rc: int, where: str) -> None:
@@ -142,6 +150,53 @@ def timing_query(which: int = 0):
     n = ctypes.c_int64(0)
     _check(_lib.epi3_timing_query(which, ctypes.byref(ms), ctypes.byref(n)), "epi3_timing_query")
     return ms.value, n.value
+
+
+def tile_rule(variant: str, min_snps: int, min_samples: int, tile) -> None:
+    """Register a tile rule (for variant "auto", `tile` names the variant)."""
+    t = _VARIANTS[tile] if isinstance(tile, str) else int(tile)
+    _check(_lib.epi3_tile_rule(_VARIANTS[variant], int(min_snps), int(min_samples), t),
+           "epi3_tile_rule")
+
+
+def tile_rules_clear() -> None:
+    _lib.epi3_tile_rules_clear()
+
+
+def tile_for(ds: "Dataset", variant: str):
+    """The tile a scan of ds with `variant` uses (for "auto": the variant's name)."""
+    r = int(_lib.epi3_tile_for(ctypes.byref(ds.c), _VARIANTS[variant]))
+    _check(r if r < 0 else OK, "epi3_tile_for")
+    if variant == "auto":
+        return {v: k for k, v in _VARIANTS.items()}[r]
+    return r
+
+
+def set_pass_bytes(nbytes: int) -> None:
+    """Scratch bytes per pass buffer of the matrix-core paths (0: default)."""
+    _check(_lib.epi3_set_pass_bytes(int(nbytes)), "epi3_set_pass_bytes")
+
+
+def load_tiles(path: str = TILES_PATH) -> int:
+    """Register the rules of a tile table written by the autotuner; returns how many."""
+    import json
+    if not os.path.exists(path):
+        return 0
+    with open(path) as f:
+        table = json.load(f)
+    for r in table.get("rules", []):
+        tile_rule(r["variant"], r["min_snps"], r["min_samples"], r["tile"])
+    return len(table.get("rules", []))
+
+
+def perm_pvalue(observed_k2: float, perm_min_k2) -> float:
+    """Family-wise permutation p-value of the observed best K2 given the best
+    K2 of each phenotype permutation (hit 0 of each job of a batched scan)."""
+    a = np.ascontiguousarray(np.asarray(perm_min_k2, dtype=np.float64))
+    p = ctypes.c_double(0.0)
+    _check(_lib.epi3_perm_pvalue(float(observed_k2), a.ctypes.data_as(ctypes.c_void_p), a.size,
+                                 ctypes.byref(p)), "epi3_perm_pvalue")
+    return p.value
 
 
 def n_triplets(M: int) -> int:
@@ -208,7 +263,8 @@ class Scanner:
         self._alloc()
 
     def _alloc(self):
-        nbytes = _lib.epi3_workspace_bytes(ctypes.byref(self.ds.c), self.k, self.cand_cap)
+        nbytes = _lib.epi3_workspace_bytes(ctypes.byref(self.ds.c), self.k, self.variant,
+                                           self.cand_cap)
         _check(int(nbytes) if nbytes < 0 else OK, "epi3_workspace_bytes")
         self.ws = _buffer(nbytes, self.ds.buf.device)
         self.hits = (CHit * max(self.k, 1))()
@@ -265,7 +321,7 @@ def scan_tables(ds: Dataset, variant: str = "auto", counts: bool = True, stream=
     dev = ds.buf.device
     k2 = torch.empty(max(T, 1), dtype=torch.float32, device=dev)
     cc = torch.empty((max(T, 1), 2, 27), dtype=torch.int32, device=dev) if counts else None
-    nbytes = _lib.epi3_workspace_bytes(ctypes.byref(ds.c), 1, 0)
+    nbytes = _lib.epi3_workspace_bytes(ctypes.byref(ds.c), 1, _VARIANTS[variant], 0)
     _check(int(nbytes) if nbytes < 0 else OK, "epi3_workspace_bytes")
     ws = _buffer(nbytes, dev)
     rc = _lib.epi3_scan_tables(ctypes.byref(ds.c), _VARIANTS[variant],
@@ -373,3 +429,7 @@ class BatchScanner:
 
 def release() -> None:
     _lib.epi3_release()
+
+
+# tuned tile table shipped with the package (written by paper_2201_10956_amd.autotune)
+load_tiles()

@@ -1,0 +1,175 @@
+"""The C ABI without a GPU: the library loads, exports every function the
+header declares, and its host-only logic (sizes, counts, bounds, tile rules,
+argument checks) behaves as documented.  No kernel is launched here."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "epi3.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(epi3_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def epi3():
+    from paper_2201_10956_amd import epi3 as e
+    return e
+
+
+def test_every_declared_symbol_is_exported(epi3):
+    names = _declared()
+    assert len(names) >= 20
+    lib = ctypes.CDLL(epi3.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(epi3.EXPORTS) == names
+
+
+def test_counts_and_bounds(epi3):
+    assert epi3.n_triplets(0) == 0 and epi3.n_triplets(2) == 0
+    assert epi3.n_triplets(3) == 1
+    assert epi3.n_triplets(2048) == math.comb(2048, 3)
+    assert epi3.n_triplets(100000) == math.comb(100000, 3)
+    # e(N) = 32 u L[N + 27], L = log factorial
+    for N in (1, 100, 16384):
+        want = 32 * 2.0 ** -24 * math.lgamma(N + 28)
+        assert epi3.k2_error_bound(N) == pytest.approx(want, rel=1e-12)
+    assert epi3.version().startswith("epi3")
+
+
+def _fake_dataset(epi3, M, N1, N0, layout=0):
+    """A struct as epi3_encode fills it; pointers are never dereferenced by
+    the size queries."""
+    c = epi3.CDataset()
+    c.n_snps, c.n_cases, c.n_controls, c.n_samples = M, N1, N0, N1 + N0
+    c.layout = layout
+    c.snp_stride = (M + 63) // 64 * 64 + 64
+    c.byte_stride = (max(N0, N1) + 255) // 256 * 256
+    c.words[0], c.words[1] = (N0 + 31) // 32, (N1 + 31) // 32
+    for f in ("planes", "bytes", "nibbles", "pairs", "lf64", "lf32", "status"):
+        setattr(c, f, 4096)
+    return c
+
+
+def test_encode_bytes(epi3):
+    lib = epi3._lib
+    assert lib.epi3_encode_bytes(10, 5, 5, 0) > 0
+    assert lib.epi3_encode_bytes(10, 0, 0, 0) == epi3.E_INVALID
+    assert lib.epi3_encode_bytes(10, 5, 5, 7) == epi3.E_INVALID
+    assert lib.epi3_encode_bytes(-1, 5, 5, 0) == epi3.E_INVALID
+    # the buffer grows with every dimension
+    a = lib.epi3_encode_bytes(100, 500, 500, 0)
+    assert lib.epi3_encode_bytes(200, 500, 500, 0) > a
+    assert lib.epi3_encode_bytes(100, 5000, 500, 0) > a
+
+
+def test_workspace_sizes(epi3):
+    lib = epi3._lib
+    d = _fake_dataset(epi3, 300, 700, 900)
+    T = epi3.n_triplets(300)
+    v = lib.epi3_workspace_bytes(ctypes.byref(d), 10, epi3.VARIANT_VALU, 0)
+    assert v >= 4 * T                      # at least the FP32 score plane
+    m = lib.epi3_workspace_bytes(ctypes.byref(d), 10, epi3.VARIANT_MFMA, 0)
+    f = lib.epi3_workspace_bytes(ctypes.byref(d), 10, epi3.VARIANT_MFMA_FP4, 0)
+    assert m > v and f == m                # plus the corner scratch
+    assert lib.epi3_workspace_bytes(ctypes.byref(d), 0, 1, 0) == epi3.E_INVALID
+    assert lib.epi3_workspace_bytes(ctypes.byref(d), 10, 9, 0) == epi3.E_INVALID
+    big = _fake_dataset(epi3, 30, 70000, 10)
+    assert lib.epi3_workspace_bytes(ctypes.byref(big), 10, epi3.VARIANT_MFMA, 0) == \
+        epi3.E_UNSUPPORTED
+    # the candidate buffers scale with the capacity
+    c1 = lib.epi3_workspace_bytes(ctypes.byref(d), 10, 1, 100000)
+    assert c1 > v
+
+
+def test_tile_rules(epi3):
+    lib = epi3._lib
+    small = _fake_dataset(epi3, 100, 500, 500)
+    large = _fake_dataset(epi3, 3000, 20000, 20000)
+    try:
+        epi3.tile_rules_clear()
+        assert lib.epi3_tile_for(ctypes.byref(small), epi3.VARIANT_VALU) == 4
+        assert lib.epi3_tile_for(ctypes.byref(large), epi3.VARIANT_VALU) == 8
+        assert lib.epi3_tile_for(ctypes.byref(small), epi3.VARIANT_MFMA) == 4
+        assert lib.epi3_tile_for(ctypes.byref(large), epi3.VARIANT_MFMA_FP4) == 4
+        assert lib.epi3_tile_for(ctypes.byref(large), epi3.VARIANT_AUTO) == epi3.VARIANT_VALU
+        # the most specific applicable rule wins
+        epi3.tile_rule("valu", 0, 0, 8)
+        epi3.tile_rule("valu", 1000, 0, 4)
+        epi3.tile_rule("valu", 1000, 50000, 8)
+        assert lib.epi3_tile_for(ctypes.byref(small), epi3.VARIANT_VALU) == 8
+        assert lib.epi3_tile_for(ctypes.byref(large), epi3.VARIANT_VALU) == 4
+        epi3.tile_rule("mfma_fp4", 64, 1000, 8)
+        assert lib.epi3_tile_for(ctypes.byref(large), epi3.VARIANT_MFMA_FP4) == 8
+        assert lib.epi3_tile_for(ctypes.byref(small), epi3.VARIANT_MFMA_FP4) == 8
+        assert lib.epi3_tile_for(ctypes.byref(large), epi3.VARIANT_MFMA) == 4
+        # the workspace follows the rules in force when it is sized (the
+        # number of tiles, hence of scratch buffers' tiles, depends on JB)
+        w2 = lib.epi3_workspace_bytes(ctypes.byref(small), 10, epi3.VARIANT_MFMA, 0)
+        epi3.tile_rule("mfma", 0, 0, 2)
+        w4 = lib.epi3_workspace_bytes(ctypes.byref(small), 10, epi3.VARIANT_MFMA, 0)
+        assert w2 != w4
+        # AUTO picks the registered variant, but not where it cannot run
+        epi3.tile_rule("auto", 500, 0, "mfma_fp4")
+        assert epi3.tile_for(_Wrap(large), "auto") == "mfma_fp4"
+        assert epi3.tile_for(_Wrap(small), "auto") == "valu"
+        unsup = _fake_dataset(epi3, 3000, 70000, 10)
+        assert epi3.tile_for(_Wrap(unsup), "auto") == "valu"
+        # invalid tiles are refused
+        assert lib.epi3_tile_rule(epi3.VARIANT_VALU, 0, 0, 5) == epi3.E_INVALID
+        assert lib.epi3_tile_rule(epi3.VARIANT_MFMA, 0, 0, 16) == epi3.E_INVALID
+        assert lib.epi3_tile_rule(epi3.VARIANT_MFMA, 0, 0, 3) == epi3.E_INVALID
+        assert lib.epi3_tile_rule(epi3.VARIANT_AUTO, 0, 0, 0) == epi3.E_INVALID
+        assert lib.epi3_tile_rule(7, 0, 0, 4) == epi3.E_INVALID
+        assert lib.epi3_tile_rule(epi3.VARIANT_VALU, -1, 0, 4) == epi3.E_INVALID
+    finally:
+        epi3.tile_rules_clear()
+        epi3.load_tiles()
+
+
+def test_pass_bytes_bound_the_scratch(epi3):
+    lib = epi3._lib
+    d = _fake_dataset(epi3, 2048, 8192, 8192)
+    try:
+        epi3.set_pass_bytes(0)
+        a = lib.epi3_workspace_bytes(ctypes.byref(d), 10, epi3.VARIANT_MFMA, 0)
+        epi3.set_pass_bytes(1 << 22)
+        b = lib.epi3_workspace_bytes(ctypes.byref(d), 10, epi3.VARIANT_MFMA, 0)
+        v = lib.epi3_workspace_bytes(ctypes.byref(d), 10, epi3.VARIANT_VALU, 0)
+        assert a - v > (1 << 30) and 0 < b - v <= 2 * (1 << 22) + 256
+        assert lib.epi3_set_pass_bytes(-5) == epi3.E_INVALID
+    finally:
+        epi3.set_pass_bytes(0)
+
+
+class _Wrap:
+    """Stands in for a Dataset in tile_for (only .c is read)."""
+
+    def __init__(self, c):
+        self.c = c
+
+
+def test_perm_pvalue(epi3):
+    """p = (1 + #{q: min_q <= obs}) / (Q + 1), counted by hand."""
+    import numpy as np
+    mins = np.array([5.0, 3.0, 7.5, 3.0, 9.0])
+    assert epi3.perm_pvalue(3.0, mins) == pytest.approx(3 / 6)      # two ties count
+    assert epi3.perm_pvalue(2.9, mins) == pytest.approx(1 / 6)      # none as low
+    assert epi3.perm_pvalue(100.0, mins) == pytest.approx(6 / 6)
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        m = rng.normal(size=rng.integers(1, 50))
+        o = float(rng.normal())
+        assert epi3.perm_pvalue(o, m) == (1 + int(np.sum(m <= o))) / (m.size + 1)
+    with pytest.raises(epi3.Epi3Error):
+        epi3.perm_pvalue(1.0, [])
+    with pytest.raises(epi3.Epi3Error):
+        epi3.perm_pvalue(float("nan"), [1.0])

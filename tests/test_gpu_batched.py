@@ -159,3 +159,17 @@ def test_fp4_and_int8_permutation_batches_agree(env):
     b = epi3.BatchScanner(ds, 25, masks=m, variant="mfma_fp4").run()
     for x, y in zip(a, b):
         assert x.tobytes() == y.tobytes()
+
+
+@pytest.mark.parametrize("variant", ["mfma", "mfma_fp4"])
+def test_permutations_large_sample_count(env, variant):
+    """30000 samples: the table-completion kernel reads the log-factorial
+    table from global memory."""
+    torch, epi3 = env
+    d = make_dataset(11, 30000, 0.4, 0.05, seed=31)
+    perms = make_permutations(d.pheno, 3, seed=32)
+    ds = epi3.encode(to_dev(d.geno), d.pheno, layout="masked")
+    res = epi3.BatchScanner(ds, 5, masks=_masks(epi3, perms), variant=variant).run()
+    for q in range(3):
+        ijk, k2, cc = oracle.scan_topk(d.geno, perms[q], 5)
+        assert_hits_equal_oracle(res[q], ijk, k2, cc)
