@@ -58,6 +58,15 @@ __global__ void __launch_bounds__(1024) tile_prefix_kernel(Job *jobs) {
   if (t == 1023) pre[M] = part[1023];
 }
 
+// acc + popcount(x) as one v_bcnt_u32_b32.  Written out because the compiler
+// may otherwise reassociate the sums of an unrolled loop into v_bcnt(x, 0)
+// plus v_add3, one more VALU op per two counts.
+__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
+  uint32_t r;
+  asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+  return r;
+}
+
 // Accumulate the 8 corner cells of P pairs over words [w0, w1).
 // acc[t][4a + 2b + c] += popcount(X_{i0+t}[a] & X_j[b] & X_k[c]).
 template <int P>
@@ -74,14 +83,14 @@ __device__ __forceinline__ void accumulate(uint32_t (&acc)[P][8], const uint32_t
     for (int t = 0; t < P; ++t) {
       const uint32_t xi0 = pc[(rowbase + i0 + t) * 2], xi1 = pc[(rowbase + i0 + t) * 2 + 1];
       const uint32_t p00 = xi0 & xj0, p01 = xi0 & xj1, p10 = xi1 & xj0, p11 = xi1 & xj1;
-      acc[t][0] += __builtin_popcount(p00 & xk.x);
-      acc[t][1] += __builtin_popcount(p00 & xk.y);
-      acc[t][2] += __builtin_popcount(p01 & xk.x);
-      acc[t][3] += __builtin_popcount(p01 & xk.y);
-      acc[t][4] += __builtin_popcount(p10 & xk.x);
-      acc[t][5] += __builtin_popcount(p10 & xk.y);
-      acc[t][6] += __builtin_popcount(p11 & xk.x);
-      acc[t][7] += __builtin_popcount(p11 & xk.y);
+      acc[t][0] = bcnt_acc(p00 & xk.x, acc[t][0]);
+      acc[t][1] = bcnt_acc(p00 & xk.y, acc[t][1]);
+      acc[t][2] = bcnt_acc(p01 & xk.x, acc[t][2]);
+      acc[t][3] = bcnt_acc(p01 & xk.y, acc[t][3]);
+      acc[t][4] = bcnt_acc(p10 & xk.x, acc[t][4]);
+      acc[t][5] = bcnt_acc(p10 & xk.y, acc[t][5]);
+      acc[t][6] = bcnt_acc(p11 & xk.x, acc[t][6]);
+      acc[t][7] = bcnt_acc(p11 & xk.y, acc[t][7]);
     }
   }
 }

@@ -61,6 +61,9 @@ assert ctypes.sizeof(CDataset) == 96 and ctypes.sizeof(CJob) == 24
 
 
 def _load():
+    # torch first: the library then binds to the HIP runtime torch already
+    # loaded, so device pointers and streams from torch are valid in it
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2201_10956_amd.build "
                           "(there is no CPU fallback)")
