@@ -261,6 +261,11 @@ int32_t epi3_tile_for(const epi3_dataset *d, int32_t variant);
 /* Scratch bytes per pass buffer of the matrix-core paths (0: default 1 GiB
  * for plain scans, 4 GiB for phenotype batches).  Same rules as above. */
 int epi3_set_pass_bytes(int64_t bytes);
+/* Entries of the compacted low end of a score plane that the selection keeps
+ * after its first histogram pass (0: default max(65536, 16 x candidate
+ * capacity)); beyond it the later passes read the whole plane again.  Same
+ * rules as above (it sizes the workspaces). */
+int epi3_set_compact_cap(int64_t n);
 
 /* Library version string. */
 const char *epi3_version(void);

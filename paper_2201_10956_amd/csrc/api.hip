@@ -110,6 +110,9 @@ struct ScanLayout {
   int64_t *cand;
   CandRec *rec;
   epi3_hit *hits;
+  uint32_t *ckey;         // compacted low end of the plane
+  int64_t *crank;
+  int64_t ccap;
   PlainJob *pjob;         // [2]: one per scratch buffer
   uint8_t *scratch;       // matrix-core variants: two buffers of pass_tiles tiles
   int64_t pass_tiles;
@@ -133,6 +136,7 @@ struct Tiles {
   std::mutex mu;
   std::vector<TileRule> rules;
   int64_t pass_bytes = 0;
+  int64_t compact_cap = 0;
 };
 Tiles &tiles() {
   static Tiles t;
@@ -155,6 +159,17 @@ int64_t pass_bytes(int64_t dflt) {
   Tiles &t = tiles();
   std::lock_guard<std::mutex> g(t.mu);
   return t.pass_bytes > 0 ? t.pass_bytes : dflt;
+}
+
+// Capacity of the compacted low end of a score plane of T triplets.
+int64_t compact_cap(int64_t T, int64_t cap) {
+  int64_t c = 16 * cap > 65536 ? 16 * cap : 65536;
+  {
+    Tiles &t = tiles();
+    std::lock_guard<std::mutex> g(t.mu);
+    if (t.compact_cap > 0) c = t.compact_cap;
+  }
+  return c < T ? c : (T > 0 ? T : 1);
 }
 
 bool mfma_supported(const epi3_dataset &d) {
@@ -190,6 +205,9 @@ ScanLayout scan_layout(void *ws, const epi3_dataset &d, int32_t k, int64_t cand_
   L.cand = c.take<int64_t>(L.cap);
   L.rec = c.take<CandRec>(L.cap);
   L.hits = c.take<epi3_hit>(std::max<int32_t>(k, 1));
+  L.ccap = compact_cap(T, L.cap);
+  L.ckey = c.take<uint32_t>(L.ccap);
+  L.crank = c.take<int64_t>(L.ccap);
   L.pjob = c.take<PlainJob>(2);
   const int v = plain_variant(d, variant);
   if (T > 0 && (v == EPI3_VARIANT_MFMA || v == EPI3_VARIANT_MFMA_FP4)) {
@@ -236,8 +254,11 @@ Job make_job(const epi3_dataset &d, float *score, uint32_t *counts, int64_t *jpr
 
 SelJob make_seljob(const epi3_dataset &d, const float *score, int64_t T, SelState *st,
                    uint32_t *hist, int64_t *cand, CandRec *rec, epi3_hit *hits, int64_t cap,
-                   int32_t k) {
+                   int32_t k, uint32_t *ckey, int64_t *crank, int64_t ccap) {
   SelJob S{};
+  S.ckey = ckey;
+  S.crank = crank;
+  S.ccap = ccap;
   S.score = score;
   S.T = T;
   S.st = st;
@@ -536,7 +557,8 @@ int epi3_scan(const epi3_dataset *d, int32_t k, int32_t variant, int64_t cand_ca
   if (ws_bytes < W.total) return EPI3_E_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t T = epi3_n_triplets(d->n_snps);
-  SelJob S = make_seljob(*d, W.score, T, W.st, W.hist, W.cand, W.rec, W.hits, W.cap, k);
+  SelJob S = make_seljob(*d, W.score, T, W.st, W.hist, W.cand, W.rec, W.hits, W.cap, k, W.ckey,
+                         W.crank, W.ccap);
   HIP_OK(launch_write_seljobs(&S, 1, W.sel, s));
   HIP_OK(launch_init_select(W.sel, 1, s));
   if (T > 0) {
@@ -634,7 +656,9 @@ struct BatchLayout {
   std::vector<float *> score;
   std::vector<int64_t *> cand;
   std::vector<CandRec *> rec;
-  std::vector<int64_t> cap, hit_off, T;
+  std::vector<uint32_t *> ckey;
+  std::vector<int64_t *> crank;
+  std::vector<int64_t> cap, ccap, hit_off, T;
   int64_t total_k = 0, total = 0;
 };
 
@@ -695,11 +719,15 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
   L.score.resize(n);
   L.cand.resize(n);
   L.rec.resize(n);
+  L.ckey.resize(n);
+  L.crank.resize(n);
   L.cap.resize(n);
+  L.ccap.resize(n);
   L.T.resize(n);
   for (int x = 0; x < n; ++x) {
     L.T[x] = epi3_n_triplets(jobs[x].d->n_snps);
     L.cap[x] = default_cap(L.T[x], jobs[x].k, cand_cap);
+    L.ccap[x] = compact_cap(L.T[x], L.cap[x]);
   }
   if (L.layout == EPI3_LAYOUT_MASKED) {
     // one block [n][T]: the matrix-core kernel addresses phenotype q at q * T
@@ -714,6 +742,8 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
     }
     L.cand[x] = c.take<int64_t>(L.cap[x]);
     L.rec[x] = c.take<CandRec>(L.cap[x]);
+    L.ckey[x] = c.take<uint32_t>(L.ccap[x]);
+    L.crank[x] = c.take<int64_t>(L.ccap[x]);
   }
   L.total = c.size();
   return L;
@@ -728,7 +758,8 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
   for (int x = 0; x < n; ++x) {
     const epi3_dataset &d = *jobs[x].d;
     sj[x] = make_seljob(d, W.score[x], W.T[x], W.st + x, W.hist + (int64_t)x * kHistBins,
-                        W.cand[x], W.rec[x], W.hits + W.hit_off[x], W.cap[x], jobs[x].k);
+                        W.cand[x], W.rec[x], W.hits + W.hit_off[x], W.cap[x], jobs[x].k,
+                        W.ckey[x], W.crank[x], W.ccap[x]);
     if (W.layout == EPI3_LAYOUT_MASKED) {
       const int g = x / kPermGroup, q = x % kPermGroup;
       sj[x].case_mask = jobs[x].case_mask;
@@ -1049,6 +1080,14 @@ int32_t epi3_tile_for(const epi3_dataset *d, int32_t variant) {
   if (variant == EPI3_VARIANT_VALU) return pick_P(*d);
   if (variant == EPI3_VARIANT_MFMA || variant == EPI3_VARIANT_MFMA_FP4) return pick_JB(*d, variant);
   return EPI3_E_INVALID;
+}
+
+int epi3_set_compact_cap(int64_t n) {
+  if (n < 0) return EPI3_E_INVALID;
+  Tiles &t = tiles();
+  std::lock_guard<std::mutex> g(t.mu);
+  t.compact_cap = n;
+  return EPI3_OK;
 }
 
 int epi3_set_pass_bytes(int64_t bytes) {

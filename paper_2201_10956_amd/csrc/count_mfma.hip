@@ -27,9 +27,16 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 constexpr int kPermKB = 16;  // k values per wave tile (4 row tiles x 4 triplets)
 constexpr int kPermT = 4;    // row tiles per wave tile
 
+// k-blocks are aligned to multiples of kPermKB for every pivot, so tiles of
+// different j share (i-block, k-block) pairs; block kb of pivot j is global
+// block perm_kb_lo(j) + kb and may start at or below j (those k are dropped).
+__host__ __device__ __forceinline__ int perm_kb_lo(int64_t j) { return (int)((j + 1) / kPermKB); }
+__host__ __device__ __forceinline__ int perm_nkb(int64_t M, int64_t j) {
+  return (int)((M - 1) / kPermKB) - perm_kb_lo(j) + 1;
+}
 __host__ __device__ __forceinline__ int64_t perm_tiles_of_j(int64_t M, int64_t j) {
   if (j < 1 || j > M - 2) return 0;
-  return ((j + 3) / 4) * ((M - 1 - j + kPermKB - 1) / kPermKB);
+  return ((j + 3) / 4) * perm_nkb(M, j);
 }
 
 __device__ __forceinline__ int64_t rfl64p(int64_t v) {
@@ -232,11 +239,11 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
       jlo = pre[j];
       jhi = pre[j + 1];
     }
-    const int nkb = (M - 1 - j + kPermKB - 1) / kPermKB;
+    const int nkb = perm_nkb(M, j);
     const int rr = (int)(t - jlo);
     const int ib = rr / nkb, kb = rr - ib * nkb;
     const int i = 4 * ib + wave;  // may be >= j (then the wave's results are dropped)
-    const int kbase = j + 1 + kb * kPermKB;
+    const int kbase = (perm_kb_lo(j) + kb) * kPermKB;  // k <= j or k >= M: dropped later
 
     // ---- staging plan: this thread's 16-byte chunks of one LDS buffer ----
     // rows [0, 64): phenotype q; [64, 96): (k, c) = k planes; [96, 112): pair rows.
@@ -343,8 +350,13 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
 }
 
 // Completes the tables of one pass of tiles and scores them.  Workgroup per
-// tile (persistent, round robin); wave w = pivot i = 4 ib + w; lane = (16 k x
-// 4 phenotypes), looping over 16 groups of 4 phenotypes.
+// tile (persistent, round robin); wave w = pivot i = 4 ib + w; lane =
+// phenotype q, looping over the tile's 16 k.  The all-sample table of each
+// triplet is wave-uniform (scalar loads, broadcast LDS reads); per-phenotype
+// corner cells and case pair tables are read as contiguous 1 KB rows.  Scores
+// are staged per wave in LDS and written as 64-byte runs of consecutive ranks.
+// (Visiting the tiles by (i-block, k-block) instead, so that one XCD's L2
+// serves a block pair's case tables to several pivots j, measured slower.)
 template <bool LDS>
 __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restrict__ pjp,
                                                           int64_t tile_begin, int64_t tile_end,
@@ -353,6 +365,7 @@ __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restr
                                                           int lf_len) {
   extern __shared__ float sLds[];
   __shared__ uint32_t sRange[64][2];
+  __shared__ float sScore[4][kPermKB][64];
   const float *sL = lf32;
   if (LDS) {
     for (int x = threadIdx.x; x < lf_len; x += blockDim.x) sLds[x] = lf32[x];
@@ -364,76 +377,98 @@ __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restr
   }
   __syncthreads();
   const PermJob pj = *pjp;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int kl = lane & 15, qs = lane >> 4;
+  const int q = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int M = pj.M, Mp = pj.Mp, Q = pj.Q, Qp = pj.Qp;
   const int64_t T = pj.T;
   cptr<int64_t> pre = as_const(pj.jprefix);
-  const int4 *tp = reinterpret_cast<const int4 *>(pj.tot_pairs);
+  typedef int i4v __attribute__((ext_vector_type(4)));
+  typedef unsigned u4v __attribute__((ext_vector_type(4)));
+  cptr<i4v> tp = as_const(reinterpret_cast<const i4v *>(pj.tot_pairs));
+  cptr<u4v> tot = as_const(reinterpret_cast<const u4v *>(pj.totals));
   const int4 *cp = reinterpret_cast<const int4 *>(pj.case_pairs);
-  int j = -1;
-  int64_t jlo = 0, jhi = 0;
+  const int qc = q < Q ? q : 0;  // lanes past Q compute on phenotype 0 and write nothing
+  const int n1 = pj.n1[qc];
+  uint32_t kmin = 0xffffffffu, kmax = 0u;
+  // pivot of tile t
+  auto pivot_of = [&](int64_t t) {
+    int lo = 0, hi = M - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (pre[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+  };
   for (int64_t t = tile_begin + blockIdx.x; t < tile_end; t += gridDim.x) {
-    if (j < 0 || t < jlo || t >= jhi) {
-      int lo = 0, hi = M - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (pre[mid] <= t) lo = mid; else hi = mid - 1;
-      }
-      j = lo;
-      jlo = pre[j];
-      jhi = pre[j + 1];
-    }
-    const int nkb = (M - 1 - j + kPermKB - 1) / kPermKB;
-    const int rr = (int)(t - jlo);
-    const int ib = rr / nkb, kb = rr - ib * nkb;
+    const int j = pivot_of(t);
+    const int64_t rr = t - pre[j];
+    const int ib = (int)(rr / perm_nkb(M, j)), kbg = perm_kb_lo(j) + (int)(rr % perm_nkb(M, j));
     const int i = 4 * ib + wave;
-    const int k = j + 1 + kb * kPermKB + kl;
+    const int k0 = kbg * kPermKB;
     if (i >= j) continue;  // wave-uniform
-    const int64_t slot = t - tile_begin;
-    const uint4 *cor = pj.corners + (slot * 4 + wave) * (int64_t)kPermKB * 64;
-    const uint4 tq = pj.totals[(slot * 4 + wave) * (int64_t)kPermKB + kl];
-    // all-sample table of triplet (i, j, k), shared by every phenotype
-    int ttab[27];
     {
-      const uint32_t tn[8] = {tq.x & 0xffffu, tq.x >> 16, tq.y & 0xffffu, tq.y >> 16,
-                              tq.z & 0xffffu, tq.z >> 16, tq.w & 0xffffu, tq.w >> 16};
-      const int4 a = tp[(int64_t)i * Mp + j], b = tp[(int64_t)i * Mp + k], c = tp[(int64_t)j * Mp + k];
-      const int4 ii4 = tp[(int64_t)i * Mp + i], jj4 = tp[(int64_t)j * Mp + j], kk4 = tp[(int64_t)k * Mp + k];
-      const int tij[4] = {a.x, a.y, a.z, a.w}, tik[4] = {b.x, b.y, b.z, b.w};
-      const int tjk[4] = {c.x, c.y, c.z, c.w};
-      const int mi[2] = {ii4.x, ii4.w}, mj[2] = {jj4.x, jj4.w}, mk[2] = {kk4.x, kk4.w};
-      complete_table(tn, tij, tik, tjk, mi, mj, mk, pj.N, ttab);
-    }
-    float tl[27];  // L[r + 1] per row (Eq. 1's first inner sum)
+      const int4 cii = cp[((int64_t)i * Mp + i) * Qp + qc];
+      const i4v tii = tp[(int64_t)i * Mp + i];
+      const int64_t slot = t - tile_begin;
+      const uint4 *cor = pj.corners + (slot * 4 + wave) * (int64_t)kPermKB * 64;
+      const int64_t tbase = (slot * 4 + wave) * (int64_t)kPermKB;
+      const i4v tij = tp[(int64_t)i * Mp + j], tjj = tp[(int64_t)j * Mp + j];
+      const int4 cij = cp[((int64_t)i * Mp + j) * Qp + qc];
+      const int4 cjj = cp[((int64_t)j * Mp + j) * Qp + qc];
+      const int kk_lo = j + 1 - k0 > 0 ? j + 1 - k0 : 0;
+      const int kk_hi = M - k0 < kPermKB ? M - k0 : kPermKB;
+      for (int kk = kk_lo; kk < kk_hi; ++kk) {
+        const int k = k0 + kk;
+        // all-sample table of (i, j, k), identical in every lane
+        int ttab[27];
+        {
+          const u4v tq = tot[tbase + kk];
+          const uint32_t tn[8] = {tq.x & 0xffffu, tq.x >> 16, tq.y & 0xffffu, tq.y >> 16,
+                                  tq.z & 0xffffu, tq.z >> 16, tq.w & 0xffffu, tq.w >> 16};
+          const i4v tik = tp[(int64_t)i * Mp + k], tjk = tp[(int64_t)j * Mp + k];
+          const i4v tkk = tp[(int64_t)k * Mp + k];
+          const int aij[4] = {tij.x, tij.y, tij.z, tij.w}, aik[4] = {tik.x, tik.y, tik.z, tik.w};
+          const int ajk[4] = {tjk.x, tjk.y, tjk.z, tjk.w};
+          const int mi[2] = {tii.x, tii.w}, mj[2] = {tjj.x, tjj.w}, mk[2] = {tkk.x, tkk.w};
+          complete_table(tn, aij, aik, ajk, mi, mj, mk, pj.N, ttab);
+        }
+        // case table of phenotype q
+        int ctab[27];
+        {
+          const uint4 cq = cor[kk * 64 + qc];
+          const uint32_t cn[8] = {cq.x & 0xffffu, cq.x >> 16, cq.y & 0xffffu, cq.y >> 16,
+                                  cq.z & 0xffffu, cq.z >> 16, cq.w & 0xffffu, cq.w >> 16};
+          const int4 cik = cp[((int64_t)i * Mp + k) * Qp + qc];
+          const int4 cjk = cp[((int64_t)j * Mp + k) * Qp + qc];
+          const int4 ckk = cp[((int64_t)k * Mp + k) * Qp + qc];
+          const int aij[4] = {cij.x, cij.y, cij.z, cij.w}, aik[4] = {cik.x, cik.y, cik.z, cik.w};
+          const int ajk[4] = {cjk.x, cjk.y, cjk.z, cjk.w};
+          const int mi[2] = {cii.x, cii.w}, mj[2] = {cjj.x, cjj.w}, mk[2] = {ckk.x, ckk.w};
+          complete_table(cn, aij, aik, ajk, mi, mj, mk, n1, ctab);
+        }
+        float k2 = 0.f;  // rows in order: L[r + 1] - (L[r_0] + L[r_1]), r_1 = cases
 #pragma unroll
-    for (int x = 0; x < 27; ++x) tl[x] = sL[ttab[x] + 1];
-    const int64_t rank = lex_base(M, i, j) + k;
-    for (int qg = 0; qg < 16; ++qg) {
-      const int q = 4 * qg + qs;
-      if (q >= Q || k >= M) continue;
-      const uint4 cq = cor[kl * 64 + q];
-      const uint32_t cn[8] = {cq.x & 0xffffu, cq.x >> 16, cq.y & 0xffffu, cq.y >> 16,
-                              cq.z & 0xffffu, cq.z >> 16, cq.w & 0xffffu, cq.w >> 16};
-      int ctab[27];
-      {
-        const int4 a = cp[((int64_t)i * Mp + j) * Qp + q], b = cp[((int64_t)i * Mp + k) * Qp + q];
-        const int4 c = cp[((int64_t)j * Mp + k) * Qp + q];
-        const int4 ii4 = cp[((int64_t)i * Mp + i) * Qp + q], jj4 = cp[((int64_t)j * Mp + j) * Qp + q];
-        const int4 kk4 = cp[((int64_t)k * Mp + k) * Qp + q];
-        const int cij[4] = {a.x, a.y, a.z, a.w}, cik[4] = {b.x, b.y, b.z, b.w};
-        const int cjk[4] = {c.x, c.y, c.z, c.w};
-        const int mi[2] = {ii4.x, ii4.w}, mj[2] = {jj4.x, jj4.w}, mk[2] = {kk4.x, kk4.w};
-        complete_table(cn, cij, cik, cjk, mi, mj, mk, pj.n1[q], ctab);
+        for (int x = 0; x < 27; ++x) k2 += sL[ttab[x] + 1] - (sL[ttab[x] - ctab[x]] + sL[ctab[x]]);
+        sScore[wave][kk][q] = k2;
+        const uint32_t key = f2key(k2);
+        kmin = key < kmin ? key : kmin;
+        kmax = key > kmax ? key : kmax;
       }
-      float k2 = 0.f;  // rows in order: L[r + 1] - (L[r_0] + L[r_1]), r_1 = cases
+      // scores of phenotype q at ranks base + k (this wave wrote them)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int64_t base = lex_base(M, i, j) + k0;
 #pragma unroll
-      for (int x = 0; x < 27; ++x) k2 += tl[x] - (sL[ttab[x] - ctab[x]] + sL[ctab[x]]);
-      pj.score[(int64_t)q * T + rank] = k2;
-      const uint32_t key = f2key(k2);
-      atomicMin(&sRange[q][0], key);
-      atomicMax(&sRange[q][1], key);
+      for (int e0 = 0; e0 < kPermKB * 64; e0 += 64) {
+        const int e = e0 + q, qq = e / kPermKB, kk = e % kPermKB;
+        if (qq < Q && kk >= kk_lo && kk < kk_hi) pj.score[(int64_t)qq * T + base + kk] = sScore[wave][kk][qq];
+      }
+      __builtin_amdgcn_wave_barrier();
     }
+  }
+  if (q < Q && kmax != 0u) {
+    atomicMin(&sRange[q][0], kmin);
+    atomicMax(&sRange[q][1], kmax);
   }
   __syncthreads();
   if (threadIdx.x < 64 && threadIdx.x < Q && sRange[threadIdx.x][1] != 0u) {

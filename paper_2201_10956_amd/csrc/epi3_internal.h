@@ -78,7 +78,10 @@ struct SelState {
   int64_t keff;            // min(k, T)
   int64_t T;
   int32_t k;
-  int32_t pad;
+  uint32_t whi;            // last key of the current window (set with lo)
+  float ub;                // compaction bound: last key of the first window + 2 e(N), as float
+  uint32_t cmode;          // 1 once the compaction pass ran
+  unsigned long long cn;   // keys <= ub found by the compaction pass
 };
 
 // One scored candidate.
@@ -131,6 +134,9 @@ struct SelJob {
   CandRec *rec;            // [cap]
   epi3_hit *hits;          // [k]
   int64_t cap;
+  uint32_t *ckey;          // [ccap] keys of the compacted low end of the plane
+  int64_t *crank;          // [ccap] their ranks
+  int64_t ccap;
   double err2;             // 2 e(N)
   // data needed to recount a candidate
   const uint32_t *planes;

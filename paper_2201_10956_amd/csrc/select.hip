@@ -5,7 +5,11 @@
 // Here, for k >= 1 and exactly:
 //   1. radix select over the FP32 score plane finds the k-th smallest FP32
 //      value T32 (3 passes of 2048 bins over a window that starts at the
-//      plane's key range);
+//      plane's key range); after the first pass, every score up to the end
+//      of the bin holding the k-th value plus 2 e(N) is compacted into a
+//      short list, and the later passes and the candidate collection read
+//      that list instead of the plane (the plane again if the list
+//      overflows its capacity);
 //   2. every triplet with K2_fp32 <= T32 + 2 e(N) is a candidate, where e(N)
 //      bounds |K2_fp32 - K2_fp64| for any table of N samples, so the candidate
 //      set contains every member of the FP64 top-k;
@@ -32,6 +36,10 @@ __global__ void init_select_kernel(SelJob *sj, int n) {
   st->thr = 0.f;
   st->overflow = 0u;
   st->ncand = 0ull;
+  st->whi = 0u;
+  st->ub = 0.f;
+  st->cmode = 0u;
+  st->cn = 0ull;
   st->T = sj[x].T;
   st->k = sj[x].k;
   st->keff = sj[x].k < sj[x].T ? sj[x].k : sj[x].T;
@@ -59,6 +67,11 @@ __global__ void window_kernel(SelJob *sj, int n) {
   st->shift = bl > 11 ? bl - 11 : 0;
 }
 
+// True when the compacted list holds every key the remaining passes need.
+__device__ __forceinline__ bool use_compact(const SelState *st, const SelJob &J) {
+  return st->cmode == 1u && st->cn <= (unsigned long long)J.ccap;
+}
+
 __global__ void __launch_bounds__(256) hist_kernel(const SelJob *__restrict__ sj) {
   const SelJob &J = sj[blockIdx.y];
   const SelState *st = J.st;
@@ -68,11 +81,12 @@ __global__ void __launch_bounds__(256) hist_kernel(const SelJob *__restrict__ sj
   __shared__ uint32_t h[kHistBins];
   for (int b = threadIdx.x; b < kHistBins; b += blockDim.x) h[b] = 0u;
   __syncthreads();
+  const bool compact = use_compact(st, J);
   const float *score = J.score;
-  const int64_t T = J.T;
-  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < T;
+  const int64_t n = compact ? (int64_t)st->cn : J.T;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
        x += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t key = f2key(score[x]);
+    const uint32_t key = compact ? J.ckey[x] : f2key(score[x]);
     if (key >= lo) {
       const uint32_t d = (key - lo) >> shift;
       if (d < (uint32_t)kHistBins) atomicAdd(&h[d], 1u);
@@ -110,7 +124,9 @@ __global__ void __launch_bounds__(1024) find_kernel(SelJob *sj) {
     const unsigned long long before = b ? cum[b - 1] : 0ull;
     if (before < krem && cum[b] >= krem) {  // exactly one bin satisfies this
       const uint32_t lo = lo0 + ((uint32_t)b << shift);
+      const uint32_t w = (1u << shift) - 1u;
       st->lo = lo;
+      st->whi = lo > 0xffffffffu - w ? 0xffffffffu : lo + w;
       st->krem = krem - before;
       if (shift == 0) {
         st->done = 1u;
@@ -136,26 +152,64 @@ __global__ void threshold_kernel(SelJob *sj, int n) {
   st->thr = f;
 }
 
-__global__ void __launch_bounds__(256) collect_kernel(const SelJob *__restrict__ sj) {
+// After the first pass: every score <= (last key of the window) + 2 e(N)
+// goes to the compacted list (key, rank).  That bound is at least the final
+// threshold, so the list holds every key the later passes and the candidate
+// collection look at.
+__global__ void __launch_bounds__(256) compact_kernel(const SelJob *__restrict__ sj) {
   const SelJob &J = sj[blockIdx.y];
   SelState *st = J.st;
-  if (st->done != 1u) return;
-  const float thr = st->thr;
+  if (st->done) return;
+  const double ubd = (double)key2f(st->whi) + J.err2;
+  float ub = (float)ubd;
+  if ((double)ub < ubd) ub = __uint_as_float(__float_as_uint(ub) + 1u);  // ub >= 0: next float up
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->ub = ub;
+    st->cmode = 1u;
+  }
   const float *score = J.score;
-  const int64_t T = J.T, cap = J.cap;
+  const int64_t T = J.T, ccap = J.ccap;
   const int lane = threadIdx.x & 63;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); base < T;
        base += stride) {
     const int64_t x = base + lane;
-    const bool pred = x < T && score[x] <= thr;
+    const float v = x < T ? score[x] : 0.f;
+    const bool pred = x < T && v <= ub;
+    const unsigned long long m = __ballot(pred);
+    if (m == 0ull) continue;
+    unsigned long long pos0 = 0;
+    if (lane == 0) pos0 = atomicAdd(&st->cn, (unsigned long long)__popcll(m));
+    pos0 = __shfl(pos0, 0);
+    const unsigned long long pos = pos0 + __popcll(m & ((1ull << lane) - 1ull));
+    if (pred && (int64_t)pos < ccap) {
+      J.ckey[pos] = f2key(v);
+      J.crank[pos] = x;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) collect_kernel(const SelJob *__restrict__ sj) {
+  const SelJob &J = sj[blockIdx.y];
+  SelState *st = J.st;
+  if (st->done != 1u) return;
+  const float thr = st->thr;
+  const bool compact = use_compact(st, J);
+  const float *score = J.score;
+  const int64_t n = compact ? (int64_t)st->cn : J.T, cap = J.cap;
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); base < n;
+       base += stride) {
+    const int64_t x = base + lane;
+    const bool pred = x < n && (compact ? key2f(J.ckey[x]) : score[x]) <= thr;
     const unsigned long long m = __ballot(pred);
     if (m == 0ull) continue;
     unsigned long long pos0 = 0;
     if (lane == 0) pos0 = atomicAdd(&st->ncand, (unsigned long long)__popcll(m));
     pos0 = __shfl(pos0, 0);
     const unsigned long long pos = pos0 + __popcll(m & ((1ull << lane) - 1ull));
-    if (pred && (int64_t)pos < cap) J.cand[pos] = x;
+    if (pred && (int64_t)pos < cap) J.cand[pos] = compact ? J.crank[x] : x;
   }
 }
 
@@ -362,6 +416,7 @@ hipError_t launch_select(SelJob *sel_dev, int32_t n_jobs, int64_t max_T, int64_t
   for (int p = 0; p < kHistPasses; ++p) {
     hipLaunchKernelGGL(hist_kernel, dim3((unsigned)hb, nj), dim3(256), 0, s, sel_dev);
     hipLaunchKernelGGL(find_kernel, dim3(nj), dim3(1024), 0, s, sel_dev);
+    if (p == 0) hipLaunchKernelGGL(compact_kernel, dim3((unsigned)hb, nj), dim3(256), 0, s, sel_dev);
   }
   hipLaunchKernelGGL(threshold_kernel, dim3((n_jobs + 63) / 64), dim3(64), 0, s, sel_dev, n_jobs);
   hipLaunchKernelGGL(collect_kernel, dim3((unsigned)hb, nj), dim3(256), 0, s, sel_dev);

@@ -92,6 +92,7 @@ def _load():
         "epi3_tile_rules_clear": (None, []),
         "epi3_tile_for": (i32, [P(CDataset), i32]),
         "epi3_set_pass_bytes": (ctypes.c_int, [i64]),
+        "epi3_set_compact_cap": (ctypes.c_int, [i64]),
         "epi3_perm_pvalue": (ctypes.c_int, [ctypes.c_double, vp, i32, P(ctypes.c_double)]),
     }
     for name, (res, args) in sigs.items():
@@ -107,7 +108,7 @@ EXPORTS = ("epi3_encode_bytes", "epi3_encode", "epi3_workspace_bytes", "epi3_sca
            "epi3_score_triplets", "epi3_score_plane", "epi3_k2_error_bound", "epi3_n_triplets", "epi3_release",
            "epi3_version", "epi3_timing_enable", "epi3_timing_query", "epi3_timing_reset",
            "epi3_tile_rule", "epi3_tile_rules_clear", "epi3_tile_for", "epi3_set_pass_bytes",
-           "epi3_perm_pvalue")
+           "epi3_perm_pvalue", "epi3_set_compact_cap")
 TILES_PATH = os.path.join(_HERE, "tiles.json")
 
 
@@ -178,6 +179,11 @@ def tile_for(ds: "Dataset", variant: str):
 def set_pass_bytes(nbytes: int) -> None:
     """Scratch bytes per pass buffer of the matrix-core paths (0: default)."""
     _check(_lib.epi3_set_pass_bytes(int(nbytes)), "epi3_set_pass_bytes")
+
+
+def set_compact_cap(n: int) -> None:
+    """Entries the selection keeps after its first pass (0: default)."""
+    _check(_lib.epi3_set_compact_cap(int(n)), "epi3_set_compact_cap")
 
 
 def load_tiles(path: str = TILES_PATH) -> int:

@@ -173,3 +173,16 @@ def test_perm_pvalue(epi3):
         epi3.perm_pvalue(1.0, [])
     with pytest.raises(epi3.Epi3Error):
         epi3.perm_pvalue(float("nan"), [1.0])
+
+
+def test_compact_cap_sizes_the_workspace(epi3):
+    lib = epi3._lib
+    d = _fake_dataset(epi3, 300, 700, 900)
+    try:
+        a = lib.epi3_workspace_bytes(ctypes.byref(d), 10, epi3.VARIANT_VALU, 0)
+        epi3.set_compact_cap(1 << 20)
+        b = lib.epi3_workspace_bytes(ctypes.byref(d), 10, epi3.VARIANT_VALU, 0)
+        assert b - a >= 12 * ((1 << 20) - 65536)
+        assert lib.epi3_set_compact_cap(-1) == epi3.E_INVALID
+    finally:
+        epi3.set_compact_cap(0)

@@ -173,3 +173,21 @@ def test_permutations_large_sample_count(env, variant):
     for q in range(3):
         ijk, k2, cc = oracle.scan_topk(d.geno, perms[q], 5)
         assert_hits_equal_oracle(res[q], ijk, k2, cc)
+
+
+@pytest.mark.parametrize("variant", ["mfma", "mfma_fp4"])
+def test_permutations_small_passes(env, variant):
+    """Passes of 3 tiles: pass boundaries cut pivots' tile runs, both scratch
+    buffers alternate many times; hits still equal the oracle's."""
+    torch, epi3 = env
+    d = make_dataset(45, 400, 0.4, 0.05, seed=41)
+    perms = make_permutations(d.pheno, 5, seed=42)
+    ds = epi3.encode(to_dev(d.geno), d.pheno, layout="masked")
+    try:
+        epi3.set_pass_bytes(3 * (64 * 64 * 16 + 64 * 16))
+        res = epi3.BatchScanner(ds, 8, masks=_masks(epi3, perms), variant=variant).run()
+    finally:
+        epi3.set_pass_bytes(0)
+    for q in range(5):
+        ijk, k2, cc = oracle.scan_topk(d.geno, perms[q], 8)
+        assert_hits_equal_oracle(res[q], ijk, k2, cc)

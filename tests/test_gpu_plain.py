@@ -196,3 +196,19 @@ def test_cfg3_full_size(env):
     cc, kf, kd = epi3.score_triplets(ds, lex)
     np.testing.assert_array_equal(cc.cpu().numpy(), rc)
     np.testing.assert_array_equal(kf.cpu().numpy(), got)
+
+
+@pytest.mark.parametrize("ccap", [1, 3, 40])
+def test_compaction_overflow_falls_back_to_plane(env, ccap):
+    """A compaction capacity too small for the low end of the plane: the later
+    selection passes read the whole plane again and the hits stay exact."""
+    torch, epi3 = env
+    d = make_config(1)
+    ds = epi3.encode(to_dev(d.geno), d.pheno)
+    try:
+        epi3.set_compact_cap(ccap)
+        h = epi3.scan_topk(ds, 10, "valu")
+    finally:
+        epi3.set_compact_cap(0)
+    ijk, k2, cc = oracle.scan_topk(d.geno, d.pheno, 10)
+    assert_hits_equal_oracle(h, ijk, k2, cc)
