@@ -513,7 +513,7 @@ static int enqueue_count_mfma(const epi3_dataset &d, bool fp4, float *score, uin
     HIP_OK(hipEventRecord(ev_cnt[b], s));
     HIP_OK(hipStreamWaitEvent(s2, ev_cnt[b], 0));
     rc = timed(3, s2, [&]() {
-      return launch_finish_plain(W.pjob + b, JB, t0, t1, d.lf32, d.n_samples + 2, s2) == hipSuccess
+      return launch_finish_plain(W.pjob + b, JB, t0, t1, d.lf32, d.n_samples + 2, counts != nullptr, s2) == hipSuccess
                  ? EPI3_OK
                  : EPI3_E_HIP;
     });

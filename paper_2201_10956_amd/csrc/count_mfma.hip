@@ -45,9 +45,20 @@ __device__ __forceinline__ int64_t rfl64p(int64_t v) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-__device__ __forceinline__ uint32_t popc4(v4i x) {
-  return __builtin_popcount((uint32_t)x.x) + __builtin_popcount((uint32_t)x.y) +
-         __builtin_popcount((uint32_t)x.z) + __builtin_popcount((uint32_t)x.w);
+// acc + popcount(x) as one v_bcnt_u32_b32 (the compiler would otherwise
+// reassociate chains of counts into v_bcnt(x, 0) plus v_add3).
+__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
+  uint32_t r;
+  asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+  return r;
+}
+
+// acc + popcounts of the four words of x.
+__device__ __forceinline__ uint32_t popc4_acc(v4i x, uint32_t acc) {
+  acc = bcnt_acc((uint32_t)x.x, acc);
+  acc = bcnt_acc((uint32_t)x.y, acc);
+  acc = bcnt_acc((uint32_t)x.z, acc);
+  return bcnt_acc((uint32_t)x.w, acc);
 }
 
 // jprefix for the permutation tiles (one block).
@@ -144,11 +155,14 @@ __global__ void __launch_bounds__(256) case_pairs_kernel(const uint32_t *__restr
     }
   }
   if (y >= Mp) return;
+  // stored as 4 x the counts: the finish kernel uses them as byte offsets
+  // into the FP32 log-factorial table
   int4 *o = reinterpret_cast<int4 *>(out) + ((int64_t)x * Mp + y) * Qp;
 #pragma unroll
   for (int t = 0; t < 16; ++t)
     if (q0 + t < Qp)
-      o[q0 + t] = make_int4((int)acc[t][0], (int)acc[t][1], (int)acc[t][2], (int)acc[t][3]);
+      o[q0 + t] = make_int4((int)acc[t][0] << 2, (int)acc[t][1] << 2, (int)acc[t][2] << 2,
+                            (int)acc[t][3] << 2);
 }
 
 __device__ __forceinline__ void load_pair(const int32_t *p, int64_t idx, int v[4]) {
@@ -311,7 +325,7 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
         for (int tt = 0; tt < kPermT; ++tt) {
           const int xrow = kRowsPH + (4 * tt + ta) * 2 + rc;
           const v4i a = p & *reinterpret_cast<const v4i *>(buf + xrow * kRow + off);
-          tot[tt] += popc4(a);
+          tot[tt] = popc4_acc(a, tot[tt]);
           acc[tt][0] = Acc::mma(a, b0, acc[tt][0]);
           acc[tt][1] = Acc::mma(a, b1, acc[tt][1]);
         }
@@ -350,30 +364,47 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
 }
 
 // Completes the tables of one pass of tiles and scores them.  Workgroup per
-// tile (persistent, round robin); wave w = pivot i = 4 ib + w; lane =
-// phenotype q, looping over the tile's 16 k.  The all-sample table of each
-// triplet is wave-uniform (scalar loads, broadcast LDS reads); per-phenotype
-// corner cells and case pair tables are read as contiguous 1 KB rows.  Scores
-// are staged per wave in LDS and written as 64-byte runs of consecutive ranks.
-// (Visiting the tiles by (i-block, k-block) instead, so that one XCD's L2
-// serves a block pair's case tables to several pivots j, measured slower.)
+// tile (persistent, round robin); wave w = pivot i = 4 ib + w.  First the
+// wave's lanes 0..15 complete the all-sample tables of the tile's 16 triplets
+// (one k each) and leave 4 x cell and L[cell + 1] per cell in LDS; then
+// lane = phenotype q loops over the 16 k, reading those as broadcasts, and
+// completes and scores its case table.  Case cells are handled as 4 x count
+// (byte offsets into the table), so each lookup needs no index arithmetic.
+// Per-phenotype corner cells and case pair tables are contiguous 1 KB rows;
+// scores are staged per wave in LDS and written as 64-byte runs of
+// consecutive ranks.  (Visiting the tiles by (i-block, k-block) instead, so
+// that one XCD's L2 serves a block pair's case tables to several pivots j,
+// measured slower.)
+// Dynamic LDS of the finish kernel: [log-factorial table (LDS variant)] then
+// the per-wave all-sample cells, staged scores and key ranges.  The kernel
+// declares no static LDS, so the dynamic block and with it the table start at
+// LDS address 0 and a lookup is one ds_read at the byte offset.
+struct FinishPermLds {
+  uint2 tt[4][kPermKB][27];  // (4 x all-sample cell, bits of L[cell + 1])
+  float score[4][kPermKB][64];
+  uint32_t range[64][2];
+};
+__host__ __device__ __forceinline__ int finish_perm_table_bytes(int lf_len) {
+  return (lf_len * 4 + 15) / 16 * 16;
+}
+
 template <bool LDS>
 __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restrict__ pjp,
                                                           int64_t tile_begin, int64_t tile_end,
                                                           SelState *__restrict__ st,
                                                           const float *__restrict__ lf32,
                                                           int lf_len) {
-  extern __shared__ float sLds[];
-  __shared__ uint32_t sRange[64][2];
-  __shared__ float sScore[4][kPermKB][64];
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   const float *sL = lf32;
+  FinishPermLds &sh = *reinterpret_cast<FinishPermLds *>(lds + (LDS ? finish_perm_table_bytes(lf_len) : 0));
   if (LDS) {
-    for (int x = threadIdx.x; x < lf_len; x += blockDim.x) sLds[x] = lf32[x];
-    sL = sLds;
+    float *tab = reinterpret_cast<float *>(lds);
+    for (int x = threadIdx.x; x < lf_len; x += blockDim.x) tab[x] = lf32[x];
+    sL = tab;
   }
   if (threadIdx.x < 64) {
-    sRange[threadIdx.x][0] = 0xffffffffu;
-    sRange[threadIdx.x][1] = 0u;
+    sh.range[threadIdx.x][0] = 0xffffffffu;
+    sh.range[threadIdx.x][1] = 0u;
   }
   __syncthreads();
   const PermJob pj = *pjp;
@@ -381,13 +412,13 @@ __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restr
   const int M = pj.M, Mp = pj.Mp, Q = pj.Q, Qp = pj.Qp;
   const int64_t T = pj.T;
   cptr<int64_t> pre = as_const(pj.jprefix);
-  typedef int i4v __attribute__((ext_vector_type(4)));
-  typedef unsigned u4v __attribute__((ext_vector_type(4)));
-  cptr<i4v> tp = as_const(reinterpret_cast<const i4v *>(pj.tot_pairs));
-  cptr<u4v> tot = as_const(reinterpret_cast<const u4v *>(pj.totals));
-  const int4 *cp = reinterpret_cast<const int4 *>(pj.case_pairs);
+  const int4 *tp = reinterpret_cast<const int4 *>(pj.tot_pairs);
+  typedef int i4e __attribute__((ext_vector_type(4)));
+  typedef unsigned u4e __attribute__((ext_vector_type(4)));
+  gptr<i4e> cp = (gptr<i4e>)pj.case_pairs;
+  gptr<u4e> corners = (gptr<u4e>)pj.corners;
   const int qc = q < Q ? q : 0;  // lanes past Q compute on phenotype 0 and write nothing
-  const int n1 = pj.n1[qc];
+  const int n1x4 = pj.n1[qc] << 2;
   uint32_t kmin = 0xffffffffu, kmax = 0u;
   // pivot of tile t
   auto pivot_of = [&](int64_t t) {
@@ -398,6 +429,8 @@ __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restr
     }
     return lo;
   };
+  // row of phenotype-major case pair tables for pair (x, y) (uniform)
+  auto cp_row = [&](int x, int y) { return cp + ((int64_t)x * Mp + y) * Qp; };
   for (int64_t t = tile_begin + blockIdx.x; t < tile_end; t += gridDim.x) {
     const int j = pivot_of(t);
     const int64_t rr = t - pre[j];
@@ -405,75 +438,98 @@ __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restr
     const int i = 4 * ib + wave;
     const int k0 = kbg * kPermKB;
     if (i >= j) continue;  // wave-uniform
-    {
-      const int4 cii = cp[((int64_t)i * Mp + i) * Qp + qc];
-      const i4v tii = tp[(int64_t)i * Mp + i];
-      const int64_t slot = t - tile_begin;
-      const uint4 *cor = pj.corners + (slot * 4 + wave) * (int64_t)kPermKB * 64;
-      const int64_t tbase = (slot * 4 + wave) * (int64_t)kPermKB;
-      const i4v tij = tp[(int64_t)i * Mp + j], tjj = tp[(int64_t)j * Mp + j];
-      const int4 cij = cp[((int64_t)i * Mp + j) * Qp + qc];
-      const int4 cjj = cp[((int64_t)j * Mp + j) * Qp + qc];
-      const int kk_lo = j + 1 - k0 > 0 ? j + 1 - k0 : 0;
-      const int kk_hi = M - k0 < kPermKB ? M - k0 : kPermKB;
-      for (int kk = kk_lo; kk < kk_hi; ++kk) {
-        const int k = k0 + kk;
-        // all-sample table of (i, j, k), identical in every lane
-        int ttab[27];
-        {
-          const u4v tq = tot[tbase + kk];
-          const uint32_t tn[8] = {tq.x & 0xffffu, tq.x >> 16, tq.y & 0xffffu, tq.y >> 16,
-                                  tq.z & 0xffffu, tq.z >> 16, tq.w & 0xffffu, tq.w >> 16};
-          const i4v tik = tp[(int64_t)i * Mp + k], tjk = tp[(int64_t)j * Mp + k];
-          const i4v tkk = tp[(int64_t)k * Mp + k];
-          const int aij[4] = {tij.x, tij.y, tij.z, tij.w}, aik[4] = {tik.x, tik.y, tik.z, tik.w};
-          const int ajk[4] = {tjk.x, tjk.y, tjk.z, tjk.w};
-          const int mi[2] = {tii.x, tii.w}, mj[2] = {tjj.x, tjj.w}, mk[2] = {tkk.x, tkk.w};
-          complete_table(tn, aij, aik, ajk, mi, mj, mk, pj.N, ttab);
-        }
-        // case table of phenotype q
-        int ctab[27];
-        {
-          const uint4 cq = cor[kk * 64 + qc];
-          const uint32_t cn[8] = {cq.x & 0xffffu, cq.x >> 16, cq.y & 0xffffu, cq.y >> 16,
-                                  cq.z & 0xffffu, cq.z >> 16, cq.w & 0xffffu, cq.w >> 16};
-          const int4 cik = cp[((int64_t)i * Mp + k) * Qp + qc];
-          const int4 cjk = cp[((int64_t)j * Mp + k) * Qp + qc];
-          const int4 ckk = cp[((int64_t)k * Mp + k) * Qp + qc];
-          const int aij[4] = {cij.x, cij.y, cij.z, cij.w}, aik[4] = {cik.x, cik.y, cik.z, cik.w};
-          const int ajk[4] = {cjk.x, cjk.y, cjk.z, cjk.w};
-          const int mi[2] = {cii.x, cii.w}, mj[2] = {cjj.x, cjj.w}, mk[2] = {ckk.x, ckk.w};
-          complete_table(cn, aij, aik, ajk, mi, mj, mk, n1, ctab);
-        }
-        float k2 = 0.f;  // rows in order: L[r + 1] - (L[r_0] + L[r_1]), r_1 = cases
+    const int64_t slot = t - tile_begin;
+    gptr<u4e> cor = corners + (slot * 4 + wave) * (int64_t)kPermKB * 64;
+    const int64_t tbase = (slot * 4 + wave) * (int64_t)kPermKB;
+    const int kk_lo = j + 1 - k0 > 0 ? j + 1 - k0 : 0;
+    const int kk_hi = M - k0 < kPermKB ? M - k0 : kPermKB;
+    // ---- all-sample tables, lane kk = triplet (i, j, k0 + kk) ----
+    if (q >= kk_lo && q < kk_hi) {
+      const int k = k0 + q;
+      const uint4 tq = pj.totals[tbase + q];
+      const uint32_t tn[8] = {(tq.x & 0xffffu) << 2, (tq.x >> 16) << 2, (tq.y & 0xffffu) << 2,
+                              (tq.y >> 16) << 2, (tq.z & 0xffffu) << 2, (tq.z >> 16) << 2,
+                              (tq.w & 0xffffu) << 2, (tq.w >> 16) << 2};
+      const int4 a = tp[(int64_t)i * Mp + j], b = tp[(int64_t)i * Mp + k], c = tp[(int64_t)j * Mp + k];
+      const int4 ii4 = tp[(int64_t)i * Mp + i], jj4 = tp[(int64_t)j * Mp + j], kk4 = tp[(int64_t)k * Mp + k];
+      const int tij[4] = {a.x << 2, a.y << 2, a.z << 2, a.w << 2};
+      const int tik[4] = {b.x << 2, b.y << 2, b.z << 2, b.w << 2};
+      const int tjk[4] = {c.x << 2, c.y << 2, c.z << 2, c.w << 2};
+      const int mi[2] = {ii4.x << 2, ii4.w << 2}, mj[2] = {jj4.x << 2, jj4.w << 2};
+      const int mk[2] = {kk4.x << 2, kk4.w << 2};
+      int t4[27];
+      complete_table(tn, tij, tik, tjk, mi, mj, mk, pj.N << 2, t4);
 #pragma unroll
-        for (int x = 0; x < 27; ++x) k2 += sL[ttab[x] + 1] - (sL[ttab[x] - ctab[x]] + sL[ctab[x]]);
-        sScore[wave][kk][q] = k2;
-        const uint32_t key = f2key(k2);
-        kmin = key < kmin ? key : kmin;
-        kmax = key > kmax ? key : kmax;
-      }
-      // scores of phenotype q at ranks base + k (this wave wrote them)
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const int64_t base = lex_base(M, i, j) + k0;
-#pragma unroll
-      for (int e0 = 0; e0 < kPermKB * 64; e0 += 64) {
-        const int e = e0 + q, qq = e / kPermKB, kk = e % kPermKB;
-        if (qq < Q && kk >= kk_lo && kk < kk_hi) pj.score[(int64_t)qq * T + base + kk] = sScore[wave][kk][qq];
-      }
-      __builtin_amdgcn_wave_barrier();
+      for (int x = 0; x < 27; ++x)
+        sh.tt[wave][q][x] = make_uint2(
+            (uint32_t)t4[x], __float_as_uint(LDS ? lf_at_lds0(t4[x] + 4) : lf_at(sL, t4[x] + 4)));
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // ---- case tables and scores, lane = phenotype q ----
+    const i4e cij = cp_row(i, j)[qc];
+    const i4e cii = cp_row(i, i)[qc], cjj = cp_row(j, j)[qc];
+    // loads of the next k are issued before the current k is scored
+    u4e cq_n = cor[kk_lo * 64 + qc];
+    i4e cik_n = cp_row(i, k0 + kk_lo)[qc], cjk_n = cp_row(j, k0 + kk_lo)[qc];
+    i4e ckk_n = cp_row(k0 + kk_lo, k0 + kk_lo)[qc];
+    for (int kk = kk_lo; kk < kk_hi; ++kk) {
+      const u4e cq = cq_n;
+      const i4e cik = cik_n, cjk = cjk_n, ckk = ckk_n;
+      if (kk + 1 < kk_hi) {
+        const int kn = k0 + kk + 1;
+        cq_n = cor[(kk + 1) * 64 + qc];
+        cik_n = cp_row(i, kn)[qc];
+        cjk_n = cp_row(j, kn)[qc];
+        ckk_n = cp_row(kn, kn)[qc];
+      }
+      int c4[27];
+      {
+        const uint32_t cn[8] = {(cq.x << 2) & 0x3fffcu, (cq.x >> 14) & 0x3fffcu,
+                                (cq.y << 2) & 0x3fffcu, (cq.y >> 14) & 0x3fffcu,
+                                (cq.z << 2) & 0x3fffcu, (cq.z >> 14) & 0x3fffcu,
+                                (cq.w << 2) & 0x3fffcu, (cq.w >> 14) & 0x3fffcu};
+        const int aij[4] = {cij.x, cij.y, cij.z, cij.w}, aik[4] = {cik.x, cik.y, cik.z, cik.w};
+        const int ajk[4] = {cjk.x, cjk.y, cjk.z, cjk.w};
+        const int mi[2] = {cii.x, cii.w}, mj[2] = {cjj.x, cjj.w}, mk[2] = {ckk.x, ckk.w};
+        complete_table(cn, aij, aik, ajk, mi, mj, mk, n1x4, c4);
+      }
+      float k2 = 0.f;  // rows in order: L[r + 1] - (L[r_0] + L[r_1]), r_1 = cases
+#pragma unroll
+      for (int x = 0; x < 27; ++x) {
+        const uint2 tt = sh.tt[wave][kk][x];
+        const int r0 = (int)tt.x - c4[x];
+        if (LDS)
+          k2 += __uint_as_float(tt.y) - (lf_at_lds0(r0) + lf_at_lds0(c4[x]));
+        else
+          k2 += __uint_as_float(tt.y) - (lf_at(sL, r0) + lf_at(sL, c4[x]));
+      }
+      sh.score[wave][kk][q] = k2;
+      const uint32_t key = f2key(k2);
+      kmin = key < kmin ? key : kmin;
+      kmax = key > kmax ? key : kmax;
+    }
+    // scores of phenotype q at ranks base + k (this wave wrote them)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int64_t base = lex_base(M, i, j) + k0;
+#pragma unroll
+    for (int e0 = 0; e0 < kPermKB * 64; e0 += 64) {
+      const int e = e0 + q, qq = e / kPermKB, kk = e % kPermKB;
+      if (qq < Q && kk >= kk_lo && kk < kk_hi) pj.score[(int64_t)qq * T + base + kk] = sh.score[wave][kk][qq];
+    }
+    __builtin_amdgcn_wave_barrier();
   }
   if (q < Q && kmax != 0u) {
-    atomicMin(&sRange[q][0], kmin);
-    atomicMax(&sRange[q][1], kmax);
+    atomicMin(&sh.range[q][0], kmin);
+    atomicMax(&sh.range[q][1], kmax);
   }
   __syncthreads();
-  if (threadIdx.x < 64 && threadIdx.x < Q && sRange[threadIdx.x][1] != 0u) {
-    atomicMin(&st[threadIdx.x].kmin, sRange[threadIdx.x][0]);
-    atomicMax(&st[threadIdx.x].kmax, sRange[threadIdx.x][1]);
+  if (threadIdx.x < 64 && threadIdx.x < Q && sh.range[threadIdx.x][1] != 0u) {
+    atomicMin(&st[threadIdx.x].kmin, sh.range[threadIdx.x][0]);
+    atomicMax(&st[threadIdx.x].kmax, sh.range[threadIdx.x][1]);
   }
 }
 
@@ -566,7 +622,7 @@ static hipError_t launch_finish_perm_l(const PermJob *pj_dev, int64_t tile_begin
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  const size_t lds = LDS ? (size_t)lf_len * sizeof(float) : 0;
+  const size_t lds = (LDS ? (size_t)finish_perm_table_bytes(lf_len) : 0) + sizeof(FinishPermLds);
   e = hipFuncSetAttribute(reinterpret_cast<const void *>(&finish_perm_kernel<LDS>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;

@@ -269,20 +269,22 @@ __global__ void __launch_bounds__(256, 2) count_mfma_plain_kernel(
 }
 
 // Completes both tables of every triplet of a pass and scores it; workgroup
-// per tile (persistent, round robin), thread per triplet of the tile.
-template <int JB, bool LDS>
+// per tile (persistent, round robin), thread per triplet of the tile.  Cells
+// are carried as 4 x count (byte offsets into the FP32 log-factorial table,
+// which sits at LDS address 0: the kernel declares no static LDS), so each
+// of the 81 lookups per triplet needs at most one add.
+template <int JB, bool LDS, bool COUNTS>
 __global__ void __launch_bounds__(256) finish_plain_kernel(const PlainJob *__restrict__ pjp,
                                                            int64_t tile_begin, int64_t tile_end,
                                                            const float *__restrict__ lf32,
                                                            int lf_len) {
   constexpr int KT = 256 / JB;
   constexpr int kTile = kPI * JB * KT;  // 4096 triplets
-  extern __shared__ float sLds[];
-  __shared__ uint32_t sRange[2];
-  const float *sL = lf32;
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  uint32_t *sRange = reinterpret_cast<uint32_t *>(lds + (LDS ? (lf_len * 4 + 15) / 16 * 16 : 0));
   if (LDS) {
-    for (int x = threadIdx.x; x < lf_len; x += blockDim.x) sLds[x] = lf32[x];
-    sL = sLds;
+    float *tab = reinterpret_cast<float *>(lds);
+    for (int x = threadIdx.x; x < lf_len; x += blockDim.x) tab[x] = lf32[x];
   }
   if (threadIdx.x == 0) {
     sRange[0] = 0xffffffffu;
@@ -293,8 +295,11 @@ __global__ void __launch_bounds__(256) finish_plain_kernel(const PlainJob *__res
   const int M = pj.M, Mp = pj.Mp;
   const int nJ = (int)plain_jblocks(M, JB);
   cptr<int64_t> pre = as_const(pj.jprefix);
-  const int4 *pr = reinterpret_cast<const int4 *>(pj.pairs);
-  const int64_t MpMp = (int64_t)Mp * Mp;
+  typedef int i4e __attribute__((ext_vector_type(4)));
+  typedef unsigned u4e __attribute__((ext_vector_type(4)));
+  gptr<i4e> pr = (gptr<i4e>)pj.pairs;
+  const uint32_t MpMp = (uint32_t)Mp * (uint32_t)Mp;  // pair tables < 4 G entries
+  const int N0x4 = pj.N0 << 2, N1x4 = pj.N1 << 2;
   uint32_t kmin = 0xffffffffu, kmax = 0u;
   TileDecoder dec;
   for (int64_t t = tile_begin + blockIdx.x; t < tile_end; t += gridDim.x) {
@@ -302,7 +307,7 @@ __global__ void __launch_bounds__(256) finish_plain_kernel(const PlainJob *__res
     int i0, j0, k0;
     plain_tile_origin(dec, t, M, JB, i0, j0, k0);
     const int64_t slot = t - tile_begin;
-    const uint4 *cor = pj.corners + slot * 2 * (int64_t)kTile;
+    gptr<u4e> cor = (gptr<u4e>)(pj.corners + slot * 2 * (int64_t)kTile);
     for (int x = threadIdx.x; x < kTile; x += blockDim.x) {
       const int il = x / (JB * KT), jl = (x / KT) % JB, kl = x % KT;
       const int i = i0 + il, j = j0 + jl, k = k0 + kl;
@@ -310,32 +315,40 @@ __global__ void __launch_bounds__(256) finish_plain_kernel(const PlainJob *__res
       int tab[2][27];
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        const uint4 q = cor[(int64_t)c * kTile + x];
-        // record order: [plane of k][a][b] -> corner index 4 a + 2 b + plane
-        const uint32_t n[8] = {q.x & 0xffffu, q.z & 0xffffu, q.x >> 16, q.z >> 16,
-                               q.y & 0xffffu, q.w & 0xffffu, q.y >> 16, q.w >> 16};
-        const int4 a4 = pr[c * MpMp + (int64_t)i * Mp + j], b4 = pr[c * MpMp + (int64_t)i * Mp + k];
-        const int4 c4 = pr[c * MpMp + (int64_t)j * Mp + k];
-        const int4 ii = pr[c * MpMp + (int64_t)i * Mp + i], jj = pr[c * MpMp + (int64_t)j * Mp + j];
-        const int4 kk = pr[c * MpMp + (int64_t)k * Mp + k];
-        const int pij[4] = {a4.x, a4.y, a4.z, a4.w}, pik[4] = {b4.x, b4.y, b4.z, b4.w};
-        const int pjk[4] = {c4.x, c4.y, c4.z, c4.w};
-        const int mi[2] = {ii.x, ii.w}, mj[2] = {jj.x, jj.w}, mk[2] = {kk.x, kk.w};
-        complete_table(n, pij, pik, pjk, mi, mj, mk, c ? pj.N1 : pj.N0, tab[c]);
+        const u4e q = cor[c * kTile + x];
+        // record order: [plane of k][a][b] -> corner index 4 a + 2 b + plane; x 4
+        const uint32_t n[8] = {(q.x << 2) & 0x3fffcu, (q.z << 2) & 0x3fffcu,
+                               (q.x >> 14) & 0x3fffcu, (q.z >> 14) & 0x3fffcu,
+                               (q.y << 2) & 0x3fffcu, (q.w << 2) & 0x3fffcu,
+                               (q.y >> 14) & 0x3fffcu, (q.w >> 14) & 0x3fffcu};
+        const uint32_t cb = (uint32_t)c * MpMp;
+        const i4e a4 = pr[cb + (uint32_t)i * Mp + j], b4 = pr[cb + (uint32_t)i * Mp + k];
+        const i4e c4 = pr[cb + (uint32_t)j * Mp + k];
+        const i4e ii = pr[cb + (uint32_t)i * Mp + i], jj = pr[cb + (uint32_t)j * Mp + j];
+        const i4e kk = pr[cb + (uint32_t)k * Mp + k];
+        const int pij[4] = {a4.x << 2, a4.y << 2, a4.z << 2, a4.w << 2};
+        const int pik[4] = {b4.x << 2, b4.y << 2, b4.z << 2, b4.w << 2};
+        const int pjk[4] = {c4.x << 2, c4.y << 2, c4.z << 2, c4.w << 2};
+        const int mi[2] = {ii.x << 2, ii.w << 2}, mj[2] = {jj.x << 2, jj.w << 2};
+        const int mk[2] = {kk.x << 2, kk.w << 2};
+        complete_table(n, pij, pik, pjk, mi, mj, mk, c ? N1x4 : N0x4, tab[c]);
       }
       float k2 = 0.f;  // rows in order, each L[r + 1] - (L[r_0] + L[r_1])
 #pragma unroll
       for (int x2 = 0; x2 < 27; ++x2) {
-        const int r0 = tab[0][x2], r1 = tab[1][x2];
-        k2 += sL[r0 + r1 + 1] - (sL[r0] + sL[r1]);
+        const int b0 = tab[0][x2], b1 = tab[1][x2];
+        if (LDS)
+          k2 += lf_at_lds0(b0 + b1 + 4) - (lf_at_lds0(b0) + lf_at_lds0(b1));
+        else
+          k2 += lf_at(lf32, b0 + b1 + 4) - (lf_at(lf32, b0) + lf_at(lf32, b1));
       }
       const int64_t rank = lex_base(M, i, j) + k;
       pj.score[rank] = k2;
-      if (pj.counts) {
+      if (COUNTS) {
         uint32_t *o = pj.counts + rank * 54;
         for (int x2 = 0; x2 < 27; ++x2) {
-          o[x2] = (uint32_t)tab[0][x2];
-          o[27 + x2] = (uint32_t)tab[1][x2];
+          o[x2] = (uint32_t)tab[0][x2] >> 2;
+          o[27 + x2] = (uint32_t)tab[1][x2] >> 2;
         }
       }
       const uint32_t key = f2key(k2);
@@ -417,7 +430,7 @@ hipError_t launch_count_mfma_plain(const PlainJob *pj_dev, int JB, bool fp4, int
   return hipErrorInvalidValue;
 }
 
-template <int JB, bool LDS>
+template <int JB, bool LDS, bool COUNTS>
 static hipError_t launch_finish_plain_t(const PlainJob *pj_dev, int64_t tile_begin,
                                         int64_t tile_end, const float *lf32, int32_t lf_len,
                                         hipStream_t s) {
@@ -426,37 +439,42 @@ static hipError_t launch_finish_plain_t(const PlainJob *pj_dev, int64_t tile_beg
   int n_cu = 0;
   hipError_t e = cu_count(&n_cu);
   if (e != hipSuccess) return e;
-  const size_t lds = LDS ? (size_t)lf_len * sizeof(float) : 0;
-  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&finish_plain_kernel<JB, LDS>),
+  const size_t lds = (LDS ? (size_t)(lf_len * 4 + 15) / 16 * 16 : 0) + 16;  // table + key range
+  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&finish_plain_kernel<JB, LDS, COUNTS>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, finish_plain_kernel<JB, LDS>, 256, lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, finish_plain_kernel<JB, LDS, COUNTS>,
+                                                   256, lds);
   if (e != hipSuccess) return e;
   if (per_cu <= 0) per_cu = 1;
   int64_t blocks = (int64_t)n_cu * per_cu;
   if (blocks > n) blocks = n;
-  hipLaunchKernelGGL((finish_plain_kernel<JB, LDS>), dim3((unsigned)blocks), dim3(256), lds, s,
-                     pj_dev, tile_begin, tile_end, lf32, lf_len);
+  hipLaunchKernelGGL((finish_plain_kernel<JB, LDS, COUNTS>), dim3((unsigned)blocks), dim3(256), lds,
+                     s, pj_dev, tile_begin, tile_end, lf32, lf_len);
   return hipGetLastError();
 }
 
 template <int JB>
 static hipError_t launch_finish_plain_j(const PlainJob *pj_dev, int64_t tile_begin,
                                         int64_t tile_end, const float *lf32, int32_t lf_len,
-                                        hipStream_t s) {
+                                        bool counts, hipStream_t s) {
+  if (counts)
+    return lf_in_lds(lf_len)
+               ? launch_finish_plain_t<JB, true, true>(pj_dev, tile_begin, tile_end, lf32, lf_len, s)
+               : launch_finish_plain_t<JB, false, true>(pj_dev, tile_begin, tile_end, lf32, lf_len, s);
   return lf_in_lds(lf_len)
-             ? launch_finish_plain_t<JB, true>(pj_dev, tile_begin, tile_end, lf32, lf_len, s)
-             : launch_finish_plain_t<JB, false>(pj_dev, tile_begin, tile_end, lf32, lf_len, s);
+             ? launch_finish_plain_t<JB, true, false>(pj_dev, tile_begin, tile_end, lf32, lf_len, s)
+             : launch_finish_plain_t<JB, false, false>(pj_dev, tile_begin, tile_end, lf32, lf_len, s);
 }
 
 hipError_t launch_finish_plain(const PlainJob *pj_dev, int JB, int64_t tile_begin,
-                               int64_t tile_end, const float *lf32, int32_t lf_len,
+                               int64_t tile_end, const float *lf32, int32_t lf_len, bool counts,
                                hipStream_t s) {
   switch (JB) {
-    case 2: return launch_finish_plain_j<2>(pj_dev, tile_begin, tile_end, lf32, lf_len, s);
-    case 4: return launch_finish_plain_j<4>(pj_dev, tile_begin, tile_end, lf32, lf_len, s);
-    case 8: return launch_finish_plain_j<8>(pj_dev, tile_begin, tile_end, lf32, lf_len, s);
+    case 2: return launch_finish_plain_j<2>(pj_dev, tile_begin, tile_end, lf32, lf_len, counts, s);
+    case 4: return launch_finish_plain_j<4>(pj_dev, tile_begin, tile_end, lf32, lf_len, counts, s);
+    case 8: return launch_finish_plain_j<8>(pj_dev, tile_begin, tile_end, lf32, lf_len, counts, s);
   }
   return hipErrorInvalidValue;
 }

@@ -100,7 +100,7 @@ struct PermJob {
   const uint8_t *bytes;       // [Mp][2][S] 0/1 genotype values (bytes, or E2M1 nibbles)
   const uint8_t *ph;          // [64][S] 0/1 case values per phenotype (same format)
   const int32_t *tot_pairs;   // [Mp][Mp][4] pairwise tables over all samples
-  const int32_t *case_pairs;  // [Mp][Mp][Qp][4] pairwise tables over each phenotype's cases
+  const int32_t *case_pairs;  // [Mp][Mp][Qp][4] pairwise tables over each phenotype's cases, 4 x count
   const int32_t *n1;          // [Qp] cases per phenotype
   float *score;               // [Q][T]
   const int64_t *jprefix;     // [M + 1]
@@ -141,7 +141,7 @@ struct SelJob {
   // data needed to recount a candidate
   const uint32_t *planes;
   const int32_t *pairs;    // [classes][Mp][Mp][4]; MASKED: totals at class 0
-  const int32_t *case_pairs; // MASKED: case pairs of the job's mask (pair (x,y) at
+  const int32_t *case_pairs; // MASKED: case pairs (4 x count) of the job's mask (pair (x,y) at
                              // int4 index (x * Mp + y) * case_stride), else NULL
   const uint32_t *case_mask; // MASKED: [W] mask words, else NULL
   const int32_t *n1_dev;     // MASKED: device count of cases (overrides N1), else NULL
@@ -194,6 +194,17 @@ __device__ __forceinline__ void complete_table(const uint32_t n[8], const int pi
 #pragma unroll
   for (int x = 0; x < 26; ++x) s += t[x];
   t[26] = Nc - s;
+}
+
+// Log-factorial table entry at byte offset b (b = 4 n for L[n]).
+__device__ __forceinline__ float lf_at(const float *L, int b) {
+  return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(L) + b);
+}
+// The same for a table at LDS address 0 (the start of the dynamic LDS block
+// of a kernel that declares no static LDS): the byte offset is the address,
+// so a lookup is a single ds_read.
+__device__ __forceinline__ float lf_at_lds0(int b) {
+  return *(const __attribute__((address_space(3))) float *)(uintptr_t)(uint32_t)b;
 }
 
 // The FP32 log-factorial table sits in LDS when it fits in this many bytes
@@ -253,7 +264,8 @@ hipError_t launch_plain_prefix(PlainJob *pj_dev, hipStream_t s);
 hipError_t launch_count_mfma_plain(const PlainJob *pj_dev, int JB, bool fp4, int64_t tile_begin,
                                    int64_t tile_end, unsigned long long *queue, hipStream_t s);
 hipError_t launch_finish_plain(const PlainJob *pj_dev, int JB, int64_t tile_begin,
-                               int64_t tile_end, const float *lf32, int32_t lf_len, hipStream_t s);
+                               int64_t tile_end, const float *lf32, int32_t lf_len, bool counts,
+                               hipStream_t s);
 
 int tile_P_default(int32_t M, int32_t N);
 

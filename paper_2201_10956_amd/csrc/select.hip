@@ -295,6 +295,17 @@ __device__ void triplet_table(const uint32_t *planes, const int32_t *pairs,
     complete_table(n, aij, aik, ajk, mi, mj, mk, N0 + N1, tot);
     corners(planes, Mp, 0, W0, i, j, k, mask, n);
     pair_args(case_pairs, Mp, i, j, k, aij, aik, ajk, mi, mj, mk, case_stride);
+    // case pair tables hold 4 x the counts
+    for (int x = 0; x < 4; ++x) {
+      aij[x] >>= 2;
+      aik[x] >>= 2;
+      ajk[x] >>= 2;
+    }
+    for (int x = 0; x < 2; ++x) {
+      mi[x] >>= 2;
+      mj[x] >>= 2;
+      mk[x] >>= 2;
+    }
     complete_table(n, aij, aik, ajk, mi, mj, mk, N1, tab[1]);
     for (int x = 0; x < 27; ++x) tab[0][x] = tot[x] - tab[1][x];
   }
