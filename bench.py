@@ -106,7 +106,8 @@ def run_plain(args, wl):
     geno = torch.from_numpy(d.geno).to("cuda")          # resident before timing
     ds = epi3.encode(geno, d.pheno)
     variant = epi3.tile_for(ds, "auto") if args.variant == "auto" else args.variant
-    if args.tile:
+    if args.tile:  # the forced tile replaces the tuned table's rules for this variant
+        epi3.tile_rules_clear()
         epi3.tile_rule(variant, 0, 0, args.tile)
     tile = epi3.tile_for(ds, variant)
     sc = epi3.Scanner(ds, k, variant)

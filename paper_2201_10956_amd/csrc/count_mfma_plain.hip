@@ -180,29 +180,34 @@ __global__ void __launch_bounds__(256, 2) count_mfma_plain_kernel(
       const int64_t cbase = (int64_t)cls * pj.Mp * 2;  // first row of this class
       // staging plan: rows [0, 32) X_i (i0 + x / 2, plane x % 2), then 2 JB
       // rows X_j, then 2 KT rows X_k (k0 + x / 2, plane x % 2)
+      // 32-bit byte offsets of this thread's 16-byte pieces (the value planes
+      // are far below 4 GB), so each load is a scalar base plus one VGPR
+      constexpr int kPieces = kPKC / 16;
+      uint32_t off[kPer];
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const int c16 = tid + 256 * u;
+        const int row = c16 / kPieces < kRows ? c16 / kPieces : kRows - 1, col = (c16 % kPieces) * 16;
+        int snp, pl;
+        if (row < kRowsI) { snp = i0 + (row >> 1); pl = row & 1; }
+        else if (row < kRowsI + kRowsJ) { const int x = row - kRowsI; snp = j0 + (x >> 1); pl = x & 1; }
+        else { const int x = row - kRowsI - kRowsJ; snp = k0 + (x >> 1); pl = x & 1; }
+        snp = snp < Mp ? snp : Mp - 1;  // rows past M read a zero row
+        off[u] = (uint32_t)((cbase + (int64_t)snp * 2 + pl) * Sb + col);
+      }
       v4i pf[kPer];
       auto fetch = [&](int ch) {
 #pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-          const int c16 = tid + 256 * u;
-          if (c16 < kChunks) {
-            const int row = c16 >> 2, col = (c16 & 3) * 16;
-            int snp, pl;
-            if (row < kRowsI) { snp = i0 + (row >> 1); pl = row & 1; }
-            else if (row < kRowsI + kRowsJ) { const int x = row - kRowsI; snp = j0 + (x >> 1); pl = x & 1; }
-            else { const int x = row - kRowsI - kRowsJ; snp = k0 + (x >> 1); pl = x & 1; }
-            snp = snp < Mp ? snp : Mp - 1;  // rows past M read a zero row
-            pf[u] = *reinterpret_cast<gptr<v4i>>(gv + (cbase + (int64_t)snp * 2 + pl) * Sb +
-                                                 (int64_t)ch * kPKC + col);
-          }
-        }
+        for (int u = 0; u < kPer; ++u)
+          if (tid + 256 * u < kChunks)
+            pf[u] = *reinterpret_cast<gptr<v4i>>(gv + (off[u] + (uint32_t)ch * kPKC));
       };
       auto store = [&](int buf) {
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
           const int c16 = tid + 256 * u;
           if (c16 < kChunks)
-            *reinterpret_cast<v4i *>(stage + buf * kBuf + (c16 >> 2) * kPRow + (c16 & 3) * 16) = pf[u];
+            *reinterpret_cast<v4i *>(stage + buf * kBuf + (c16 / kPieces) * kPRow + (c16 % kPieces) * 16) = pf[u];
         }
       };
       typename Acc::type acc[2][2][2];  // [i-block][j of the pair][B tile]
