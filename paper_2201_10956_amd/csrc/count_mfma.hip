@@ -267,26 +267,40 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
     // and are ANDed only when stored, so no load is waited for before the
     // current chunk's matrix products are issued.
     static_assert(kRowsPH + kRowsXK == 96 && kRowsP == 16 && kKC / 16 == 8, "staging plan");
+    // 32-bit byte offsets of this thread's pieces for chunk 0 (the value
+    // planes and phenotype rows are far below 4 GB): scalar base + one VGPR
+    uint32_t off[3], offa = 0, offb = 0;
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int c16 = tid + 256 * u;
+      const int row = c16 >> 3, col = (c16 & 7) * 16;
+      if (row < kRowsPH) {
+        off[u] = (uint32_t)(row * S + col);
+      } else {
+        const int x = row - kRowsPH;
+        off[u] = (uint32_t)((((int64_t)(kbase + (x >> 1)) * 2 + (x & 1)) * S) + col);
+      }
+    }
+    if (tid < 128) {
+      const int x = tid >> 3, col = (tid & 7) * 16;  // pair row x: wave x >> 2, (a, b) = x & 3
+      const int ii = 4 * ib + (x >> 2);
+      offa = (uint32_t)(((int64_t)ii * 2 + ((x >> 1) & 1)) * S + col);
+      offb = (uint32_t)(((int64_t)j * 2 + (x & 1)) * S + col);
+    }
     v4i pf[3], pa, pb;
     auto fetch = [&](int ch) {
+      const uint32_t c0 = (uint32_t)ch * kKC;
 #pragma unroll
       for (int u = 0; u < 3; ++u) {
-        const int c16 = tid + 256 * u;
-        const int row = c16 >> 3, col = (c16 & 7) * 16;
-        const int64_t s0 = (int64_t)ch * kKC + col;
-        if (row < kRowsPH) {
-          pf[u] = *reinterpret_cast<gptr<v4i>>(gph + (int64_t)row * S + s0);
-        } else {
-          const int x = row - kRowsPH;
-          pf[u] = *reinterpret_cast<gptr<v4i>>(gb + ((int64_t)(kbase + (x >> 1)) * 2 + (x & 1)) * S + s0);
-        }
+        const int row = (tid + 256 * u) >> 3;
+        if (row < kRowsPH)
+          pf[u] = *reinterpret_cast<gptr<v4i>>(gph + (off[u] + c0));
+        else
+          pf[u] = *reinterpret_cast<gptr<v4i>>(gb + (off[u] + c0));
       }
       if (tid < 128) {
-        const int x = tid >> 3, col = (tid & 7) * 16;  // pair row x: wave x >> 2, (a, b) = x & 3
-        const int64_t s0 = (int64_t)ch * kKC + col;
-        const int ii = 4 * ib + (x >> 2);
-        pa = *reinterpret_cast<gptr<v4i>>(gb + ((int64_t)ii * 2 + ((x >> 1) & 1)) * S + s0);
-        pb = *reinterpret_cast<gptr<v4i>>(gb + ((int64_t)j * 2 + (x & 1)) * S + s0);
+        pa = *reinterpret_cast<gptr<v4i>>(gb + (offa + c0));
+        pb = *reinterpret_cast<gptr<v4i>>(gb + (offb + c0));
       }
     };
     auto store = [&](int buf) {
