@@ -259,21 +259,25 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
     const int i = 4 * ib + wave;  // may be >= j (then the wave's results are dropped)
     const int kbase = (perm_kb_lo(j) + kb) * kPermKB;  // k <= j or k >= M: dropped later
 
-    // ---- staging plan: this thread's 16-byte chunks of one LDS buffer ----
+    // ---- staging plan: this thread's 16-byte pieces of one LDS buffer ----
     // rows [0, 64): phenotype q; [64, 96): (k, c) = k planes; [96, 112): pair rows.
-    // Each chunk is loaded into registers one chunk ahead.  Thread chunks
-    // c16 = tid + 256 u: u = 0..2 cover the phenotype and k rows (row < 96),
-    // u = 3 covers the 16 pair rows (tid < 128), which keep both source words
-    // and are ANDed only when stored, so no load is waited for before the
-    // current chunk's matrix products are issued.
-    static_assert(kRowsPH + kRowsXK == 96 && kRowsP == 16 && kKC / 16 == 8, "staging plan");
+    // Each chunk is loaded into registers one chunk ahead.  Pieces
+    // c16 = tid + 256 u cover the phenotype and k rows (row < 96); threads
+    // tid < 16 kPc cover the 16 pair rows, which keep both source words and
+    // are ANDed only when stored, so no load is waited for before the current
+    // chunk's matrix products are issued.
+    constexpr int kPc = kKC / 16;                // pieces per row
+    constexpr int kMainU = 96 * kPc / 256;       // main pieces per thread
+    constexpr int kPairPieces = kRowsP * kPc;    // pair pieces (<= 256)
+    static_assert(kRowsPH + kRowsXK == 96 && (96 * kPc) % 256 == 0 && kPairPieces <= 256,
+                  "staging plan");
     // 32-bit byte offsets of this thread's pieces for chunk 0 (the value
     // planes and phenotype rows are far below 4 GB): scalar base + one VGPR
-    uint32_t off[3], offa = 0, offb = 0;
+    uint32_t off[kMainU], offa = 0, offb = 0;
 #pragma unroll
-    for (int u = 0; u < 3; ++u) {
+    for (int u = 0; u < kMainU; ++u) {
       const int c16 = tid + 256 * u;
-      const int row = c16 >> 3, col = (c16 & 7) * 16;
+      const int row = c16 / kPc, col = (c16 % kPc) * 16;
       if (row < kRowsPH) {
         off[u] = (uint32_t)(row * S + col);
       } else {
@@ -281,24 +285,24 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
         off[u] = (uint32_t)((((int64_t)(kbase + (x >> 1)) * 2 + (x & 1)) * S) + col);
       }
     }
-    if (tid < 128) {
-      const int x = tid >> 3, col = (tid & 7) * 16;  // pair row x: wave x >> 2, (a, b) = x & 3
+    if (tid < kPairPieces) {
+      const int x = tid / kPc, col = (tid % kPc) * 16;  // pair row x: wave x >> 2, (a, b) = x & 3
       const int ii = 4 * ib + (x >> 2);
       offa = (uint32_t)(((int64_t)ii * 2 + ((x >> 1) & 1)) * S + col);
       offb = (uint32_t)(((int64_t)j * 2 + (x & 1)) * S + col);
     }
-    v4i pf[3], pa, pb;
+    v4i pf[kMainU], pa, pb;
     auto fetch = [&](int ch) {
       const uint32_t c0 = (uint32_t)ch * kKC;
 #pragma unroll
-      for (int u = 0; u < 3; ++u) {
-        const int row = (tid + 256 * u) >> 3;
+      for (int u = 0; u < kMainU; ++u) {
+        const int row = (tid + 256 * u) / kPc;
         if (row < kRowsPH)
           pf[u] = *reinterpret_cast<gptr<v4i>>(gph + (off[u] + c0));
         else
           pf[u] = *reinterpret_cast<gptr<v4i>>(gb + (off[u] + c0));
       }
-      if (tid < 128) {
+      if (tid < kPairPieces) {
         pa = *reinterpret_cast<gptr<v4i>>(gb + (offa + c0));
         pb = *reinterpret_cast<gptr<v4i>>(gb + (offb + c0));
       }
@@ -306,12 +310,12 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
     auto store = [&](int buf) {
       uint8_t *dst = stage + buf * kStageBytes;
 #pragma unroll
-      for (int u = 0; u < 3; ++u) {
+      for (int u = 0; u < kMainU; ++u) {
         const int c16 = tid + 256 * u;
-        *reinterpret_cast<v4i *>(dst + (c16 >> 3) * kRow + (c16 & 7) * 16) = pf[u];
+        *reinterpret_cast<v4i *>(dst + (c16 / kPc) * kRow + (c16 % kPc) * 16) = pf[u];
       }
-      if (tid < 128)
-        *reinterpret_cast<v4i *>(dst + (96 + (tid >> 3)) * kRow + (tid & 7) * 16) = pa & pb;
+      if (tid < kPairPieces)
+        *reinterpret_cast<v4i *>(dst + (96 + tid / kPc) * kRow + (tid % kPc) * 16) = pa & pb;
     };
 
     typename Acc::type acc[kPermT][2];
