@@ -46,8 +46,9 @@ DEFAULT_WORKLOAD = "perm4"
 
 
 def recorded_traffic(key: str):
-    """HBM bytes per launch from the committed counter summary (profiles/traffic.json),
-    or None when the kernel's sources changed since the counters were taken."""
+    """HBM bytes per launch of the dominant kernel of "workload|variant" from the
+    committed counter summary (profiles/traffic.json), or None when the kernel's
+    sources changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -130,7 +131,7 @@ def run_plain(args, wl):
         out["roofline"] = {
             "bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
             "unit": "T int32-lane-ops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-            "traffic": recorded_traffic(f"count_valu_kernel|{args.workload}"),
+            "traffic": recorded_traffic(f"{args.workload}|valu"),
             "traffic_unit": "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
             "kernel": "count_valu_kernel", "kernel_ms": round(cnt_ms / max(cnt_n, 1), 4),
             "ops_per_launch": work * VALU_OPS_PER_ST / max(cnt_n, 1)}
@@ -141,7 +142,7 @@ def run_plain(args, wl):
             "bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
             "unit": "TFLOP/s (fp4)" if variant == "mfma_fp4" else "TOP/s (int8)",
             "frac": round(achieved / peak, 4),
-            "traffic": recorded_traffic(f"count_mfma_plain_kernel|{args.workload}"),
+            "traffic": recorded_traffic(f"{args.workload}|{variant}"),
             "traffic_unit": "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
             "kernel": "count_mfma_plain_kernel", "kernel_ms": round(cnt_ms / max(cnt_n, 1), 4),
             "launches_per_step": cnt_n,
@@ -267,7 +268,7 @@ def run_perm(args, wl):
     out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                        "unit": "TFLOP/s (fp4)" if variant == "mfma_fp4" else "TOP/s (int8)",
                        "frac": round(achieved / peak, 4),
-                       "traffic": recorded_traffic(f"count_mfma_perm_kernel|{args.workload}"),
+                       "traffic": recorded_traffic(f"{args.workload}|{variant}"),
                        "traffic_unit": "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
                        "kernel": "count_mfma_perm_kernel", "kernel_ms": round(k_ms / max(k_n, 1), 4),
                        "launches_per_step": k_n,
@@ -321,7 +322,7 @@ def run_uneven(args, wl):
                          "how": "one plain scan per data set", "hits_identical": bool(same)}
     out["roofline"] = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
                        "unit": "T int32-lane-ops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                       "traffic": recorded_traffic(f"count_valu_kernel|{args.workload}"),
+                       "traffic": recorded_traffic(f"{args.workload}|valu"),
                        "kernel": "count_valu_kernel", "kernel_ms": round(k_ms, 4),
                        "ops_per_launch": work * VALU_OPS_PER_ST}
     out["breakdown_ms"] = {"count_kernel": round(k_ms, 4), "selection": round(sel_ms, 4)}
