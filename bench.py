@@ -296,7 +296,8 @@ def run_uneven(args, wl):
     k = c["k"]
     genos = [torch.from_numpy(d.geno).to("cuda") for d in dsets]
     enc = [epi3.encode(g, d.pheno) for g, d in zip(genos, dsets)]
-    bs = epi3.BatchScanner(enc, k, variant="valu")
+    variant = args.variant if args.variant in ("auto", "valu", "mfma", "mfma_fp4") else "auto"
+    bs = epi3.BatchScanner(enc, k, variant=variant)
 
     def step():
         for x, (g, d) in enumerate(zip(genos, dsets)):
@@ -306,26 +307,54 @@ def run_uneven(args, wl):
     dt, res = _timed_steps(step, args.steps, args.warmup)
     work = sum(comb(d.n_snps, 3) * d.n_samples for d in dsets)
     value = work / dt / 1e12
-    k_ms, k_n, sel_ms, _ = _kernel_times(bs.run)
-    achieved = work * VALU_OPS_PER_ST / (k_ms / 1e3) / 1e12
+    k_ms, k_n, sel_ms, fin_ms = _kernel_times(bs.run)
+    # roofline of the count kernel family that does most of the work, timed on
+    # its own subset of the data sets (one batched call each)
+    kinds = [epi3.tile_for(e, "auto") if variant == "auto" else variant for e in enc]
+    on_mfma = [x for x in range(len(enc)) if kinds[x] != "valu"]
+    on_valu = [x for x in range(len(enc)) if kinds[x] == "valu"]
+    w_mfma = sum(comb(dsets[x].n_snps, 3) * dsets[x].n_samples for x in on_mfma)
+    w_valu = work - w_mfma
+    if w_mfma >= w_valu:
+        sub = epi3.BatchScanner([enc[x] for x in on_mfma], k, variant=variant)
+        m_ms, m_n, _, m_fin = _kernel_times(sub.run)
+        fp4 = all(kinds[x] == "mfma_fp4" for x in on_mfma)
+        peak = MFMA_FP4_PEAK_TFLOPS if fp4 else MFMA_I8_PEAK_TOPS
+        achieved = MFMA_OPS_PER_STQ * w_mfma / (m_ms / 1e3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
+                "unit": "TFLOP/s (fp4)" if fp4 else "TOP/s (int8)", "frac": round(achieved / peak, 4),
+                "traffic": None, "kernel": "count_mfma_plain_kernel",
+                "kernel_ms": round(m_ms / max(m_n, 1), 4), "launches": m_n,
+                "datasets_timed": len(on_mfma), "ops": MFMA_OPS_PER_STQ * w_mfma}
+    else:
+        sub = epi3.BatchScanner([enc[x] for x in on_valu], k, variant=variant) if on_mfma else bs
+        v_ms, v_n, _, _ = _kernel_times(sub.run)
+        achieved = w_valu * VALU_OPS_PER_ST / (v_ms / 1e3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
+                "unit": "T int32-lane-ops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                "traffic": recorded_traffic(f"{args.workload}|valu"),
+                "kernel": "count_valu_kernel", "kernel_ms": round(v_ms, 4),
+                "datasets_timed": len(on_valu), "ops": w_valu * VALU_OPS_PER_ST}
 
     def seq():
-        return [epi3.scan_topk(e, k, "valu") for e in enc]
+        return [epi3.scan_topk(e, k, variant) for e in enc]
 
     s_dt, seq_res = _timed_steps(seq, 1, 1)
     same = all(a.tobytes() == b.tobytes() for a, b in zip(res, seq_res))
-    out = _base(args, wl, value, dt * 1e3, "u32", {
+    dtype = "u32" if variant == "valu" else ("i8" if variant == "mfma" else "fp4+u32")
+    out = _base(args, wl, value, dt * 1e3, dtype, {
         "workload": wl["desc"], "datasets": len(dsets), "top_k": k,
         "snps": [d.n_snps for d in dsets], "samples": [d.n_samples for d in dsets],
-        "sample_triplets": work, "variant": "valu"})
+        "sample_triplets": work, "variant": variant,
+        "count_kernels_per_dataset": [epi3.tile_for(e, "auto") if variant == "auto" else variant
+                                      for e in enc]})
     out["sequential"] = {"value": round(work / s_dt / 1e12, 4), "ms": round(s_dt * 1e3, 3),
                          "how": "one plain scan per data set", "hits_identical": bool(same)}
-    out["roofline"] = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
-                       "unit": "T int32-lane-ops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                       "traffic": recorded_traffic(f"{args.workload}|valu"),
-                       "kernel": "count_valu_kernel", "kernel_ms": round(k_ms, 4),
-                       "ops_per_launch": work * VALU_OPS_PER_ST}
-    out["breakdown_ms"] = {"count_kernel": round(k_ms, 4), "selection": round(sel_ms, 4)}
+    out["roofline"] = roof
+    out["breakdown_ms"] = {"count_kernels": round(k_ms, 4), "finish_kernels": round(fin_ms, 4),
+                           "selection": round(sel_ms, 4)}
+    out["work_split"] = {"matrix_core_datasets": len(on_mfma), "vector_alu_datasets": len(on_valu),
+                         "matrix_core_sample_triplets": w_mfma, "vector_alu_sample_triplets": w_valu}
     if not args.no_cpu_baseline:
         big = max(dsets, key=lambda d: d.n_samples)
         out["cpu_baseline"] = cpu_baseline(big, k, args.cpu_budget)

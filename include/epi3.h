@@ -186,7 +186,13 @@ int epi3_score_plane(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *w
  * hits_host holds sum_j k_j hits, job after job; n_out_host [n_jobs].
  * ------------------------------------------------------------------------ */
 
-int64_t epi3_batched_workspace_bytes(const epi3_job *jobs, int32_t n_jobs, int64_t cand_cap);
+/* variant: SPLIT jobs run the count kernel each would run in a plain scan
+ * with that variant (AUTO follows the tile table per data set; vector-ALU
+ * jobs share one persistent launch, matrix-core jobs run their passes one
+ * after another); MASKED jobs run on the matrix cores (AUTO = FP4; VALU is
+ * EPI3_E_UNSUPPORTED).  The workspace depends on the variant. */
+int64_t epi3_batched_workspace_bytes(const epi3_job *jobs, int32_t n_jobs, int32_t variant,
+                                     int64_t cand_cap);
 
 int epi3_scan_batched(const epi3_job *jobs, int32_t n_jobs, int32_t variant, int64_t cand_cap,
                       void *ws_dev, int64_t ws_bytes, epi3_hit *hits_host,

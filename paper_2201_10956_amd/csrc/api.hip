@@ -360,6 +360,84 @@ int timed(int which, hipStream_t s, F &&fn) {
   return rc;
 }
 
+// Buffers of one matrix-core plain count: two scratch buffers of pass_tiles
+// tiles, two PlainJob slots, the pivot-block prefix, the tile queue and the
+// job's key range.
+struct MfmaBufs {
+  uint8_t *scratch;
+  int64_t pass_tiles;
+  PlainJob *pjob;
+  int64_t *jprefix;
+  unsigned long long *queue;
+  uint32_t *keyrange;
+};
+
+int enqueue_count_mfma(const epi3_dataset &d, bool fp4, float *score, uint32_t *counts,
+                       const MfmaBufs &W, hipStream_t s) {
+  const int JB = pick_JB(d, fp4 ? EPI3_VARIANT_MFMA_FP4 : EPI3_VARIANT_MFMA);
+  const int64_t tiles = host_plain_tiles(d.n_snps, JB);
+  const int32_t unit = fp4 ? 128 : 64;  // samples per 64-byte staged chunk
+  PlainJob pj{};
+  pj.vals = static_cast<const uint8_t *>(fp4 ? d.nibbles : d.bytes);
+  pj.pairs = d.pairs;
+  pj.score = score;
+  pj.counts = counts;
+  pj.keyrange = W.keyrange;
+  pj.jprefix = W.jprefix;
+  pj.corners = reinterpret_cast<uint4 *>(W.scratch);
+  pj.n_tiles = tiles;
+  pj.T = epi3_n_triplets(d.n_snps);
+  pj.M = d.n_snps;
+  pj.Mp = d.snp_stride;
+  pj.Sb = fp4 ? d.byte_stride / 2 : d.byte_stride;
+  pj.Sb0 = (d.n_controls + unit - 1) / unit * 64;
+  pj.Sb1 = (d.n_cases + unit - 1) / unit * 64;
+  pj.N0 = d.n_controls;
+  pj.N1 = d.n_cases;
+  pj.JB = JB;
+  if (pj.Sb0 > pj.Sb || pj.Sb1 > pj.Sb) return EPI3_E_INVALID;
+  PlainJob pjb[2] = {pj, pj};
+  pjb[1].corners = reinterpret_cast<uint4 *>(W.scratch + W.pass_tiles * kPlainTileScratch);
+  HIP_OK(launch_write_plainjob(pjb[0], W.pjob + 0, s));
+  HIP_OK(launch_write_plainjob(pjb[1], W.pjob + 1, s));
+  HIP_OK(launch_plain_prefix(W.pjob, s));
+  // Pass p counts into scratch buffer p % 2 on `s`; its finish kernel runs on
+  // the second stream while `s` counts pass p + 1.  Count p + 2 waits for
+  // finish p (same buffer).
+  hipStream_t s2 = nullptr;
+  hipEvent_t ev[5];
+  int rc = aux_get(&s2, ev, 5);
+  if (rc != EPI3_OK) return rc;
+  hipEvent_t ev_start = ev[0], ev_cnt[2] = {ev[1], ev[2]}, ev_fin[2] = {ev[3], ev[4]};
+  HIP_OK(hipEventRecord(ev_start, s));
+  HIP_OK(hipStreamWaitEvent(s2, ev_start, 0));
+  int p = 0;
+  for (int64_t t0 = 0; t0 < tiles; t0 += W.pass_tiles, ++p) {
+    const int64_t t1 = std::min(tiles, t0 + W.pass_tiles);
+    const int b = p & 1;
+    if (p >= 2) HIP_OK(hipStreamWaitEvent(s, ev_fin[b], 0));
+    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
+    rc = timed(0, s, [&]() {
+      return launch_count_mfma_plain(W.pjob + b, JB, fp4, t0, t1, W.queue, s) == hipSuccess
+                 ? EPI3_OK
+                 : EPI3_E_HIP;
+    });
+    if (rc != EPI3_OK) return rc;
+    HIP_OK(hipEventRecord(ev_cnt[b], s));
+    HIP_OK(hipStreamWaitEvent(s2, ev_cnt[b], 0));
+    rc = timed(3, s2, [&]() {
+      return launch_finish_plain(W.pjob + b, JB, t0, t1, d.lf32, d.n_samples + 2, counts != nullptr, s2) == hipSuccess
+                 ? EPI3_OK
+                 : EPI3_E_HIP;
+    });
+    if (rc != EPI3_OK) return rc;
+    HIP_OK(hipEventRecord(ev_fin[b], s2));
+  }
+  HIP_OK(hipEventRecord(ev_fin[0], s2));
+  HIP_OK(hipStreamWaitEvent(s, ev_fin[0], 0));
+  return EPI3_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -459,79 +537,14 @@ int64_t epi3_workspace_bytes(const epi3_dataset *d, int32_t k, int32_t variant, 
   return scan_layout(nullptr, *d, k, cand_cap, variant).total;
 }
 
-static int enqueue_count_mfma(const epi3_dataset &d, bool fp4, float *score, uint32_t *counts,
-                              const ScanLayout &W, hipStream_t s) {
-  const int JB = pick_JB(d, fp4 ? EPI3_VARIANT_MFMA_FP4 : EPI3_VARIANT_MFMA);
-  const int64_t tiles = host_plain_tiles(d.n_snps, JB);
-  const int32_t unit = fp4 ? 128 : 64;  // samples per 64-byte staged chunk
-  PlainJob pj{};
-  pj.vals = static_cast<const uint8_t *>(fp4 ? d.nibbles : d.bytes);
-  pj.pairs = d.pairs;
-  pj.score = score;
-  pj.counts = counts;
-  pj.keyrange = &W.st->kmin;
-  pj.jprefix = W.jprefix;
-  pj.corners = reinterpret_cast<uint4 *>(W.scratch);
-  pj.n_tiles = tiles;
-  pj.T = epi3_n_triplets(d.n_snps);
-  pj.M = d.n_snps;
-  pj.Mp = d.snp_stride;
-  pj.Sb = fp4 ? d.byte_stride / 2 : d.byte_stride;
-  pj.Sb0 = (d.n_controls + unit - 1) / unit * 64;
-  pj.Sb1 = (d.n_cases + unit - 1) / unit * 64;
-  pj.N0 = d.n_controls;
-  pj.N1 = d.n_cases;
-  pj.JB = JB;
-  if (pj.Sb0 > pj.Sb || pj.Sb1 > pj.Sb) return EPI3_E_INVALID;
-  PlainJob pjb[2] = {pj, pj};
-  pjb[1].corners = reinterpret_cast<uint4 *>(W.scratch + W.pass_tiles * kPlainTileScratch);
-  HIP_OK(launch_write_plainjob(pjb[0], W.pjob + 0, s));
-  HIP_OK(launch_write_plainjob(pjb[1], W.pjob + 1, s));
-  HIP_OK(launch_plain_prefix(W.pjob, s));
-  // Pass p counts into scratch buffer p % 2 on `s`; its finish kernel runs on
-  // the second stream while `s` counts pass p + 1.  Count p + 2 waits for
-  // finish p (same buffer).
-  hipStream_t s2 = nullptr;
-  hipEvent_t ev[5];
-  int rc = aux_get(&s2, ev, 5);
-  if (rc != EPI3_OK) return rc;
-  hipEvent_t ev_start = ev[0], ev_cnt[2] = {ev[1], ev[2]}, ev_fin[2] = {ev[3], ev[4]};
-  HIP_OK(hipEventRecord(ev_start, s));
-  HIP_OK(hipStreamWaitEvent(s2, ev_start, 0));
-  int p = 0;
-  for (int64_t t0 = 0; t0 < tiles; t0 += W.pass_tiles, ++p) {
-    const int64_t t1 = std::min(tiles, t0 + W.pass_tiles);
-    const int b = p & 1;
-    if (p >= 2) HIP_OK(hipStreamWaitEvent(s, ev_fin[b], 0));
-    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
-    rc = timed(0, s, [&]() {
-      return launch_count_mfma_plain(W.pjob + b, JB, fp4, t0, t1, W.queue, s) == hipSuccess
-                 ? EPI3_OK
-                 : EPI3_E_HIP;
-    });
-    if (rc != EPI3_OK) return rc;
-    HIP_OK(hipEventRecord(ev_cnt[b], s));
-    HIP_OK(hipStreamWaitEvent(s2, ev_cnt[b], 0));
-    rc = timed(3, s2, [&]() {
-      return launch_finish_plain(W.pjob + b, JB, t0, t1, d.lf32, d.n_samples + 2, counts != nullptr, s2) == hipSuccess
-                 ? EPI3_OK
-                 : EPI3_E_HIP;
-    });
-    if (rc != EPI3_OK) return rc;
-    HIP_OK(hipEventRecord(ev_fin[b], s2));
-  }
-  HIP_OK(hipEventRecord(ev_fin[0], s2));
-  HIP_OK(hipStreamWaitEvent(s, ev_fin[0], 0));
-  return EPI3_OK;
-}
-
 static int enqueue_count(const epi3_dataset &d, int32_t variant, float *score, uint32_t *counts,
                          const ScanLayout &W, hipStream_t s) {
   const int v = plain_variant(d, variant);
   if (v < 0) return v;
   if (v == EPI3_VARIANT_MFMA || v == EPI3_VARIANT_MFMA_FP4) {
     if (!W.scratch) return EPI3_E_WORKSPACE;
-    return enqueue_count_mfma(d, v == EPI3_VARIANT_MFMA_FP4, score, counts, W, s);
+    const MfmaBufs B{W.scratch, W.pass_tiles, W.pjob, W.jprefix, W.queue, &W.st->kmin};
+    return enqueue_count_mfma(d, v == EPI3_VARIANT_MFMA_FP4, score, counts, B, s);
   }
   const int P = pick_P(d);
   Job J = make_job(d, score, counts, W.jprefix, &W.st->kmin, P);
@@ -659,6 +672,10 @@ struct BatchLayout {
   std::vector<uint32_t *> ckey;
   std::vector<int64_t *> crank;
   std::vector<int64_t> cap, ccap, hit_off, T;
+  std::vector<int> vsplit;        // SPLIT: count kernel of each job (EPI3_VARIANT_*)
+  PlainJob *pjobs_plain = nullptr;// SPLIT: two slots per matrix-core job
+  uint8_t *plain_scratch = nullptr;
+  int64_t plain_pass_tiles = 0;
   int64_t total_k = 0, total = 0;
 };
 
@@ -667,13 +684,19 @@ bool same_dataset(const epi3_dataset *a, const epi3_dataset *b) {
          a->layout == b->layout;
 }
 
-int check_jobs(const epi3_job *jobs, int32_t n) {
+int check_jobs(const epi3_job *jobs, int32_t n, int32_t variant) {
   if (!jobs || n <= 0) return EPI3_E_INVALID;
+  if (variant < EPI3_VARIANT_AUTO || variant > EPI3_VARIANT_MFMA_FP4) return EPI3_E_INVALID;
   const int layout = jobs[0].d ? jobs[0].d->layout : -1;
+  if (layout == EPI3_LAYOUT_MASKED && variant == EPI3_VARIANT_VALU) return EPI3_E_UNSUPPORTED;
   for (int x = 0; x < n; ++x) {
     const epi3_job &J = jobs[x];
     if (!valid_dataset(J.d) || J.k <= 0 || J.d->layout != layout) return EPI3_E_INVALID;
     if (layout == EPI3_LAYOUT_SPLIT && J.case_mask) return EPI3_E_INVALID;
+    if (layout == EPI3_LAYOUT_SPLIT) {
+      const int v = plain_variant(*J.d, variant);
+      if (v < 0) return v;
+    }
     if (layout == EPI3_LAYOUT_MASKED) {
       if (!J.case_mask || !J.d->bytes || !same_dataset(J.d, jobs[0].d)) return EPI3_E_INVALID;
     }
@@ -681,7 +704,8 @@ int check_jobs(const epi3_job *jobs, int32_t n) {
   return EPI3_OK;
 }
 
-BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand_cap) {
+BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand_cap,
+                         int32_t variant) {
   BatchLayout L;
   L.n = n;
   L.layout = jobs[0].d->layout;
@@ -698,6 +722,26 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
   L.hits = c.take<epi3_hit>(L.total_k);
   if (L.layout == EPI3_LAYOUT_SPLIT) {
     L.jobs = c.take<Job>(n);
+    // per job: the vector-ALU kernel (all such jobs share one launch) or a
+    // matrix-core plain count of its own, sharing one scratch
+    L.vsplit.resize(n);
+    int64_t max_tiles = 0;
+    int n_mfma = 0;
+    for (int x = 0; x < n; ++x) {
+      const epi3_dataset &d = *jobs[x].d;
+      L.vsplit[x] = plain_variant(d, variant);
+      if ((L.vsplit[x] == EPI3_VARIANT_MFMA || L.vsplit[x] == EPI3_VARIANT_MFMA_FP4) &&
+          epi3_n_triplets(d.n_snps) > 0) {
+        ++n_mfma;
+        max_tiles = std::max(max_tiles, host_plain_tiles(d.n_snps, pick_JB(d, L.vsplit[x])));
+      }
+    }
+    if (n_mfma > 0) {
+      L.pjobs_plain = c.take<PlainJob>(2 * (int64_t)n);
+      L.plain_pass_tiles = std::max<int64_t>(
+          1, std::min<int64_t>(max_tiles, pass_bytes(kPlainPassBytes) / kPlainTileScratch));
+      L.plain_scratch = c.take<uint8_t>(2 * L.plain_pass_tiles * kPlainTileScratch);
+    }
   } else {
     const epi3_dataset &d = *jobs[0].d;
     L.groups = (n + kPermGroup - 1) / kPermGroup;
@@ -781,18 +825,31 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
   }
 
   if (W.layout == EPI3_LAYOUT_SPLIT) {
-    // one persistent launch over every job's tiles; jobs with the most
-    // samples per tile first so the queue ends on the cheapest tiles
-    std::vector<int> order(n);
-    for (int x = 0; x < n; ++x) order[x] = x;
+    // matrix-core jobs: one plain count each (passes through the shared scratch)
+    for (int x = 0; x < n; ++x) {
+      const int v = W.vsplit[x];
+      if (v < 0) return v;
+      if (v == EPI3_VARIANT_VALU || W.T[x] == 0) continue;
+      const MfmaBufs B{W.plain_scratch, W.plain_pass_tiles, W.pjobs_plain + 2 * (int64_t)x,
+                       W.jprefix[x], W.queue, &W.st[x].kmin};
+      const int rc = enqueue_count_mfma(*jobs[x].d, v == EPI3_VARIANT_MFMA_FP4, W.score[x], nullptr,
+                                        B, s);
+      if (rc != EPI3_OK) return rc;
+    }
+    // vector-ALU jobs: one persistent launch over all their tiles; jobs with
+    // the most samples per tile first so the queue ends on the cheapest tiles
+    std::vector<int> order;
+    for (int x = 0; x < n; ++x)
+      if (W.vsplit[x] == EPI3_VARIANT_VALU) order.push_back(x);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
       const epi3_dataset &da = *jobs[a].d, &db = *jobs[b].d;
       return da.words[0] + da.words[1] > db.words[0] + db.words[1];
     });
+    const int nv = (int)order.size();
     int P_lo = 8, P_hi = 4;
     int32_t lf_len = 2;
     const float *lf32 = nullptr;
-    for (int x = 0; x < n; ++x) {
+    for (int x : order) {
       P_lo = std::min(P_lo, pick_P(*jobs[x].d));
       P_hi = std::max(P_hi, pick_P(*jobs[x].d));
       if (jobs[x].d->n_samples + 2 > lf_len) {
@@ -800,21 +857,23 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
         lf32 = jobs[x].d->lf32;
       }
     }
-    std::vector<Job> J(n);
+    std::vector<Job> J(nv);
     int64_t begin = 0;
-    for (int y = 0; y < n; ++y) {
+    for (int y = 0; y < nv; ++y) {
       const int x = order[y];
       J[y] = make_job(*jobs[x].d, W.score[x], nullptr, W.jprefix[x], &W.st[x].kmin,
                       pick_P(*jobs[x].d));
       J[y].tile_begin = begin;
       begin += J[y].n_tiles;
     }
-    HIP_OK(launch_write_jobs(J.data(), n, W.jobs, s));
-    HIP_OK(launch_tile_prefix(W.jobs, n, s));
-    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
+    if (nv > 0) {
+      HIP_OK(launch_write_jobs(J.data(), nv, W.jobs, s));
+      HIP_OK(launch_tile_prefix(W.jobs, nv, s));
+      HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
+    }
     if (begin > 0) {
       const int rc = timed(0, s, [&]() {
-        return launch_count_valu(W.jobs, n, begin, W.queue, lf32, lf_len, P_lo, P_hi, false, s) ==
+        return launch_count_valu(W.jobs, nv, begin, W.queue, lf32, lf_len, P_lo, P_hi, false, s) ==
                        hipSuccess
                    ? EPI3_OK
                    : EPI3_E_HIP;
@@ -944,25 +1003,21 @@ std::vector<uint64_t> signature(const epi3_job *jobs, int32_t n, int32_t variant
 
 extern "C" {
 
-int64_t epi3_batched_workspace_bytes(const epi3_job *jobs, int32_t n_jobs, int64_t cand_cap) {
-  const int rc = check_jobs(jobs, n_jobs);
+int64_t epi3_batched_workspace_bytes(const epi3_job *jobs, int32_t n_jobs, int32_t variant,
+                                     int64_t cand_cap) {
+  const int rc = check_jobs(jobs, n_jobs, variant);
   if (rc != EPI3_OK) return rc;
-  return batch_layout(nullptr, jobs, n_jobs, cand_cap).total;
+  return batch_layout(nullptr, jobs, n_jobs, cand_cap, variant).total;
 }
 
 int epi3_scan_batched(const epi3_job *jobs, int32_t n_jobs, int32_t variant, int64_t cand_cap,
                       void *ws_dev, int64_t ws_bytes, epi3_hit *hits_host, int32_t *n_out_host,
                       void *stream) {
-  int rc = check_jobs(jobs, n_jobs);
+  int rc = check_jobs(jobs, n_jobs, variant);
   if (rc != EPI3_OK) return rc;
   if (!ws_dev || !hits_host || !n_out_host) return EPI3_E_INVALID;
   if (reinterpret_cast<uintptr_t>(ws_dev) % kAlign) return EPI3_E_INVALID;
-  const int layout = jobs[0].d->layout;
-  if (layout == EPI3_LAYOUT_SPLIT && variant == EPI3_VARIANT_MFMA) return EPI3_E_UNSUPPORTED;
-  if (layout == EPI3_LAYOUT_MASKED && variant == EPI3_VARIANT_VALU) return EPI3_E_UNSUPPORTED;
-  if (layout == EPI3_LAYOUT_SPLIT && variant == EPI3_VARIANT_MFMA_FP4) return EPI3_E_UNSUPPORTED;
-  if (variant < EPI3_VARIANT_AUTO || variant > EPI3_VARIANT_MFMA_FP4) return EPI3_E_INVALID;
-  BatchLayout W = batch_layout(ws_dev, jobs, n_jobs, cand_cap);
+  BatchLayout W = batch_layout(ws_dev, jobs, n_jobs, cand_cap, variant);
   if (ws_bytes < W.total) return EPI3_E_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
 

@@ -76,7 +76,7 @@ def _load():
         "epi3_workspace_bytes": (i64, [P(CDataset), i32, i32, i64]),
         "epi3_scan": (ctypes.c_int, [P(CDataset), i32, i32, i64, vp, i64, vp]),
         "epi3_topk": (ctypes.c_int, [P(CDataset), i32, i64, vp, vp, P(i32), vp]),
-        "epi3_batched_workspace_bytes": (i64, [P(CJob), i32, i64]),
+        "epi3_batched_workspace_bytes": (i64, [P(CJob), i32, i32, i64]),
         "epi3_scan_batched": (ctypes.c_int, [P(CJob), i32, i32, i64, vp, i64, vp, vp, vp]),
         "epi3_scan_tables": (ctypes.c_int, [P(CDataset), i32, vp, vp, vp, i64, vp]),
         "epi3_score_triplets": (ctypes.c_int, [P(CDataset), vp, i64, vp, vp, vp, vp]),
@@ -411,7 +411,8 @@ class BatchScanner:
         self._alloc()
 
     def _alloc(self):
-        nbytes = _lib.epi3_batched_workspace_bytes(self.jobs, len(self.jobs), self.cand_cap)
+        nbytes = _lib.epi3_batched_workspace_bytes(self.jobs, len(self.jobs), self.variant,
+                                                   self.cand_cap)
         _check(int(nbytes) if nbytes < 0 else OK, "epi3_batched_workspace_bytes")
         self.ws = _buffer(nbytes, self.device)
         self.hits = (CHit * sum(self.ks))()

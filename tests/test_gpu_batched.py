@@ -191,3 +191,22 @@ def test_permutations_small_passes(env, variant):
     for q in range(5):
         ijk, k2, cc = oracle.scan_topk(d.geno, perms[q], 8)
         assert_hits_equal_oracle(res[q], ijk, k2, cc)
+
+
+@pytest.mark.parametrize("variant", ["auto", "mfma", "mfma_fp4"])
+def test_uneven_datasets_matrix_cores(env, variant):
+    """Data sets of different shapes in one batched call with matrix-core
+    counts (AUTO mixes them with the vector-ALU launch per the tile table);
+    graph replays repeat the hits."""
+    torch, epi3 = env
+    ds_host = make_uneven(5, seed=79, scale=0.3)
+    ds = [epi3.encode(to_dev(d.geno), d.pheno) for d in ds_host]
+    ks = [5, 12, 1, 7, 20]
+    bs = epi3.BatchScanner(ds, ks, variant=variant)
+    first = bs.run()
+    for d, h, k in zip(ds_host, first, ks):
+        ijk, k2, cc = oracle.scan_topk(d.geno, d.pheno, k)
+        assert_hits_equal_oracle(h, ijk, k2, cc)
+    again = bs.run()
+    for a, b in zip(first, again):
+        assert a.tobytes() == b.tobytes()
