@@ -25,7 +25,7 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kPermKB = 16;  // k values per wave tile (4 row tiles x 4 triplets)
-constexpr int kPermT = 4;    // row tiles per wave tile
+constexpr int kPermT = 4;    // row tiles per wave tile (one per lane of a quad)
 
 // k-blocks are aligned to multiples of kPermKB for every pivot, so tiles of
 // different j share (i-block, k-block) pairs; block kb of pivot j is global
@@ -215,6 +215,31 @@ struct PermAcc<true> {
   static __device__ __forceinline__ uint32_t get(const type &c, int v) { return (uint32_t)c[v]; }
 };
 
+// x from quad lane TT in every lane of each quad (DPP quad_perm broadcast;
+// the compiler folds it into the AND that consumes it).
+template <int TT>
+__device__ __forceinline__ v4i quad_bcast(v4i x) {
+  constexpr int sel = TT * 0x55;
+  v4i y;
+  y.x = __builtin_amdgcn_update_dpp(0, x.x, sel, 0xf, 0xf, true);
+  y.y = __builtin_amdgcn_update_dpp(0, x.y, sel, 0xf, 0xf, true);
+  y.z = __builtin_amdgcn_update_dpp(0, x.z, sel, 0xf, 0xf, true);
+  y.w = __builtin_amdgcn_update_dpp(0, x.w, sel, 0xf, 0xf, true);
+  return y;
+}
+
+// One 32-sample (int8) or 64-sample (FP4) step of row tile TT: A rows
+// X_i[a] & X_j[b] & X_k[c] for the tile's 4 triplets, the all-sample count of
+// each row, and the products with both 32-phenotype column tiles.
+template <int TT, typename Acc>
+__device__ __forceinline__ void perm_step_t(v4i p, v4i x, v4i b0, v4i b1, uint32_t &tot,
+                                            typename Acc::type (&acc)[2]) {
+  const v4i a = p & quad_bcast<TT>(x);
+  tot = popc4_acc(a, tot);
+  acc[0] = Acc::mma(a, b0, acc[0]);
+  acc[1] = Acc::mma(a, b1, acc[1]);
+}
+
 template <bool FP4>
 __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
     const PermJob *__restrict__ pjp, int64_t tile_begin, int64_t tile_end,
@@ -227,7 +252,11 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int r = lane & 31, g = lane >> 5;
-  const int ta = r >> 3, ra = (r >> 2) & 1, rb = (r >> 1) & 1, rc = r & 1;
+  // A row r of a row tile = (triplet ta = r / 8, corner c = (r / 4) % 2,
+  // a = (r / 2) % 2, b = r % 2): the four lanes of a quad share (ta, c) and
+  // differ in (a, b), so each lane loads the k row of a different row tile
+  // and the quad broadcasts it by DPP (one LDS read for the four row tiles)
+  const int ta = r >> 3, rc = (r >> 2) & 1, ra = (r >> 1) & 1, rb = r & 1;
   const int M = pj.M, S = pj.S;
   gptr<uint8_t> gb = (gptr<uint8_t>)pj.bytes;
   gptr<uint8_t> gph = (gptr<uint8_t>)pj.ph;
@@ -330,6 +359,7 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
     store(0);
     __syncthreads();
     const int prow = kRowsPH + kRowsXK + wave * 4 + (ra * 2 + rb);
+    const int xrow = kRowsPH + (4 * (r & 3) + ta) * 2 + rc;  // k row of row tile r % 4
     for (int ch = 0; ch < nch; ++ch) {
       if (ch + 1 < nch) fetch(ch + 1);
       const uint8_t *buf = stage + (ch & 1) * kStageBytes;
@@ -337,16 +367,13 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
       for (int stp = 0; stp < kKC / 32; ++stp) {
         const int off = stp * 32 + 16 * g;
         const v4i p = *reinterpret_cast<const v4i *>(buf + prow * kRow + off);
+        const v4i x = *reinterpret_cast<const v4i *>(buf + xrow * kRow + off);
         const v4i b0 = *reinterpret_cast<const v4i *>(buf + r * kRow + off);
         const v4i b1 = *reinterpret_cast<const v4i *>(buf + (32 + r) * kRow + off);
-#pragma unroll
-        for (int tt = 0; tt < kPermT; ++tt) {
-          const int xrow = kRowsPH + (4 * tt + ta) * 2 + rc;
-          const v4i a = p & *reinterpret_cast<const v4i *>(buf + xrow * kRow + off);
-          tot[tt] = popc4_acc(a, tot[tt]);
-          acc[tt][0] = Acc::mma(a, b0, acc[tt][0]);
-          acc[tt][1] = Acc::mma(a, b1, acc[tt][1]);
-        }
+        perm_step_t<0, Acc>(p, x, b0, b1, tot[0], acc[0]);
+        perm_step_t<1, Acc>(p, x, b0, b1, tot[1], acc[1]);
+        perm_step_t<2, Acc>(p, x, b0, b1, tot[2], acc[2]);
+        perm_step_t<3, Acc>(p, x, b0, b1, tot[3], acc[3]);
       }
       if (ch + 1 < nch) store((ch + 1) & 1);
       __syncthreads();
@@ -361,12 +388,12 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
 #pragma unroll
     for (int tt = 0; tt < kPermT; ++tt) {
       const uint32_t full = tot[tt] + __shfl_xor(tot[tt], 32);
-      if (g == 0) tot16[(4 * tt + ta) * 8 + (r & 7)] = (uint16_t)full;
+      if (g == 0) tot16[(4 * tt + ta) * 8 + 4 * ra + 2 * rb + rc] = (uint16_t)full;
     }
     // lane (q, h) holds, for each of the 4 triplets of a row tile, the 4 case
-    // cells with genotype a = h at SNP i: registers 4 t + (2 b + c).  Each lane
+    // cells with genotype c = h at SNP k: registers 4 t + (2 a + b).  Each lane
     // writes them as 4 x uint16; halves h = 0, 1 of one (triplet, phenotype)
-    // are adjacent, so the 16 bytes hold cells 4 a + 2 b + c in order.
+    // are adjacent, so the 16 bytes hold cells in the order 4 c + 2 a + b.
     uint2 *cor2 = reinterpret_cast<uint2 *>(cor);
 #pragma unroll
     for (int tt = 0; tt < kPermT; ++tt)
@@ -504,10 +531,11 @@ __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restr
       }
       int c4[27];
       {
-        const uint32_t cn[8] = {(cq.x << 2) & 0x3fffcu, (cq.x >> 14) & 0x3fffcu,
-                                (cq.y << 2) & 0x3fffcu, (cq.y >> 14) & 0x3fffcu,
-                                (cq.z << 2) & 0x3fffcu, (cq.z >> 14) & 0x3fffcu,
-                                (cq.w << 2) & 0x3fffcu, (cq.w >> 14) & 0x3fffcu};
+        // record order 4 c + 2 a + b -> corner index 4 a + 2 b + c; x 4
+        const uint32_t cn[8] = {(cq.x << 2) & 0x3fffcu, (cq.z << 2) & 0x3fffcu,
+                                (cq.x >> 14) & 0x3fffcu, (cq.z >> 14) & 0x3fffcu,
+                                (cq.y << 2) & 0x3fffcu, (cq.w << 2) & 0x3fffcu,
+                                (cq.y >> 14) & 0x3fffcu, (cq.w >> 14) & 0x3fffcu};
         const int aij[4] = {cij.x, cij.y, cij.z, cij.w}, aik[4] = {cik.x, cik.y, cik.z, cik.w};
         const int ajk[4] = {cjk.x, cjk.y, cjk.z, cjk.w};
         const int mi[2] = {cii.x, cii.w}, mj[2] = {cjj.x, cjj.w}, mk[2] = {ckk.x, ckk.w};

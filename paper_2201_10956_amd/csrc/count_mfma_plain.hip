@@ -52,6 +52,19 @@ __host__ __device__ __forceinline__ int64_t plain_jblocks(int64_t M, int JB) {
   return M < 3 ? 0 : (M - 1 + JB - 1) / JB;
 }
 
+// Lane n of every quad takes x from quad lane (SEL >> 2 n) & 3 (DPP
+// quad_perm; the compiler folds it into the instruction that consumes it
+// where it can).
+template <int SEL>
+__device__ __forceinline__ v4i quad_perm(v4i x) {
+  v4i y;
+  y.x = __builtin_amdgcn_update_dpp(0, x.x, SEL, 0xf, 0xf, true);
+  y.y = __builtin_amdgcn_update_dpp(0, x.y, SEL, 0xf, 0xf, true);
+  y.z = __builtin_amdgcn_update_dpp(0, x.z, SEL, 0xf, 0xf, true);
+  y.w = __builtin_amdgcn_update_dpp(0, x.w, SEL, 0xf, 0xf, true);
+  return y;
+}
+
 __device__ __forceinline__ int64_t rfl64q(int64_t v) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
   const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
@@ -163,6 +176,9 @@ __global__ void __launch_bounds__(256, 2) count_mfma_plain_kernel(
   // lane roles: A row r = 4 i8 + 2 a + b; B column r = 2 k16 + g_k
   const int ri8 = r >> 2, ra = (r >> 1) & 1, rb = r & 1;
   const int ck16 = r >> 1, cpl = r & 1;
+  // LDS byte offsets (within a buffer) of the rows this lane loads for its quad
+  const int xi_off = (2 * (8 * rb + ri8) + ra) * kPRow;
+  const int xj_off = (kRowsI + 2 * (2 * wj + ra) + rb) * kPRow;
 
   for (;;) {
     __syncthreads();
@@ -230,22 +246,25 @@ __global__ void __launch_bounds__(256, 2) count_mfma_plain_kernel(
 #pragma unroll 1
         for (int stp = 0; stp < kPKC / 32; ++stp) {
           const int off = stp * 32 + 16 * g;
-          v4i xi[2], xj[2], b[2];
-#pragma unroll
-          for (int x = 0; x < 2; ++x) {
-            xi[x] = *reinterpret_cast<const v4i *>(buf + (2 * (8 * x + ri8) + ra) * kPRow + off);
-            xj[x] = *reinterpret_cast<const v4i *>(buf + (kRowsI + 2 * (2 * wj + x) + rb) * kPRow + off);
-            b[x] = *reinterpret_cast<const v4i *>(
-                buf + (kRowsI + kRowsJ + 2 * (16 * (2 * wb + x) + ck16) + cpl) * kPRow + off);
-          }
+          // the quad (a, b) loads X_i[a] of i-block b and X_j[b] of pivot a;
+          // DPP hands each lane the two rows its A rows need
+          const v4i xiq = *reinterpret_cast<const v4i *>(buf + xi_off + off);
+          const v4i xjq = *reinterpret_cast<const v4i *>(buf + xj_off + off);
+          v4i b[2];
 #pragma unroll
           for (int x = 0; x < 2; ++x)
+            b[x] = *reinterpret_cast<const v4i *>(
+                buf + (kRowsI + kRowsJ + 2 * (16 * (2 * wb + x) + ck16) + cpl) * kPRow + off);
+          const v4i xi[2] = {quad_perm<0xA0>(xiq), quad_perm<0xF5>(xiq)};  // [0,0,2,2], [1,1,3,3]
 #pragma unroll
-            for (int y = 0; y < 2; ++y) {
-              const v4i a = xi[x] & xj[y];
-#pragma unroll
-              for (int z = 0; z < 2; ++z) acc[x][y][z] = Acc::mma(a, b[z], acc[x][y][z]);
-            }
+          for (int x = 0; x < 2; ++x) {
+            const v4i a0 = xi[x] & quad_perm<0x44>(xjq);  // [0,1,0,1]: X_j[b] of pivot 0
+            acc[x][0][0] = Acc::mma(a0, b[0], acc[x][0][0]);
+            acc[x][0][1] = Acc::mma(a0, b[1], acc[x][0][1]);
+            const v4i a1 = xi[x] & quad_perm<0xEE>(xjq);  // [2,3,2,3]: X_j[b] of pivot 1
+            acc[x][1][0] = Acc::mma(a1, b[0], acc[x][1][0]);
+            acc[x][1][1] = Acc::mma(a1, b[1], acc[x][1][1]);
+          }
         }
         if (ch + 1 < nch) store((ch + 1) & 1);
         __syncthreads();
