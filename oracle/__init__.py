@@ -36,6 +36,12 @@ def load(path: Optional[str] = None):
     lib.oracle_scan_topk.restype = i32
     lib.oracle_score_list.argtypes = [ptr, i64, ptr, i32, ptr, i64, i32, ptr, ptr]
     lib.oracle_scan_all.argtypes = [ptr, i64, ptr, i32, i32, i32, ptr, ptr]
+    lib.oracle_table2.argtypes = [ptr, i64, ptr, i32, i32, i32, ptr]
+    lib.oracle_k2_rows.argtypes = [ptr, i32, ptr]
+    lib.oracle_k2_rows.restype = ctypes.c_double
+    lib.oracle_scan_pairs_all.argtypes = [ptr, i64, ptr, i32, i32, i32, ptr, ptr]
+    lib.oracle_scan_pairs_topk.argtypes = [ptr, i64, ptr, i32, i32, i32, i32, ptr, ptr, ptr]
+    lib.oracle_scan_pairs_topk.restype = i32
     if path is None:
         _lib = lib
     return lib
@@ -128,3 +134,56 @@ def lex_triplets(M: int) -> np.ndarray:
             if ks.size:
                 out.append(np.stack([np.full_like(ks, i), np.full_like(ks, j), ks], axis=1))
     return np.concatenate(out) if out else np.zeros((0, 3), dtype=np.int32)
+
+
+# ---- second order: SNP pairs (9 rows per class, row 3 g_i + g_j) ----
+
+def pair_table(geno, pheno, i: int, j: int, lib=None) -> np.ndarray:
+    """[2][9] int32 frequency table of the pair (i, j); 0 = controls."""
+    lib = lib or load()
+    G, ph = _prep(geno, pheno)
+    t = np.empty((2, 9), dtype=np.int32)
+    lib.oracle_table2(_p(G), G.shape[1], _p(ph), G.shape[1], i, j, _p(t))
+    return t
+
+
+def k2_rows(t: np.ndarray, L: np.ndarray, lib=None) -> float:
+    """Eq. 1 for a [2][rows] table."""
+    lib = lib or load()
+    tt = np.ascontiguousarray(t, dtype=np.int32)
+    rows = tt.size // 2
+    LL = np.ascontiguousarray(L, dtype=np.float64)
+    return float(lib.oracle_k2_rows(_p(tt.reshape(-1)), rows, _p(LL)))
+
+
+def scan_pairs_all(geno, pheno, counts: bool = True, nthreads: Optional[int] = None, lib=None):
+    """All pairs in lexicographic order: (k2 [C(M,2)], tables [C(M,2)][2][9])."""
+    lib = lib or load()
+    G, ph = _prep(geno, pheno)
+    M, N = G.shape
+    P = M * (M - 1) // 2
+    kk = np.empty(P, dtype=np.float64)
+    cc = np.empty((P, 2, 9), dtype=np.int32) if counts else None
+    lib.oracle_scan_pairs_all(_p(G), N, _p(ph), M, N, nthreads or nthreads_default(), _p(kk),
+                              _p(cc) if cc is not None else None)
+    return kk, cc
+
+
+def scan_pairs_topk(geno, pheno, k: int, nthreads: Optional[int] = None, counts: bool = True,
+                    lib=None):
+    """k lowest (K2, i, j): returns (ij [n][2], k2 [n], tables [n][2][9])."""
+    lib = lib or load()
+    G, ph = _prep(geno, pheno)
+    M, N = G.shape
+    ij = np.zeros((max(k, 0), 2), dtype=np.int32)
+    kk = np.zeros(max(k, 0), dtype=np.float64)
+    cc = np.zeros((max(k, 0), 2, 9), dtype=np.int32) if counts else None
+    n = lib.oracle_scan_pairs_topk(_p(G), N, _p(ph), M, N, k, nthreads or nthreads_default(),
+                                   _p(ij), _p(kk), _p(cc) if cc is not None else None)
+    return ij[:n], kk[:n], (cc[:n] if cc is not None else None)
+
+
+def lex_pairs(M: int) -> np.ndarray:
+    """All (i, j), i < j < M, in lexicographic order, int32 [C(M,2)][2]."""
+    i, j = np.triu_indices(M, k=1)
+    return np.stack([i, j], axis=1).astype(np.int32)

@@ -25,6 +25,9 @@
  *     the total order (K2, i, j, k), all indices 0-based with i < j < k.
  *   - Every combination with i < j < k is evaluated (both algorithms guard
  *     on the strict order of the three SNP indices).
+ *   - The same for pairs of SNPs (3^2 = 9 rows per class, row 3 g_i + g_j),
+ *     Eq. 1 being stated for any number of interacting SNPs; see the
+ *     second-order section at the end.
  *
  * Parity of the K2 values with numbers printed in the paper is unpinned: the
  * paper prints none (its worked-example figure is not available).  The tests
@@ -244,4 +247,116 @@ void oracle_scan_all(const uint8_t *G, int64_t ld, const uint8_t *ph, int32_t M,
     }
     free(off);
     free(L);
+}
+
+/* -------- second order: SNP pairs --------
+ *
+ * Eq. 1 is stated for any number of interacting SNPs: with two SNPs the
+ * table has 3^2 = 9 rows per class, row 3 g_i + g_j, and K2 sums the same
+ * row term over those 9 rows.  Pairs are i < j, ordered by (K2, i, j).
+ */
+#define ROWS2 9
+
+/* Frequency table of one pair: t[class * 9 + 3 g_i + g_j]. */
+void oracle_table2(const uint8_t *G, int64_t ld, const uint8_t *ph, int32_t N,
+                   int32_t i, int32_t j, int32_t *t)
+{
+    memset(t, 0, sizeof(int32_t) * 2 * ROWS2);
+    const uint8_t *gi = G + (int64_t)i * ld, *gj = G + (int64_t)j * ld;
+    for (int32_t s = 0; s < N; ++s)
+        t[ph[s] * ROWS2 + 3 * gi[s] + gj[s]] += 1;
+}
+
+/* Eq. 1 for a table of `rows` rows (controls t[0..rows), cases t[rows..2 rows)),
+ * same bracketing and row order as oracle_k2. */
+double oracle_k2_rows(const int32_t *t, int32_t rows, const double *L)
+{
+    double k2 = 0.0;
+    for (int32_t c = 0; c < rows; ++c) {
+        int32_t p0 = t[c], p1 = t[rows + c];
+        k2 += L[p0 + p1 + 1] - (L[p0] + L[p1]);
+    }
+    return k2;
+}
+
+/* Every pair in lexicographic (i, j) order: K2 [C(M,2)] and, when non-NULL,
+ * tables [C(M,2)][18]. */
+void oracle_scan_pairs_all(const uint8_t *G, int64_t ld, const uint8_t *ph, int32_t M, int32_t N,
+                           int32_t nthreads, double *out_k2, int32_t *out_counts)
+{
+    if (M < 2) return;
+    double *L = (double *)malloc(sizeof(double) * ((size_t)N + 2));
+    oracle_log_factorial(N + 1, L);
+    int nt = nthreads > 0 ? nthreads : 1;
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 1)
+    for (int32_t i = 0; i < M - 1; ++i) {
+        /* pairs before row i: sum over i' < i of (M - 1 - i') */
+        int64_t x = (int64_t)i * (M - 1) - (int64_t)i * (i - 1) / 2;
+        int32_t t[2 * ROWS2];
+        for (int32_t j = i + 1; j < M; ++j, ++x) {
+            oracle_table2(G, ld, ph, N, i, j, t);
+            out_k2[x] = oracle_k2_rows(t, ROWS2, L);
+            if (out_counts) memcpy(out_counts + 2 * ROWS2 * x, t, sizeof(t));
+        }
+    }
+    free(L);
+}
+
+/* Exhaustive pair scan keeping the `topk` lowest under (K2, i, j); returns
+ * the number of hits (min(topk, C(M,2))) written to out_ij [n][2], out_k2 [n]
+ * and, when non-NULL, out_counts [n][18]. */
+int32_t oracle_scan_pairs_topk(const uint8_t *G, int64_t ld, const uint8_t *ph,
+                               int32_t M, int32_t N, int32_t topk, int32_t nthreads,
+                               int32_t *out_ij, double *out_k2, int32_t *out_counts)
+{
+    if (M < 2 || topk <= 0) return 0;
+    double *L = (double *)malloc(sizeof(double) * ((size_t)N + 2));
+    oracle_log_factorial(N + 1, L);
+    int nt = nthreads > 0 ? nthreads : 1;
+#ifndef _OPENMP
+    nt = 1;
+#endif
+    heap_t *heaps = (heap_t *)calloc((size_t)nt, sizeof(heap_t));
+    for (int t = 0; t < nt; ++t) {
+        heaps[t].h = (cand_t *)malloc(sizeof(cand_t) * (size_t)topk);
+        heaps[t].cap = topk;
+    }
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        heap_t *H = &heaps[tid];
+        int32_t t[2 * ROWS2];
+#pragma omp for schedule(dynamic, 1)
+        for (int32_t i = 0; i < M - 1; ++i)
+            for (int32_t j = i + 1; j < M; ++j) {
+                oracle_table2(G, ld, ph, N, i, j, t);
+                cand_t c = { oracle_k2_rows(t, ROWS2, L), i, j, 0 };
+                heap_push(H, c);
+            }
+    }
+    int64_t total = 0;
+    for (int t = 0; t < nt; ++t) total += heaps[t].n;
+    cand_t *all = (cand_t *)malloc(sizeof(cand_t) * (size_t)(total > 0 ? total : 1));
+    int64_t pos = 0;
+    for (int t = 0; t < nt; ++t) {
+        memcpy(all + pos, heaps[t].h, sizeof(cand_t) * (size_t)heaps[t].n);
+        pos += heaps[t].n;
+        free(heaps[t].h);
+    }
+    free(heaps);
+    qsort(all, (size_t)total, sizeof(cand_t), cand_cmp);
+    int32_t n = (int32_t)(total < topk ? total : topk);
+    for (int32_t x = 0; x < n; ++x) {
+        out_ij[2 * x + 0] = all[x].i;
+        out_ij[2 * x + 1] = all[x].j;
+        out_k2[x] = all[x].k2;
+        if (out_counts)
+            oracle_table2(G, ld, ph, N, all[x].i, all[x].j, out_counts + (int64_t)2 * ROWS2 * x);
+    }
+    free(all);
+    free(L);
+    return n;
 }

@@ -180,6 +180,87 @@ def test_planted_triplet_recovered(seed):
     assert k2[1] - k2[0] > 20.0
 
 
+# ---- second order: pairs of SNPs (9 rows per class) ----
+
+def _pair_tables_and_k2_vs_brute(lib, seeds=range(30)):
+    """Every pair table equals the brute-force tally; K2 equals ln Q."""
+    for seed in seeds:
+        M = 2 + seed % 7
+        N = 1 + (seed * 5) % 45
+        geno, pheno = tiny(700 + seed, M, N, p_case=(seed % 5) / 4.0)
+        k2, cc = oracle.scan_pairs_all(geno, pheno, lib=lib, nthreads=2)
+        for x, snps in enumerate(itertools.combinations(range(M), 2)):
+            t = brute.table(geno.tolist(), pheno.tolist(), snps)
+            assert cc[x].tolist() == t, (seed, snps)
+            want = brute.k2_exact(t)
+            assert abs(k2[x] - want) <= 1e-12 * max(1.0, abs(want)), (seed, snps, k2[x], want)
+
+
+def _pair_topk_vs_brute(lib, seeds=range(8)):
+    for seed in seeds:
+        M, N = 7 + seed % 4, 20 + 3 * seed
+        geno, pheno = tiny(800 + seed, M, N)
+        ij, k2, cc = oracle.scan_pairs_topk(geno, pheno, 9, lib=lib, nthreads=2)
+        full = brute.scan(geno.tolist(), pheno.tolist(), order=2)
+        full.sort(key=lambda r: (r[0], r[1]))
+        ref = full[:9]
+        assert [brute.q_value(c.tolist()) for c in cc] == [q for q, _, _ in ref]
+        allq = [r[0] for r in full]
+        for x in range(len(ref)):
+            assert cc[x].tolist() == brute.table(geno.tolist(), pheno.tolist(), tuple(ij[x]))
+            if allq.count(ref[x][0]) == 1:
+                assert tuple(ij[x]) == ref[x][1]
+
+
+def test_pair_tables_and_k2_match_bruteforce():
+    _pair_tables_and_k2_vs_brute(oracle.load())
+
+
+def test_pair_topk_matches_exact_integer_order():
+    _pair_topk_vs_brute(oracle.load(), seeds=range(12))
+
+
+def test_pair_tables_are_margins_of_triplet_tables():
+    """Summing a triplet table over one SNP's genotype gives the pair table of
+    the other two (ties the pair oracle to the triplet oracle)."""
+    d = make_dataset(9, 700, 0.4, 0.05, seed=12)
+    _, pcc = oracle.scan_pairs_all(d.geno, d.pheno)
+    idx = {tuple(int(v) for v in p): x for x, p in enumerate(oracle.lex_pairs(9))}
+    assert len(idx) == 36 and list(idx)[:3] == [(0, 1), (0, 2), (0, 3)]
+    for (i, j, k) in [(0, 1, 2), (2, 5, 8), (1, 3, 7), (4, 6, 8)]:
+        t = oracle.table(d.geno, d.pheno, i, j, k).reshape(2, 3, 3, 3)
+        assert np.array_equal(t.sum(axis=3).reshape(2, 9), pcc[idx[(i, j)]])
+        assert np.array_equal(t.sum(axis=2).reshape(2, 9), pcc[idx[(i, k)]])
+        assert np.array_equal(t.sum(axis=1).reshape(2, 9), pcc[idx[(j, k)]])
+        assert np.array_equal(oracle.pair_table(d.geno, d.pheno, i, j), pcc[idx[(i, j)]])
+
+
+@pytest.mark.parametrize("N,n1", [(1, 1), (64, 0), (1000, 413), (16384, 8192)])
+def test_pair_single_cell_closed_form(N, n1):
+    """All samples in one row: K2 = ln((N+1)! / (N0! N1!))."""
+    G = np.full((2, N), 1, dtype=np.uint8)
+    ph = np.zeros(N, dtype=np.uint8)
+    ph[:n1] = 1
+    ij, k2, cc = oracle.scan_pairs_topk(G, ph, 1)
+    want = math.lgamma(N + 2) - math.lgamma(N - n1 + 1) - math.lgamma(n1 + 1)
+    assert abs(k2[0] - want) <= 1e-12 * max(1.0, want)
+    assert cc[0][:, 3 * 1 + 1].tolist() == [N - n1, n1]
+    assert oracle.k2_rows(cc[0], oracle.log_factorial(N + 1)) == k2[0]
+
+
+def test_pair_edge_sizes_and_ties():
+    geno, pheno = tiny(4, 5, 20)
+    ij, _, _ = oracle.scan_pairs_topk(geno, pheno, 100)
+    assert len(ij) == 10                     # C(5,2)
+    assert len(oracle.scan_pairs_topk(geno[:1], pheno, 5)[0]) == 0
+    assert len(oracle.scan_pairs_topk(geno, pheno, 0)[0]) == 0
+    base, ph = tiny(21, 1, 50)
+    G = np.repeat(base, 5, axis=0)           # identical rows: equal K2, index order
+    ij, k2, _ = oracle.scan_pairs_topk(G, ph, 10)
+    assert np.all(k2 == k2[0])
+    assert [tuple(x) for x in ij] == list(itertools.combinations(range(5), 2))
+
+
 # ---- the pins above must catch plausible mistakes planted in the oracle ----
 
 MUTANTS = {
@@ -190,6 +271,10 @@ MUTANTS = {
     "log_index": ("L[n - 1] + log((double)n)", "L[n - 1] + log((double)n + 1.0)"),
     "row_digit_k": ("t[row[s] + gk[s]] += 1;", "t[row[s] + (gk[s] ? 1 : 0)] += 1;"),
     "guard_j": ("for (int32_t j = i + 1; j < M - 1; ++j) {", "for (int32_t j = i; j < M - 1; ++j) {"),
+    "pair_digits": ("3 * gi[s] + gj[s]", "gi[s] + 3 * gj[s]"),
+    "pair_plus_one": ("L[p0 + p1 + 1] - (L[p0] + L[p1])", "L[p0 + p1] - (L[p0] + L[p1])"),
+    "pair_guard": ("for (int32_t j = i + 1; j < M; ++j) {", "for (int32_t j = i; j < M; ++j) {"),
+    "pair_offset": ("(int64_t)i * (M - 1) - (int64_t)i * (i - 1) / 2", "(int64_t)i * (M - 1) - (int64_t)i * (i + 1) / 2"),
 }
 
 
@@ -203,6 +288,8 @@ def _pin_suite(lib) -> None:
         assert [brute.q_value(c.tolist()) for c in cc] == [r[0] for r in ref]
         for x in range(len(ref)):
             assert cc[x].tolist() == brute.table(geno.tolist(), pheno.tolist(), tuple(ijk[x]))
+    _pair_tables_and_k2_vs_brute(lib, seeds=range(10))
+    _pair_topk_vs_brute(lib, seeds=range(3))
     L = oracle.log_factorial(5000, lib=lib)
     assert abs(L[4000] - math.lgamma(4001.0)) < 1e-8
 
