@@ -208,6 +208,53 @@ int epi3_scan_batched(const epi3_job *jobs, int32_t n_jobs, int32_t variant, int
 int epi3_perm_pvalue(double observed_k2, const double *perm_min_k2, int32_t n_perm, double *p_out);
 
 /* ---------------------------------------------------------------------------
+ * Second-order scan: pairs of SNPs (SPLIT data sets).  Not the paper's target
+ * order, but Eq. 1 is stated for any number of interacting SNPs (I = 3^k rows);
+ * here I = 9.  A pair is (i, j), i < j < M; the table row of (g_i, g_j) is
+ * 3 g_i + g_j.  The four cells with g_i, g_j in {0, 1} of each class are the
+ * pairwise tables epi3_encode computes; the other five follow from the
+ * per-SNP counts and the class size.  Hits are the k lowest under (K2, i, j)
+ * with the same FP32 screen and FP64 re-score as the triplet scan (the
+ * re-score recounts the table from the bit planes).
+ * ------------------------------------------------------------------------ */
+
+/* One hit of a pair scan.  counts[c][3 g_i + g_j], c = 0 controls, 1 cases. */
+typedef struct {
+    uint32_t i, j;
+    float k2_f32;         /* FP32 screen value */
+    uint32_t reserved;
+    double k2;            /* FP64 value of Eq. 1 over the 9 rows, in row order */
+    uint32_t counts[2][9];
+} epi3_pair_hit;
+
+/* Number of pairs C(M,2). */
+int64_t epi3_n_pairs(int32_t n_snps);
+
+/* Upper bound on |K2_fp32 - K2_fp64| of a 9-row table of N samples. */
+double epi3_k2_error_bound_pairs(int32_t n_samples);
+
+/* Workspace bytes for epi3_scan_pairs + epi3_pairs_topk (cand_cap as for
+ * epi3_workspace_bytes).  EPI3_E_UNSUPPORTED for a MASKED data set. */
+int64_t epi3_pairs_workspace_bytes(const epi3_dataset *d, int32_t k, int64_t cand_cap);
+
+/* Score every pair (FP32, from the encoded pairwise tables) and select
+ * candidates; asynchronous.  ws_dev: 256-byte aligned device workspace of
+ * epi3_pairs_workspace_bytes(d, k, cand_cap) bytes. */
+int epi3_scan_pairs(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
+                    int64_t ws_bytes, void *stream);
+
+/* Copy min(k, C(M,2)) hits to hits_host [k]; *n_out receives the count.
+ * Synchronises `stream`; EPI3_E_CAPACITY as for epi3_topk. */
+int epi3_pairs_topk(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
+                    epi3_pair_hit *hits_host, int32_t *n_out, void *stream);
+
+/* Device address of the pair scan's FP32 score plane: K2_fp32 of every pair
+ * in lexicographic (i, j) order, C(M,2) floats, valid once the stream has run
+ * epi3_scan_pairs. */
+int epi3_pairs_score_plane(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
+                           float **plane_dev);
+
+/* ---------------------------------------------------------------------------
  * Test hooks.
  * ------------------------------------------------------------------------ */
 

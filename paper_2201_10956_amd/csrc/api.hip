@@ -220,6 +220,41 @@ ScanLayout scan_layout(void *ws, const epi3_dataset &d, int32_t k, int64_t cand_
   return L;
 }
 
+// Workspace of one pair scan.
+struct PairLayout {
+  SelJob *sel;
+  SelState *st;
+  uint32_t *hist;
+  float *score;
+  int64_t *cand;
+  CandRec *rec;
+  epi3_pair_hit *hits;
+  uint32_t *ckey;
+  int64_t *crank;
+  int64_t ccap;
+  int64_t cap;
+  int64_t total;
+};
+
+PairLayout pair_layout(void *ws, const epi3_dataset &d, int32_t k, int64_t cand_cap) {
+  PairLayout L{};
+  const int64_t P = c2(d.n_snps);
+  L.cap = default_cap(P, k, cand_cap);
+  Carver c(ws);
+  L.sel = c.take<SelJob>(1);
+  L.st = c.take<SelState>(1);
+  L.hist = c.take<uint32_t>(kHistBins);
+  L.score = c.take<float>(P);
+  L.cand = c.take<int64_t>(L.cap);
+  L.rec = c.take<CandRec>(L.cap);
+  L.hits = c.take<epi3_pair_hit>(std::max<int32_t>(k, 1));
+  L.ccap = compact_cap(P, L.cap);
+  L.ckey = c.take<uint32_t>(L.ccap);
+  L.crank = c.take<int64_t>(L.ccap);
+  L.total = c.size();
+  return L;
+}
+
 bool valid_dataset(const epi3_dataset *d) {
   return d && d->n_snps >= 0 && d->n_samples > 0 && d->planes && d->pairs && d->lf64 && d->lf32 &&
          d->status && (d->layout == EPI3_LAYOUT_SPLIT || d->layout == EPI3_LAYOUT_MASKED);
@@ -456,6 +491,16 @@ double epi3_k2_error_bound(int32_t n_samples) {
   return 32.0 * ldexp(1.0, -24) * log_factorial_at((int64_t)n_samples + 27);
 }
 
+double epi3_k2_error_bound_pairs(int32_t n_samples) {
+  // As for triplets with 9 rows: 4u L[r+1] per row, 8u sum_rows L[r+1] for
+  // the summation, sum_rows L[r+1] <= L[N + 9]; 14u L[N + 9] covers both plus
+  // the second-order terms and the FP64 evaluation's own rounding.
+  if (n_samples < 0) return 0.0;
+  return 14.0 * ldexp(1.0, -24) * log_factorial_at((int64_t)n_samples + 9);
+}
+
+int64_t epi3_n_pairs(int32_t n_snps) { return c2(n_snps); }
+
 int64_t epi3_encode_bytes(int32_t n_snps, int32_t n_cases, int32_t n_controls, int32_t layout) {
   if (n_snps < 0 || n_cases < 0 || n_controls < 0 || n_cases + n_controls <= 0) return EPI3_E_INVALID;
   if (layout != EPI3_LAYOUT_SPLIT && layout != EPI3_LAYOUT_MASKED) return EPI3_E_INVALID;
@@ -629,6 +674,73 @@ int epi3_scan_tables(const epi3_dataset *d, int32_t variant, uint32_t *counts_de
   HIP_OK(launch_fill_u32(&W.st->kmin, 0xffffffffu, 1, s));
   HIP_OK(launch_fill_u32(&W.st->kmax, 0u, 1, s));
   return enqueue_count(*d, variant, k2_dev, counts_dev ? counts_dev : nullptr, W, s);
+}
+
+int64_t epi3_pairs_workspace_bytes(const epi3_dataset *d, int32_t k, int64_t cand_cap) {
+  if (!valid_dataset(d) || k <= 0) return EPI3_E_INVALID;
+  if (d->layout != EPI3_LAYOUT_SPLIT) return EPI3_E_UNSUPPORTED;
+  return pair_layout(nullptr, *d, k, cand_cap).total;
+}
+
+int epi3_scan_pairs(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
+                    int64_t ws_bytes, void *stream) {
+  if (!valid_dataset(d) || k <= 0 || !ws_dev) return EPI3_E_INVALID;
+  if (d->layout != EPI3_LAYOUT_SPLIT) return EPI3_E_UNSUPPORTED;
+  if (reinterpret_cast<uintptr_t>(ws_dev) % kAlign) return EPI3_E_INVALID;
+  PairLayout W = pair_layout(ws_dev, *d, k, cand_cap);
+  if (ws_bytes < W.total) return EPI3_E_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t P = c2(d->n_snps);
+  SelJob S = make_seljob(*d, W.score, P, W.st, W.hist, W.cand, W.rec, nullptr, W.cap, k, W.ckey,
+                         W.crank, W.ccap);
+  S.order = 2;
+  S.pair_hits = W.hits;
+  S.err2 = 2.0 * epi3_k2_error_bound_pairs(d->n_samples);
+  HIP_OK(launch_write_seljobs(&S, 1, W.sel, s));
+  HIP_OK(launch_init_select(W.sel, 1, s));
+  if (P > 0) {
+    const int rc = timed(0, s, [&]() {
+      return launch_pair_scores(*d, W.score, &W.st->kmin, s) == hipSuccess ? EPI3_OK : EPI3_E_HIP;
+    });
+    if (rc != EPI3_OK) return rc;
+  }
+  return timed(1, s, [&]() {
+    return launch_select(W.sel, 1, P, W.cap, k, s) == hipSuccess ? EPI3_OK : EPI3_E_HIP;
+  });
+}
+
+int epi3_pairs_topk(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
+                    epi3_pair_hit *hits_host, int32_t *n_out, void *stream) {
+  if (!valid_dataset(d) || k <= 0 || !ws_dev || !hits_host || !n_out) return EPI3_E_INVALID;
+  if (d->layout != EPI3_LAYOUT_SPLIT) return EPI3_E_UNSUPPORTED;
+  PairLayout W = pair_layout(ws_dev, *d, k, cand_cap);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SelState st;
+  int32_t status = 0;
+  HIP_OK(hipMemcpyAsync(&st, W.st, sizeof(st), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(&status, d->status, sizeof(status), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  *n_out = 0;
+  if (status & 1) return EPI3_E_GENOTYPE;
+  if ((int64_t)st.ncand > W.cap) {
+    *n_out = (int32_t)std::min<unsigned long long>(st.ncand, 0x7fffffffull);
+    return EPI3_E_CAPACITY;
+  }
+  const int64_t keff = st.keff;
+  if (keff > 0) {
+    HIP_OK(hipMemcpyAsync(hits_host, W.hits, keff * sizeof(epi3_pair_hit), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+  }
+  *n_out = (int32_t)keff;
+  return EPI3_OK;
+}
+
+int epi3_pairs_score_plane(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
+                           float **plane_dev) {
+  if (!valid_dataset(d) || k <= 0 || !ws_dev || !plane_dev) return EPI3_E_INVALID;
+  if (d->layout != EPI3_LAYOUT_SPLIT) return EPI3_E_UNSUPPORTED;
+  *plane_dev = pair_layout(ws_dev, *d, k, cand_cap).score;
+  return EPI3_OK;
 }
 
 int epi3_score_triplets(const epi3_dataset *d, const uint32_t *ijk_dev, int64_t n,

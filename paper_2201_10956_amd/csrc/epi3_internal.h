@@ -30,6 +30,10 @@ __host__ __device__ __forceinline__ int64_t c3(int64_t x) {
 }
 
 // Lexicographic rank of i < j < k < M among all triplets.
+// Lexicographic rank of the pair (i, j), i < j < M.
+__host__ __device__ __forceinline__ int64_t pair_rank(int64_t M, int64_t i, int64_t j) {
+  return c2(M) - c2(M - i) + (j - i - 1);
+}
 __host__ __device__ __forceinline__ int64_t lex_base(int64_t M, int64_t i, int64_t j) {
   return c3(M) - c3(M - i) + c2(M - 1 - i) - c2(M - j) - j - 1;  // + k gives the rank
 }
@@ -150,6 +154,8 @@ struct SelJob {
   int32_t M, Mp, W0, W1, N0, N1;
   int32_t layout;
   int32_t k;
+  int32_t order;           // 2: pair scan (ranks of pairs, 9-row tables, pair_hits); else triplets
+  epi3_pair_hit *pair_hits;  // [k] (order 2)
 };
 
 // The 27 cells of one class from the 8 counted corner cells n[4a + 2b + c]
@@ -197,6 +203,22 @@ __device__ __forceinline__ void complete_table(const uint32_t n[8], const int pi
 }
 
 // Log-factorial table entry at byte offset b (b = 4 n for L[n]).
+// The 9 cells t[3 a + b] of one class of a pair (a, b in {0, 1, 2}) from the
+// counted cells n[2 a + b] (a, b in {0, 1}), the per-SNP counts mi[a], mj[b]
+// and the class size: every sample of the class is in exactly one row.
+__device__ __forceinline__ void pair_cells(const int n[4], const int mi[2], const int mj[2], int Nc,
+                                           int t[9]) {
+  t[0] = n[0];
+  t[1] = n[1];
+  t[3] = n[2];
+  t[4] = n[3];
+  t[2] = mi[0] - n[0] - n[1];
+  t[5] = mi[1] - n[2] - n[3];
+  t[6] = mj[0] - n[0] - n[2];
+  t[7] = mj[1] - n[1] - n[3];
+  t[8] = Nc - (t[0] + t[1] + t[2] + t[3] + t[4] + t[5] + t[6] + t[7]);
+}
+
 __device__ __forceinline__ float lf_at(const float *L, int b) {
   return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(L) + b);
 }
@@ -246,6 +268,9 @@ hipError_t launch_mask_bytes(const uint32_t *const *masks_dev, int32_t Q, int32_
 hipError_t launch_case_pairs(const uint32_t *planes, int32_t Mp, int32_t W,
                              const uint32_t *const *masks_dev, int32_t Q, int32_t Qp, int32_t *out,
                              hipStream_t s);
+// Pair scan: FP32 K2 of every pair of a SPLIT data set from its pairwise
+// tables, by lexicographic pair rank; key range into keyrange[0..1].
+hipError_t launch_pair_scores(const epi3_dataset &d, float *score, uint32_t *keyrange, hipStream_t s);
 int64_t host_perm_tiles(int64_t M);
 hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,
                                   unsigned long long *queue, bool fp4, hipStream_t s);

@@ -311,6 +311,56 @@ __device__ void triplet_table(const uint32_t *planes, const int32_t *pairs,
   }
 }
 
+// Pair (i, j) of lexicographic rank `rank` among the pairs of M SNPs.
+__device__ __forceinline__ void decode_pair_rank(int64_t M, int64_t rank, int &i, int &j) {
+  int lo = 0, hi = (int)M - 2;  // last i whose first rank <= rank
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pair_rank(M, mid, mid + 1) <= rank) lo = mid; else hi = mid - 1;
+  }
+  i = lo;
+  j = (int)(rank - pair_rank(M, i, i + 1)) + i + 1;
+}
+
+// Both 9-row tables of the pair (i, j) of a SPLIT data set, recounted from
+// the planes by the lanes of one wave: the four cells with genotypes in
+// {0, 1} and the per-SNP counts, then the rest by pair_cells.
+__device__ void pair_table(const uint32_t *planes, int64_t Mp, int W0, int W1, int N0, int N1,
+                           int i, int j, int tab[2][27]) {
+  const int lane = threadIdx.x & 63;
+  for (int c = 0; c < 2; ++c) {
+    const int w0 = c ? W0 : 0, w1 = c ? W0 + W1 : W0;
+    uint32_t a[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // n[2a + b] (4), mi[a] (2), mj[b] (2)
+    for (int w = w0 + lane; w < w1; w += 64) {
+      const uint2 *row = reinterpret_cast<const uint2 *>(planes) + (int64_t)w * Mp;
+      const uint2 xi = row[i], xj = row[j];
+      a[0] += __builtin_popcount(xi.x & xj.x);
+      a[1] += __builtin_popcount(xi.x & xj.y);
+      a[2] += __builtin_popcount(xi.y & xj.x);
+      a[3] += __builtin_popcount(xi.y & xj.y);
+      a[4] += __builtin_popcount(xi.x);
+      a[5] += __builtin_popcount(xi.y);
+      a[6] += __builtin_popcount(xj.x);
+      a[7] += __builtin_popcount(xj.y);
+    }
+    int v[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) v[p] = (int)wave_sum(a[p]);
+    const int n[4] = {v[0], v[1], v[2], v[3]}, mi[2] = {v[4], v[5]}, mj[2] = {v[6], v[7]};
+    pair_cells(n, mi, mj, c ? N1 : N0, tab[c]);
+  }
+}
+
+// Eq. 1 in FP64: rows in order, each row L[r + 1] - (L[r_0] + L[r_1]).
+__device__ __forceinline__ double k2_fp64_rows(const int tab[2][27], int rows, const double *L) {
+  double k2 = 0.0;
+  for (int x = 0; x < rows; ++x) {
+    const int r0 = tab[0][x], r1 = tab[1][x];
+    k2 += L[r0 + r1 + 1] - (L[r0] + L[r1]);
+  }
+  return k2;
+}
+
 // Eq. 1 in FP64: rows in order, each row L[r + 1] - (L[r_0] + L[r_1]).
 __device__ __forceinline__ double k2_fp64(const int tab[2][27], const double *L) {
   double k2 = 0.0;
@@ -331,9 +381,28 @@ __global__ void __launch_bounds__(256) rescore_kernel(const SelJob *__restrict__
   for (int64_t c = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); c < n;
        c += waves) {
     const int64_t rank = J.cand[c];
+    int tab[2][27];
+    if (J.order == 2) {
+      int i, j;
+      decode_pair_rank(J.M, rank, i, j);
+      pair_table(J.planes, J.Mp, J.W0, J.W1, J.N0, J.N1, i, j, tab);
+      if (lane == 0) {
+        CandRec &R = J.rec[c];
+        const double k2 = k2_fp64_rows(tab, 9, J.lf64);
+        R.key = (uint64_t)__double_as_longlong(k2);
+        R.rank = rank;
+        R.i = i; R.j = j; R.k = 0;
+        R.k2f = J.score[rank];
+        R.k2 = k2;
+        for (int x = 0; x < 9; ++x) {
+          R.counts[x] = (uint32_t)tab[0][x];
+          R.counts[27 + x] = (uint32_t)tab[1][x];
+        }
+      }
+      continue;
+    }
     int i, j, k;
     decode_rank(J.M, rank, i, j, k);
-    int tab[2][27];
     int N0 = J.N0, N1 = J.N1;
     if (J.n1_dev) {
       N1 = *J.n1_dev;
@@ -388,7 +457,18 @@ __global__ void __launch_bounds__(256) rank_kernel(const SelJob *__restrict__ sj
         pos += (kz < mykey) || (kz == mykey && srank[z] < myrank);
       }
     }
-    if (x < n && pos < keff) {
+    if (x < n && pos < keff && J.order == 2) {
+      const CandRec &R = J.rec[x];
+      epi3_pair_hit &H = J.pair_hits[pos];
+      H.i = R.i; H.j = R.j;
+      H.k2_f32 = R.k2f;
+      H.reserved = 0u;
+      H.k2 = R.k2;
+      for (int q = 0; q < 9; ++q) {
+        H.counts[0][q] = R.counts[q];
+        H.counts[1][q] = R.counts[27 + q];
+      }
+    } else if (x < n && pos < keff) {
       const CandRec &R = J.rec[x];
       epi3_hit &H = J.hits[pos];
       H.i = R.i; H.j = R.j; H.k = R.k;

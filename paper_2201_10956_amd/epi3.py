@@ -49,6 +49,12 @@ class CHit(ctypes.Structure):
                 ("counts", (ctypes.c_uint32 * 27) * 2)]
 
 
+class CPairHit(ctypes.Structure):
+    _fields_ = [("i", ctypes.c_uint32), ("j", ctypes.c_uint32), ("k2_f32", ctypes.c_float),
+                ("reserved", ctypes.c_uint32), ("k2", ctypes.c_double),
+                ("counts", (ctypes.c_uint32 * 9) * 2)]
+
+
 class CJob(ctypes.Structure):
     _fields_ = [("d", ctypes.POINTER(CDataset)), ("case_mask", ctypes.c_void_p),
                 ("k", ctypes.c_int32), ("reserved", ctypes.c_int32)]
@@ -57,6 +63,9 @@ class CJob(ctypes.Structure):
 HIT_DTYPE = np.dtype([("i", "<u4"), ("j", "<u4"), ("k", "<u4"), ("k2_f32", "<f4"),
                       ("k2", "<f8"), ("counts", "<u4", (2, 27))])
 assert HIT_DTYPE.itemsize == ctypes.sizeof(CHit) == 240
+PAIR_HIT_DTYPE = np.dtype([("i", "<u4"), ("j", "<u4"), ("k2_f32", "<f4"), ("reserved", "<u4"),
+                           ("k2", "<f8"), ("counts", "<u4", (2, 9))])
+assert PAIR_HIT_DTYPE.itemsize == ctypes.sizeof(CPairHit) == 96
 assert ctypes.sizeof(CDataset) == 96 and ctypes.sizeof(CJob) == 24
 
 
@@ -94,6 +103,12 @@ def _load():
         "epi3_set_pass_bytes": (ctypes.c_int, [i64]),
         "epi3_set_compact_cap": (ctypes.c_int, [i64]),
         "epi3_perm_pvalue": (ctypes.c_int, [ctypes.c_double, vp, i32, P(ctypes.c_double)]),
+        "epi3_n_pairs": (i64, [i32]),
+        "epi3_k2_error_bound_pairs": (ctypes.c_double, [i32]),
+        "epi3_pairs_workspace_bytes": (i64, [P(CDataset), i32, i64]),
+        "epi3_scan_pairs": (ctypes.c_int, [P(CDataset), i32, i64, vp, i64, vp]),
+        "epi3_pairs_topk": (ctypes.c_int, [P(CDataset), i32, i64, vp, vp, P(i32), vp]),
+        "epi3_pairs_score_plane": (ctypes.c_int, [P(CDataset), i32, i64, vp, P(vp)]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -108,7 +123,9 @@ EXPORTS = ("epi3_encode_bytes", "epi3_encode", "epi3_workspace_bytes", "epi3_sca
            "epi3_score_triplets", "epi3_score_plane", "epi3_k2_error_bound", "epi3_n_triplets", "epi3_release",
            "epi3_version", "epi3_timing_enable", "epi3_timing_query", "epi3_timing_reset",
            "epi3_tile_rule", "epi3_tile_rules_clear", "epi3_tile_for", "epi3_set_pass_bytes",
-           "epi3_perm_pvalue", "epi3_set_compact_cap")
+           "epi3_perm_pvalue", "epi3_set_compact_cap", "epi3_n_pairs", "epi3_k2_error_bound_pairs",
+           "epi3_pairs_workspace_bytes", "epi3_scan_pairs", "epi3_pairs_topk",
+           "epi3_pairs_score_plane")
 TILES_PATH = os.path.join(_HERE, "tiles.json")
 
 
@@ -317,6 +334,70 @@ class Scanner:
         off = (ptr.value or 0) - self.ws.data_ptr()
         T = n_triplets(self.ds.M)
         return self.ws[off: off + 4 * T].view(torch.float32)
+
+
+def n_pairs(M: int) -> int:
+    return int(_lib.epi3_n_pairs(int(M)))
+
+
+def k2_error_bound_pairs(N: int) -> float:
+    return float(_lib.epi3_k2_error_bound_pairs(int(N)))
+
+
+class PairScanner:
+    """Workspace + calls for repeated second-order (pair) scans of one SPLIT data set."""
+
+    def __init__(self, ds: Dataset, k: int, cand_cap: int = 0):
+        self.ds, self.k, self.cand_cap = ds, int(k), int(cand_cap)
+        self._alloc()
+
+    def _alloc(self):
+        nbytes = _lib.epi3_pairs_workspace_bytes(ctypes.byref(self.ds.c), self.k, self.cand_cap)
+        _check(int(nbytes) if nbytes < 0 else OK, "epi3_pairs_workspace_bytes")
+        self.ws = _buffer(nbytes, self.ds.buf.device)
+        self.hits = (CPairHit * max(self.k, 1))()
+
+    def scan(self, stream=None) -> None:
+        rc = _lib.epi3_scan_pairs(ctypes.byref(self.ds.c), self.k, self.cand_cap,
+                                  ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                  _stream(stream))
+        _check(rc, "epi3_scan_pairs")
+
+    def topk(self, stream=None):
+        n = ctypes.c_int32(0)
+        rc = _lib.epi3_pairs_topk(ctypes.byref(self.ds.c), self.k, self.cand_cap,
+                                  ctypes.c_void_p(self.ws.data_ptr()),
+                                  ctypes.cast(self.hits, ctypes.c_void_p), ctypes.byref(n),
+                                  _stream(stream))
+        return rc, n.value
+
+    def run(self, stream=None, retry: bool = True) -> np.ndarray:
+        self.scan(stream)
+        rc, n = self.topk(stream)
+        if rc == E_CAPACITY and retry:
+            self.cand_cap = int(n)
+            self._alloc()
+            return self.run(stream, retry=False)
+        _check(rc, "epi3_pairs_topk")
+        raw = np.frombuffer(self.hits, dtype=PAIR_HIT_DTYPE, count=len(self.hits))
+        return raw[:n].copy()
+
+    def score_plane(self):
+        """FP32 K2 of every pair (lexicographic order): a torch view into the workspace,
+        valid after scan()."""
+        torch = _torch()
+        ptr = ctypes.c_void_p(0)
+        rc = _lib.epi3_pairs_score_plane(ctypes.byref(self.ds.c), self.k, self.cand_cap,
+                                         ctypes.c_void_p(self.ws.data_ptr()), ctypes.byref(ptr))
+        _check(rc, "epi3_pairs_score_plane")
+        off = (ptr.value or 0) - self.ws.data_ptr()
+        P = n_pairs(self.ds.M)
+        return self.ws[off: off + 4 * P].view(torch.float32)
+
+
+def scan_pairs(ds: Dataset, k: int, cand_cap: int = 0, stream=None) -> np.ndarray:
+    """The k lowest (K2, i, j) pairs of a SPLIT data set (structured array, PAIR_HIT_DTYPE)."""
+    return PairScanner(ds, k, cand_cap).run(stream)
 
 
 def scan_topk(ds: Dataset, k: int, variant: str = "auto", cand_cap: int = 0, stream=None):

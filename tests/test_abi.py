@@ -186,3 +186,21 @@ def test_compact_cap_sizes_the_workspace(epi3):
         assert lib.epi3_set_compact_cap(-1) == epi3.E_INVALID
     finally:
         epi3.set_compact_cap(0)
+
+
+def test_pair_scan_host_side(epi3):
+    """Pair counts, the 9-row error bound and the pair workspace queries."""
+    lib = epi3._lib
+    assert epi3.n_pairs(0) == 0 and epi3.n_pairs(1) == 0 and epi3.n_pairs(2) == 1
+    assert epi3.n_pairs(2048) == math.comb(2048, 2)
+    for N in (1, 100, 16384):
+        want = 14 * 2.0 ** -24 * math.lgamma(N + 10)
+        assert epi3.k2_error_bound_pairs(N) == pytest.approx(want, rel=1e-12)
+        assert epi3.k2_error_bound_pairs(N) < epi3.k2_error_bound(N)
+    d = _fake_dataset(epi3, 300, 700, 900)
+    w = lib.epi3_pairs_workspace_bytes(ctypes.byref(d), 10, 0)
+    assert w >= 4 * math.comb(300, 2)
+    assert lib.epi3_pairs_workspace_bytes(ctypes.byref(d), 10, 100000) > w
+    assert lib.epi3_pairs_workspace_bytes(ctypes.byref(d), 0, 0) == epi3.E_INVALID
+    m = _fake_dataset(epi3, 300, 700, 900, layout=1)
+    assert lib.epi3_pairs_workspace_bytes(ctypes.byref(m), 10, 0) == epi3.E_UNSUPPORTED
