@@ -32,6 +32,7 @@ VALU_OPS_PER_ST = 16.0 / 32.0                  # 8 AND + 8 v_bcnt per triplet pe
 MFMA_I8_PEAK_TOPS = 5000.0                     # dense int8 matrix-core ops/s (MI355X)
 MFMA_FP4_PEAK_TFLOPS = 10100.0                 # dense FP4 matrix-core flop/s (MI355X)
 MFMA_OPS_PER_STQ = 16.0                        # 8 corner cells x (multiply + add) per sample-triplet-phenotype
+PAIR_OPS_PER_SP = 8.0 / 32.0                   # 4 AND + 4 v_bcnt per pair per 32 samples (pairwise tables)
 
 WORKLOADS = {
     "plain1": dict(cfg=1, kind="plain", desc="plain scan, 64 SNPs x 1024 samples (512 cases), top-10"),
@@ -39,6 +40,8 @@ WORKLOADS = {
     "plain3": dict(cfg=3, kind="plain", desc="plain scan, 2048 SNPs x 16384 samples (50% cases), top-1000"),
     "perm4": dict(cfg=4, kind="perm", desc="batched permutations: 1024 SNPs x 8192 samples (3277 cases), "
                   "64 phenotype permutations in one launch, top-10 each"),
+    "pairs3": dict(cfg=3, kind="pairs", desc="second-order (pair) scan, 2048 SNPs x 16384 samples "
+                   "(50% cases), top-1000"),
     "uneven5": dict(cfg=5, kind="uneven", desc="batched uneven data sets: 32 data sets, SNPs ~ U[128,1024], "
                     "samples ~ U[1024,16384], one launch, top-10 each"),
 }
@@ -153,6 +156,82 @@ def run_plain(args, wl):
                    "k2": float(hits["k2"][0])}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d, k, args.cpu_budget)
+    return out
+
+
+def cpu_baseline_pairs(d, k: int, budget_s: float = 20.0) -> dict:
+    """The oracle's pair scan timed on the first M' SNPs (all of them when the
+    whole scan fits the budget)."""
+    import oracle
+    from math import comb
+    cores = cpu_cores()
+    N = d.n_samples
+    m0 = min(d.n_snps, 256)
+    t0 = time.perf_counter()
+    oracle.scan_pairs_topk(d.geno[:m0], d.pheno, k, nthreads=cores, counts=False)
+    rate = comb(m0, 2) * N / max(time.perf_counter() - t0, 1e-6)
+    m = m0
+    while m < d.n_snps and comb(m + 1, 2) * N / rate < budget_s:
+        m += 1
+    t0 = time.perf_counter()
+    oracle.scan_pairs_topk(d.geno[:m], d.pheno, k, nthreads=cores, counts=False)
+    dt = time.perf_counter() - t0
+    work = comb(m, 2) * N
+    return {"value": work / dt / 1e12, "unit": "T sample-pairs/s", "cores": cores,
+            "kind": "oracle", "seconds": round(dt, 3),
+            "sample": f"first {m} of {d.n_snps} SNPs x all {N} samples, top-{k} "
+                      f"({work:.3e} sample-pairs)"}
+
+
+def run_pairs(args, wl):
+    import torch
+    from paper_2201_10956_amd import epi3
+    from synth import CONFIGS, make_config
+
+    c = CONFIGS[wl["cfg"]]
+    d = make_config(wl["cfg"])
+    M, N, k = d.n_snps, d.n_samples, c["k"]
+    geno = torch.from_numpy(d.geno).to("cuda")
+    ds = epi3.encode(geno, d.pheno)
+    sc = epi3.PairScanner(ds, k)
+
+    def step():  # encode (planes + pairwise tables) + pair scores + exact top-k
+        epi3.encode(geno, d.pheno, into=ds)
+        return sc.run()
+
+    dt, hits = _timed_steps(step, args.steps, args.warmup)
+    torch.cuda.synchronize()
+    epi3.timing_reset()
+    epi3.timing_enable(True)
+    reps = 2
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    epi3.timing_enable(False)
+    pt_ms, pt_n = epi3.timing_query(4)
+    sc_ms, _ = epi3.timing_query(0)
+    se_ms, _ = epi3.timing_query(1)
+    P = epi3.n_pairs(M)
+    work = P * N
+    out = _base(args, wl, work / dt / 1e12, dt * 1e3, "u32", {
+        "workload": wl["desc"], "snps": M, "samples": N, "cases": int(d.pheno.sum()),
+        "top_k": k, "pairs": P})
+    out["metric"] = "tera sample-pairs/s at exact top-k (second-order scan)"
+    out["unit"] = "T sample-pairs/s"
+    ops = work * PAIR_OPS_PER_SP
+    kern_ms = pt_ms / max(pt_n, 1)
+    achieved = ops / (kern_ms / 1e3) / 1e12
+    out["roofline"] = {
+        "bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
+        "unit": "T int32-lane-ops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+        "traffic": recorded_traffic(f"{args.workload}|valu"),
+        "traffic_unit": "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
+        "kernel": "pairs_kernel", "kernel_ms": round(kern_ms, 4), "ops_per_launch": ops}
+    out["breakdown_ms"] = {"pairwise_tables": round(pt_ms / reps, 4),
+                           "pair_scores": round(sc_ms / reps, 4), "selection": round(se_ms / reps, 4)}
+    out["best"] = {"ij": [int(hits["i"][0]), int(hits["j"][0])], "k2": float(hits["k2"][0])}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_pairs(d, k, args.cpu_budget)
     return out
 
 
@@ -394,7 +473,7 @@ def main():
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
     wl = WORKLOADS[args.workload]
-    run = {"plain": run_plain, "perm": run_perm, "uneven": run_uneven}[wl["kind"]]
+    run = {"plain": run_plain, "perm": run_perm, "uneven": run_uneven, "pairs": run_pairs}[wl["kind"]]
     out = run(args, wl)
     print(json.dumps(out), flush=True)
 

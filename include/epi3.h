@@ -283,8 +283,9 @@ void epi3_release(void);
 /* Kernel timing for measurement: while enabled, the library records a HIP
  * event pair on the call's stream around each launch of the count stage
  * (which = 0), of the selection pipeline (which = 1), of a whole batched
- * scan (which = 2) and of the table-completion/scoring kernel that follows the
- * matrix-core count of phenotype batches (which = 3); batched scans run without graph capture while timing is
+ * scan (which = 2), of the table-completion/scoring kernel that follows the
+ * matrix-core count of phenotype batches (which = 3) and of the pairwise-table
+ * kernel of epi3_encode (which = 4); batched scans run without graph capture while timing is
  * enabled so that their kernels can be timed.  epi3_timing_query waits for the
  * recorded events and returns the summed milliseconds and the number of
  * launches since the last reset.  Off by default. */

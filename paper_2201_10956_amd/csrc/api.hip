@@ -354,7 +354,7 @@ struct Timing {
   std::mutex mu;
   bool on = false;
   std::vector<hipEvent_t> pool;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[4];  // 0: count, 1: selection, 2: batched, 3: finish
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[5];  // 0: count, 1: selection, 2: batched, 3: finish, 4: pairwise tables
 };
 Timing &timing() {
   static Timing t;
@@ -551,8 +551,13 @@ int epi3_encode(const uint8_t *geno_dev, int64_t ld, const uint8_t *pheno_host, 
   else
     HIP_OK(launch_encode_values(geno_dev, ld, L.list, 0, n0, L.W0 * 32, n1, 2, n_snps, L.Mp, L.S,
                                 L.bytes, L.nibbles, s));
-  HIP_OK(launch_pairs(L.planes, L.Mp, n_snps, L.W0, layout == EPI3_LAYOUT_SPLIT ? L.W1 : 0,
-                      L.classes, nullptr, L.pairs, s));
+  const int prc = timed(4, s, [&]() {
+    return launch_pairs(L.planes, L.Mp, n_snps, L.W0, layout == EPI3_LAYOUT_SPLIT ? L.W1 : 0,
+                        L.classes, nullptr, L.pairs, s) == hipSuccess
+               ? EPI3_OK
+               : EPI3_E_HIP;
+  });
+  if (prc != EPI3_OK) return prc;
   HIP_OK(hipStreamSynchronize(s));  // host vectors above must outlive the copies
 
   memset(out, 0, sizeof(*out));
@@ -1272,7 +1277,7 @@ void epi3_timing_enable(int enable) {
 }
 
 int epi3_timing_query(int32_t which, double *ms, int64_t *launches) {
-  if (which < 0 || which > 3 || !ms || !launches) return EPI3_E_INVALID;
+  if (which < 0 || which > 4 || !ms || !launches) return EPI3_E_INVALID;
   Timing &t = timing();
   std::lock_guard<std::mutex> g(t.mu);
   double sum = 0.0;

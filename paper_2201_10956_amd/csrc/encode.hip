@@ -137,43 +137,54 @@ __global__ void __launch_bounds__(256) encode_values_kernel(
   }
 }
 
-// Pairwise tables: pairs[c][x][y] = (n(0,0), n(0,1), n(1,0), n(1,1)) with
-// n(a,b) = number of class-c samples where SNP x has genotype a and SNP y has
-// genotype b.  The diagonal holds the per-SNP counts (n_x(0), 0, 0, n_x(1)).
-// With `mask`, only samples whose mask bit is set are counted (one class).
-// One wave per (x, 64 consecutive y); x is wave-uniform so its words are
-// scalar loads.
+// Pairwise tables out[c][x][y] = (n00, n01, n10, n11), n_ab = number of
+// samples of class c with genotype a at SNP x and b at SNP y (a, b in {0, 1}),
+// by AND + POPCNT over the class's words (the MASKED layout's case tables
+// restrict x to the mask's samples).  The diagonal holds the per-SNP counts
+// (n_x(0), 0, 0, n_x(1)).  Workgroup tile: 64 x by 64 y, 16 x per
+// wave read as wave-uniform scalars, y = lane; a word of y planes feeds 64
+// AND + 64 popcounts.  Only tiles on or above the diagonal count; each writes
+// (x, y) and its mirror (y, x) = (n00, n10, n01, n11).
+constexpr int kPairX = 16;  // x rows per wave
+
 __global__ void __launch_bounds__(256) pairs_kernel(const uint32_t *__restrict__ planes, int32_t Mp,
                                                     int32_t W0, int32_t W1,
                                                     const uint32_t *__restrict__ mask,
                                                     int32_t *__restrict__ pairs) {
+  const int xb = blockIdx.y, yb = blockIdx.x;
+  if (yb < xb) return;  // below the diagonal: written as mirrors
   const int lane = threadIdx.x & 63;
-  const int x = __builtin_amdgcn_readfirstlane(blockIdx.y * 4 + (threadIdx.x >> 6));
-  const int y = blockIdx.x * 64 + lane;
+  const int x0 = __builtin_amdgcn_readfirstlane(xb * 64 + (threadIdx.x >> 6) * kPairX);
+  const int y = yb * 64 + lane;
   const int c = blockIdx.z;
-  if (x >= Mp) return;
   const int w0 = c == 0 ? 0 : W0;
   const int w1 = c == 0 ? W0 : W0 + W1;
-  uint32_t n00 = 0, n01 = 0, n10 = 0, n11 = 0;
+  uint32_t acc[kPairX][4];
+#pragma unroll
+  for (int r = 0; r < kPairX; ++r) acc[r][0] = acc[r][1] = acc[r][2] = acc[r][3] = 0u;
   cptr<uint32_t> pc = as_const(planes);
   const uint2 *pv = reinterpret_cast<const uint2 *>(planes);
   for (int w = w0; w < w1; ++w) {
-    uint32_t x0 = pc[((int64_t)w * Mp + x) * 2 + 0];
-    uint32_t x1 = pc[((int64_t)w * Mp + x) * 2 + 1];
-    if (mask) {
-      const uint32_t mk = as_const(mask)[w];
-      x0 &= mk;
-      x1 &= mk;
+    const uint2 yv = pv[(int64_t)w * Mp + y];
+    const uint32_t mk = mask ? as_const(mask)[w] : 0xffffffffu;
+    cptr<uint32_t> xr = pc + ((int64_t)w * Mp + x0) * 2;
+#pragma unroll
+    for (int r = 0; r < kPairX; ++r) {
+      const uint32_t a0 = xr[2 * r] & mk, a1 = xr[2 * r + 1] & mk;
+      acc[r][0] += __builtin_popcount(a0 & yv.x);
+      acc[r][1] += __builtin_popcount(a0 & yv.y);
+      acc[r][2] += __builtin_popcount(a1 & yv.x);
+      acc[r][3] += __builtin_popcount(a1 & yv.y);
     }
-    const uint2 yv = (y < Mp) ? pv[(int64_t)w * Mp + y] : make_uint2(0u, 0u);
-    n00 += __builtin_popcount(x0 & yv.x);
-    n01 += __builtin_popcount(x0 & yv.y);
-    n10 += __builtin_popcount(x1 & yv.x);
-    n11 += __builtin_popcount(x1 & yv.y);
   }
-  if (y < Mp)
-    reinterpret_cast<int4 *>(pairs)[((int64_t)c * Mp + x) * Mp + y] =
-        make_int4((int)n00, (int)n01, (int)n10, (int)n11);
+  int4 *out = reinterpret_cast<int4 *>(pairs) + (int64_t)c * Mp * Mp;
+#pragma unroll
+  for (int r = 0; r < kPairX; ++r) {
+    const int x = x0 + r;
+    out[(int64_t)x * Mp + y] = make_int4((int)acc[r][0], (int)acc[r][1], (int)acc[r][2], (int)acc[r][3]);
+    if (y != x)
+      out[(int64_t)y * Mp + x] = make_int4((int)acc[r][0], (int)acc[r][2], (int)acc[r][1], (int)acc[r][3]);
+  }
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n) {
@@ -225,7 +236,8 @@ hipError_t launch_encode_values(const uint8_t *geno, int64_t ld, const int32_t *
 hipError_t launch_pairs(const uint32_t *planes, int32_t Mp, int32_t M, int32_t W0, int32_t W1,
                         int32_t n_classes, const uint32_t *mask, int32_t *pairs, hipStream_t s) {
   (void)M;
-  dim3 grid((Mp + 63) / 64, (Mp + 3) / 4, n_classes);
+  if (Mp % 64 != 0) return hipErrorInvalidValue;  // tiles of 64 x 64 SNPs cover the stride exactly
+  dim3 grid(Mp / 64, Mp / 64, n_classes);
   hipLaunchKernelGGL(pairs_kernel, grid, dim3(256), 0, s, planes, Mp, W0, W1, mask, pairs);
   return hipGetLastError();
 }
