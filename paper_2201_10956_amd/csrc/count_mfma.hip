@@ -124,8 +124,10 @@ __global__ void __launch_bounds__(256) mask_bytes_kernel(const uint32_t *const *
 }
 
 // Case pairs of every phenotype: out[x][y][q] = (n(0,0), n(0,1), n(1,0), n(1,1))
-// over the samples whose bit is set in mask q.  One wave per (x, 64 y); the
-// block's z index selects a group of 16 phenotypes.
+// over the samples whose bit is set in mask q, for y >= x (every reader looks
+// up pairs in increasing SNP order, and the diagonal for the per-SNP counts;
+// waves whose 64 y all lie below x write nothing).  One wave per (x, 64 y);
+// the block's z index selects a group of 16 phenotypes.
 __global__ void __launch_bounds__(256) case_pairs_kernel(const uint32_t *__restrict__ planes,
                                                          int32_t Mp, int32_t W,
                                                          const uint32_t *const *masks, int32_t Q,
@@ -134,7 +136,7 @@ __global__ void __launch_bounds__(256) case_pairs_kernel(const uint32_t *__restr
   const int x = __builtin_amdgcn_readfirstlane(blockIdx.y * 4 + (threadIdx.x >> 6));
   const int y = blockIdx.x * 64 + lane;
   const int q0 = blockIdx.z * 16;
-  if (x >= Mp) return;
+  if (x >= Mp || (int)blockIdx.x * 64 + 63 < x) return;
   uint32_t acc[16][4];
 #pragma unroll
   for (int t = 0; t < 16; ++t) acc[t][0] = acc[t][1] = acc[t][2] = acc[t][3] = 0u;
