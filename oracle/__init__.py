@@ -42,6 +42,10 @@ def load(path: Optional[str] = None):
     lib.oracle_scan_pairs_all.argtypes = [ptr, i64, ptr, i32, i32, i32, ptr, ptr]
     lib.oracle_scan_pairs_topk.argtypes = [ptr, i64, ptr, i32, i32, i32, i32, ptr, ptr, ptr]
     lib.oracle_scan_pairs_topk.restype = i32
+    lib.oracle_table4.argtypes = [ptr, i64, ptr, i32, i32, i32, i32, i32, ptr]
+    lib.oracle_scan_quads_all.argtypes = [ptr, i64, ptr, i32, i32, i32, ptr, ptr]
+    lib.oracle_scan_quads_topk.argtypes = [ptr, i64, ptr, i32, i32, i32, i32, ptr, ptr, ptr]
+    lib.oracle_scan_quads_topk.restype = i32
     if path is None:
         _lib = lib
     return lib
@@ -187,3 +191,47 @@ def lex_pairs(M: int) -> np.ndarray:
     """All (i, j), i < j < M, in lexicographic order, int32 [C(M,2)][2]."""
     i, j = np.triu_indices(M, k=1)
     return np.stack([i, j], axis=1).astype(np.int32)
+
+
+# ---- fourth order: SNP quads (81 rows per class, row 27 g_i + 9 g_j + 3 g_k + g_l) ----
+
+def quad_table(geno, pheno, i: int, j: int, k: int, l: int, lib=None) -> np.ndarray:
+    """[2][81] int32 frequency table of the quad (i, j, k, l); 0 = controls."""
+    lib = lib or load()
+    G, ph = _prep(geno, pheno)
+    t = np.empty((2, 81), dtype=np.int32)
+    lib.oracle_table4(_p(G), G.shape[1], _p(ph), G.shape[1], i, j, k, l, _p(t))
+    return t
+
+
+def scan_quads_all(geno, pheno, counts: bool = True, nthreads: Optional[int] = None, lib=None):
+    """All quads in lexicographic order: (k2 [C(M,4)], tables [C(M,4)][2][81])."""
+    lib = lib or load()
+    G, ph = _prep(geno, pheno)
+    M, N = G.shape
+    Q = M * (M - 1) * (M - 2) * (M - 3) // 24
+    kk = np.empty(Q, dtype=np.float64)
+    cc = np.empty((Q, 2, 81), dtype=np.int32) if counts else None
+    lib.oracle_scan_quads_all(_p(G), N, _p(ph), M, N, nthreads or nthreads_default(), _p(kk),
+                              _p(cc) if cc is not None else None)
+    return kk, cc
+
+
+def scan_quads_topk(geno, pheno, k: int, nthreads: Optional[int] = None, counts: bool = True,
+                    lib=None):
+    """k lowest (K2, i, j, k, l): returns (ijkl [n][4], k2 [n], tables [n][2][81])."""
+    lib = lib or load()
+    G, ph = _prep(geno, pheno)
+    M, N = G.shape
+    q = np.zeros((max(k, 0), 4), dtype=np.int32)
+    kk = np.zeros(max(k, 0), dtype=np.float64)
+    cc = np.zeros((max(k, 0), 2, 81), dtype=np.int32) if counts else None
+    n = lib.oracle_scan_quads_topk(_p(G), N, _p(ph), M, N, k, nthreads or nthreads_default(),
+                                   _p(q), _p(kk), _p(cc) if cc is not None else None)
+    return q[:n], kk[:n], (cc[:n] if cc is not None else None)
+
+
+def lex_quads(M: int) -> np.ndarray:
+    """All (i, j, k, l), i < j < k < l < M, in lexicographic order, int32 [C(M,4)][4]."""
+    import itertools
+    return np.array(list(itertools.combinations(range(M), 4)), dtype=np.int32).reshape(-1, 4)

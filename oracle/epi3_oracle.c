@@ -25,9 +25,10 @@
  *     the total order (K2, i, j, k), all indices 0-based with i < j < k.
  *   - Every combination with i < j < k is evaluated (both algorithms guard
  *     on the strict order of the three SNP indices).
- *   - The same for pairs of SNPs (3^2 = 9 rows per class, row 3 g_i + g_j),
- *     Eq. 1 being stated for any number of interacting SNPs; see the
- *     second-order section at the end.
+ *   - The same for pairs of SNPs (3^2 = 9 rows per class, row 3 g_i + g_j)
+ *     and quads (3^4 = 81 rows, row 27 g_i + 9 g_j + 3 g_k + g_l), Eq. 1
+ *     being stated for any number of interacting SNPs; see the second- and
+ *     fourth-order sections at the end.
  *
  * Parity of the K2 values with numbers printed in the paper is unpinned: the
  * paper prints none (its worked-example figure is not available).  The tests
@@ -357,6 +358,143 @@ int32_t oracle_scan_pairs_topk(const uint8_t *G, int64_t ld, const uint8_t *ph,
             oracle_table2(G, ld, ph, N, all[x].i, all[x].j, out_counts + (int64_t)2 * ROWS2 * x);
     }
     free(all);
+    free(L);
+    return n;
+}
+
+/* -------- fourth order: SNP quads --------
+ *
+ * Four interacting SNPs: 3^4 = 81 rows per class, row 27 g_i + 9 g_j +
+ * 3 g_k + g_l, i < j < k < l, ordered by (K2, i, j, k, l).
+ */
+#define ROWS4 81
+
+typedef struct { double k2; int32_t i, j, k, l; } cand4_t;
+
+static int cand4_less(const cand4_t *a, const cand4_t *b)
+{
+    if (a->k2 != b->k2) return a->k2 < b->k2;
+    if (a->i != b->i) return a->i < b->i;
+    if (a->j != b->j) return a->j < b->j;
+    if (a->k != b->k) return a->k < b->k;
+    return a->l < b->l;
+}
+
+static int cand4_cmp(const void *a, const void *b)
+{
+    const cand4_t *x = (const cand4_t *)a, *y = (const cand4_t *)b;
+    if (cand4_less(x, y)) return -1;
+    if (cand4_less(y, x)) return 1;
+    return 0;
+}
+
+/* Frequency table of one quad: t[class * 81 + 27 g_i + 9 g_j + 3 g_k + g_l]. */
+void oracle_table4(const uint8_t *G, int64_t ld, const uint8_t *ph, int32_t N,
+                   int32_t i, int32_t j, int32_t k, int32_t l, int32_t *t)
+{
+    memset(t, 0, sizeof(int32_t) * 2 * ROWS4);
+    const uint8_t *gi = G + (int64_t)i * ld, *gj = G + (int64_t)j * ld;
+    const uint8_t *gk = G + (int64_t)k * ld, *gl = G + (int64_t)l * ld;
+    for (int32_t s = 0; s < N; ++s)
+        t[ph[s] * ROWS4 + 27 * gi[s] + 9 * gj[s] + 3 * gk[s] + gl[s]] += 1;
+}
+
+/* Every quad in lexicographic (i, j, k, l) order: K2 [C(M,4)] and, when
+ * non-NULL, tables [C(M,4)][162].  For small inputs only. */
+void oracle_scan_quads_all(const uint8_t *G, int64_t ld, const uint8_t *ph, int32_t M, int32_t N,
+                           int32_t nthreads, double *out_k2, int32_t *out_counts)
+{
+    if (M < 4) return;
+    double *L = (double *)malloc(sizeof(double) * ((size_t)N + 2));
+    oracle_log_factorial(N + 1, L);
+    /* offset of the first quad with a given i: sum over i' < i of C(M-1-i', 3) */
+    int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (size_t)M);
+    int64_t acc = 0;
+    for (int32_t i = 0; i < M; ++i) {
+        off[i] = acc;
+        int64_t rest = M - 1 - i;
+        acc += rest * (rest - 1) * (rest - 2) / 6;
+    }
+    int nt = nthreads > 0 ? nthreads : 1;
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 1)
+    for (int32_t i = 0; i < M - 3; ++i) {
+        int64_t x = off[i];
+        int32_t t[2 * ROWS4];
+        for (int32_t j = i + 1; j < M - 2; ++j)
+            for (int32_t k = j + 1; k < M - 1; ++k)
+                for (int32_t l = k + 1; l < M; ++l, ++x) {
+                    oracle_table4(G, ld, ph, N, i, j, k, l, t);
+                    out_k2[x] = oracle_k2_rows(t, ROWS4, L);
+                    if (out_counts) memcpy(out_counts + 2 * ROWS4 * x, t, sizeof(t));
+                }
+    }
+    free(off);
+    free(L);
+}
+
+/* Exhaustive quad scan keeping the `topk` lowest under (K2, i, j, k, l):
+ * returns min(topk, C(M,4)) hits in out_ijkl [n][4], out_k2 [n] and, when
+ * non-NULL, out_counts [n][162]. */
+int32_t oracle_scan_quads_topk(const uint8_t *G, int64_t ld, const uint8_t *ph,
+                               int32_t M, int32_t N, int32_t topk, int32_t nthreads,
+                               int32_t *out_ijkl, double *out_k2, int32_t *out_counts)
+{
+    if (M < 4 || topk <= 0) return 0;
+    double *L = (double *)malloc(sizeof(double) * ((size_t)N + 2));
+    oracle_log_factorial(N + 1, L);
+    int nt = nthreads > 0 ? nthreads : 1;
+#ifndef _OPENMP
+    nt = 1;
+#endif
+    /* per-thread sorted arrays of the best `topk` (insertion; topk is small) */
+    cand4_t *best = (cand4_t *)malloc(sizeof(cand4_t) * (size_t)topk * (size_t)nt);
+    int32_t *nbest = (int32_t *)calloc((size_t)nt, sizeof(int32_t));
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        cand4_t *B = best + (size_t)tid * topk;
+        int32_t nb = 0;
+        int32_t t[2 * ROWS4];
+#pragma omp for schedule(dynamic, 1)
+        for (int32_t i = 0; i < M - 3; ++i)
+            for (int32_t j = i + 1; j < M - 2; ++j)
+                for (int32_t k = j + 1; k < M - 1; ++k)
+                    for (int32_t l = k + 1; l < M; ++l) {
+                        oracle_table4(G, ld, ph, N, i, j, k, l, t);
+                        cand4_t c = { oracle_k2_rows(t, ROWS4, L), i, j, k, l };
+                        if (nb == topk && !cand4_less(&c, &B[nb - 1])) continue;
+                        int32_t p = nb < topk ? nb++ : topk - 1;
+                        while (p > 0 && cand4_less(&c, &B[p - 1])) { B[p] = B[p - 1]; --p; }
+                        B[p] = c;
+                    }
+        nbest[tid] = nb;
+    }
+    int64_t total = 0;
+    for (int t = 0; t < nt; ++t) total += nbest[t];
+    cand4_t *all = (cand4_t *)malloc(sizeof(cand4_t) * (size_t)(total > 0 ? total : 1));
+    int64_t pos = 0;
+    for (int t = 0; t < nt; ++t) {
+        memcpy(all + pos, best + (size_t)t * topk, sizeof(cand4_t) * (size_t)nbest[t]);
+        pos += nbest[t];
+    }
+    qsort(all, (size_t)total, sizeof(cand4_t), cand4_cmp);
+    int32_t n = (int32_t)(total < topk ? total : topk);
+    for (int32_t x = 0; x < n; ++x) {
+        out_ijkl[4 * x + 0] = all[x].i;
+        out_ijkl[4 * x + 1] = all[x].j;
+        out_ijkl[4 * x + 2] = all[x].k;
+        out_ijkl[4 * x + 3] = all[x].l;
+        out_k2[x] = all[x].k2;
+        if (out_counts)
+            oracle_table4(G, ld, ph, N, all[x].i, all[x].j, all[x].k, all[x].l,
+                          out_counts + (int64_t)2 * ROWS4 * x);
+    }
+    free(all);
+    free(nbest);
+    free(best);
     free(L);
     return n;
 }

@@ -261,6 +261,84 @@ def test_pair_edge_sizes_and_ties():
     assert [tuple(x) for x in ij] == list(itertools.combinations(range(5), 2))
 
 
+# ---- fourth order: quads of SNPs (81 rows per class) ----
+
+def _quad_tables_and_k2_vs_brute(lib, seeds=range(12)):
+    """Every quad table equals the brute-force tally; K2 equals ln Q."""
+    for seed in seeds:
+        M = 4 + seed % 3
+        N = 1 + (seed * 7) % 40
+        geno, pheno = tiny(900 + seed, M, N, p_case=(seed % 5) / 4.0)
+        k2, cc = oracle.scan_quads_all(geno, pheno, lib=lib, nthreads=2)
+        for x, snps in enumerate(itertools.combinations(range(M), 4)):
+            t = brute.table(geno.tolist(), pheno.tolist(), snps)
+            assert cc[x].tolist() == t, (seed, snps)
+            want = brute.k2_exact(t)
+            assert abs(k2[x] - want) <= 1e-12 * max(1.0, abs(want)), (seed, snps, k2[x], want)
+
+
+def _quad_topk_vs_brute(lib, seeds=range(4)):
+    for seed in seeds:
+        M, N = 7 + seed % 2, 18 + 4 * seed
+        geno, pheno = tiny(950 + seed, M, N)
+        q, k2, cc = oracle.scan_quads_topk(geno, pheno, 8, lib=lib, nthreads=2)
+        full = brute.scan(geno.tolist(), pheno.tolist(), order=4)
+        full.sort(key=lambda r: (r[0], r[1]))
+        ref = full[:8]
+        assert [brute.q_value(c.tolist()) for c in cc] == [v for v, _, _ in ref]
+        allq = [r[0] for r in full]
+        for x in range(len(ref)):
+            assert cc[x].tolist() == brute.table(geno.tolist(), pheno.tolist(), tuple(q[x]))
+            if allq.count(ref[x][0]) == 1:
+                assert tuple(q[x]) == ref[x][1]
+
+
+def test_quad_tables_and_k2_match_bruteforce():
+    _quad_tables_and_k2_vs_brute(oracle.load())
+
+
+def test_quad_topk_matches_exact_integer_order():
+    _quad_topk_vs_brute(oracle.load(), seeds=range(8))
+
+
+def test_quad_tables_are_margins_of_triplet_tables():
+    """Summing a quad table over one SNP's genotype gives the triplet table of
+    the other three (ties the quad oracle to the triplet oracle)."""
+    d = make_dataset(8, 600, 0.45, 0.05, seed=14)
+    _, qcc = oracle.scan_quads_all(d.geno, d.pheno)
+    quads = [tuple(int(v) for v in q) for q in oracle.lex_quads(8)]
+    assert len(quads) == 70 and quads[:2] == [(0, 1, 2, 3), (0, 1, 2, 4)]
+    for (i, j, k, l) in [(0, 1, 2, 3), (1, 3, 5, 7), (0, 2, 6, 7), (4, 5, 6, 7)]:
+        t = qcc[quads.index((i, j, k, l))].reshape(2, 3, 3, 3, 3)
+        for axis, sub in ((4, (i, j, k)), (3, (i, j, l)), (2, (i, k, l)), (1, (j, k, l))):
+            want = oracle.table(d.geno, d.pheno, *sub).reshape(2, 27)
+            assert np.array_equal(t.sum(axis=axis).reshape(2, 27), want), ((i, j, k, l), sub)
+        assert np.array_equal(oracle.quad_table(d.geno, d.pheno, i, j, k, l), t.reshape(2, 81))
+
+
+@pytest.mark.parametrize("N,n1", [(1, 0), (64, 64), (1000, 413)])
+def test_quad_single_cell_closed_form(N, n1):
+    """All samples in one row: K2 = ln((N+1)! / (N0! N1!))."""
+    G = np.full((4, N), 2, dtype=np.uint8)
+    ph = np.zeros(N, dtype=np.uint8)
+    ph[:n1] = 1
+    q, k2, cc = oracle.scan_quads_topk(G, ph, 1)
+    want = math.lgamma(N + 2) - math.lgamma(N - n1 + 1) - math.lgamma(n1 + 1)
+    assert abs(k2[0] - want) <= 1e-12 * max(1.0, want)
+    assert cc[0][:, 80].tolist() == [N - n1, n1]
+
+
+def test_quad_edge_sizes_and_ties():
+    geno, pheno = tiny(6, 6, 25)
+    assert len(oracle.scan_quads_topk(geno, pheno, 100)[0]) == 15   # C(6,4)
+    assert len(oracle.scan_quads_topk(geno[:3], pheno, 5)[0]) == 0
+    base, ph = tiny(22, 1, 40)
+    G = np.repeat(base, 6, axis=0)
+    q, k2, _ = oracle.scan_quads_topk(G, ph, 15)
+    assert np.all(k2 == k2[0])
+    assert [tuple(x) for x in q] == list(itertools.combinations(range(6), 4))
+
+
 # ---- the pins above must catch plausible mistakes planted in the oracle ----
 
 MUTANTS = {
@@ -275,6 +353,10 @@ MUTANTS = {
     "pair_plus_one": ("L[p0 + p1 + 1] - (L[p0] + L[p1])", "L[p0 + p1] - (L[p0] + L[p1])"),
     "pair_guard": ("for (int32_t j = i + 1; j < M; ++j) {", "for (int32_t j = i; j < M; ++j) {"),
     "pair_offset": ("(int64_t)i * (M - 1) - (int64_t)i * (i - 1) / 2", "(int64_t)i * (M - 1) - (int64_t)i * (i + 1) / 2"),
+    "quad_digits": ("27 * gi[s] + 9 * gj[s] + 3 * gk[s] + gl[s]", "27 * gi[s] + 9 * gj[s] + gk[s] + 3 * gl[s]"),
+    "quad_guard": ("for (int32_t l = k + 1; l < M; ++l) {", "for (int32_t l = k; l < M; ++l) {"),
+    "quad_keep_worse": ("if (nb == topk && !cand4_less(&c, &B[nb - 1])) continue;", "if (nb == topk && cand4_less(&c, &B[nb - 1])) continue;"),
+    "quad_offset": ("acc += rest * (rest - 1) * (rest - 2) / 6;", "acc += rest * (rest - 1) / 2;"),
 }
 
 
@@ -290,6 +372,8 @@ def _pin_suite(lib) -> None:
             assert cc[x].tolist() == brute.table(geno.tolist(), pheno.tolist(), tuple(ijk[x]))
     _pair_tables_and_k2_vs_brute(lib, seeds=range(10))
     _pair_topk_vs_brute(lib, seeds=range(3))
+    _quad_tables_and_k2_vs_brute(lib, seeds=range(6))
+    _quad_topk_vs_brute(lib, seeds=range(2))
     L = oracle.log_factorial(5000, lib=lib)
     assert abs(L[4000] - math.lgamma(4001.0)) < 1e-8
 
