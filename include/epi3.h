@@ -255,6 +255,56 @@ int epi3_pairs_score_plane(const epi3_dataset *d, int32_t k, int64_t cand_cap, v
                            float **plane_dev);
 
 /* ---------------------------------------------------------------------------
+ * Fourth-order scan: quads of SNPs (SPLIT data sets), Eq. 1 with I = 81
+ * rows.  A quad is (i, j, k, l), i < j < k < l < M; the table row of
+ * (g_i, g_j, g_k, g_l) is 27 g_i + 9 g_j + 3 g_k + g_l.  Per class, the 16
+ * cells with all four genotypes in {0, 1} and the corner cells of the four
+ * sub-triplets are counted by AND + POPCNT over the bit planes; every other
+ * cell follows by inclusion-exclusion from those, the pairwise tables of
+ * epi3_encode and the class size.  Hits are the k lowest under
+ * (K2, i, j, k, l) with the same FP32 screen and FP64 re-score as the other
+ * orders.  The score plane holds C(M,4) floats, so M is limited by memory
+ * (M = 256: 0.7 GB; M = 512: 11 GB); M > 4096 is EPI3_E_UNSUPPORTED.
+ * ------------------------------------------------------------------------ */
+
+/* One hit of a quad scan.  counts[c][27 g_i + 9 g_j + 3 g_k + g_l]. */
+typedef struct {
+    uint32_t i, j, k, l;
+    float k2_f32;         /* FP32 screen value */
+    uint32_t reserved;
+    double k2;            /* FP64 value of Eq. 1 over the 81 rows, in row order */
+    uint32_t counts[2][81];
+} epi3_quad_hit;
+
+/* Number of quads C(M,4). */
+int64_t epi3_n_quads(int32_t n_snps);
+
+/* Upper bound on |K2_fp32 - K2_fp64| of an 81-row table of N samples. */
+double epi3_k2_error_bound_quads(int32_t n_samples);
+
+/* Workspace bytes for epi3_scan_quads + epi3_quads_topk (cand_cap as for
+ * epi3_workspace_bytes).  EPI3_E_UNSUPPORTED for a MASKED data set or
+ * M > 4096. */
+int64_t epi3_quads_workspace_bytes(const epi3_dataset *d, int32_t k, int64_t cand_cap);
+
+/* Count and score every quad (FP32) and select candidates; asynchronous.
+ * ws_dev: 256-byte aligned device workspace of epi3_quads_workspace_bytes
+ * bytes. */
+int epi3_scan_quads(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
+                    int64_t ws_bytes, void *stream);
+
+/* Copy min(k, C(M,4)) hits to hits_host [k]; *n_out receives the count.
+ * Synchronises `stream`; EPI3_E_CAPACITY as for epi3_topk. */
+int epi3_quads_topk(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
+                    epi3_quad_hit *hits_host, int32_t *n_out, void *stream);
+
+/* Device address of the quad scan's FP32 score plane (lexicographic
+ * (i, j, k, l) order, C(M,4) floats), valid once the stream has run
+ * epi3_scan_quads. */
+int epi3_quads_score_plane(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
+                           float **plane_dev);
+
+/* ---------------------------------------------------------------------------
  * Test hooks.
  * ------------------------------------------------------------------------ */
 

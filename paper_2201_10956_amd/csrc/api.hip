@@ -220,15 +220,15 @@ ScanLayout scan_layout(void *ws, const epi3_dataset &d, int32_t k, int64_t cand_
   return L;
 }
 
-// Workspace of one pair scan.
-struct PairLayout {
+// Workspace of one scan of another interaction order (2: pairs, 4: quads).
+struct OrderLayout {
   SelJob *sel;
   SelState *st;
   uint32_t *hist;
   float *score;
   int64_t *cand;
   CandRec *rec;
-  epi3_pair_hit *hits;
+  uint8_t *hits;
   uint32_t *ckey;
   int64_t *crank;
   int64_t ccap;
@@ -236,19 +236,26 @@ struct PairLayout {
   int64_t total;
 };
 
-PairLayout pair_layout(void *ws, const epi3_dataset &d, int32_t k, int64_t cand_cap) {
-  PairLayout L{};
-  const int64_t P = c2(d.n_snps);
-  L.cap = default_cap(P, k, cand_cap);
+constexpr int32_t kQuadMaxSnps = 4096;
+
+int64_t order_combos(int order, int32_t M) { return order == 2 ? c2(M) : c4(M); }
+int64_t order_hit_bytes(int order) {
+  return order == 2 ? (int64_t)sizeof(epi3_pair_hit) : (int64_t)sizeof(epi3_quad_hit);
+}
+
+OrderLayout order_layout(void *ws, const epi3_dataset &d, int order, int32_t k, int64_t cand_cap) {
+  OrderLayout L{};
+  const int64_t T = order_combos(order, d.n_snps);
+  L.cap = default_cap(T, k, cand_cap);
   Carver c(ws);
   L.sel = c.take<SelJob>(1);
   L.st = c.take<SelState>(1);
   L.hist = c.take<uint32_t>(kHistBins);
-  L.score = c.take<float>(P);
+  L.score = c.take<float>(T);
   L.cand = c.take<int64_t>(L.cap);
   L.rec = c.take<CandRec>(L.cap);
-  L.hits = c.take<epi3_pair_hit>(std::max<int32_t>(k, 1));
-  L.ccap = compact_cap(P, L.cap);
+  L.hits = c.take<uint8_t>(std::max<int32_t>(k, 1) * order_hit_bytes(order));
+  L.ccap = compact_cap(T, L.cap);
   L.ckey = c.take<uint32_t>(L.ccap);
   L.crank = c.take<int64_t>(L.ccap);
   L.total = c.size();
@@ -475,6 +482,88 @@ int enqueue_count_mfma(const epi3_dataset &d, bool fp4, float *score, uint32_t *
 
 }  // namespace
 
+// Scans of another interaction order (2: pairs, 4: quads) on a SPLIT data set.
+static int order_check(const epi3_dataset *d, int order, int32_t k) {
+  if (!valid_dataset(d) || k <= 0) return EPI3_E_INVALID;
+  if (d->layout != EPI3_LAYOUT_SPLIT) return EPI3_E_UNSUPPORTED;
+  if (order == 4 && d->n_snps > kQuadMaxSnps) return EPI3_E_UNSUPPORTED;
+  return EPI3_OK;
+}
+
+static int64_t order_workspace_bytes(const epi3_dataset *d, int order, int32_t k, int64_t cand_cap) {
+  const int rc = order_check(d, order, k);
+  if (rc != EPI3_OK) return rc;
+  return order_layout(nullptr, *d, order, k, cand_cap).total;
+}
+
+static double order_error_bound(int order, int32_t n_samples);
+
+static int order_scan(const epi3_dataset *d, int order, int32_t k, int64_t cand_cap, void *ws_dev,
+               int64_t ws_bytes, void *stream) {
+  int rc = order_check(d, order, k);
+  if (rc != EPI3_OK) return rc;
+  if (!ws_dev || reinterpret_cast<uintptr_t>(ws_dev) % kAlign) return EPI3_E_INVALID;
+  OrderLayout W = order_layout(ws_dev, *d, order, k, cand_cap);
+  if (ws_bytes < W.total) return EPI3_E_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t T = order_combos(order, d->n_snps);
+  SelJob S = make_seljob(*d, W.score, T, W.st, W.hist, W.cand, W.rec, nullptr, W.cap, k, W.ckey,
+                         W.crank, W.ccap);
+  S.order = order;
+  if (order == 2) S.pair_hits = reinterpret_cast<epi3_pair_hit *>(W.hits);
+  else S.quad_hits = reinterpret_cast<epi3_quad_hit *>(W.hits);
+  S.err2 = 2.0 * order_error_bound(order, d->n_samples);
+  HIP_OK(launch_write_seljobs(&S, 1, W.sel, s));
+  HIP_OK(launch_init_select(W.sel, 1, s));
+  if (T > 0) {
+    rc = timed(0, s, [&]() {
+      const hipError_t e = order == 2 ? launch_pair_scores(*d, W.score, &W.st->kmin, s)
+                                      : launch_quad_scores(*d, W.score, &W.st->kmin, s);
+      return e == hipSuccess ? EPI3_OK : EPI3_E_HIP;
+    });
+    if (rc != EPI3_OK) return rc;
+  }
+  return timed(1, s, [&]() {
+    return launch_select(W.sel, 1, T, W.cap, k, s) == hipSuccess ? EPI3_OK : EPI3_E_HIP;
+  });
+}
+
+static int order_topk(const epi3_dataset *d, int order, int32_t k, int64_t cand_cap, void *ws_dev,
+               void *hits_host, int32_t *n_out, void *stream) {
+  const int rc = order_check(d, order, k);
+  if (rc != EPI3_OK) return rc;
+  if (!ws_dev || !hits_host || !n_out) return EPI3_E_INVALID;
+  OrderLayout W = order_layout(ws_dev, *d, order, k, cand_cap);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SelState st;
+  int32_t status = 0;
+  HIP_OK(hipMemcpyAsync(&st, W.st, sizeof(st), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(&status, d->status, sizeof(status), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  *n_out = 0;
+  if (status & 1) return EPI3_E_GENOTYPE;
+  if ((int64_t)st.ncand > W.cap) {
+    *n_out = (int32_t)std::min<unsigned long long>(st.ncand, 0x7fffffffull);
+    return EPI3_E_CAPACITY;
+  }
+  const int64_t keff = st.keff;
+  if (keff > 0) {
+    HIP_OK(hipMemcpyAsync(hits_host, W.hits, keff * order_hit_bytes(order), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+  }
+  *n_out = (int32_t)keff;
+  return EPI3_OK;
+}
+
+static int order_score_plane(const epi3_dataset *d, int order, int32_t k, int64_t cand_cap, void *ws_dev,
+                      float **plane_dev) {
+  const int rc = order_check(d, order, k);
+  if (rc != EPI3_OK) return rc;
+  if (!ws_dev || !plane_dev) return EPI3_E_INVALID;
+  *plane_dev = order_layout(ws_dev, *d, order, k, cand_cap).score;
+  return EPI3_OK;
+}
+
 extern "C" {
 
 const char *epi3_version(void) { return "epi3 0.1 (gfx950)"; }
@@ -500,6 +589,16 @@ double epi3_k2_error_bound_pairs(int32_t n_samples) {
 }
 
 int64_t epi3_n_pairs(int32_t n_snps) { return c2(n_snps); }
+
+double epi3_k2_error_bound_quads(int32_t n_samples) {
+  // As for triplets with 81 rows: 4u L[r+1] per row, 80u sum_rows L[r+1] for
+  // the summation, sum_rows L[r+1] <= L[N + 81]; 86u L[N + 81] covers both plus
+  // the second-order terms and the FP64 evaluation's own rounding.
+  if (n_samples < 0) return 0.0;
+  return 86.0 * ldexp(1.0, -24) * log_factorial_at((int64_t)n_samples + 81);
+}
+
+int64_t epi3_n_quads(int32_t n_snps) { return c4(n_snps); }
 
 int64_t epi3_encode_bytes(int32_t n_snps, int32_t n_cases, int32_t n_controls, int32_t layout) {
   if (n_snps < 0 || n_cases < 0 || n_controls < 0 || n_cases + n_controls <= 0) return EPI3_E_INVALID;
@@ -682,70 +781,35 @@ int epi3_scan_tables(const epi3_dataset *d, int32_t variant, uint32_t *counts_de
 }
 
 int64_t epi3_pairs_workspace_bytes(const epi3_dataset *d, int32_t k, int64_t cand_cap) {
-  if (!valid_dataset(d) || k <= 0) return EPI3_E_INVALID;
-  if (d->layout != EPI3_LAYOUT_SPLIT) return EPI3_E_UNSUPPORTED;
-  return pair_layout(nullptr, *d, k, cand_cap).total;
+  return order_workspace_bytes(d, 2, k, cand_cap);
 }
-
 int epi3_scan_pairs(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
                     int64_t ws_bytes, void *stream) {
-  if (!valid_dataset(d) || k <= 0 || !ws_dev) return EPI3_E_INVALID;
-  if (d->layout != EPI3_LAYOUT_SPLIT) return EPI3_E_UNSUPPORTED;
-  if (reinterpret_cast<uintptr_t>(ws_dev) % kAlign) return EPI3_E_INVALID;
-  PairLayout W = pair_layout(ws_dev, *d, k, cand_cap);
-  if (ws_bytes < W.total) return EPI3_E_WORKSPACE;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const int64_t P = c2(d->n_snps);
-  SelJob S = make_seljob(*d, W.score, P, W.st, W.hist, W.cand, W.rec, nullptr, W.cap, k, W.ckey,
-                         W.crank, W.ccap);
-  S.order = 2;
-  S.pair_hits = W.hits;
-  S.err2 = 2.0 * epi3_k2_error_bound_pairs(d->n_samples);
-  HIP_OK(launch_write_seljobs(&S, 1, W.sel, s));
-  HIP_OK(launch_init_select(W.sel, 1, s));
-  if (P > 0) {
-    const int rc = timed(0, s, [&]() {
-      return launch_pair_scores(*d, W.score, &W.st->kmin, s) == hipSuccess ? EPI3_OK : EPI3_E_HIP;
-    });
-    if (rc != EPI3_OK) return rc;
-  }
-  return timed(1, s, [&]() {
-    return launch_select(W.sel, 1, P, W.cap, k, s) == hipSuccess ? EPI3_OK : EPI3_E_HIP;
-  });
+  return order_scan(d, 2, k, cand_cap, ws_dev, ws_bytes, stream);
 }
-
 int epi3_pairs_topk(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
                     epi3_pair_hit *hits_host, int32_t *n_out, void *stream) {
-  if (!valid_dataset(d) || k <= 0 || !ws_dev || !hits_host || !n_out) return EPI3_E_INVALID;
-  if (d->layout != EPI3_LAYOUT_SPLIT) return EPI3_E_UNSUPPORTED;
-  PairLayout W = pair_layout(ws_dev, *d, k, cand_cap);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  SelState st;
-  int32_t status = 0;
-  HIP_OK(hipMemcpyAsync(&st, W.st, sizeof(st), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipMemcpyAsync(&status, d->status, sizeof(status), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
-  *n_out = 0;
-  if (status & 1) return EPI3_E_GENOTYPE;
-  if ((int64_t)st.ncand > W.cap) {
-    *n_out = (int32_t)std::min<unsigned long long>(st.ncand, 0x7fffffffull);
-    return EPI3_E_CAPACITY;
-  }
-  const int64_t keff = st.keff;
-  if (keff > 0) {
-    HIP_OK(hipMemcpyAsync(hits_host, W.hits, keff * sizeof(epi3_pair_hit), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
-  }
-  *n_out = (int32_t)keff;
-  return EPI3_OK;
+  return order_topk(d, 2, k, cand_cap, ws_dev, hits_host, n_out, stream);
 }
-
 int epi3_pairs_score_plane(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
                            float **plane_dev) {
-  if (!valid_dataset(d) || k <= 0 || !ws_dev || !plane_dev) return EPI3_E_INVALID;
-  if (d->layout != EPI3_LAYOUT_SPLIT) return EPI3_E_UNSUPPORTED;
-  *plane_dev = pair_layout(ws_dev, *d, k, cand_cap).score;
-  return EPI3_OK;
+  return order_score_plane(d, 2, k, cand_cap, ws_dev, plane_dev);
+}
+
+int64_t epi3_quads_workspace_bytes(const epi3_dataset *d, int32_t k, int64_t cand_cap) {
+  return order_workspace_bytes(d, 4, k, cand_cap);
+}
+int epi3_scan_quads(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
+                    int64_t ws_bytes, void *stream) {
+  return order_scan(d, 4, k, cand_cap, ws_dev, ws_bytes, stream);
+}
+int epi3_quads_topk(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
+                    epi3_quad_hit *hits_host, int32_t *n_out, void *stream) {
+  return order_topk(d, 4, k, cand_cap, ws_dev, hits_host, n_out, stream);
+}
+int epi3_quads_score_plane(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
+                           float **plane_dev) {
+  return order_score_plane(d, 4, k, cand_cap, ws_dev, plane_dev);
 }
 
 int epi3_score_triplets(const epi3_dataset *d, const uint32_t *ijk_dev, int64_t n,
@@ -1306,3 +1370,7 @@ void epi3_timing_reset(void) {
 }
 
 }  // extern "C"
+
+static double order_error_bound(int order, int32_t n_samples) {
+  return order == 2 ? epi3_k2_error_bound_pairs(n_samples) : epi3_k2_error_bound_quads(n_samples);
+}

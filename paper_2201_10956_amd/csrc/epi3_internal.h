@@ -92,10 +92,10 @@ struct SelState {
 struct CandRec {
   uint64_t key;            // bit pattern of the FP64 K2 (non-negative => ordered)
   int64_t rank;            // lexicographic rank (tie-break)
-  uint32_t i, j, k;
+  uint32_t i, j, k, l;
   float k2f;
   double k2;
-  uint32_t counts[54];
+  uint32_t counts[162];     // [class][cells]: 27 (triplets), 9 (pairs) or 81 (quads) per class
 };
 
 // Phenotype batch for the matrix-core kernel: one MASKED data set and up to
@@ -154,8 +154,10 @@ struct SelJob {
   int32_t M, Mp, W0, W1, N0, N1;
   int32_t layout;
   int32_t k;
-  int32_t order;           // 2: pair scan (ranks of pairs, 9-row tables, pair_hits); else triplets
+  int32_t order;           // 2: pairs (9-row tables, pair_hits); 4: quads (81 rows, quad_hits);
+                           // else triplets
   epi3_pair_hit *pair_hits;  // [k] (order 2)
+  epi3_quad_hit *quad_hits;  // [k] (order 4)
 };
 
 // The 27 cells of one class from the 8 counted corner cells n[4a + 2b + c]
@@ -202,7 +204,6 @@ __device__ __forceinline__ void complete_table(const uint32_t n[8], const int pi
   t[26] = Nc - s;
 }
 
-// Log-factorial table entry at byte offset b (b = 4 n for L[n]).
 // The 9 cells t[3 a + b] of one class of a pair (a, b in {0, 1, 2}) from the
 // counted cells n[2 a + b] (a, b in {0, 1}), the per-SNP counts mi[a], mj[b]
 // and the class size: every sample of the class is in exactly one row.
@@ -219,6 +220,159 @@ __device__ __forceinline__ void pair_cells(const int n[4], const int mi[2], cons
   t[8] = Nc - (t[0] + t[1] + t[2] + t[3] + t[4] + t[5] + t[6] + t[7]);
 }
 
+// Counts of one class of the quad (i, j, k, l) over words [w0, w1) with
+// stride `step` (one thread: 1; the lanes of a wave: 64 from w0 + lane):
+// cnt[8 a + 4 b + 2 c + d] = sum popc(X_i[a] & X_j[b] & X_k[c] & X_l[d]),
+// then the corner cells of the four sub-triplets, each indexed by its own
+// (x, y, z) in {0, 1}^3 as 4 x + 2 y + z: cnt[16 + ...] (i, j, k),
+// cnt[24 + ...] (i, j, l), cnt[32 + ...] (i, k, l), cnt[40 + ...] (j, k, l).
+__device__ __forceinline__ void quad_counts(const uint32_t *planes, int64_t Mp, int w0, int w1,
+                                            int step, int i, int j, int k, int l,
+                                            uint32_t cnt[48]) {
+#pragma unroll
+  for (int x = 0; x < 48; ++x) cnt[x] = 0u;
+  const uint2 *pv = reinterpret_cast<const uint2 *>(planes);
+  for (int w = w0; w < w1; w += step) {
+    const uint2 *row = pv + (int64_t)w * Mp;
+    const uint2 xi = row[i], xj = row[j], xk = row[k], xl = row[l];
+    const uint32_t X[4][2] = {{xi.x, xi.y}, {xj.x, xj.y}, {xk.x, xk.y}, {xl.x, xl.y}};
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const uint32_t ij = X[0][a] & X[1][b];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const uint32_t ijk = ij & X[2][c];
+          cnt[16 + 4 * a + 2 * b + c] += __builtin_popcount(ijk);
+#pragma unroll
+          for (int d = 0; d < 2; ++d)
+            cnt[8 * a + 4 * b + 2 * c + d] += __builtin_popcount(ijk & X[3][d]);
+        }
+#pragma unroll
+        for (int d = 0; d < 2; ++d) cnt[24 + 4 * a + 2 * b + d] += __builtin_popcount(ij & X[3][d]);
+      }
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        const uint32_t kl = X[2][c] & X[3][d];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) cnt[32 + 4 * a + 2 * c + d] += __builtin_popcount(X[0][a] & kl);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) cnt[40 + 4 * b + 2 * c + d] += __builtin_popcount(X[1][b] & kl);
+      }
+  }
+}
+
+// The 81 cells t[27 a + 9 b + 3 c + d] (a, b, c, d in {0, 1, 2}) of one class
+// of the quad (i, j, k, l) from its counts (quad_counts) and the class's
+// pairwise tables pairs[x][y] (int4 (n00, n01, n10, n11), per-SNP counts on
+// the diagonal) and size.  Each sub-triplet's 27 cells come from its corners
+// (complete_table); then the rows with a 2 at SNP i, j, k, l in turn: a count
+// with a 2 at one SNP is the sub-triplet table without that SNP minus the
+// rows with 0 and 1 there (every sample of the class is in one row).
+__device__ __forceinline__ void quad_cells(const uint32_t cnt[48], const int32_t *pairs, int64_t Mp,
+                                           int i, int j, int k, int l, int Nc, int t[81]) {
+  const int4 *pr = reinterpret_cast<const int4 *>(pairs);
+  auto pair = [&](int x, int y, int v[4]) {
+    const int4 p = pr[(int64_t)x * Mp + y];
+    v[0] = p.x; v[1] = p.y; v[2] = p.z; v[3] = p.w;
+  };
+  auto marg = [&](int x, int v[2]) {
+    const int4 p = pr[(int64_t)x * Mp + x];
+    v[0] = p.x; v[1] = p.w;
+  };
+  int pij[4], pik[4], pil[4], pjk[4], pjl[4], pkl[4], mi[2], mj[2], mk[2], ml[2];
+  pair(i, j, pij); pair(i, k, pik); pair(i, l, pil);
+  pair(j, k, pjk); pair(j, l, pjl); pair(k, l, pkl);
+  marg(i, mi); marg(j, mj); marg(k, mk); marg(l, ml);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int d = 0; d < 2; ++d) t[27 * a + 9 * b + 3 * c + d] = (int)cnt[8 * a + 4 * b + 2 * c + d];
+  int T[27];
+  // a = 2 (b, c, d in {0, 1}) from the (j, k, l) table
+  complete_table(cnt + 40, pjk, pjl, pkl, mj, mk, ml, Nc, T);
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+        t[54 + 9 * b + 3 * c + d] = T[9 * b + 3 * c + d] - t[9 * b + 3 * c + d] - t[27 + 9 * b + 3 * c + d];
+  // b = 2 (c, d in {0, 1}) from the (i, k, l) table
+  complete_table(cnt + 32, pik, pil, pkl, mi, mk, ml, Nc, T);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+        t[27 * a + 18 + 3 * c + d] = T[9 * a + 3 * c + d] - t[27 * a + 3 * c + d] - t[27 * a + 9 + 3 * c + d];
+  // c = 2 (d in {0, 1}) from the (i, j, l) table
+  complete_table(cnt + 24, pij, pil, pjl, mi, mj, ml, Nc, T);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+        t[27 * a + 9 * b + 6 + d] = T[9 * a + 3 * b + d] - t[27 * a + 9 * b + d] - t[27 * a + 9 * b + 3 + d];
+  // d = 2 from the (i, j, k) table
+  complete_table(cnt + 16, pij, pik, pjk, mi, mj, mk, Nc, T);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        t[27 * a + 9 * b + 3 * c + 2] = T[9 * a + 3 * b + c] - t[27 * a + 9 * b + 3 * c] - t[27 * a + 9 * b + 3 * c + 1];
+}
+
+// Lexicographic rank of the quad (i, j, k, l), i < j < k < l < M.
+__host__ __device__ __forceinline__ int64_t c4(int64_t x) {
+  return x < 4 ? 0 : x * (x - 1) / 2 * (x - 2) / 3 * (x - 3) / 4;
+}
+__host__ __device__ __forceinline__ int64_t quad_rank(int64_t M, int64_t i, int64_t j, int64_t k,
+                                                      int64_t l) {
+  return c4(M) - c4(M - i) + c3(M - 1 - i) - c3(M - j) + c2(M - 1 - j) - c2(M - k) + (l - k - 1);
+}
+
+// Quad (i, j, k, l) of lexicographic rank `rank` among the quads of M SNPs.
+__device__ __forceinline__ void decode_quad_rank(int64_t M, int64_t rank, int &i, int &j, int &k,
+                                                 int &l) {
+  const int64_t C = c4(M);
+  int lo = 0, hi = (int)M - 4;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (C - c4(M - mid) <= rank) lo = mid; else hi = mid - 1;
+  }
+  i = lo;
+  const int64_t r1 = rank - (C - c4(M - i));
+  lo = i + 1;
+  hi = (int)M - 3;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (c3(M - 1 - i) - c3(M - mid) <= r1) lo = mid; else hi = mid - 1;
+  }
+  j = lo;
+  const int64_t r2 = r1 - (c3(M - 1 - i) - c3(M - j));
+  lo = j + 1;
+  hi = (int)M - 2;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (c2(M - 1 - j) - c2(M - mid) <= r2) lo = mid; else hi = mid - 1;
+  }
+  k = lo;
+  l = (int)(r2 - (c2(M - 1 - j) - c2(M - k))) + k + 1;
+}
+
+// Log-factorial table entry at byte offset b (b = 4 n for L[n]).
 __device__ __forceinline__ float lf_at(const float *L, int b) {
   return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(L) + b);
 }
@@ -271,6 +425,9 @@ hipError_t launch_case_pairs(const uint32_t *planes, int32_t Mp, int32_t W,
 // Pair scan: FP32 K2 of every pair of a SPLIT data set from its pairwise
 // tables, by lexicographic pair rank; key range into keyrange[0..1].
 hipError_t launch_pair_scores(const epi3_dataset &d, float *score, uint32_t *keyrange, hipStream_t s);
+// Quad scan: FP32 K2 of every quad of a SPLIT data set, by lexicographic quad
+// rank; key range into keyrange[0..1].
+hipError_t launch_quad_scores(const epi3_dataset &d, float *score, uint32_t *keyrange, hipStream_t s);
 int64_t host_perm_tiles(int64_t M);
 hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,
                                   unsigned long long *queue, bool fp4, hipStream_t s);

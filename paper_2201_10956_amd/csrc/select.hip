@@ -382,6 +382,37 @@ __global__ void __launch_bounds__(256) rescore_kernel(const SelJob *__restrict__
        c += waves) {
     const int64_t rank = J.cand[c];
     int tab[2][27];
+    if (J.order == 4) {
+      int i, j, k, l;
+      decode_quad_rank(J.M, rank, i, j, k, l);
+      int q[2][81];
+      const int64_t MpMp4 = (int64_t)J.Mp * J.Mp * 4;
+      for (int cl = 0; cl < 2; ++cl) {
+        uint32_t cnt[48];
+        const int w0 = cl ? J.W0 : 0, w1 = cl ? J.W0 + J.W1 : J.W0;
+        quad_counts(J.planes, J.Mp, w0 + lane, w1, 64, i, j, k, l, cnt);
+        for (int x = 0; x < 48; ++x) cnt[x] = wave_sum(cnt[x]);
+        quad_cells(cnt, J.pairs + cl * MpMp4, J.Mp, i, j, k, l, cl ? J.N1 : J.N0, q[cl]);
+      }
+      if (lane == 0) {
+        CandRec &R = J.rec[c];
+        double k2 = 0.0;  // Eq. 1 in FP64: rows in order
+        for (int x = 0; x < 81; ++x) {
+          const int r0 = q[0][x], r1 = q[1][x];
+          k2 += J.lf64[r0 + r1 + 1] - (J.lf64[r0] + J.lf64[r1]);
+        }
+        R.key = (uint64_t)__double_as_longlong(k2);
+        R.rank = rank;
+        R.i = i; R.j = j; R.k = k; R.l = l;
+        R.k2f = J.score[rank];
+        R.k2 = k2;
+        for (int x = 0; x < 81; ++x) {
+          R.counts[x] = (uint32_t)q[0][x];
+          R.counts[81 + x] = (uint32_t)q[1][x];
+        }
+      }
+      continue;
+    }
     if (J.order == 2) {
       int i, j;
       decode_pair_rank(J.M, rank, i, j);
@@ -457,7 +488,18 @@ __global__ void __launch_bounds__(256) rank_kernel(const SelJob *__restrict__ sj
         pos += (kz < mykey) || (kz == mykey && srank[z] < myrank);
       }
     }
-    if (x < n && pos < keff && J.order == 2) {
+    if (x < n && pos < keff && J.order == 4) {
+      const CandRec &R = J.rec[x];
+      epi3_quad_hit &H = J.quad_hits[pos];
+      H.i = R.i; H.j = R.j; H.k = R.k; H.l = R.l;
+      H.k2_f32 = R.k2f;
+      H.reserved = 0u;
+      H.k2 = R.k2;
+      for (int q = 0; q < 81; ++q) {
+        H.counts[0][q] = R.counts[q];
+        H.counts[1][q] = R.counts[81 + q];
+      }
+    } else if (x < n && pos < keff && J.order == 2) {
       const CandRec &R = J.rec[x];
       epi3_pair_hit &H = J.pair_hits[pos];
       H.i = R.i; H.j = R.j;

@@ -55,6 +55,12 @@ class CPairHit(ctypes.Structure):
                 ("counts", (ctypes.c_uint32 * 9) * 2)]
 
 
+class CQuadHit(ctypes.Structure):
+    _fields_ = [("i", ctypes.c_uint32), ("j", ctypes.c_uint32), ("k", ctypes.c_uint32),
+                ("l", ctypes.c_uint32), ("k2_f32", ctypes.c_float), ("reserved", ctypes.c_uint32),
+                ("k2", ctypes.c_double), ("counts", (ctypes.c_uint32 * 81) * 2)]
+
+
 class CJob(ctypes.Structure):
     _fields_ = [("d", ctypes.POINTER(CDataset)), ("case_mask", ctypes.c_void_p),
                 ("k", ctypes.c_int32), ("reserved", ctypes.c_int32)]
@@ -66,6 +72,10 @@ assert HIT_DTYPE.itemsize == ctypes.sizeof(CHit) == 240
 PAIR_HIT_DTYPE = np.dtype([("i", "<u4"), ("j", "<u4"), ("k2_f32", "<f4"), ("reserved", "<u4"),
                            ("k2", "<f8"), ("counts", "<u4", (2, 9))])
 assert PAIR_HIT_DTYPE.itemsize == ctypes.sizeof(CPairHit) == 96
+QUAD_HIT_DTYPE = np.dtype([("i", "<u4"), ("j", "<u4"), ("k", "<u4"), ("l", "<u4"),
+                           ("k2_f32", "<f4"), ("reserved", "<u4"), ("k2", "<f8"),
+                           ("counts", "<u4", (2, 81))])
+assert QUAD_HIT_DTYPE.itemsize == ctypes.sizeof(CQuadHit) == 680
 assert ctypes.sizeof(CDataset) == 96 and ctypes.sizeof(CJob) == 24
 
 
@@ -109,6 +119,12 @@ def _load():
         "epi3_scan_pairs": (ctypes.c_int, [P(CDataset), i32, i64, vp, i64, vp]),
         "epi3_pairs_topk": (ctypes.c_int, [P(CDataset), i32, i64, vp, vp, P(i32), vp]),
         "epi3_pairs_score_plane": (ctypes.c_int, [P(CDataset), i32, i64, vp, P(vp)]),
+        "epi3_n_quads": (i64, [i32]),
+        "epi3_k2_error_bound_quads": (ctypes.c_double, [i32]),
+        "epi3_quads_workspace_bytes": (i64, [P(CDataset), i32, i64]),
+        "epi3_scan_quads": (ctypes.c_int, [P(CDataset), i32, i64, vp, i64, vp]),
+        "epi3_quads_topk": (ctypes.c_int, [P(CDataset), i32, i64, vp, vp, P(i32), vp]),
+        "epi3_quads_score_plane": (ctypes.c_int, [P(CDataset), i32, i64, vp, P(vp)]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -125,7 +141,9 @@ EXPORTS = ("epi3_encode_bytes", "epi3_encode", "epi3_workspace_bytes", "epi3_sca
            "epi3_tile_rule", "epi3_tile_rules_clear", "epi3_tile_for", "epi3_set_pass_bytes",
            "epi3_perm_pvalue", "epi3_set_compact_cap", "epi3_n_pairs", "epi3_k2_error_bound_pairs",
            "epi3_pairs_workspace_bytes", "epi3_scan_pairs", "epi3_pairs_topk",
-           "epi3_pairs_score_plane")
+           "epi3_pairs_score_plane", "epi3_n_quads", "epi3_k2_error_bound_quads",
+           "epi3_quads_workspace_bytes", "epi3_scan_quads", "epi3_quads_topk",
+           "epi3_quads_score_plane")
 TILES_PATH = os.path.join(_HERE, "tiles.json")
 
 
@@ -344,31 +362,45 @@ def k2_error_bound_pairs(N: int) -> float:
     return float(_lib.epi3_k2_error_bound_pairs(int(N)))
 
 
-class PairScanner:
-    """Workspace + calls for repeated second-order (pair) scans of one SPLIT data set."""
+def n_quads(M: int) -> int:
+    return int(_lib.epi3_n_quads(int(M)))
+
+
+def k2_error_bound_quads(N: int) -> float:
+    return float(_lib.epi3_k2_error_bound_quads(int(N)))
+
+
+class _OrderScanner:
+    """Workspace + calls for repeated scans of one SPLIT data set at another
+    interaction order (pairs or quads)."""
+    _names = None  # (workspace_bytes, scan, topk, score_plane) entry points
+    _hit = None    # ctypes hit structure
+    _dtype = None  # numpy dtype of a hit
+    _order = 0
 
     def __init__(self, ds: Dataset, k: int, cand_cap: int = 0):
         self.ds, self.k, self.cand_cap = ds, int(k), int(cand_cap)
         self._alloc()
 
+    def _fn(self, x):
+        return getattr(_lib, self._names[x])
+
     def _alloc(self):
-        nbytes = _lib.epi3_pairs_workspace_bytes(ctypes.byref(self.ds.c), self.k, self.cand_cap)
-        _check(int(nbytes) if nbytes < 0 else OK, "epi3_pairs_workspace_bytes")
+        nbytes = self._fn(0)(ctypes.byref(self.ds.c), self.k, self.cand_cap)
+        _check(int(nbytes) if nbytes < 0 else OK, self._names[0])
         self.ws = _buffer(nbytes, self.ds.buf.device)
-        self.hits = (CPairHit * max(self.k, 1))()
+        self.hits = (self._hit * max(self.k, 1))()
 
     def scan(self, stream=None) -> None:
-        rc = _lib.epi3_scan_pairs(ctypes.byref(self.ds.c), self.k, self.cand_cap,
-                                  ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
-                                  _stream(stream))
-        _check(rc, "epi3_scan_pairs")
+        rc = self._fn(1)(ctypes.byref(self.ds.c), self.k, self.cand_cap,
+                         ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(), _stream(stream))
+        _check(rc, self._names[1])
 
     def topk(self, stream=None):
         n = ctypes.c_int32(0)
-        rc = _lib.epi3_pairs_topk(ctypes.byref(self.ds.c), self.k, self.cand_cap,
-                                  ctypes.c_void_p(self.ws.data_ptr()),
-                                  ctypes.cast(self.hits, ctypes.c_void_p), ctypes.byref(n),
-                                  _stream(stream))
+        rc = self._fn(2)(ctypes.byref(self.ds.c), self.k, self.cand_cap,
+                         ctypes.c_void_p(self.ws.data_ptr()),
+                         ctypes.cast(self.hits, ctypes.c_void_p), ctypes.byref(n), _stream(stream))
         return rc, n.value
 
     def run(self, stream=None, retry: bool = True) -> np.ndarray:
@@ -378,21 +410,40 @@ class PairScanner:
             self.cand_cap = int(n)
             self._alloc()
             return self.run(stream, retry=False)
-        _check(rc, "epi3_pairs_topk")
-        raw = np.frombuffer(self.hits, dtype=PAIR_HIT_DTYPE, count=len(self.hits))
+        _check(rc, self._names[2])
+        raw = np.frombuffer(self.hits, dtype=self._dtype, count=len(self.hits))
         return raw[:n].copy()
 
     def score_plane(self):
-        """FP32 K2 of every pair (lexicographic order): a torch view into the workspace,
-        valid after scan()."""
+        """FP32 K2 of every combination (lexicographic order): a torch view into
+        the workspace, valid after scan()."""
         torch = _torch()
         ptr = ctypes.c_void_p(0)
-        rc = _lib.epi3_pairs_score_plane(ctypes.byref(self.ds.c), self.k, self.cand_cap,
-                                         ctypes.c_void_p(self.ws.data_ptr()), ctypes.byref(ptr))
-        _check(rc, "epi3_pairs_score_plane")
+        rc = self._fn(3)(ctypes.byref(self.ds.c), self.k, self.cand_cap,
+                         ctypes.c_void_p(self.ws.data_ptr()), ctypes.byref(ptr))
+        _check(rc, self._names[3])
         off = (ptr.value or 0) - self.ws.data_ptr()
-        P = n_pairs(self.ds.M)
-        return self.ws[off: off + 4 * P].view(torch.float32)
+        T = n_pairs(self.ds.M) if self._order == 2 else n_quads(self.ds.M)
+        return self.ws[off: off + 4 * T].view(torch.float32)
+
+
+class PairScanner(_OrderScanner):
+    """Second-order scans (pairs of SNPs, 9-row tables)."""
+    _names = ("epi3_pairs_workspace_bytes", "epi3_scan_pairs", "epi3_pairs_topk",
+              "epi3_pairs_score_plane")
+    _hit, _dtype, _order = CPairHit, PAIR_HIT_DTYPE, 2
+
+
+class QuadScanner(_OrderScanner):
+    """Fourth-order scans (quads of SNPs, 81-row tables)."""
+    _names = ("epi3_quads_workspace_bytes", "epi3_scan_quads", "epi3_quads_topk",
+              "epi3_quads_score_plane")
+    _hit, _dtype, _order = CQuadHit, QUAD_HIT_DTYPE, 4
+
+
+def scan_quads(ds: Dataset, k: int, cand_cap: int = 0, stream=None) -> np.ndarray:
+    """The k lowest (K2, i, j, k, l) quads of a SPLIT data set (QUAD_HIT_DTYPE)."""
+    return QuadScanner(ds, k, cand_cap).run(stream)
 
 
 def scan_pairs(ds: Dataset, k: int, cand_cap: int = 0, stream=None) -> np.ndarray:

@@ -204,3 +204,21 @@ def test_pair_scan_host_side(epi3):
     assert lib.epi3_pairs_workspace_bytes(ctypes.byref(d), 0, 0) == epi3.E_INVALID
     m = _fake_dataset(epi3, 300, 700, 900, layout=1)
     assert lib.epi3_pairs_workspace_bytes(ctypes.byref(m), 10, 0) == epi3.E_UNSUPPORTED
+
+
+def test_quad_scan_host_side(epi3):
+    lib = epi3._lib
+    assert epi3.n_quads(3) == 0 and epi3.n_quads(4) == 1
+    assert epi3.n_quads(256) == math.comb(256, 4)
+    assert epi3.n_quads(4096) == math.comb(4096, 4)
+    for N in (1, 100, 16384):
+        want = 86 * 2.0 ** -24 * math.lgamma(N + 82)
+        assert epi3.k2_error_bound_quads(N) == pytest.approx(want, rel=1e-12)
+    d = _fake_dataset(epi3, 64, 700, 900)
+    w = lib.epi3_quads_workspace_bytes(ctypes.byref(d), 10, 0)
+    assert w >= 4 * math.comb(64, 4)
+    assert lib.epi3_quads_workspace_bytes(ctypes.byref(d), 0, 0) == epi3.E_INVALID
+    m = _fake_dataset(epi3, 64, 700, 900, layout=1)
+    assert lib.epi3_quads_workspace_bytes(ctypes.byref(m), 10, 0) == epi3.E_UNSUPPORTED
+    big = _fake_dataset(epi3, 5000, 700, 900)
+    assert lib.epi3_quads_workspace_bytes(ctypes.byref(big), 10, 0) == epi3.E_UNSUPPORTED
