@@ -33,6 +33,7 @@ MFMA_I8_PEAK_TOPS = 5000.0                     # dense int8 matrix-core ops/s (M
 MFMA_FP4_PEAK_TFLOPS = 10100.0                 # dense FP4 matrix-core flop/s (MI355X)
 MFMA_OPS_PER_STQ = 16.0                        # 8 corner cells x (multiply + add) per sample-triplet-phenotype
 PAIR_OPS_PER_SP = 8.0 / 32.0                   # 4 AND + 4 v_bcnt per pair per 32 samples (pairwise tables)
+QUAD_OPS_PER_SQ = 32.0 / 32.0                  # 16 AND + 16 v_bcnt per quad per 32 samples (quad corners)
 
 WORKLOADS = {
     "plain1": dict(cfg=1, kind="plain", desc="plain scan, 64 SNPs x 1024 samples (512 cases), top-10"),
@@ -42,6 +43,8 @@ WORKLOADS = {
                   "64 phenotype permutations in one launch, top-10 each"),
     "pairs3": dict(cfg=3, kind="pairs", desc="second-order (pair) scan, 2048 SNPs x 16384 samples "
                    "(50% cases), top-1000"),
+    "quads2": dict(cfg=2, kind="quads", snps=256, desc="fourth-order (quad) scan, first 256 SNPs of the "
+                   "512 x 4096 data set (50% cases), top-100"),
     "uneven5": dict(cfg=5, kind="uneven", desc="batched uneven data sets: 32 data sets, SNPs ~ U[128,1024], "
                     "samples ~ U[1024,16384], one launch, top-10 each"),
 }
@@ -232,6 +235,71 @@ def run_pairs(args, wl):
     out["best"] = {"ij": [int(hits["i"][0]), int(hits["j"][0])], "k2": float(hits["k2"][0])}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_pairs(d, k, args.cpu_budget)
+    return out
+
+
+def cpu_baseline_quads(geno, pheno, k: int, budget_s: float = 20.0) -> dict:
+    """The oracle's quad scan timed on the first M' SNPs."""
+    import oracle
+    from math import comb
+    cores = cpu_cores()
+    N = pheno.size
+    m0 = min(geno.shape[0], 24)
+    t0 = time.perf_counter()
+    oracle.scan_quads_topk(geno[:m0], pheno, k, nthreads=cores, counts=False)
+    rate = comb(m0, 4) * N / max(time.perf_counter() - t0, 1e-6)
+    m = m0
+    while m < geno.shape[0] and comb(m + 1, 4) * N / rate < budget_s:
+        m += 1
+    t0 = time.perf_counter()
+    oracle.scan_quads_topk(geno[:m], pheno, k, nthreads=cores, counts=False)
+    dt = time.perf_counter() - t0
+    work = comb(m, 4) * N
+    return {"value": work / dt / 1e12, "unit": "T sample-quads/s", "cores": cores,
+            "kind": "oracle", "seconds": round(dt, 3),
+            "sample": f"first {m} of {geno.shape[0]} SNPs x all {N} samples, top-{k} "
+                      f"({work:.3e} sample-quads)"}
+
+
+def run_quads(args, wl):
+    import torch
+    from paper_2201_10956_amd import epi3
+    from synth import CONFIGS, make_config
+
+    c = CONFIGS[wl["cfg"]]
+    d = make_config(wl["cfg"])
+    M, N, k = wl["snps"], d.n_samples, c["k"]
+    g_host = np.ascontiguousarray(d.geno[:M])
+    geno = torch.from_numpy(g_host).to("cuda")
+    ds = epi3.encode(geno, d.pheno)
+    sc = epi3.QuadScanner(ds, k)
+
+    def step():  # encode (planes + pairwise tables) + quad counts and scores + exact top-k
+        epi3.encode(geno, d.pheno, into=ds)
+        return sc.run()
+
+    dt, hits = _timed_steps(step, args.steps, args.warmup)
+    cnt_ms, cnt_n, sel_ms, _ = _kernel_times(step)
+    Qn = epi3.n_quads(M)
+    work = Qn * N
+    out = _base(args, wl, work / dt / 1e12, dt * 1e3, "u32", {
+        "workload": wl["desc"], "snps": M, "samples": N, "cases": int(d.pheno.sum()),
+        "top_k": k, "quads": Qn})
+    out["metric"] = "tera sample-quads/s at exact top-k (fourth-order scan)"
+    out["unit"] = "T sample-quads/s"
+    ops = work * QUAD_OPS_PER_SQ
+    kern_ms = cnt_ms / max(cnt_n, 1)
+    achieved = ops / (kern_ms / 1e3) / 1e12
+    out["roofline"] = {
+        "bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 3),
+        "unit": "T int32-lane-ops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+        "traffic": recorded_traffic(f"{args.workload}|valu"),
+        "traffic_unit": "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
+        "kernel": "quad_scores_kernel", "kernel_ms": round(kern_ms, 4), "ops_per_launch": ops}
+    out["breakdown_ms"] = {"quad_count_and_score": round(cnt_ms, 4), "selection": round(sel_ms, 4)}
+    out["best"] = {"ijkl": [int(hits[f][0]) for f in ("i", "j", "k", "l")], "k2": float(hits["k2"][0])}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_quads(g_host, d.pheno, k, args.cpu_budget)
     return out
 
 
@@ -473,7 +541,8 @@ def main():
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
     wl = WORKLOADS[args.workload]
-    run = {"plain": run_plain, "perm": run_perm, "uneven": run_uneven, "pairs": run_pairs}[wl["kind"]]
+    run = {"plain": run_plain, "perm": run_perm, "uneven": run_uneven, "pairs": run_pairs,
+           "quads": run_quads}[wl["kind"]]
     out = run(args, wl)
     print(json.dumps(out), flush=True)
 
