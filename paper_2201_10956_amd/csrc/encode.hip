@@ -14,33 +14,41 @@ namespace epi3 {
 
 // planes[w][m][0..1]: bit b of word w = sample list[w * 32 + b] has genotype
 // 0 (plane 0) / 1 (plane 1).  list < 0 marks padding; padding bits stay 0 in
-// both planes.  SNP slots m >= M are zero.
+// both planes.  SNP slots m >= M are zero.  One wave per SNP and group of 64
+// words: per step the 64 lanes read the genotype bytes of 64 consecutive
+// list positions (two words; within a class the list is in sample order, so
+// the reads fall in a few cache lines of the SNP's row) and two ballots form
+// both planes of both words.
+constexpr int kEncWords = 64;  // words per wave
+
 __global__ void __launch_bounds__(256) encode_kernel(const uint8_t *__restrict__ geno, int64_t ld,
                                                      const int32_t *__restrict__ list, int32_t M,
                                                      int32_t Mp, int32_t Wtot,
                                                      uint32_t *__restrict__ planes,
                                                      int32_t *__restrict__ status) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  const int w = blockIdx.y;
-  if (m >= Mp || w >= Wtot) return;
-  uint32_t b0 = 0, b1 = 0;
+  const int lane = threadIdx.x & 63;
+  const int m = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (m >= Mp) return;
+  const int w0 = blockIdx.y * kEncWords;
+  const uint8_t *row = geno + (int64_t)(m < M ? m : 0) * ld;
+  uint2 *out = reinterpret_cast<uint2 *>(planes);
   bool bad = false;
-  if (m < M) {
-    const uint8_t *row = geno + (int64_t)m * ld;
-    const int32_t *ls = list + (int64_t)w * 32;
-#pragma unroll 8
-    for (int b = 0; b < 32; ++b) {
-      const int s = ls[b];
-      if (s >= 0) {
-        const uint32_t g = row[s];
-        bad |= g > 2u;
-        b0 |= (uint32_t)(g == 0u) << b;
-        b1 |= (uint32_t)(g == 1u) << b;
+  for (int w = w0; w < w0 + kEncWords && w < Wtot; w += 2) {
+    const int wl = w + (lane >> 5);  // this lane's word
+    int g = 3;                       // no genotype: padding, SNP slot >= M, word >= Wtot
+    if (m < M && wl < Wtot) {
+      const int sidx = list[(int64_t)wl * 32 + (lane & 31)];
+      if (sidx >= 0) {
+        g = row[sidx];
+        bad |= g > 2;
       }
     }
+    const unsigned long long z = __ballot(g == 0), o = __ballot(g == 1);
+    if (lane == 0) out[(int64_t)w * Mp + m] = make_uint2((uint32_t)z, (uint32_t)o);
+    if (lane == 32 && w + 1 < Wtot)
+      out[(int64_t)(w + 1) * Mp + m] = make_uint2((uint32_t)(z >> 32), (uint32_t)(o >> 32));
   }
-  reinterpret_cast<uint2 *>(planes)[(int64_t)w * Mp + m] = make_uint2(b0, b1);
-  if (bad) atomicOr(status, 1);
+  if (__ballot(bad) != 0ull && lane == 0) atomicOr(status, 1);
 }
 
 // bytes[m][p][s] = 1 if sample s of SNP m has genotype p (p = 0, 1), else 0;
@@ -198,7 +206,7 @@ hipError_t launch_encode(const uint8_t *geno, int64_t ld, const int32_t *sample_
                          hipStream_t s) {
   const int Wtot = W0 + W1;
   if (Wtot <= 0) return hipSuccess;
-  dim3 grid((Mp + 255) / 256, Wtot);
+  dim3 grid((Mp + 3) / 4, (Wtot + kEncWords - 1) / kEncWords);
   hipLaunchKernelGGL(encode_kernel, grid, dim3(256), 0, s, geno, ld, sample_list, M, Mp, Wtot,
                      planes, status);
   return hipGetLastError();
