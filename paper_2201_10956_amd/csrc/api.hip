@@ -841,7 +841,7 @@ struct BatchLayout {
   const uint32_t **masks = nullptr;
   uint8_t *ph = nullptr;          // MASKED: [groups][64][S]
   int32_t *n1 = nullptr;          // MASKED: [groups][64]
-  int32_t *case_pairs = nullptr;  // MASKED: [groups][Mp][Mp][64][4]
+  int32_t *case_pairs = nullptr;  // MASKED: [groups][Mp][Mp][64] uint2 (16-bit counts)
   int64_t *perm_prefix = nullptr; // MASKED: [M + 1]
   uint8_t *perm_scratch = nullptr;// MASKED: counts of one pass of tiles
   int64_t pass_tiles = 0;
@@ -880,6 +880,8 @@ int check_jobs(const epi3_job *jobs, int32_t n, int32_t variant) {
     }
     if (layout == EPI3_LAYOUT_MASKED) {
       if (!J.case_mask || !J.d->bytes || !same_dataset(J.d, jobs[0].d)) return EPI3_E_INVALID;
+      // counted cells and case pair tables are 16-bit
+      if (J.d->n_samples > 65535) return EPI3_E_UNSUPPORTED;
     }
   }
   return EPI3_OK;
@@ -931,7 +933,7 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
     L.masks = c.take<const uint32_t *>((int64_t)L.groups * kPermGroup);
     L.ph = c.take<uint8_t>((int64_t)L.groups * kPermGroup * d.byte_stride);
     L.n1 = c.take<int32_t>((int64_t)L.groups * kPermGroup);
-    L.case_pairs = c.take<int32_t>((int64_t)L.groups * d.snp_stride * d.snp_stride * kPermGroup * 4);
+    L.case_pairs = c.take<int32_t>((int64_t)L.groups * d.snp_stride * d.snp_stride * kPermGroup * 2);
     L.perm_prefix = c.take<int64_t>((int64_t)d.n_snps + 1);
     // counts of up to kPermPassBytes worth of tiles per pass
     const int64_t tiles = host_perm_tiles(d.n_snps);
@@ -989,7 +991,7 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
       const int g = x / kPermGroup, q = x % kPermGroup;
       sj[x].case_mask = jobs[x].case_mask;
       sj[x].case_pairs = W.case_pairs +
-                         ((int64_t)g * d.snp_stride * d.snp_stride * kPermGroup + q) * 4;
+                         ((int64_t)g * d.snp_stride * d.snp_stride * kPermGroup + q) * 2;
       sj[x].case_stride = kPermGroup;
       sj[x].n1_dev = W.n1 + (int64_t)g * kPermGroup + q;
     }
@@ -1074,7 +1076,7 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
       pj.bytes = static_cast<const uint8_t *>(fp4 ? d.nibbles : d.bytes);
       pj.ph = W.ph + (int64_t)g * kPermGroup * d.byte_stride;  // FP4 rows use the first half
       pj.tot_pairs = d.pairs;
-      pj.case_pairs = W.case_pairs + (int64_t)g * d.snp_stride * d.snp_stride * kPermGroup * 4;
+      pj.case_pairs = W.case_pairs + (int64_t)g * d.snp_stride * d.snp_stride * kPermGroup * 2;
       pj.n1 = W.n1 + (int64_t)g * kPermGroup;
       pj.score = W.score[g * kPermGroup];
       pj.jprefix = W.perm_prefix;

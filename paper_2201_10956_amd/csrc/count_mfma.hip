@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(256) mask_bytes_kernel(const uint32_t *const *
   if (threadIdx.x == 0) n1[q] = red[0];
 }
 
-// Case pairs of every phenotype: out[x][y][q] = (n(0,0), n(0,1), n(1,0), n(1,1))
+// Case pairs of every phenotype: out[x][y][q] = (n(0,0) | n(0,1) << 16, n(1,0) | n(1,1) << 16)
 // over the samples whose bit is set in mask q, for y >= x (every reader looks
 // up pairs in increasing SNP order, and the diagonal for the per-SNP counts;
 // waves whose 64 y all lie below x write nothing).  One wave per (x, 64 y);
@@ -157,14 +157,13 @@ __global__ void __launch_bounds__(256) case_pairs_kernel(const uint32_t *__restr
     }
   }
   if (y >= Mp) return;
-  // stored as 4 x the counts: the finish kernel uses them as byte offsets
-  // into the FP32 log-factorial table
-  int4 *o = reinterpret_cast<int4 *>(out) + ((int64_t)x * Mp + y) * Qp;
+  // two 16-bit counts per word (counts stay below 2^16: the matrix-core paths
+  // take at most 65535 samples per class)
+  uint2 *o = reinterpret_cast<uint2 *>(out) + ((int64_t)x * Mp + y) * Qp;
 #pragma unroll
   for (int t = 0; t < 16; ++t)
     if (q0 + t < Qp)
-      o[q0 + t] = make_int4((int)acc[t][0] << 2, (int)acc[t][1] << 2, (int)acc[t][2] << 2,
-                            (int)acc[t][3] << 2);
+      o[q0 + t] = make_uint2(acc[t][0] | (acc[t][1] << 16), acc[t][2] | (acc[t][3] << 16));
 }
 
 __device__ __forceinline__ void load_pair(const int32_t *p, int64_t idx, int v[4]) {
@@ -460,9 +459,12 @@ __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restr
   const int64_t T = pj.T;
   cptr<int64_t> pre = as_const(pj.jprefix);
   const int4 *tp = reinterpret_cast<const int4 *>(pj.tot_pairs);
-  typedef int i4e __attribute__((ext_vector_type(4)));
   typedef unsigned u4e __attribute__((ext_vector_type(4)));
-  gptr<i4e> cp = (gptr<i4e>)pj.case_pairs;
+  typedef unsigned u2e __attribute__((ext_vector_type(2)));
+  gptr<u2e> cp = (gptr<u2e>)pj.case_pairs;
+  // case pair words -> 4 x counts (byte offsets into the log-factorial table)
+  auto lo4 = [](unsigned v) { return (int)((v & 0xffffu) << 2); };
+  auto hi4 = [](unsigned v) { return (int)((v >> 16) << 2); };
   gptr<u4e> corners = (gptr<u4e>)pj.corners;
   const int qc = q < Q ? q : 0;  // lanes past Q compute on phenotype 0 and write nothing
   const int n1x4 = pj.n1[qc] << 2;
@@ -515,15 +517,17 @@ __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restr
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // ---- case tables and scores, lane = phenotype q ----
-    const i4e cij = cp_row(i, j)[qc];
-    const i4e cii = cp_row(i, i)[qc], cjj = cp_row(j, j)[qc];
+    const u2e cij = cp_row(i, j)[qc];
+    const u2e cii = cp_row(i, i)[qc], cjj = cp_row(j, j)[qc];
+    const int aij[4] = {lo4(cij.x), hi4(cij.x), lo4(cij.y), hi4(cij.y)};
+    const int mi[2] = {lo4(cii.x), hi4(cii.y)}, mj[2] = {lo4(cjj.x), hi4(cjj.y)};
     // loads of the next k are issued before the current k is scored
     u4e cq_n = cor[kk_lo * 64 + qc];
-    i4e cik_n = cp_row(i, k0 + kk_lo)[qc], cjk_n = cp_row(j, k0 + kk_lo)[qc];
-    i4e ckk_n = cp_row(k0 + kk_lo, k0 + kk_lo)[qc];
+    u2e cik_n = cp_row(i, k0 + kk_lo)[qc], cjk_n = cp_row(j, k0 + kk_lo)[qc];
+    u2e ckk_n = cp_row(k0 + kk_lo, k0 + kk_lo)[qc];
     for (int kk = kk_lo; kk < kk_hi; ++kk) {
       const u4e cq = cq_n;
-      const i4e cik = cik_n, cjk = cjk_n, ckk = ckk_n;
+      const u2e cik = cik_n, cjk = cjk_n, ckk = ckk_n;
       if (kk + 1 < kk_hi) {
         const int kn = k0 + kk + 1;
         cq_n = cor[(kk + 1) * 64 + qc];
@@ -538,9 +542,9 @@ __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restr
                                 (cq.x >> 14) & 0x3fffcu, (cq.z >> 14) & 0x3fffcu,
                                 (cq.y << 2) & 0x3fffcu, (cq.w << 2) & 0x3fffcu,
                                 (cq.y >> 14) & 0x3fffcu, (cq.w >> 14) & 0x3fffcu};
-        const int aij[4] = {cij.x, cij.y, cij.z, cij.w}, aik[4] = {cik.x, cik.y, cik.z, cik.w};
-        const int ajk[4] = {cjk.x, cjk.y, cjk.z, cjk.w};
-        const int mi[2] = {cii.x, cii.w}, mj[2] = {cjj.x, cjj.w}, mk[2] = {ckk.x, ckk.w};
+        const int aik[4] = {lo4(cik.x), hi4(cik.x), lo4(cik.y), hi4(cik.y)};
+        const int ajk[4] = {lo4(cjk.x), hi4(cjk.x), lo4(cjk.y), hi4(cjk.y)};
+        const int mk[2] = {lo4(ckk.x), hi4(ckk.y)};
         complete_table(cn, aij, aik, ajk, mi, mj, mk, n1x4, c4);
       }
       float k2 = 0.f;  // rows in order: L[r + 1] - (L[r_0] + L[r_1]), r_1 = cases

@@ -104,7 +104,8 @@ struct PermJob {
   const uint8_t *bytes;       // [Mp][2][S] 0/1 genotype values (bytes, or E2M1 nibbles)
   const uint8_t *ph;          // [64][S] 0/1 case values per phenotype (same format)
   const int32_t *tot_pairs;   // [Mp][Mp][4] pairwise tables over all samples
-  const int32_t *case_pairs;  // [Mp][Mp][Qp][4] pairwise tables over each phenotype's cases, 4 x count
+  const int32_t *case_pairs;  // [Mp][Mp][Qp] uint2 (n00 | n01 << 16, n10 | n11 << 16): pairwise tables
+                              // over each phenotype's cases (y >= x)
   const int32_t *n1;          // [Qp] cases per phenotype
   float *score;               // [Q][T]
   const int64_t *jprefix;     // [M + 1]
@@ -145,8 +146,8 @@ struct SelJob {
   // data needed to recount a candidate
   const uint32_t *planes;
   const int32_t *pairs;    // [classes][Mp][Mp][4]; MASKED: totals at class 0
-  const int32_t *case_pairs; // MASKED: case pairs (4 x count) of the job's mask (pair (x,y) at
-                             // int4 index (x * Mp + y) * case_stride), else NULL
+  const int32_t *case_pairs; // MASKED: case pairs (uint2, 16-bit counts) of the job's mask (pair (x,y) at
+                             // uint2 index (x * Mp + y) * case_stride), else NULL
   const uint32_t *case_mask; // MASKED: [W] mask words, else NULL
   const int32_t *n1_dev;     // MASKED: device count of cases (overrides N1), else NULL
   int64_t case_stride;

@@ -294,17 +294,19 @@ __device__ void triplet_table(const uint32_t *planes, const int32_t *pairs,
     pair_args(pairs, Mp, i, j, k, aij, aik, ajk, mi, mj, mk);
     complete_table(n, aij, aik, ajk, mi, mj, mk, N0 + N1, tot);
     corners(planes, Mp, 0, W0, i, j, k, mask, n);
-    pair_args(case_pairs, Mp, i, j, k, aij, aik, ajk, mi, mj, mk, case_stride);
-    // case pair tables hold 4 x the counts
-    for (int x = 0; x < 4; ++x) {
-      aij[x] >>= 2;
-      aik[x] >>= 2;
-      ajk[x] >>= 2;
-    }
-    for (int x = 0; x < 2; ++x) {
-      mi[x] >>= 2;
-      mj[x] >>= 2;
-      mk[x] >>= 2;
+    // case pair tables: two 16-bit counts per word
+    {
+      const uint2 *cp = reinterpret_cast<const uint2 *>(case_pairs);
+      auto unpack = [&](int x, int y, int v[4]) {
+        const uint2 w = cp[((int64_t)x * Mp + y) * case_stride];
+        v[0] = (int)(w.x & 0xffffu); v[1] = (int)(w.x >> 16);
+        v[2] = (int)(w.y & 0xffffu); v[3] = (int)(w.y >> 16);
+      };
+      int d[4];
+      unpack(i, j, aij); unpack(i, k, aik); unpack(j, k, ajk);
+      unpack(i, i, d); mi[0] = d[0]; mi[1] = d[3];
+      unpack(j, j, d); mj[0] = d[0]; mj[1] = d[3];
+      unpack(k, k, d); mk[0] = d[0]; mk[1] = d[3];
     }
     complete_table(n, aij, aik, ajk, mi, mj, mk, N1, tab[1]);
     for (int x = 0; x < 27; ++x) tab[0][x] = tot[x] - tab[1][x];

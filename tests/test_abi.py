@@ -222,3 +222,19 @@ def test_quad_scan_host_side(epi3):
     assert lib.epi3_quads_workspace_bytes(ctypes.byref(m), 10, 0) == epi3.E_UNSUPPORTED
     big = _fake_dataset(epi3, 5000, 700, 900)
     assert lib.epi3_quads_workspace_bytes(ctypes.byref(big), 10, 0) == epi3.E_UNSUPPORTED
+
+
+def test_phenotype_batches_limit_sample_count(epi3):
+    """Phenotype batches count cells in 16 bits: more than 65535 samples is
+    EPI3_E_UNSUPPORTED (checked before anything is launched)."""
+    lib = epi3._lib
+    ok = _fake_dataset(epi3, 50, 30000, 0, layout=1)
+    big = _fake_dataset(epi3, 50, 70000, 0, layout=1)
+    for d, want_ok in ((ok, True), (big, False)):
+        jobs = (epi3.CJob * 2)()
+        for q in range(2):
+            jobs[q].d = ctypes.pointer(d)
+            jobs[q].case_mask = ctypes.c_void_p(4096)
+            jobs[q].k = 5
+        r = lib.epi3_batched_workspace_bytes(jobs, 2, epi3.VARIANT_MFMA_FP4, 0)
+        assert (r > 0) if want_ok else (r == epi3.E_UNSUPPORTED), r
