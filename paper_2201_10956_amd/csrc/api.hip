@@ -325,6 +325,7 @@ SelJob make_seljob(const epi3_dataset &d, const float *score, int64_t T, SelStat
   S.N1 = d.n_cases;
   S.layout = d.layout;
   S.k = k;
+  S.sample = sample_select(T, k) ? 1 : 0;
   return S;
 }
 
@@ -524,7 +525,8 @@ static int order_scan(const epi3_dataset *d, int order, int32_t k, int64_t cand_
     if (rc != EPI3_OK) return rc;
   }
   return timed(1, s, [&]() {
-    return launch_select(W.sel, 1, T, W.cap, k, s) == hipSuccess ? EPI3_OK : EPI3_E_HIP;
+    return launch_select(W.sel, 1, T, W.cap, k, S.sample != 0, s) == hipSuccess ? EPI3_OK
+                                                                                : EPI3_E_HIP;
   });
 }
 
@@ -728,7 +730,8 @@ int epi3_scan(const epi3_dataset *d, int32_t k, int32_t variant, int64_t cand_ca
     if (rc != EPI3_OK) return rc;
   }
   return timed(1, s, [&]() {
-    return launch_select(W.sel, 1, T, W.cap, k, s) == hipSuccess ? EPI3_OK : EPI3_E_HIP;
+    return launch_select(W.sel, 1, T, W.cap, k, S.sample != 0, s) == hipSuccess ? EPI3_OK
+                                                                                : EPI3_E_HIP;
   });
 }
 
@@ -982,11 +985,13 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
   const bool fp4 = variant != EPI3_VARIANT_MFMA;  // MASKED: AUTO and MFMA_FP4 use FP4
   // selection state first: the count kernels write each job's key range into it
   std::vector<SelJob> sj(n);
+  bool any_sample = false;
   for (int x = 0; x < n; ++x) {
     const epi3_dataset &d = *jobs[x].d;
     sj[x] = make_seljob(d, W.score[x], W.T[x], W.st + x, W.hist + (int64_t)x * kHistBins,
                         W.cand[x], W.rec[x], W.hits + W.hit_off[x], W.cap[x], jobs[x].k,
                         W.ckey[x], W.crank[x], W.ccap[x]);
+    any_sample = any_sample || sj[x].sample;
     if (W.layout == EPI3_LAYOUT_MASKED) {
       const int g = x / kPermGroup, q = x % kPermGroup;
       sj[x].case_mask = jobs[x].case_mask;
@@ -1143,7 +1148,8 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
     }
   }
   return timed(1, s, [&]() {
-    return launch_select(W.sel, n, max_T, max_cap, max_k, s) == hipSuccess ? EPI3_OK : EPI3_E_HIP;
+    return launch_select(W.sel, n, max_T, max_cap, max_k, any_sample, s) == hipSuccess ? EPI3_OK
+                                                                                    : EPI3_E_HIP;
   });
 }
 

@@ -12,6 +12,12 @@ constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kSnpPad = 64;      // plane arrays hold roundup(M, 64) + 64 SNP slots
 constexpr int kHistBins = 2048;  // radix-select bins per pass
 constexpr int kHistPasses = 3;   // 3 x 11 bits >= 32-bit keys
+// Sampled first bound: every kSampleStride-th block of kSampleBlock scores.
+constexpr int kSampleBlock = 1024;
+constexpr int kSampleStride = 32;
+// Whether a selection over T scores for k hits starts from the sampled bound
+// (the sample must hold comfortably more than k scores).
+inline bool sample_select(int64_t T, int64_t k) { return T >= (1ll << 22) && k * 512 <= T; }
 
 // Pointer into the constant address space: uniform loads through it become
 // scalar (s_load) instructions.  Only used for memory no kernel writes while
@@ -155,6 +161,7 @@ struct SelJob {
   int32_t M, Mp, W0, W1, N0, N1;
   int32_t layout;
   int32_t k;
+  int32_t sample;          // 1: the first bound comes from a radix select on a sample (sample_select)
   int32_t order;           // 2: pairs (9-row tables, pair_hits); 4: quads (81 rows, quad_hits);
                            // else triplets
   epi3_pair_hit *pair_hits;  // [k] (order 2)
@@ -410,8 +417,9 @@ hipError_t launch_write_jobs(const Job *jobs_host, int32_t n, Job *dst_dev, hipS
 hipError_t launch_count_valu(const Job *jobs_dev, int32_t n_jobs, int64_t total_tiles,
                              unsigned long long *queue, const float *lf32, int32_t lf_len,
                              int32_t P_lo, int32_t P_hi, bool counts, hipStream_t s);
+// sampled: at least one job has SelJob::sample set.
 hipError_t launch_select(SelJob *sel_dev, int32_t n_jobs, int64_t max_T, int64_t max_cap,
-                         int32_t max_k, hipStream_t s);
+                         int32_t max_k, bool sampled, hipStream_t s);
 hipError_t launch_write_seljobs(const SelJob *h, int32_t n, SelJob *dst_dev, hipStream_t s);
 hipError_t launch_init_select(SelJob *sel_dev, int32_t n_jobs, hipStream_t s);
 hipError_t launch_score_triplets(const epi3_dataset &d, const uint32_t *ijk, int64_t n,

@@ -9,7 +9,11 @@
 //      of the bin holding the k-th value plus 2 e(N) is compacted into a
 //      short list, and the later passes and the candidate collection read
 //      that list instead of the plane (the plane again if the list
-//      overflows its capacity);
+//      overflows its capacity).  For large planes the first bound comes
+//      instead from the same radix select run on a sample (every 32nd block
+//      of 1024 scores): the sample's k-th smallest value is at least T32
+//      (its k smallest are k scores of the plane), so compacting every score
+//      up to it plus 2 e(N) takes one pass over the plane instead of two;
 //   2. every triplet with K2_fp32 <= T32 + 2 e(N) is a candidate, where e(N)
 //      bounds |K2_fp32 - K2_fp64| for any table of N samples, so the candidate
 //      set contains every member of the FP64 top-k;
@@ -72,21 +76,36 @@ __device__ __forceinline__ bool use_compact(const SelState *st, const SelJob &J)
   return st->cmode == 1u && st->cn <= (unsigned long long)J.ccap;
 }
 
-__global__ void __launch_bounds__(256) hist_kernel(const SelJob *__restrict__ sj) {
+// Plane index of element e of the sample (every kSampleStride-th block).
+__device__ __forceinline__ int64_t sample_at(int64_t e) {
+  return (e / kSampleBlock) * kSampleBlock * kSampleStride + e % kSampleBlock;
+}
+// Elements of the sample of a plane of T scores (the last block may be short).
+__host__ __device__ __forceinline__ int64_t sample_len(int64_t T) {
+  const int64_t nb = (T + kSampleBlock - 1) / kSampleBlock;          // blocks of the plane
+  const int64_t ns = (nb + kSampleStride - 1) / kSampleStride;      // sampled blocks
+  const int64_t last = (ns - 1) * kSampleStride;                    // index of the last one
+  return ns <= 0 ? 0 : (ns - 1) * kSampleBlock + (T - last * kSampleBlock < kSampleBlock
+                                                       ? T - last * kSampleBlock
+                                                       : kSampleBlock);
+}
+
+// sampled: histogram of the sample of sampling jobs (other jobs skip).
+__global__ void __launch_bounds__(256) hist_kernel(const SelJob *__restrict__ sj, int sampled) {
   const SelJob &J = sj[blockIdx.y];
   const SelState *st = J.st;
-  if (st->done) return;
+  if (st->done || (sampled && !J.sample)) return;
   const uint32_t lo = st->lo;
   const int shift = st->shift;
   __shared__ uint32_t h[kHistBins];
   for (int b = threadIdx.x; b < kHistBins; b += blockDim.x) h[b] = 0u;
   __syncthreads();
-  const bool compact = use_compact(st, J);
+  const bool compact = !sampled && use_compact(st, J);
   const float *score = J.score;
-  const int64_t n = compact ? (int64_t)st->cn : J.T;
+  const int64_t n = sampled ? sample_len(J.T) : compact ? (int64_t)st->cn : J.T;
   for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n;
        x += (int64_t)gridDim.x * blockDim.x) {
-    const uint32_t key = compact ? J.ckey[x] : f2key(score[x]);
+    const uint32_t key = compact ? J.ckey[x] : f2key(score[sampled ? sample_at(x) : x]);
     if (key >= lo) {
       const uint32_t d = (key - lo) >> shift;
       if (d < (uint32_t)kHistBins) atomicAdd(&h[d], 1u);
@@ -98,10 +117,11 @@ __global__ void __launch_bounds__(256) hist_kernel(const SelJob *__restrict__ sj
 }
 
 // One block per job: find the bin holding the krem-th key, narrow the window.
-__global__ void __launch_bounds__(1024) find_kernel(SelJob *sj) {
+// sampled: only the sampling jobs (their sample's krem-th key).
+__global__ void __launch_bounds__(1024) find_kernel(SelJob *sj, int sampled) {
   SelJob &J = sj[blockIdx.x];
   SelState *st = J.st;
-  if (st->done) return;
+  if (st->done || (sampled && !J.sample)) return;
   __shared__ unsigned long long cum[kHistBins];
   const int t = threadIdx.x;
   // every thread reads the state before any thread updates it (barriers below)
@@ -152,14 +172,36 @@ __global__ void threshold_kernel(SelJob *sj, int n) {
   st->thr = f;
 }
 
-// After the first pass: every score <= (last key of the window) + 2 e(N)
-// goes to the compacted list (key, rank).  That bound is at least the final
-// threshold, so the list holds every key the later passes and the candidate
-// collection look at.
-__global__ void __launch_bounds__(256) compact_kernel(const SelJob *__restrict__ sj) {
+// After the sample's select (sampling jobs: whi = the sample's k-th key):
+// the plane's window restarts at its key range with the exact rank k.
+__global__ void bound_kernel(SelJob *sj, int n) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n || !sj[x].sample) return;
+  SelState *st = sj[x].st;
+  if (st->done != 1u) return;  // nothing to select
+  const uint32_t ub = st->kth;
+  st->lo = st->kmin;
+  st->whi = ub;
+  st->krem = (uint64_t)st->keff;
+  const uint32_t range = ub - st->kmin;
+  if (range == 0u) {  // at least k scores equal the minimum
+    st->kth = st->kmin;
+    return;
+  }
+  st->done = 0u;
+  const int bl = 32 - __builtin_clz(range);
+  st->shift = bl > 11 ? bl - 11 : 0;
+}
+
+// Every score <= (last key of the window) + 2 e(N) goes to the compacted list
+// (key, rank): after the first pass (post), or right after the sample's
+// bound (pre, sampling jobs).  That bound is at least the final threshold, so
+// the list holds every key the later passes and the candidate collection
+// look at.
+__global__ void __launch_bounds__(256) compact_kernel(const SelJob *__restrict__ sj, int pre) {
   const SelJob &J = sj[blockIdx.y];
   SelState *st = J.st;
-  if (st->done) return;
+  if (st->done || (pre ? !J.sample : J.sample)) return;
   const double ubd = (double)key2f(st->whi) + J.err2;
   float ub = (float)ubd;
   if ((double)ub < ubd) ub = __uint_as_float(__float_as_uint(ub) + 1u);  // ub >= 0: next float up
@@ -541,17 +583,29 @@ hipError_t launch_init_select(SelJob *sel_dev, int32_t n_jobs, hipStream_t s) {
 }
 
 hipError_t launch_select(SelJob *sel_dev, int32_t n_jobs, int64_t max_T, int64_t max_cap,
-                         int32_t max_k, hipStream_t s) {
+                         int32_t max_k, bool sampled, hipStream_t s) {
   (void)max_k;
   const unsigned nj = (unsigned)n_jobs;
   hipLaunchKernelGGL(window_kernel, dim3((n_jobs + 63) / 64), dim3(64), 0, s, sel_dev, n_jobs);
   int64_t hb = (max_T + 256 * 16 - 1) / (256 * 16);
   if (hb > 2048) hb = 2048;
   if (hb < 1) hb = 1;
+  if (sampled) {
+    int64_t hs = (sample_len(max_T) + 256 * 16 - 1) / (256 * 16);
+    if (hs > 2048) hs = 2048;
+    if (hs < 1) hs = 1;
+    for (int p = 0; p < kHistPasses; ++p) {
+      hipLaunchKernelGGL(hist_kernel, dim3((unsigned)hs, nj), dim3(256), 0, s, sel_dev, 1);
+      hipLaunchKernelGGL(find_kernel, dim3(nj), dim3(1024), 0, s, sel_dev, 1);
+    }
+    hipLaunchKernelGGL(bound_kernel, dim3((n_jobs + 63) / 64), dim3(64), 0, s, sel_dev, n_jobs);
+    hipLaunchKernelGGL(compact_kernel, dim3((unsigned)hb, nj), dim3(256), 0, s, sel_dev, 1);
+  }
   for (int p = 0; p < kHistPasses; ++p) {
-    hipLaunchKernelGGL(hist_kernel, dim3((unsigned)hb, nj), dim3(256), 0, s, sel_dev);
-    hipLaunchKernelGGL(find_kernel, dim3(nj), dim3(1024), 0, s, sel_dev);
-    if (p == 0) hipLaunchKernelGGL(compact_kernel, dim3((unsigned)hb, nj), dim3(256), 0, s, sel_dev);
+    hipLaunchKernelGGL(hist_kernel, dim3((unsigned)hb, nj), dim3(256), 0, s, sel_dev, 0);
+    hipLaunchKernelGGL(find_kernel, dim3(nj), dim3(1024), 0, s, sel_dev, 0);
+    if (p == 0)
+      hipLaunchKernelGGL(compact_kernel, dim3((unsigned)hb, nj), dim3(256), 0, s, sel_dev, 0);
   }
   hipLaunchKernelGGL(threshold_kernel, dim3((n_jobs + 63) / 64), dim3(64), 0, s, sel_dev, n_jobs);
   hipLaunchKernelGGL(collect_kernel, dim3((unsigned)hb, nj), dim3(256), 0, s, sel_dev);
