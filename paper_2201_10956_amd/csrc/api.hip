@@ -233,6 +233,7 @@ struct OrderLayout {
   int64_t *crank;
   int64_t ccap;
   int64_t cap;
+  uint8_t *t3;  // quads: triplet corner table (NULL: counted per quad)
   int64_t total;
 };
 
@@ -258,6 +259,8 @@ OrderLayout order_layout(void *ws, const epi3_dataset &d, int order, int32_t k, 
   L.ccap = compact_cap(T, L.cap);
   L.ckey = c.take<uint32_t>(L.ccap);
   L.crank = c.take<int64_t>(L.ccap);
+  if (order == 4 && d.n_cases <= 65535 && d.n_controls <= 65535)
+    L.t3 = c.take<uint8_t>(quad_triplet_table_bytes(d.n_snps));
   L.total = c.size();
   return L;
 }
@@ -519,7 +522,7 @@ static int order_scan(const epi3_dataset *d, int order, int32_t k, int64_t cand_
   if (T > 0) {
     rc = timed(0, s, [&]() {
       const hipError_t e = order == 2 ? launch_pair_scores(*d, W.score, &W.st->kmin, s)
-                                      : launch_quad_scores(*d, W.score, &W.st->kmin, s);
+                                      : launch_quad_scores(*d, W.t3, W.score, &W.st->kmin, s);
       return e == hipSuccess ? EPI3_OK : EPI3_E_HIP;
     });
     if (rc != EPI3_OK) return rc;

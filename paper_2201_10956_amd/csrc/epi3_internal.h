@@ -273,6 +273,32 @@ __device__ __forceinline__ void quad_counts(const uint32_t *planes, int64_t Mp, 
   }
 }
 
+// Only the 16 quad corner cells of quad_counts (cnt[0..15]).
+__device__ __forceinline__ void quad_corner_counts(const uint32_t *planes, int64_t Mp, int w0, int w1,
+                                                   int i, int j, int k, int l, uint32_t cnt[16]) {
+#pragma unroll
+  for (int x = 0; x < 16; ++x) cnt[x] = 0u;
+  const uint2 *pv = reinterpret_cast<const uint2 *>(planes);
+  for (int w = w0; w < w1; ++w) {
+    const uint2 *row = pv + (int64_t)w * Mp;
+    const uint2 xi = row[i], xj = row[j], xk = row[k], xl = row[l];
+    const uint32_t X[4][2] = {{xi.x, xi.y}, {xj.x, xj.y}, {xk.x, xk.y}, {xl.x, xl.y}};
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const uint32_t ij = X[0][a] & X[1][b];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const uint32_t ijk = ij & X[2][c];
+#pragma unroll
+          for (int d = 0; d < 2; ++d)
+            cnt[8 * a + 4 * b + 2 * c + d] += __builtin_popcount(ijk & X[3][d]);
+        }
+      }
+  }
+}
+
 // The 81 cells t[27 a + 9 b + 3 c + d] (a, b, c, d in {0, 1, 2}) of one class
 // of the quad (i, j, k, l) from its counts (quad_counts) and the class's
 // pairwise tables pairs[x][y] (int4 (n00, n01, n10, n11), per-SNP counts on
@@ -349,6 +375,26 @@ __host__ __device__ __forceinline__ int64_t c4(int64_t x) {
 __host__ __device__ __forceinline__ int64_t quad_rank(int64_t M, int64_t i, int64_t j, int64_t k,
                                                       int64_t l) {
   return c4(M) - c4(M - i) + c3(M - 1 - i) - c3(M - j) + c2(M - 1 - j) - c2(M - k) + (l - k - 1);
+}
+
+// Triplet (i, j, k) of lexicographic rank `rank` among the triplets of M SNPs.
+__device__ __forceinline__ void decode_rank(int64_t M, int64_t rank, int &i, int &j, int &k) {
+  const int64_t C = c3(M);
+  int lo = 0, hi = (int)M - 3;  // last i with first rank <= rank
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (C - c3(M - mid) <= rank) lo = mid; else hi = mid - 1;
+  }
+  i = lo;
+  const int64_t r1 = rank - (C - c3(M - i));
+  // within i: pivots j > i, each with M - 1 - j values of k
+  int jl = i + 1, jh = (int)M - 2;
+  while (jl < jh) {
+    const int mid = (jl + jh + 1) >> 1;
+    if (c2(M - 1 - i) - c2(M - mid) <= r1) jl = mid; else jh = mid - 1;
+  }
+  j = jl;
+  k = (int)(rank - lex_base(M, i, j));
 }
 
 // Quad (i, j, k, l) of lexicographic rank `rank` among the quads of M SNPs.
@@ -435,8 +481,12 @@ hipError_t launch_case_pairs(const uint32_t *planes, int32_t Mp, int32_t W,
 // tables, by lexicographic pair rank; key range into keyrange[0..1].
 hipError_t launch_pair_scores(const epi3_dataset &d, float *score, uint32_t *keyrange, hipStream_t s);
 // Quad scan: FP32 K2 of every quad of a SPLIT data set, by lexicographic quad
-// rank; key range into keyrange[0..1].
-hipError_t launch_quad_scores(const epi3_dataset &d, float *score, uint32_t *keyrange, hipStream_t s);
+// rank; key range into keyrange[0..1].  t3: device buffer of
+// quad_triplet_table_bytes for the triplet corner table (classes of at most
+// 65535 samples), or NULL to count the sub-triplet corners per quad.
+inline int64_t quad_triplet_table_bytes(int64_t M) { return 2 * 16 * (M < 3 ? 0 : M * (M - 1) / 2 * (M - 2) / 3); }
+hipError_t launch_quad_scores(const epi3_dataset &d, void *t3, float *score, uint32_t *keyrange,
+                              hipStream_t s);
 int64_t host_perm_tiles(int64_t M);
 hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,
                                   unsigned long long *queue, bool fp4, hipStream_t s);

@@ -256,25 +256,6 @@ __global__ void __launch_bounds__(256) collect_kernel(const SelJob *__restrict__
 }
 
 // ----------------------------------------------------- FP64 re-score ----
-__device__ __forceinline__ void decode_rank(int64_t M, int64_t rank, int &i, int &j, int &k) {
-  const int64_t C = c3(M);
-  int lo = 0, hi = (int)M - 3;  // last i with first rank <= rank
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (C - c3(M - mid) <= rank) lo = mid; else hi = mid - 1;
-  }
-  i = lo;
-  const int64_t r1 = rank - (C - c3(M - i));
-  // within i: pivots j > i, each with M - 1 - j values of k
-  int jl = i + 1, jh = (int)M - 2;
-  while (jl < jh) {
-    const int mid = (jl + jh + 1) >> 1;
-    if (c2(M - 1 - i) - c2(M - mid) <= r1) jl = mid; else jh = mid - 1;
-  }
-  j = jl;
-  k = (int)(rank - lex_base(M, i, j));
-}
-
 __device__ __forceinline__ unsigned wave_sum(unsigned v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
