@@ -212,3 +212,23 @@ def test_compaction_overflow_falls_back_to_plane(env, ccap):
         epi3.set_compact_cap(0)
     ijk, k2, cc = oracle.scan_topk(d.geno, d.pheno, 10)
     assert_hits_equal_oracle(h, ijk, k2, cc)
+
+
+@pytest.mark.parametrize("variant", ["valu", "mfma_fp4"])
+def test_sampled_bound_with_compaction_overflow(env, variant):
+    """512 SNPs x 4096 samples (22 M triplets): the first bound comes from the
+    sampled select; with a compaction capacity of 16 the list overflows and the
+    later passes read the plane.  Hits stay exact either way."""
+    torch, epi3 = env
+    print(f"[case] sampled bound, {variant}", flush=True)
+    d = make_config(2)
+    ds = epi3.encode(to_dev(d.geno), d.pheno)
+    ijk, k2, cc = oracle.scan_topk(d.geno, d.pheno, 100)
+    h = epi3.scan_topk(ds, 100, variant)
+    assert_hits_equal_oracle(h, ijk, k2, cc)
+    try:
+        epi3.set_compact_cap(16)
+        h = epi3.scan_topk(ds, 100, variant)
+    finally:
+        epi3.set_compact_cap(0)
+    assert_hits_equal_oracle(h, ijk, k2, cc)
