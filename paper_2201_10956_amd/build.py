@@ -40,5 +40,22 @@ def build(out: str = LIB, extra=(), verbose: bool = False) -> str:
     return out
 
 
+HOST_SRC = os.path.join(PKG, "host", "epi3_host.c")
+HOST_LIB = os.path.join(PKG, "host", "libepi3_host.so")
+
+
+def build_host(out: str = HOST_LIB) -> str:
+    """The host-CPU scan (a baseline beside the GPU library): gcc, OpenMP;
+    the vector loops carry their own target attributes and are chosen at run
+    time from the CPU's features, so the library runs on any x86-64 host."""
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall", "-Wextra",
+           "-I", os.path.join(ROOT, "include"), HOST_SRC, "-o", tmp, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_host())
