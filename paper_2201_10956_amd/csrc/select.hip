@@ -484,35 +484,49 @@ __global__ void __launch_bounds__(256) rescore_kernel(const SelJob *__restrict__
 }
 
 // Position of each candidate under (key, rank); the first keff go out.
-__global__ void __launch_bounds__(256) rank_kernel(const SelJob *__restrict__ sj) {
+// Rank of every candidate = number of candidates before it under
+// (K2_fp64, rank); each workgroup takes 64 candidates (one per lane) and its
+// 16 waves split the comparisons, so chains stay short for a few thousand
+// candidates.
+constexpr int kRankThreads = 1024;
+__global__ void __launch_bounds__(kRankThreads) rank_kernel(const SelJob *__restrict__ sj) {
   const SelJob &J = sj[blockIdx.y];
   SelState *st = J.st;
   if (st->done != 1u) return;
   const int64_t n = (int64_t)st->ncand < J.cap ? (int64_t)st->ncand : J.cap;
   const int64_t keff = st->keff;
-  __shared__ uint64_t skey[256];
-  __shared__ int64_t srank[256];
-  for (int64_t xb = blockIdx.x; xb * 256 < n; xb += gridDim.x) {
-    const int64_t x = xb * 256 + threadIdx.x;
+  __shared__ uint64_t skey[kRankThreads];
+  __shared__ int64_t srank[kRankThreads];
+  __shared__ int64_t spos[kRankThreads / 64][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t xb = blockIdx.x; xb * 64 < n; xb += gridDim.x) {
+    const int64_t x = xb * 64 + lane;
     uint64_t mykey = ~0ull;
     int64_t myrank = 0;
     if (x < n) {
       mykey = J.rec[x].key;
       myrank = J.rec[x].rank;
     }
-    int64_t pos = 0;
-    for (int64_t yb = 0; yb < n; yb += 256) {
+    int64_t part = 0;
+    for (int64_t yb = 0; yb < n; yb += kRankThreads) {
       const int64_t y = yb + threadIdx.x;
       __syncthreads();
       skey[threadIdx.x] = y < n ? J.rec[y].key : ~0ull;
       srank[threadIdx.x] = y < n ? J.rec[y].rank : INT64_MAX;
       __syncthreads();
-      const int lim = (n - yb) < 256 ? (int)(n - yb) : 256;
-      for (int z = 0; z < lim; ++z) {
+      // wave w compares with entries [64 w, 64 w + 64) of the chunk
+      const int64_t left = n - yb - 64 * wave;
+      const int lim = left < 0 ? 0 : (left < 64 ? (int)left : 64);
+      for (int z = 64 * wave; z < 64 * wave + lim; ++z) {
         const uint64_t kz = skey[z];
-        pos += (kz < mykey) || (kz == mykey && srank[z] < myrank);
+        part += (kz < mykey) || (kz == mykey && srank[z] < myrank);
       }
     }
+    spos[wave][lane] = part;
+    __syncthreads();
+    if (wave != 0) continue;
+    int64_t pos = 0;
+    for (int w = 0; w < kRankThreads / 64; ++w) pos += spos[w][lane];
     if (x < n && pos < keff && J.order == 4) {
       const CandRec &R = J.rec[x];
       epi3_quad_hit &H = J.quad_hits[pos];
@@ -594,10 +608,10 @@ hipError_t launch_select(SelJob *sel_dev, int32_t n_jobs, int64_t max_T, int64_t
   if (rb > 4096) rb = 4096;
   if (rb < 1) rb = 1;
   hipLaunchKernelGGL(rescore_kernel, dim3((unsigned)rb, nj), dim3(256), 0, s, sel_dev);
-  int64_t kb = (max_cap + 255) / 256;
+  int64_t kb = (max_cap + 63) / 64;
   if (kb > 1024) kb = 1024;
   if (kb < 1) kb = 1;
-  hipLaunchKernelGGL(rank_kernel, dim3((unsigned)kb, nj), dim3(256), 0, s, sel_dev);
+  hipLaunchKernelGGL(rank_kernel, dim3((unsigned)kb, nj), dim3(kRankThreads), 0, s, sel_dev);
   return hipGetLastError();
 }
 
