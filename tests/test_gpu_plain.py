@@ -87,6 +87,23 @@ def test_k_larger_than_triplets_and_too_few_snps(env):
     assert len(epi3.scan_topk(ds2, 5, "valu")) == 0
 
 
+@pytest.mark.parametrize("variant", ["valu", "mfma_fp4"])
+def test_many_exact_ties_rank_over_several_chunks(env, variant):
+    """30 SNPs drawn from 4 distinct rows: thousands of triplets share their
+    K2 exactly, and k = all 4060 triplets puts every one through the rank
+    kernel (several 1024-candidate chunks, ties broken by (i, j, k))."""
+    torch, epi3 = env
+    print(f"[case] exact ties, 30 SNPs x 200 samples, k=4060, {variant}", flush=True)
+    base, pheno = _tiny(77, 4, 200, 0.4)
+    pick = SplitMix64(78, 1).uniform(0, 30)
+    geno = np.ascontiguousarray(base[np.minimum((pick * 4).astype(np.int64), 3)])
+    ds = epi3.encode(to_dev(geno), pheno)
+    h = epi3.scan_topk(ds, 4060, variant)
+    ijk, k2, cc = oracle.scan_topk(geno, pheno, 4060)
+    assert len(h) == 4060 and len(np.unique(k2)) < 400
+    assert_hits_equal_oracle(h, ijk, k2, cc)
+
+
 def test_bad_genotype_and_phenotype(env):
     torch, epi3 = env
     geno, pheno = _tiny(9, 5, 40, 0.5)

@@ -11,6 +11,8 @@
 import itertools
 import math
 import os
+import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -384,6 +386,11 @@ def test_pin_suite_passes_on_oracle():
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_catch_planted_mistake(name, tmp_path):
+    """Each planted mistake makes the pin suite fail.  The mutant runs in a
+    child interpreter: some mistakes (a loop guard, a rank offset) also write
+    outside the caller's output arrays, which must not corrupt this
+    process's heap; the child then either fails a pin (exit 3) or is ended by
+    the C library's heap checks, and both count as caught."""
     src = open(os.path.join(os.path.dirname(oracle.__file__), "epi3_oracle.c")).read()
     a, b = MUTANTS[name]
     assert src.count(a) >= 1, name
@@ -392,6 +399,13 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     p.write_text(mut)
     from oracle.build import build_oracle
     lib_path = build_oracle(str(p), str(tmp_path / f"lib_{name}.so"))
-    lib = oracle.load(lib_path)
-    with pytest.raises(AssertionError):
-        _pin_suite(lib)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (f"import sys\nsys.path.insert(0, {root!r})\n"
+            "import oracle\n"
+            "from tests.test_oracle_pins import _pin_suite\n"
+            f"lib = oracle.load({lib_path!r})\n"
+            "try:\n    _pin_suite(lib)\nexcept AssertionError:\n    sys.exit(3)\n"
+            "sys.exit(0)\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"pins passed on mutant {name}"
+    assert r.returncode == 3 or r.returncode < 0 or r.returncode in (134, 139), (r.returncode, r.stderr[-2000:])
