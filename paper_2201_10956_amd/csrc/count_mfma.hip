@@ -422,11 +422,10 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
 // that one XCD's L2 serves a block pair's case tables to several pivots j,
 // measured slower.)
 // Dynamic LDS of the finish kernel: [log-factorial table (LDS variant)] then
-// the per-wave all-sample cells, staged scores and key ranges.  The kernel
+// the per-wave staged scores and the key ranges.  The kernel
 // declares no static LDS, so the dynamic block and with it the table start at
 // LDS address 0 and a lookup is one ds_read at the byte offset.
 struct FinishPermLds {
-  uint2 tt[4][kPermKB][27];  // (4 x all-sample cell, bits of L[cell + 1])
   float score[4][kPermKB][64];
   uint32_t range[64][2];
 };
@@ -493,6 +492,13 @@ __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restr
     const int kk_lo = j + 1 - k0 > 0 ? j + 1 - k0 : 0;
     const int kk_hi = M - k0 < kPermKB ? M - k0 : kPermKB;
     // ---- all-sample tables, lane kk = triplet (i, j, k0 + kk) ----
+    // Kept in registers, two cell counts per register (16 bits each); the
+    // phenotype loop below reads lane kk's counts into scalar registers and
+    // fetches L[count + 1] by scalar loads, so neither LDS bandwidth nor
+    // vector instructions are spent broadcasting them.
+    uint32_t pk[14];
+#pragma unroll
+    for (int x = 0; x < 14; ++x) pk[x] = 0u;
     if (q >= kk_lo && q < kk_hi) {
       const int k = k0 + q;
       const uint4 tq = pj.totals[tbase + q];
@@ -509,13 +515,8 @@ __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restr
       int t4[27];
       complete_table(tn, tij, tik, tjk, mi, mj, mk, pj.N << 2, t4);
 #pragma unroll
-      for (int x = 0; x < 27; ++x)
-        sh.tt[wave][q][x] = make_uint2(
-            (uint32_t)t4[x], __float_as_uint(LDS ? lf_at_lds0(t4[x] + 4) : lf_at(sL, t4[x] + 4)));
+      for (int x = 0; x < 27; ++x) pk[x >> 1] |= ((uint32_t)t4[x] >> 2) << (16 * (x & 1));
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     // ---- case tables and scores, lane = phenotype q ----
     const u2e cij = cp_row(i, j)[qc];
     const u2e cii = cp_row(i, i)[qc], cjj = cp_row(j, j)[qc];
@@ -547,15 +548,20 @@ __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restr
         const int mk[2] = {lo4(ckk.x), hi4(ckk.y)};
         complete_table(cn, aij, aik, ajk, mi, mj, mk, n1x4, c4);
       }
+      uint32_t spk[14];
+#pragma unroll
+      for (int x = 0; x < 14; ++x) spk[x] = __builtin_amdgcn_readlane(pk[x], kk);
       float k2 = 0.f;  // rows in order: L[r + 1] - (L[r_0] + L[r_1]), r_1 = cases
 #pragma unroll
       for (int x = 0; x < 27; ++x) {
-        const uint2 tt = sh.tt[wave][kk][x];
-        const int r0 = (int)tt.x - c4[x];
+        const uint32_t nall = (spk[x >> 1] >> (16 * (x & 1))) & 0xffffu;
+        const int tall = (int)(nall << 2);
+        const float l1 = lf32[nall + 1];  // uniform address: a scalar load
+        const int r0 = tall - c4[x];
         if (LDS)
-          k2 += __uint_as_float(tt.y) - (lf_at_lds0(r0) + lf_at_lds0(c4[x]));
+          k2 += l1 - (lf_at_lds0(r0) + lf_at_lds0(c4[x]));
         else
-          k2 += __uint_as_float(tt.y) - (lf_at(sL, r0) + lf_at(sL, c4[x]));
+          k2 += l1 - (lf_at(sL, r0) + lf_at(sL, c4[x]));
       }
       sh.score[wave][kk][q] = k2;
       const uint32_t key = f2key(k2);
