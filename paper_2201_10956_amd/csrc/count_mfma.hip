@@ -412,9 +412,10 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
 // Completes the tables of one pass of tiles and scores them.  Workgroup per
 // tile (persistent, round robin); wave w = pivot i = 4 ib + w.  First the
 // wave's lanes 0..15 complete the all-sample tables of the tile's 16 triplets
-// (one k each) and leave 4 x cell and L[cell + 1] per cell in LDS; then
-// lane = phenotype q loops over the 16 k, reading those as broadcasts, and
-// completes and scores its case table.  Case cells are handled as 4 x count
+// (one k each) and keep the cells in registers; then lane = phenotype q
+// loops over the 16 k, reading lane k's cells into scalar registers
+// (readlane) and their L[cell + 1] by scalar loads, and completes and scores
+// its case table.  Case cells are handled as 4 x count
 // (byte offsets into the table), so each lookup needs no index arithmetic.
 // Per-phenotype corner cells and case pair tables are contiguous 1 KB rows;
 // scores are staged per wave in LDS and written as 64-byte runs of
