@@ -222,11 +222,11 @@ def run_pairs(args, wl):
     d = make_config(wl["cfg"])
     M, N, k = d.n_snps, d.n_samples, c["k"]
     geno = torch.from_numpy(d.geno).to("cuda")
-    ds = epi3.encode(geno, d.pheno)
+    ds = epi3.encode(geno, d.pheno, values=False)
     sc = epi3.PairScanner(ds, k)
 
     def step():  # encode (planes + pairwise tables) + pair scores + exact top-k
-        epi3.encode(geno, d.pheno, into=ds)
+        epi3.encode(geno, d.pheno, into=ds, values=False)
         return sc.run()
 
     dt, hits = _timed_steps(step, args.steps, args.warmup)
@@ -298,11 +298,11 @@ def run_quads(args, wl):
     M, N, k = wl["snps"], d.n_samples, c["k"]
     g_host = np.ascontiguousarray(d.geno[:M])
     geno = torch.from_numpy(g_host).to("cuda")
-    ds = epi3.encode(geno, d.pheno)
+    ds = epi3.encode(geno, d.pheno, values=False)
     sc = epi3.QuadScanner(ds, k)
 
     def step():  # encode (planes + pairwise tables) + quad counts and scores + exact top-k
-        epi3.encode(geno, d.pheno, into=ds)
+        epi3.encode(geno, d.pheno, into=ds, values=False)
         return sc.run()
 
     dt, hits = _timed_steps(step, args.steps, args.warmup)

@@ -67,6 +67,14 @@ enum {
     EPI3_LAYOUT_MASKED = 1
 };
 
+/* Flag OR'ed into the layout of epi3_encode_bytes / epi3_encode (SPLIT only):
+ * encode the bit planes, pairwise tables and log-factorial tables but not the
+ * 0/1 value planes (out->bytes = out->nibbles = NULL).  The pair and quad
+ * scans and the vector-ALU triplet scan read bit planes only; on such a data
+ * set the matrix-core variants return EPI3_E_UNSUPPORTED and
+ * EPI3_VARIANT_AUTO takes the vector-ALU kernel. */
+enum { EPI3_ENCODE_BITS_ONLY = 0x100 };
+
 /* Count-stage kernels. */
 enum {
     EPI3_VARIANT_AUTO = 0,  /* library choice (see epi3_tile_rule) */

@@ -628,6 +628,7 @@ int64_t epi3_n_quads(int32_t n_snps) { return c4(n_snps); }
 
 int64_t epi3_encode_bytes(int32_t n_snps, int32_t n_cases, int32_t n_controls, int32_t layout) {
   if (n_snps < 0 || n_cases < 0 || n_controls < 0 || n_cases + n_controls <= 0) return EPI3_E_INVALID;
+  if (layout == (EPI3_LAYOUT_SPLIT | EPI3_ENCODE_BITS_ONLY)) layout = EPI3_LAYOUT_SPLIT;
   if (layout != EPI3_LAYOUT_SPLIT && layout != EPI3_LAYOUT_MASKED) return EPI3_E_INVALID;
   return encode_layout(nullptr, n_snps, n_cases, n_controls, layout).total;
 }
@@ -638,6 +639,8 @@ int epi3_encode(const uint8_t *geno_dev, int64_t ld, const uint8_t *pheno_host, 
   if (!out || !pheno_host || !buf_dev || n_snps < 0 || n_samples <= 0 || ld < n_samples ||
       (n_snps > 0 && !geno_dev))
     return EPI3_E_INVALID;
+  const bool values = layout != (EPI3_LAYOUT_SPLIT | EPI3_ENCODE_BITS_ONLY);
+  if (!values) layout = EPI3_LAYOUT_SPLIT;
   if (layout != EPI3_LAYOUT_SPLIT && layout != EPI3_LAYOUT_MASKED) return EPI3_E_INVALID;
   if (reinterpret_cast<uintptr_t>(buf_dev) % kAlign) return EPI3_E_INVALID;
   int32_t n1 = 0;
@@ -672,7 +675,7 @@ int epi3_encode(const uint8_t *geno_dev, int64_t ld, const uint8_t *pheno_host, 
   if (layout == EPI3_LAYOUT_MASKED)
     HIP_OK(launch_encode_values(geno_dev, ld, L.list, 0, n_samples, 0, 0, 1, n_snps, L.Mp, L.S,
                                 L.bytes, L.nibbles, s));
-  else
+  else if (values)
     HIP_OK(launch_encode_values(geno_dev, ld, L.list, 0, n0, L.W0 * 32, n1, 2, n_snps, L.Mp, L.S,
                                 L.bytes, L.nibbles, s));
   const int prc = timed(4, s, [&]() {
@@ -695,8 +698,8 @@ int epi3_encode(const uint8_t *geno_dev, int64_t ld, const uint8_t *pheno_host, 
   out->snp_stride = L.Mp;
   out->byte_stride = L.S;
   out->planes = L.planes;
-  out->bytes = L.bytes;
-  out->nibbles = L.nibbles;
+  out->bytes = values ? L.bytes : nullptr;
+  out->nibbles = values ? L.nibbles : nullptr;
   out->pairs = L.pairs;
   out->lf64 = L.lf64;
   out->lf32 = L.lf32;

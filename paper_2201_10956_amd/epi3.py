@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libepi3.so")
 OK, E_INVALID, E_GENOTYPE, E_PHENOTYPE, E_WORKSPACE, E_CAPACITY, E_HIP, E_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5, -6, -7
 LAYOUT_SPLIT, LAYOUT_MASKED = 0, 1
+ENCODE_BITS_ONLY = 0x100
 VARIANT_AUTO, VARIANT_VALU, VARIANT_MFMA, VARIANT_MFMA_FP4 = 0, 1, 2, 3
 _VARIANTS = {"auto": VARIANT_AUTO, "valu": VARIANT_VALU, "mfma": VARIANT_MFMA,
              "mfma_fp4": VARIANT_MFMA_FP4}
@@ -266,16 +267,20 @@ class Dataset:
         return self.c.n_samples
 
 
-def encode(geno, pheno, layout: str = "split", stream=None, into: Optional[Dataset] = None) -> Dataset:
+def encode(geno, pheno, layout: str = "split", stream=None, into: Optional[Dataset] = None,
+           values: bool = True) -> Dataset:
     """geno: torch uint8 [M][N] on the GPU (rows may be strided); pheno: host uint8 [N].
     With `into`, the encoding reuses that Dataset's device buffer and struct (same
-    addresses, so cached batched graphs stay valid)."""
+    addresses, so cached batched graphs stay valid).  values=False (SPLIT only)
+    skips the 0/1 value planes that only the matrix-core triplet kernels read."""
     torch = _torch()
     assert geno.dtype == torch.uint8 and geno.dim() == 2 and geno.is_cuda
     assert geno.stride(1) == 1
     ph = np.ascontiguousarray(np.asarray(pheno, dtype=np.uint8))
     M, N = int(geno.shape[0]), int(geno.shape[1])
     lay = LAYOUT_SPLIT if layout == "split" else LAYOUT_MASKED
+    if not values:
+        lay |= ENCODE_BITS_ONLY
     n1 = int(ph.sum()) if ph.size else 0
     nbytes = _lib.epi3_encode_bytes(M, n1, N - n1, lay)
     _check(int(nbytes) if nbytes < 0 else OK, "epi3_encode_bytes")

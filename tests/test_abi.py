@@ -65,6 +65,9 @@ def test_encode_bytes(epi3):
     assert lib.epi3_encode_bytes(10, 0, 0, 0) == epi3.E_INVALID
     assert lib.epi3_encode_bytes(10, 5, 5, 7) == epi3.E_INVALID
     assert lib.epi3_encode_bytes(-1, 5, 5, 0) == epi3.E_INVALID
+    # bit planes only: SPLIT with the flag is accepted, MASKED with it is not
+    assert lib.epi3_encode_bytes(10, 5, 5, epi3.ENCODE_BITS_ONLY) == lib.epi3_encode_bytes(10, 5, 5, 0)
+    assert lib.epi3_encode_bytes(10, 5, 5, 1 | epi3.ENCODE_BITS_ONLY) == epi3.E_INVALID
     # the buffer grows with every dimension
     a = lib.epi3_encode_bytes(100, 500, 500, 0)
     assert lib.epi3_encode_bytes(200, 500, 500, 0) > a

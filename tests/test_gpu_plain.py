@@ -104,6 +104,32 @@ def test_many_exact_ties_rank_over_several_chunks(env, variant):
     assert_hits_equal_oracle(h, ijk, k2, cc)
 
 
+def test_bits_only_encoding(env):
+    """A data set encoded without value planes scans with the popcount kernel
+    (AUTO falls back to it) to the oracle's hits, and the matrix-core kernels
+    refuse it; pair and quad scans on it equal those on a full encoding."""
+    torch, epi3 = env
+    print("[case] bits-only encoding, 24 SNPs x 900 samples", flush=True)
+    d = make_dataset(24, 900, 0.4, 0.05, seed=91)
+    g = to_dev(d.geno)
+    ds = epi3.encode(g, d.pheno, values=False)
+    assert not ds.c.bytes and not ds.c.nibbles
+    ijk, k2, cc = oracle.scan_topk(d.geno, d.pheno, 15)
+    for variant in ("auto", "valu"):
+        assert_hits_equal_oracle(epi3.scan_topk(ds, 15, variant), ijk, k2, cc)
+    for variant in ("mfma", "mfma_fp4"):
+        with pytest.raises(epi3.Epi3Error) as e:
+            epi3.scan_topk(ds, 15, variant)
+        assert e.value.code == epi3.E_UNSUPPORTED
+    full = epi3.encode(g, d.pheno)
+    assert epi3.scan_pairs(ds, 20).tobytes() == epi3.scan_pairs(full, 20).tobytes()
+    assert epi3.scan_quads(ds, 20).tobytes() == epi3.scan_quads(full, 20).tobytes()
+    # re-encoding into the same buffer keeps the flag's effect
+    again = epi3.encode(g, d.pheno, into=ds, values=False)
+    assert not again.c.bytes
+    assert_hits_equal_oracle(epi3.scan_topk(again, 15, "valu"), ijk, k2, cc)
+
+
 def test_bad_genotype_and_phenotype(env):
     torch, epi3 = env
     geno, pheno = _tiny(9, 5, 40, 0.5)
