@@ -110,7 +110,7 @@ def cpu_host_scan(d, k: int, budget_s: float = 5.0) -> dict:
     from paper_2201_10956_amd import host
     cores = cpu_cores()
     N = d.n_samples
-    m0 = min(d.n_snps, 96)
+    m0 = min(d.n_snps, 192)
     t0 = time.perf_counter()
     host.scan_topk(d.geno[:m0], d.pheno, k, threads=cores)
     rate = comb(m0, 3) * N / max(time.perf_counter() - t0, 1e-6)
