@@ -105,9 +105,13 @@ def cpu_baseline(d, k: int, budget_s: float = 20.0) -> dict:
 def cpu_host_scan(d, k: int, budget_s: float = 5.0) -> dict:
     """The host-CPU scan (vector popcount, OpenMP; a separate library the GPU
     path never calls) timed on a bounded sample of the workload, like the
-    oracle baseline: the first M' SNPs, M' sized to about `budget_s` seconds."""
+    oracle baseline: the first M' SNPs, M' sized to about `budget_s` seconds.
+    An auxiliary figure: if its library is not built, the line says so."""
     from math import comb
-    from paper_2201_10956_amd import host
+    try:
+        from paper_2201_10956_amd import host
+    except (ImportError, OSError) as e:
+        return {"value": None, "error": f"host scan library unavailable: {e}"}
     cores = cpu_cores()
     N = d.n_samples
     m0 = min(d.n_snps, 192)
