@@ -572,7 +572,7 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "this benchmark measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
     wl = WORKLOADS[args.workload]
     run = {"plain": run_plain, "perm": run_perm, "uneven": run_uneven, "pairs": run_pairs,
