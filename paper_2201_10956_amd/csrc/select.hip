@@ -213,13 +213,10 @@ __global__ void __launch_bounds__(256) compact_kernel(const SelJob *__restrict__
   const int64_t T = J.T, ccap = J.ccap;
   const int lane = threadIdx.x & 63;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); base < T;
-       base += stride) {
-    const int64_t x = base + lane;
-    const float v = x < T ? score[x] : 0.f;
-    const bool pred = x < T && v <= ub;
+  // appends the wave's scores with pred set (wave-uniform call)
+  auto emit = [&](bool pred, float v, int64_t x) {
     const unsigned long long m = __ballot(pred);
-    if (m == 0ull) continue;
+    if (m == 0ull) return;
     unsigned long long pos0 = 0;
     if (lane == 0) pos0 = atomicAdd(&st->cn, (unsigned long long)__popcll(m));
     pos0 = __shfl(pos0, 0);
@@ -228,6 +225,32 @@ __global__ void __launch_bounds__(256) compact_kernel(const SelJob *__restrict__
       J.ckey[pos] = f2key(v);
       J.crank[pos] = x;
     }
+  };
+  int64_t done = 0;
+  if ((reinterpret_cast<uintptr_t>(score) & 15u) == 0) {
+    // 16-byte loads: four scores per lane and step; nearly every step holds
+    // no candidate, so one ballot decides
+    const int64_t T4 = T >> 2;
+    const float4 *s4 = reinterpret_cast<const float4 *>(score);
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); base < T4;
+         base += stride) {
+      const int64_t x4 = base + lane;
+      const bool in = x4 < T4;
+      const float4 v = in ? s4[x4] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const bool any = in && (v.x <= ub || v.y <= ub || v.z <= ub || v.w <= ub);
+      if (__ballot(any) == 0ull) continue;
+      emit(in && v.x <= ub, v.x, 4 * x4);
+      emit(in && v.y <= ub, v.y, 4 * x4 + 1);
+      emit(in && v.z <= ub, v.z, 4 * x4 + 2);
+      emit(in && v.w <= ub, v.w, 4 * x4 + 3);
+    }
+    done = T4 << 2;
+  }
+  for (int64_t base = done + blockIdx.x * (int64_t)blockDim.x + (threadIdx.x & ~63); base < T;
+       base += stride) {
+    const int64_t x = base + lane;
+    const float v = x < T ? score[x] : 0.f;
+    emit(x < T && v <= ub, v, x);
   }
 }
 
