@@ -31,7 +31,9 @@ VALU_OPS_PER_ST = 16.0 / 32.0                  # 8 AND + 8 v_bcnt per triplet pe
 
 MFMA_I8_PEAK_TOPS = 5000.0                     # dense int8 matrix-core ops/s (MI355X)
 MFMA_FP4_PEAK_TFLOPS = 10100.0                 # dense FP4 matrix-core flop/s (MI355X)
-MFMA_OPS_PER_STQ = 16.0                        # 8 corner cells x (multiply + add) per sample-triplet-phenotype
+MFMA_OPS_PER_ST = 16.0                         # plain: 8 corner cells x (multiply + add) per sample-triplet
+MFMA_OPS_PER_STQ = 16.0 * 65.0 / 64.0          # batch: the same per phenotype plus the all-sample
+                                               # (totals) column shared by 64 phenotypes
 PAIR_OPS_PER_SP = 8.0 / 32.0                   # 4 AND + 4 v_bcnt per pair per 32 samples (pairwise tables)
 QUAD_OPS_PER_SQ = 32.0 / 32.0                  # 16 AND + 16 v_bcnt per quad per 32 samples (quad corners)
 
@@ -173,7 +175,7 @@ def run_plain(args, wl):
             "ops_per_launch": work * VALU_OPS_PER_ST / max(cnt_n, 1)}
     else:
         peak = MFMA_FP4_PEAK_TFLOPS if variant == "mfma_fp4" else MFMA_I8_PEAK_TOPS
-        achieved = MFMA_OPS_PER_STQ * work / (cnt_ms / 1e3) / 1e12
+        achieved = MFMA_OPS_PER_ST * work / (cnt_ms / 1e3) / 1e12
         out["roofline"] = {
             "bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
             "unit": "TFLOP/s (fp4)" if variant == "mfma_fp4" else "TOP/s (int8)",
@@ -182,11 +184,15 @@ def run_plain(args, wl):
             "traffic_unit": "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
             "kernel": "count_mfma_plain_kernel", "kernel_ms": round(cnt_ms / max(cnt_n, 1), 4),
             "launches_per_step": cnt_n,
-            "ops_per_launch": MFMA_OPS_PER_STQ * work / max(cnt_n, 1)}
+            "ops_per_launch": MFMA_OPS_PER_ST * work / max(cnt_n, 1)}
     out["breakdown_ms"] = {"count_kernels": round(cnt_ms, 4), "finish_kernels": round(fin_ms, 4),
                            "selection": round(sel_ms, 4)}
     out["best"] = {"ijk": [int(hits["i"][0]), int(hits["j"][0]), int(hits["k"][0])],
                    "k2": float(hits["k2"][0])}
+    sc.run()
+    out["k2_fp32_error"] = plane_k2_error(epi3, ds, sc.score_plane())
+    out["k2_fp32_error_hits"] = k2_error(hits["k2_f32"], hits["k2"], epi3.k2_error_bound(N),
+                                         f"the {len(hits)} hits")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d, k, args.cpu_budget)
         out["cpu_fast"] = cpu_host_scan(d, k)
@@ -334,6 +340,61 @@ def run_quads(args, wl):
     return out
 
 
+def k2_error(k2_32, k2_64, bound: float, where: str) -> dict:
+    """Largest |K2_fp32 - K2_fp64| (absolute and relative) over matched
+    scores, next to the error bound e(N) the selection screens with."""
+    a = np.asarray(k2_32, dtype=np.float64)
+    b = np.asarray(k2_64, dtype=np.float64)
+    d = np.abs(a - b)
+    return {"max_abs": float(d.max()), "max_rel": float((d / np.abs(b)).max()),
+            "bound": bound, "n": int(d.size), "over": where}
+
+
+def plane_k2_error(epi3, ds, plane, n: int = 10000, seed: int = 5) -> dict:
+    """The error report on n sampled ranks of a score plane: FP32 from the
+    plane, FP64 from the library's re-score of the same triplets."""
+    import torch
+    from math import comb
+    from synth import SplitMix64
+    M = ds.M
+    T = comb(M, 3)
+    ranks = np.unique((SplitMix64(seed, 0).uniform(0, n) * T).astype(np.int64))
+    ijk = _unrank3(M, ranks)
+    _, _, k64 = epi3.score_triplets(ds, ijk)
+    got = plane[torch.as_tensor(ranks, device=plane.device)].cpu().numpy()
+    return k2_error(got, k64.cpu().numpy(), epi3.k2_error_bound(ds.N),
+                    f"{ranks.size} sampled triplets of the score plane")
+
+
+def _unrank3(M: int, ranks) -> np.ndarray:
+    """(i, j, k) of lexicographic ranks among the triplets of M SNPs: the
+    first index is the last whose block of triplets starts at or before the
+    rank (binary search), then likewise for the second."""
+    from math import comb
+    C = comb(M, 3)
+    out = np.empty((len(ranks), 3), dtype=np.uint32)
+    for x, r in enumerate(ranks):
+        r = int(r)
+        lo, hi = 0, M - 3
+        while lo < hi:
+            mid = (lo + hi + 1) // 2
+            if C - comb(M - mid, 3) <= r:
+                lo = mid
+            else:
+                hi = mid - 1
+        i, r1 = lo, r - (C - comb(M - lo, 3))
+        lo, hi = i + 1, M - 2
+        while lo < hi:
+            mid = (lo + hi + 1) // 2
+            if comb(M - 1 - i, 2) - comb(M - mid, 2) <= r1:
+                lo = mid
+            else:
+                hi = mid - 1
+        j = lo
+        out[x] = (i, j, r1 - (comb(M - 1 - i, 2) - comb(M - j, 2)) + j + 1)
+    return out
+
+
 def hits_equal(a, b) -> bool:
     """Same triplets, FP64 K2 and counts (the FP32 screen value may differ in
     its last bits between count kernels that sum a table in another order)."""
@@ -456,6 +517,20 @@ def run_perm(args, wl):
     out["breakdown_ms"] = {"count_kernels": round(k_ms, 3), "finish_kernels": round(fin_ms, 3),
                            "selection": round(sel_ms, 3)}
     out["min_k2_per_phenotype"] = [round(float(h["k2"][0]), 6) for h in res[:4]] + ["..."]
+    out["k2_fp32_error"] = k2_error(np.concatenate([h["k2_f32"] for h in res]),
+                                    np.concatenate([h["k2"] for h in res]),
+                                    epi3.k2_error_bound(N), f"the {sum(len(h) for h in res)} hits "
+                                    f"of all {Q} phenotypes")
+    # permutation significance of the observed phenotype's best triplet: its
+    # lowest K2 from a plain scan of the unpermuted phenotype (untimed), the
+    # permutations' lowest from hit 0 of each job of the timed batch
+    obs = epi3.scan_topk(epi3.encode(geno, d.pheno), 1, best_variant)
+    obs_k2 = float(obs["k2"][0])
+    out["significance"] = {
+        "observed_best": {"ijk": [int(obs["i"][0]), int(obs["j"][0]), int(obs["k"][0])],
+                          "k2": obs_k2, "planted": [int(x) for x in d.planted]},
+        "p_value": epi3.perm_pvalue(obs_k2, [float(h["k2"][0]) for h in res]),
+        "permutations": Q, "how": "(1 + #{q: min K2_q <= observed}) / (Q + 1)"}
     if not args.no_cpu_baseline:
         d0 = type(d)(d.geno, perms[0], d.planted, d.maf, d.seed)
         out["cpu_baseline"] = cpu_baseline(d0, k, args.cpu_budget)
@@ -500,12 +575,12 @@ def run_uneven(args, wl):
         m_ms, m_n, _, m_fin = _kernel_times(sub.run)
         fp4 = all(kinds[x] == "mfma_fp4" for x in on_mfma)
         peak = MFMA_FP4_PEAK_TFLOPS if fp4 else MFMA_I8_PEAK_TOPS
-        achieved = MFMA_OPS_PER_STQ * w_mfma / (m_ms / 1e3) / 1e12
+        achieved = MFMA_OPS_PER_ST * w_mfma / (m_ms / 1e3) / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                 "unit": "TFLOP/s (fp4)" if fp4 else "TOP/s (int8)", "frac": round(achieved / peak, 4),
                 "traffic": None, "kernel": "count_mfma_plain_kernel",
                 "kernel_ms": round(m_ms / max(m_n, 1), 4), "launches": m_n,
-                "datasets_timed": len(on_mfma), "ops": MFMA_OPS_PER_STQ * w_mfma}
+                "datasets_timed": len(on_mfma), "ops": MFMA_OPS_PER_ST * w_mfma}
     else:
         sub = epi3.BatchScanner([enc[x] for x in on_valu], k, variant=variant) if on_mfma else bs
         v_ms, v_n, _, _ = _kernel_times(sub.run)

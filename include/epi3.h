@@ -29,7 +29,12 @@
  *   - Return value: EPI3_OK or a negative EPI3_E_* code; no exception crosses
  *     the ABI.  Data errors detected on the device (a genotype byte outside
  *     {0,1,2}) are reported by the next call that returns host results.
- *   - Calls on distinct streams with distinct workspaces may run concurrently.
+ *   - Calls on distinct streams with distinct workspaces may run concurrently
+ *     (the matrix-core paths order their finish kernels with a second stream
+ *     and events of their own, taken from a library pool for the duration of
+ *     the call).  The tile rules, pass bytes and other process-wide settings
+ *     must not change while a scan is in progress; the kernel-timing hooks
+ *     sum the launches of all threads.
  *
  * K2 is screened in FP32 from a table of log factorials and the returned
  * order is decided by an FP64 re-score of every candidate that the FP32
@@ -206,6 +211,17 @@ int epi3_scan_batched(const epi3_job *jobs, int32_t n_jobs, int32_t variant, int
                       void *ws_dev, int64_t ws_bytes, epi3_hit *hits_host,
                       int32_t *n_out_host, void *stream);
 
+/* Device address of job `job`'s FP32 score plane inside a batched workspace:
+ * K2_fp32 of every triplet of that job's data set (and, for MASKED jobs, its
+ * case mask) in lexicographic (i, j, k) order, C(M,3) floats; the arguments
+ * are those of the epi3_scan_batched call that filled it, and the plane is
+ * valid once the stream has run that call (until the workspace is reused).
+ * A test hook: the FP32 screen values of the batched count kernels.
+ * EPI3_E_UNSUPPORTED when the batch keeps no plane (see
+ * epi3_set_batch_select). */
+int epi3_batched_score_plane(const epi3_job *jobs, int32_t n_jobs, int32_t variant,
+                             int64_t cand_cap, void *ws_dev, int32_t job, float **plane_dev);
+
 /* Family-wise permutation p-value of an observed best score (not in the
  * paper): p = (1 + #{q : perm_min_k2[q] <= observed_k2}) / (n_perm + 1), where
  * perm_min_k2[q] is the lowest K2 of phenotype permutation q (hit 0 of job q of
@@ -335,7 +351,14 @@ double epi3_k2_error_bound(int32_t n_samples);
 /* Number of triplets C(M,3). */
 int64_t epi3_n_triplets(int32_t n_snps);
 
-/* Release cached graphs. */
+/* Optional set-up on the current device: creates the library's second
+ * stream and events of the matrix-core paths and the stream batched scans
+ * are captured on, which the first call that needs them would otherwise
+ * create.  Returns EPI3_E_HIP if the runtime refuses. */
+int epi3_init(void);
+
+/* Release cached graphs and the library's idle streams and events.  Must not
+ * run while another call of the library is in progress. */
 void epi3_release(void);
 
 /* Kernel timing for measurement: while enabled, the library records a HIP

@@ -158,6 +158,7 @@ struct Tiles {
   std::vector<TileRule> rules;
   int64_t pass_bytes = 0;
   int64_t compact_cap = 0;
+  uint64_t gen = 0;  // bumped by every setter: part of the cached graphs' key
 };
 Tiles &tiles() {
   static Tiles t;
@@ -175,6 +176,11 @@ int rule_tile(int32_t variant, int32_t M, int32_t N, int dflt) {
       best = &r;
   }
   return best ? best->tile : dflt;
+}
+uint64_t settings_gen() {
+  Tiles &t = tiles();
+  std::lock_guard<std::mutex> g(t.mu);
+  return t.gen;
 }
 int64_t pass_bytes(int64_t dflt) {
   Tiles &t = tiles();
@@ -357,29 +363,68 @@ int pick_P(const epi3_dataset &d) {
   return rule_tile(EPI3_VARIANT_VALU, d.n_snps, d.n_samples, tile_P_default(d.n_snps, d.n_samples));
 }
 
-// Second stream and events for the count / finish overlap (created once).
-struct Aux {
-  std::mutex mu;
+// Second stream and events of the count / finish overlap of one matrix-core
+// scan.  A call holds a context of its own (AuxLease) for as long as it
+// enqueues work and hands it back before it returns, so two calls running at
+// the same time never record or wait on the same events, and a graph capture
+// forks only its own context's stream.  A context handed back may still have
+// the previous call's finish kernels queued on its stream: the next holder's
+// work queues behind them (an ordering, never a mix of data: every wait is
+// issued while its event's latest record is the holder's own).
+struct AuxCtx {
   hipStream_t s2 = nullptr;
-  std::vector<hipEvent_t> ev;
+  hipEvent_t ev[5] = {};
 };
-Aux &aux() {
-  static Aux a;
-  return a;
+struct AuxPool {
+  std::mutex mu;
+  std::vector<AuxCtx *> idle;
+};
+AuxPool &aux_pool() {
+  static AuxPool p;
+  return p;
 }
-int aux_get(hipStream_t *s2, hipEvent_t *ev, int n_ev) {
-  Aux &a = aux();
-  std::lock_guard<std::mutex> g(a.mu);
-  if (!a.s2 && hipStreamCreateWithFlags(&a.s2, hipStreamNonBlocking) != hipSuccess) return EPI3_E_HIP;
-  while ((int)a.ev.size() < n_ev) {
-    hipEvent_t e = nullptr;
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return EPI3_E_HIP;
-    a.ev.push_back(e);
+void aux_destroy(AuxCtx *c) {
+  for (hipEvent_t e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->s2) (void)hipStreamDestroy(c->s2);
+  delete c;
+}
+AuxCtx *aux_make(int *rc) {
+  AuxCtx *c = new AuxCtx;
+  *rc = EPI3_OK;
+  if (hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking) != hipSuccess) *rc = EPI3_E_HIP;
+  for (int x = 0; x < 5 && *rc == EPI3_OK; ++x)
+    if (hipEventCreateWithFlags(&c->ev[x], hipEventDisableTiming) != hipSuccess) *rc = EPI3_E_HIP;
+  if (*rc != EPI3_OK) {
+    aux_destroy(c);
+    return nullptr;
   }
-  *s2 = a.s2;
-  for (int x = 0; x < n_ev; ++x) ev[x] = a.ev[x];
-  return EPI3_OK;
+  return c;
 }
+struct AuxLease {
+  AuxCtx *c = nullptr;
+  int rc = EPI3_OK;
+  AuxLease() {
+    AuxPool &p = aux_pool();
+    {
+      std::lock_guard<std::mutex> g(p.mu);
+      if (!p.idle.empty()) {
+        c = p.idle.back();
+        p.idle.pop_back();
+        return;
+      }
+    }
+    c = aux_make(&rc);
+  }
+  ~AuxLease() {
+    if (!c) return;
+    AuxPool &p = aux_pool();
+    std::lock_guard<std::mutex> g(p.mu);
+    p.idle.push_back(c);
+  }
+  AuxLease(const AuxLease &) = delete;
+  AuxLease &operator=(const AuxLease &) = delete;
+};
 
 // ---- optional kernel timing: HIP events on the call's stream ----
 struct Timing {
@@ -440,7 +485,7 @@ struct MfmaBufs {
 };
 
 int enqueue_count_mfma(const epi3_dataset &d, bool fp4, float *score, uint32_t *counts,
-                       const MfmaBufs &W, hipStream_t s) {
+                       const MfmaBufs &W, hipStream_t s, AuxCtx *ctx) {
   const int JB = pick_JB(d, fp4 ? EPI3_VARIANT_MFMA_FP4 : EPI3_VARIANT_MFMA);
   const int64_t tiles = host_plain_tiles(d.n_snps, JB);
   const int32_t unit = fp4 ? 128 : 64;  // samples per 64-byte staged chunk
@@ -471,11 +516,10 @@ int enqueue_count_mfma(const epi3_dataset &d, bool fp4, float *score, uint32_t *
   // Pass p counts into scratch buffer p % 2 on `s`; its finish kernel runs on
   // the second stream while `s` counts pass p + 1.  Count p + 2 waits for
   // finish p (same buffer).
-  hipStream_t s2 = nullptr;
-  hipEvent_t ev[5];
-  int rc = aux_get(&s2, ev, 5);
-  if (rc != EPI3_OK) return rc;
-  hipEvent_t ev_start = ev[0], ev_cnt[2] = {ev[1], ev[2]}, ev_fin[2] = {ev[3], ev[4]};
+  hipStream_t s2 = ctx->s2;
+  int rc = EPI3_OK;
+  hipEvent_t ev_start = ctx->ev[0], ev_cnt[2] = {ctx->ev[1], ctx->ev[2]},
+             ev_fin[2] = {ctx->ev[3], ctx->ev[4]};
   HIP_OK(hipEventRecord(ev_start, s));
   HIP_OK(hipStreamWaitEvent(s2, ev_start, 0));
   int p = 0;
@@ -721,7 +765,9 @@ static int enqueue_count(const epi3_dataset &d, int32_t variant, float *score, u
   if (v == EPI3_VARIANT_MFMA || v == EPI3_VARIANT_MFMA_FP4) {
     if (!W.scratch) return EPI3_E_WORKSPACE;
     const MfmaBufs B{W.scratch, W.pass_tiles, W.pjob, W.jprefix, W.queue, &W.st->kmin};
-    return enqueue_count_mfma(d, v == EPI3_VARIANT_MFMA_FP4, score, counts, B, s);
+    AuxLease lease;
+    if (lease.rc != EPI3_OK) return lease.rc;
+    return enqueue_count_mfma(d, v == EPI3_VARIANT_MFMA_FP4, score, counts, B, s, lease.c);
   }
   const int P = pick_P(d);
   Job J = make_job(d, score, counts, W.jprefix, &W.st->kmin, P);
@@ -1009,6 +1055,8 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
 int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32_t variant,
                     hipStream_t s) {
   const bool fp4 = variant != EPI3_VARIANT_MFMA;  // MASKED: AUTO and MFMA_FP4 use FP4
+  AuxLease lease;  // second stream and events of the matrix-core passes
+  if (lease.rc != EPI3_OK) return lease.rc;
   // selection state first: the count kernels write each job's key range into it
   std::vector<SelJob> sj(n);
   bool any_sample = false;
@@ -1047,7 +1095,7 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
       const MfmaBufs B{W.plain_scratch, W.plain_pass_tiles, W.pjobs_plain + 2 * (int64_t)x,
                        W.jprefix[x], W.queue, &W.st[x].kmin};
       const int rc = enqueue_count_mfma(*jobs[x].d, v == EPI3_VARIANT_MFMA_FP4, W.score[x], nullptr,
-                                        B, s);
+                                        B, s, lease.c);
       if (rc != EPI3_OK) return rc;
     }
     // vector-ALU jobs: one persistent launch over all their tiles; jobs with
@@ -1132,11 +1180,10 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
       // Pass p counts into scratch buffer p % 2 on `s`; its finish kernel runs on
       // the second stream while `s` counts pass p + 1.  Count p + 2 waits for
       // finish p (same buffer).  Events order the two streams (also when captured).
-      hipStream_t s2 = nullptr;
-      hipEvent_t ev[5];
-      int rc = aux_get(&s2, ev, 5);
-      if (rc != EPI3_OK) return rc;
-      hipEvent_t ev_start = ev[0], ev_cnt[2] = {ev[1], ev[2]}, ev_fin[2] = {ev[3], ev[4]};
+      hipStream_t s2 = lease.c->s2;
+      int rc = EPI3_OK;
+      hipEvent_t ev_start = lease.c->ev[0], ev_cnt[2] = {lease.c->ev[1], lease.c->ev[2]},
+                 ev_fin[2] = {lease.c->ev[3], lease.c->ev[4]};
       HIP_OK(hipEventRecord(ev_start, s));
       HIP_OK(hipStreamWaitEvent(s2, ev_start, 0));
       PermJob pjb[2] = {pj, pj};
@@ -1204,6 +1251,8 @@ std::vector<uint64_t> signature(const epi3_job *jobs, int32_t n, int32_t variant
   sig.push_back((uint64_t)cap);
   sig.push_back((uint64_t)(uintptr_t)ws);
   sig.push_back((uint64_t)ws_bytes);
+  // tile rules, pass bytes and the compacted-list size change the captured work
+  sig.push_back(settings_gen());
   for (int x = 0; x < n; ++x) {
     const epi3_dataset &d = *jobs[x].d;
     const uint64_t *raw = reinterpret_cast<const uint64_t *>(&d);
@@ -1223,6 +1272,17 @@ int64_t epi3_batched_workspace_bytes(const epi3_job *jobs, int32_t n_jobs, int32
   const int rc = check_jobs(jobs, n_jobs, variant);
   if (rc != EPI3_OK) return rc;
   return batch_layout(nullptr, jobs, n_jobs, cand_cap, variant).total;
+}
+
+int epi3_batched_score_plane(const epi3_job *jobs, int32_t n_jobs, int32_t variant,
+                             int64_t cand_cap, void *ws_dev, int32_t job, float **plane_dev) {
+  const int rc = check_jobs(jobs, n_jobs, variant);
+  if (rc != EPI3_OK) return rc;
+  if (!ws_dev || !plane_dev || job < 0 || job >= n_jobs) return EPI3_E_INVALID;
+  const BatchLayout W = batch_layout(ws_dev, jobs, n_jobs, cand_cap, variant);
+  if (!W.score[job]) return EPI3_E_UNSUPPORTED;
+  *plane_dev = W.score[job];
+  return EPI3_OK;
 }
 
 int epi3_scan_batched(const epi3_job *jobs, int32_t n_jobs, int32_t variant, int64_t cand_cap,
@@ -1287,14 +1347,23 @@ int epi3_scan_batched(const epi3_job *jobs, int32_t n_jobs, int32_t variant, int
   return worst;
 }
 
+int epi3_init(void) {
+  {
+    AuxLease lease;  // one idle context in the pool from now on
+    if (lease.rc != EPI3_OK) return lease.rc;
+  }
+  GraphCache &G = graphs();
+  std::lock_guard<std::mutex> lk(G.mu);
+  if (!G.capture) HIP_OK(hipStreamCreateWithFlags(&G.capture, hipStreamNonBlocking));
+  return EPI3_OK;
+}
+
 void epi3_release(void) {
   {
-    Aux &a = aux();
-    std::lock_guard<std::mutex> lk(a.mu);
-    for (auto e : a.ev) (void)hipEventDestroy(e);
-    a.ev.clear();
-    if (a.s2) (void)hipStreamDestroy(a.s2);
-    a.s2 = nullptr;
+    AuxPool &p = aux_pool();
+    std::lock_guard<std::mutex> lk(p.mu);
+    for (AuxCtx *c : p.idle) aux_destroy(c);
+    p.idle.clear();
   }
   GraphCache &G = graphs();
   std::lock_guard<std::mutex> lk(G.mu);
@@ -1331,10 +1400,12 @@ int epi3_tile_rule(int32_t variant, int32_t min_snps, int32_t min_samples, int32
   for (TileRule &r : t.rules) {
     if (r.variant == variant && r.min_snps == min_snps && r.min_samples == min_samples) {
       r.tile = tile;
+      ++t.gen;
       return EPI3_OK;
     }
   }
   t.rules.push_back({variant, min_snps, min_samples, tile});
+  ++t.gen;
   return EPI3_OK;
 }
 
@@ -1342,6 +1413,7 @@ void epi3_tile_rules_clear(void) {
   Tiles &t = tiles();
   std::lock_guard<std::mutex> g(t.mu);
   t.rules.clear();
+  ++t.gen;
 }
 
 int32_t epi3_tile_for(const epi3_dataset *d, int32_t variant) {
@@ -1357,6 +1429,7 @@ int epi3_set_compact_cap(int64_t n) {
   Tiles &t = tiles();
   std::lock_guard<std::mutex> g(t.mu);
   t.compact_cap = n;
+  ++t.gen;
   return EPI3_OK;
 }
 
@@ -1365,6 +1438,7 @@ int epi3_set_pass_bytes(int64_t bytes) {
   Tiles &t = tiles();
   std::lock_guard<std::mutex> g(t.mu);
   t.pass_bytes = bytes;
+  ++t.gen;
   return EPI3_OK;
 }
 
@@ -1395,7 +1469,7 @@ void epi3_timing_reset(void) {
   std::lock_guard<std::mutex> g(t.mu);
   for (auto &r : t.rec) {
     for (auto &p : r) {
-      hipEventSynchronize(p.second);
+      (void)hipEventSynchronize(p.second);
       t.pool.push_back(p.first);
       t.pool.push_back(p.second);
     }

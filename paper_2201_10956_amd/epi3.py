@@ -98,6 +98,8 @@ def _load():
         "epi3_topk": (ctypes.c_int, [P(CDataset), i32, i64, vp, vp, P(i32), vp]),
         "epi3_batched_workspace_bytes": (i64, [P(CJob), i32, i32, i64]),
         "epi3_scan_batched": (ctypes.c_int, [P(CJob), i32, i32, i64, vp, i64, vp, vp, vp]),
+        "epi3_batched_score_plane": (ctypes.c_int, [P(CJob), i32, i32, i64, vp, i32, P(vp)]),
+        "epi3_init": (ctypes.c_int, []),
         "epi3_scan_tables": (ctypes.c_int, [P(CDataset), i32, vp, vp, vp, i64, vp]),
         "epi3_score_triplets": (ctypes.c_int, [P(CDataset), vp, i64, vp, vp, vp, vp]),
         "epi3_score_plane": (ctypes.c_int, [P(CDataset), i32, i64, vp, P(vp)]),
@@ -136,7 +138,8 @@ def _load():
 
 _lib = _load()
 EXPORTS = ("epi3_encode_bytes", "epi3_encode", "epi3_workspace_bytes", "epi3_scan", "epi3_topk",
-           "epi3_batched_workspace_bytes", "epi3_scan_batched", "epi3_scan_tables",
+           "epi3_batched_workspace_bytes", "epi3_scan_batched", "epi3_batched_score_plane",
+           "epi3_init", "epi3_scan_tables",
            "epi3_score_triplets", "epi3_score_plane", "epi3_k2_error_bound", "epi3_n_triplets", "epi3_release",
            "epi3_version", "epi3_timing_enable", "epi3_timing_query", "epi3_timing_reset",
            "epi3_tile_rule", "epi3_tile_rules_clear", "epi3_tile_for", "epi3_set_pass_bytes",
@@ -572,6 +575,24 @@ class BatchScanner:
             out.append(allh[off: off + int(self.n_out[x])].copy())
             off += kk
         return out
+
+    def score_plane(self, job: int):
+        """FP32 K2 of every triplet of job `job` (lexicographic order): a torch
+        view into the workspace, valid after run()."""
+        torch = _torch()
+        ptr = ctypes.c_void_p(0)
+        rc = _lib.epi3_batched_score_plane(self.jobs, len(self.jobs), self.variant, self.cand_cap,
+                                           ctypes.c_void_p(self.ws.data_ptr()), int(job),
+                                           ctypes.byref(ptr))
+        _check(rc, "epi3_batched_score_plane")
+        off = (ptr.value or 0) - self.ws.data_ptr()
+        T = n_triplets(self.jobs[job].d.contents.n_snps)
+        return self.ws[off: off + 4 * T].view(torch.float32)
+
+
+def init() -> None:
+    """Create the library's streams and events now rather than in the first scan."""
+    _check(_lib.epi3_init(), "epi3_init")
 
 
 def release() -> None:

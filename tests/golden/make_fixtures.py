@@ -8,6 +8,8 @@ still reproduces them.
     python tests/golden/make_fixtures.py 3          # plain 2048 x 16384, top-1000
     python tests/golden/make_fixtures.py 4 --perm 0:64
     python tests/golden/make_fixtures.py 5
+    python tests/golden/make_fixtures.py 4 --observed   # the unpermuted phenotype, top-10
+    python tests/golden/make_fixtures.py 2 --quads 256  # quads of the first 256 SNPs, top-100
 """
 from __future__ import annotations
 
@@ -61,6 +63,32 @@ def perm(cfg: int, threads: int, lo: int, hi: int) -> None:
         print(f"cfg{cfg} perm {p}: {dt:.1f}s", flush=True)
 
 
+def observed(cfg: int, threads: int) -> None:
+    """The permutation workload's own (unpermuted) phenotype."""
+    c = CONFIGS[cfg]
+    d, _ = make_config(cfg)
+    t0 = time.time()
+    ijk, k2, cc = oracle.scan_topk(d.geno, d.pheno, c["k"], nthreads=threads)
+    dt = time.time() - t0
+    p = _save(f"oracle_cfg{cfg}_observed_top{c['k']}.npz", ijk=ijk, k2=k2, counts=cc,
+              sha256=np.array(manifest_sha256([d.geno, d.pheno])),
+              seconds=np.array(dt), threads=np.array(threads))
+    print(f"cfg{cfg} observed: {dt:.1f}s -> {p}", flush=True)
+
+
+def quads(cfg: int, snps: int, threads: int, k: int = 100) -> None:
+    """Fourth-order scan of the first `snps` SNPs of a plain workload."""
+    d = make_config(cfg)
+    g = np.ascontiguousarray(d.geno[:snps])
+    t0 = time.time()
+    q, k2, cc = oracle.scan_quads_topk(g, d.pheno, k, nthreads=threads)
+    dt = time.time() - t0
+    p = _save(f"oracle_cfg{cfg}_quads{snps}_top{k}.npz", ijkl=q, k2=k2, counts=cc,
+              sha256=np.array(manifest_sha256([g, d.pheno])),
+              seconds=np.array(dt), threads=np.array(threads))
+    print(f"cfg{cfg} quads of {snps} SNPs: {dt:.1f}s -> {p}", flush=True)
+
+
 def uneven(cfg: int, threads: int) -> None:
     c = CONFIGS[cfg]
     ds = make_config(cfg)
@@ -84,9 +112,15 @@ if __name__ == "__main__":
     ap.add_argument("cfg", type=int)
     ap.add_argument("--threads", type=int, default=oracle.nthreads_default())
     ap.add_argument("--perm", default="0:64")
+    ap.add_argument("--observed", action="store_true")
+    ap.add_argument("--quads", type=int, default=0)
     a = ap.parse_args()
     kind = CONFIGS[a.cfg]["kind"]
-    if kind == "plain":
+    if a.quads:
+        quads(a.cfg, a.quads, a.threads)
+    elif a.observed:
+        observed(a.cfg, a.threads)
+    elif kind == "plain":
         plain(a.cfg, a.threads)
     elif kind == "perm":
         lo, hi = (int(x) for x in a.perm.split(":"))
