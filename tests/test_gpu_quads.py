@@ -23,6 +23,21 @@ def _tiny(seed, M, N, p_case):
     return geno, pheno
 
 
+def _quad_unrank(M, r):
+    """The quad of lexicographic rank r among all i < j < k < l < M: walk the
+    first index up while whole blocks of quads fit below r, then the next."""
+    from math import comb
+    out, lo = [], 0
+    for left in (4, 3, 2, 1):
+        x = lo
+        while comb(M - 1 - x, left - 1) <= r:
+            r -= comb(M - 1 - x, left - 1)
+            x += 1
+        out.append(x)
+        lo = x + 1
+    return tuple(out)
+
+
 def assert_quad_hits_equal_oracle(h, q, k2, counts):
     assert len(h) == len(q), (len(h), len(q))
     got = np.stack([h["i"], h["j"], h["k"], h["l"]], axis=1).astype(np.int32)
@@ -117,3 +132,29 @@ def test_quads_candidate_capacity_retry(env):
     h = epi3.QuadScanner(ds, 20, cand_cap=need).run()
     q, rk2, rcc = oracle.scan_quads_topk(d.geno, d.pheno, 20)
     assert_quad_hits_equal_oracle(h, q, rk2, rcc)
+
+
+def test_quads_256_snps_bench_workload(env):
+    """The benchmark's fourth-order workload, the first 256 SNPs of the
+    512 x 4096 data set (174 M quads): top-100 equal to the stored oracle
+    result, 2000 sampled FP32 scores within the bound."""
+    import os
+    from synth import CONFIGS, make_config, manifest_sha256
+    torch, epi3 = env
+    print("[case] quads 256 x 4096", flush=True)
+    d = make_config(2)
+    g = np.ascontiguousarray(d.geno[:256])
+    ds = epi3.encode(to_dev(g), d.pheno, values=False)
+    sc = epi3.QuadScanner(ds, 100)
+    h = sc.run()
+    z = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                             "oracle_cfg2_quads256_top100.npz"))
+    assert str(z["sha256"]) == manifest_sha256([g, d.pheno])
+    assert_quad_hits_equal_oracle(h, z["ijkl"], z["k2"], z["counts"])
+    Q = epi3.n_quads(256)
+    ranks = np.unique((SplitMix64(79, 0).uniform(0, 2000) * Q).astype(np.int64))
+    lex = [_quad_unrank(256, int(r)) for r in ranks]
+    L = oracle.log_factorial(d.n_samples + 1)
+    ref = np.array([oracle.k2_rows(oracle.quad_table(g, d.pheno, *map(int, x)), L) for x in lex])
+    got = sc.score_plane()[torch.as_tensor(ranks, device="cuda")].cpu().numpy()
+    assert_quad_k2_close(got, ref, d.n_samples, epi3)
