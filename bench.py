@@ -630,6 +630,35 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 3) -> None:
                       "reps": reps}), flush=True)
 
 
+def peak_microbench(reps: int = 5) -> dict:
+    """Sustained rates of register-only chains on this GPU (paper_2201_10956_amd/peak):
+    FP4 32x32x64 and int8 32x32x32 matrix-core products, AND + v_bcnt on the
+    vector ALU; 2048 workgroups of 256 threads (8 waves per SIMD)."""
+    import ctypes
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2201_10956_amd", "peak", "libepi3_peak.so"))
+    lib.epi3_peak_run.restype = ctypes.c_int
+    lib.epi3_peak_run.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)]
+    blocks = torch.cuda.get_device_properties(0).multi_processor_count * 8
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    res = {}
+    for kind, name, iters, unit, pub in ((0, "mfma_fp4_32x32x64", 200, "TFLOP/s", MFMA_FP4_PEAK_TFLOPS),
+                                         (1, "mfma_i8_32x32x32", 200, "TOP/s", MFMA_I8_PEAK_TOPS),
+                                         (2, "valu_and_bcnt", 200000, "T int32-lane-ops/s",
+                                          VALU_PEAK_TOPS)):
+        ms, ops = ctypes.c_double(0), ctypes.c_double(0)
+        rc = lib.epi3_peak_run(kind, iters, blocks, reps, ctypes.c_void_p(out.data_ptr()),
+                               ctypes.byref(ms), ctypes.byref(ops))
+        if rc != 0:
+            raise RuntimeError(f"epi3_peak_run({name}) returned {rc}")
+        rate = ops.value / (ms.value / 1e3) / 1e12
+        res[name] = {"rate": round(rate, 2), "unit": unit, "ms_per_launch": round(ms.value, 4),
+                     "published_peak": round(pub, 2), "frac_of_published": round(rate / pub, 4)}
+    return {"peak_microbench": res, "blocks": blocks, "threads_per_block": 256}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -642,9 +671,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--peak", action="store_true",
+                    help="print the peak-rate microbenchmarks instead of a workload")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.peak:
+        print(json.dumps(peak_microbench()), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this benchmark measures one GPU only; run with --gpus 1"}))

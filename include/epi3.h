@@ -215,12 +215,27 @@ int epi3_scan_batched(const epi3_job *jobs, int32_t n_jobs, int32_t variant, int
  * K2_fp32 of every triplet of that job's data set (and, for MASKED jobs, its
  * case mask) in lexicographic (i, j, k) order, C(M,3) floats; the arguments
  * are those of the epi3_scan_batched call that filled it, and the plane is
- * valid once the stream has run that call (until the workspace is reused).
- * A test hook: the FP32 screen values of the batched count kernels.
+ * valid once the stream has run that call (until the workspace is reused);
+ * the process-wide settings (tile rules, pass bytes, compacted-list size,
+ * batch selection) must still be those of that call, since they lay the
+ * workspace out.  A test hook: the FP32 screen values of the batched count
+ * kernels.
  * EPI3_E_UNSUPPORTED when the batch keeps no plane (see
  * epi3_set_batch_select). */
 int epi3_batched_score_plane(const epi3_job *jobs, int32_t n_jobs, int32_t variant,
                              int64_t cand_cap, void *ws_dev, int32_t job, float **plane_dev);
+
+/* Test hook of a phenotype batch selected by bound (EPI3_BATCH_SELECT_BOUNDED):
+ * job `job`'s list as the last epi3_scan_batched call on this workspace left
+ * it.  *keys_dev / *ranks_dev: device arrays of *count entries in no
+ * particular order, each the key of an FP32 score (its bit pattern with the
+ * sign bit set; scores are non-negative) and the triplet's lexicographic
+ * rank; *bound: the list's bound (every score <= it is listed).  Arguments
+ * as for epi3_batched_score_plane; synchronises `stream`.
+ * EPI3_E_UNSUPPORTED when the batch keeps a score plane instead. */
+int epi3_batched_bound_list(const epi3_job *jobs, int32_t n_jobs, int32_t variant,
+                            int64_t cand_cap, void *ws_dev, int32_t job, uint32_t **keys_dev,
+                            int64_t **ranks_dev, int64_t *count, float *bound, void *stream);
 
 /* Family-wise permutation p-value of an observed best score (not in the
  * paper): p = (1 + #{q : perm_min_k2[q] <= observed_k2}) / (n_perm + 1), where
@@ -401,6 +416,24 @@ int epi3_set_pass_bytes(int64_t bytes);
  * capacity)); beyond it the later passes read the whole plane again.  Same
  * rules as above (it sizes the workspaces). */
 int epi3_set_compact_cap(int64_t n);
+
+/* How phenotype batches (MASKED jobs) find each job's k lowest, process-wide
+ * (same rules as epi3_set_pass_bytes; it sizes the workspaces):
+ *   PLANE    every FP32 score is written to a score plane per job (C(M,3)
+ *            floats each) and the selection reads it;
+ *   BOUNDED  no plane: every sample_stride-th tile of the batch is scored
+ *            first, the k-th smallest score of that sample plus 2 e(N) bounds
+ *            the FP32 score of every member of the exact top-k (the sample's
+ *            k lowest are k real scores), and the full pass appends only the
+ *            scores under that bound to a short list per job, which the
+ *            selection then reads.  Workspace grows with k, not C(M,3);
+ *            epi3_batched_score_plane returns EPI3_E_UNSUPPORTED.  A list that
+ *            overflows ends the job with EPI3_E_CAPACITY (n_out = -(the
+ *            cand_cap to retry with));
+ *   AUTO     (default) BOUNDED for batches of at least 2^22 triplets.
+ * EPI3_E_INVALID for another value. */
+enum { EPI3_BATCH_SELECT_AUTO = 0, EPI3_BATCH_SELECT_PLANE = 1, EPI3_BATCH_SELECT_BOUNDED = 2 };
+int epi3_set_batch_select(int32_t mode);
 
 /* Library version string. */
 const char *epi3_version(void);

@@ -40,6 +40,23 @@ def build(out: str = LIB, extra=(), verbose: bool = False) -> str:
     return out
 
 
+PEAK_SRC = os.path.join(PKG, "peak", "peak.hip")
+PEAK_LIB = os.path.join(PKG, "peak", "libepi3_peak.so")
+
+
+def build_peak(out: str = PEAK_LIB) -> str:
+    """The peak-rate microbenchmarks (matrix-core and vector-ALU chains)."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    tmp = out + ".tmp"
+    cmd = [hipcc, *FLAGS, PEAK_SRC, "-o", tmp]
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout)
+        raise RuntimeError("hipcc failed (peak microbenchmarks)")
+    os.replace(tmp, out)
+    return out
+
+
 HOST_SRC = os.path.join(PKG, "host", "epi3_host.c")
 HOST_LIB = os.path.join(PKG, "host", "libepi3_host.so")
 
@@ -59,3 +76,4 @@ def build_host(out: str = HOST_LIB) -> str:
 if __name__ == "__main__":
     print(build(verbose=True))
     print(build_host())
+    print(build_peak())

@@ -129,12 +129,14 @@ struct ScanLayout {
   uint32_t *hist;
   float *score;
   int64_t *cand;
+  uint32_t *candkey;
   CandRec *rec;
   epi3_hit *hits;
   uint32_t *ckey;         // compacted low end of the plane
   int64_t *crank;
   int64_t ccap;
-  PlainJob *pjob;         // [2]: one per scratch buffer
+  PlainJob *pjob;         // matrix-core variants: the job record
+  int64_t *jbegin;        // and its tile range [2]
   uint8_t *scratch;       // matrix-core variants: two buffers of pass_tiles tiles
   int64_t pass_tiles;
   int64_t cap;
@@ -158,6 +160,7 @@ struct Tiles {
   std::vector<TileRule> rules;
   int64_t pass_bytes = 0;
   int64_t compact_cap = 0;
+  int32_t batch_select = EPI3_BATCH_SELECT_AUTO;
   uint64_t gen = 0;  // bumped by every setter: part of the cached graphs' key
 };
 Tiles &tiles() {
@@ -177,6 +180,14 @@ int rule_tile(int32_t variant, int32_t M, int32_t N, int dflt) {
   }
   return best ? best->tile : dflt;
 }
+int batch_select_mode() {
+  Tiles &t = tiles();
+  std::lock_guard<std::mutex> g(t.mu);
+  return t.batch_select;
+}
+// Phenotype batches of at least this many triplets select by bound (AUTO).
+constexpr int64_t kBoundedMinTriplets = 1ll << 22;
+
 uint64_t settings_gen() {
   Tiles &t = tiles();
   std::lock_guard<std::mutex> g(t.mu);
@@ -186,6 +197,12 @@ int64_t pass_bytes(int64_t dflt) {
   Tiles &t = tiles();
   std::lock_guard<std::mutex> g(t.mu);
   return t.pass_bytes > 0 ? t.pass_bytes : dflt;
+}
+
+int64_t compact_cap_override() {
+  Tiles &t = tiles();
+  std::lock_guard<std::mutex> g(t.mu);
+  return t.compact_cap;
 }
 
 // Capacity of the compacted low end of a score plane of T triplets.
@@ -230,12 +247,14 @@ ScanLayout scan_layout(void *ws, const epi3_dataset &d, int32_t k, int64_t cand_
   L.hist = c.take<uint32_t>(kHistBins);
   L.score = c.take<float>(T);
   L.cand = c.take<int64_t>(L.cap);
+  L.candkey = c.take<uint32_t>(L.cap);
   L.rec = c.take<CandRec>(L.cap);
   L.hits = c.take<epi3_hit>(std::max<int32_t>(k, 1));
   L.ccap = compact_cap(T, L.cap);
   L.ckey = c.take<uint32_t>(L.ccap);
   L.crank = c.take<int64_t>(L.ccap);
-  L.pjob = c.take<PlainJob>(2);
+  L.pjob = c.take<PlainJob>(1);
+  L.jbegin = c.take<int64_t>(2);
   const int v = plain_variant(d, variant);
   if (T > 0 && (v == EPI3_VARIANT_MFMA || v == EPI3_VARIANT_MFMA_FP4)) {
     const int64_t tiles = host_plain_tiles(d.n_snps, pick_JB(d, v));
@@ -254,6 +273,7 @@ struct OrderLayout {
   uint32_t *hist;
   float *score;
   int64_t *cand;
+  uint32_t *candkey;
   CandRec *rec;
   uint8_t *hits;
   uint32_t *ckey;
@@ -281,6 +301,7 @@ OrderLayout order_layout(void *ws, const epi3_dataset &d, int order, int32_t k, 
   L.hist = c.take<uint32_t>(kHistBins);
   L.score = c.take<float>(T);
   L.cand = c.take<int64_t>(L.cap);
+  L.candkey = c.take<uint32_t>(L.cap);
   L.rec = c.take<CandRec>(L.cap);
   L.hits = c.take<uint8_t>(std::max<int32_t>(k, 1) * order_hit_bytes(order));
   L.ccap = compact_cap(T, L.cap);
@@ -325,9 +346,10 @@ Job make_job(const epi3_dataset &d, float *score, uint32_t *counts, int64_t *jpr
 }
 
 SelJob make_seljob(const epi3_dataset &d, const float *score, int64_t T, SelState *st,
-                   uint32_t *hist, int64_t *cand, CandRec *rec, epi3_hit *hits, int64_t cap,
-                   int32_t k, uint32_t *ckey, int64_t *crank, int64_t ccap) {
+                   uint32_t *hist, int64_t *cand, uint32_t *candkey, CandRec *rec, epi3_hit *hits,
+                   int64_t cap, int32_t k, uint32_t *ckey, int64_t *crank, int64_t ccap) {
   SelJob S{};
+  S.candkey = candkey;
   S.ckey = ckey;
   S.crank = crank;
   S.ccap = ccap;
@@ -472,47 +494,73 @@ int timed(int which, hipStream_t s, F &&fn) {
   return rc;
 }
 
-// Buffers of one matrix-core plain count: two scratch buffers of pass_tiles
-// tiles, two PlainJob slots, the pivot-block prefix, the tile queue and the
-// job's key range.
+// Buffers of a matrix-core plain count over one or more data sets: two
+// scratch buffers of pass_tiles tiles, the jobs' PlainJob records and their
+// first global tiles, and the tile queue.
 struct MfmaBufs {
   uint8_t *scratch;
   int64_t pass_tiles;
-  PlainJob *pjob;
-  int64_t *jprefix;
+  PlainJob *pjobs;            // [n]
+  int64_t *job_begin;         // [n + 1]
   unsigned long long *queue;
-  uint32_t *keyrange;
 };
 
-int enqueue_count_mfma(const epi3_dataset &d, bool fp4, float *score, uint32_t *counts,
-                       const MfmaBufs &W, hipStream_t s, AuxCtx *ctx) {
-  const int JB = pick_JB(d, fp4 ? EPI3_VARIANT_MFMA_FP4 : EPI3_VARIANT_MFMA);
-  const int64_t tiles = host_plain_tiles(d.n_snps, JB);
+// One data set of a matrix-core plain count.
+struct MfmaTask {
+  const epi3_dataset *d;
+  float *score;
+  uint32_t *counts;           // optional tables [T][2][27]
+  int64_t *jprefix;           // [M + 1]
+  uint32_t *keyrange;         // [2]
+};
+
+// Counts and scores every triplet of the tasks' data sets (all with the same
+// operand type and tile JB) in one sequence of passes over their tiles taken
+// in task order: data set x owns global tiles job_begin[x] .. job_begin[x + 1]
+// and the persistent count and finish kernels walk the global tile order, so
+// one data set's last tiles share a launch with the next one's first.
+int enqueue_count_mfma(const std::vector<MfmaTask> &tasks, bool fp4, int JB, const MfmaBufs &W,
+                       hipStream_t s, AuxCtx *ctx) {
   const int32_t unit = fp4 ? 128 : 64;  // samples per 64-byte staged chunk
-  PlainJob pj{};
-  pj.vals = static_cast<const uint8_t *>(fp4 ? d.nibbles : d.bytes);
-  pj.pairs = d.pairs;
-  pj.score = score;
-  pj.counts = counts;
-  pj.keyrange = W.keyrange;
-  pj.jprefix = W.jprefix;
-  pj.corners = reinterpret_cast<uint4 *>(W.scratch);
-  pj.n_tiles = tiles;
-  pj.T = epi3_n_triplets(d.n_snps);
-  pj.M = d.n_snps;
-  pj.Mp = d.snp_stride;
-  pj.Sb = fp4 ? d.byte_stride / 2 : d.byte_stride;
-  pj.Sb0 = (d.n_controls + unit - 1) / unit * 64;
-  pj.Sb1 = (d.n_cases + unit - 1) / unit * 64;
-  pj.N0 = d.n_controls;
-  pj.N1 = d.n_cases;
-  pj.JB = JB;
-  if (pj.Sb0 > pj.Sb || pj.Sb1 > pj.Sb) return EPI3_E_INVALID;
-  PlainJob pjb[2] = {pj, pj};
-  pjb[1].corners = reinterpret_cast<uint4 *>(W.scratch + W.pass_tiles * kPlainTileScratch);
-  HIP_OK(launch_write_plainjob(pjb[0], W.pjob + 0, s));
-  HIP_OK(launch_write_plainjob(pjb[1], W.pjob + 1, s));
-  HIP_OK(launch_plain_prefix(W.pjob, s));
+  const int n = (int)tasks.size();
+  std::vector<int64_t> begin(n + 1, 0);
+  const float *lf32 = nullptr;
+  int32_t lf_len = 0;
+  for (int x = 0; x < n; ++x) {
+    const epi3_dataset &d = *tasks[x].d;
+    PlainJob pj{};
+    pj.vals = static_cast<const uint8_t *>(fp4 ? d.nibbles : d.bytes);
+    pj.pairs = d.pairs;
+    pj.score = tasks[x].score;
+    pj.counts = tasks[x].counts;
+    pj.keyrange = tasks[x].keyrange;
+    pj.jprefix = tasks[x].jprefix;
+    pj.n_tiles = host_plain_tiles(d.n_snps, JB);
+    pj.T = epi3_n_triplets(d.n_snps);
+    pj.M = d.n_snps;
+    pj.Mp = d.snp_stride;
+    pj.Sb = fp4 ? d.byte_stride / 2 : d.byte_stride;
+    pj.Sb0 = (d.n_controls + unit - 1) / unit * 64;
+    pj.Sb1 = (d.n_cases + unit - 1) / unit * 64;
+    pj.N0 = d.n_controls;
+    pj.N1 = d.n_cases;
+    pj.JB = JB;
+    if (pj.Sb0 > pj.Sb || pj.Sb1 > pj.Sb) return EPI3_E_INVALID;
+    HIP_OK(launch_write_plainjob(pj, W.pjobs + x, s));
+    HIP_OK(launch_plain_prefix(W.pjobs + x, s));
+    begin[x + 1] = begin[x] + pj.n_tiles;
+    // log factorials are prefix sums, so the longest table serves every set
+    if (d.n_samples + 2 > lf_len) {
+      lf_len = d.n_samples + 2;
+      lf32 = d.lf32;
+    }
+  }
+  const int64_t tiles = begin[n];
+  if (tiles == 0) return EPI3_OK;
+  HIP_OK(launch_write_i64(begin.data(), n + 1, W.job_begin, s));
+  const bool counts = n > 0 && tasks[0].counts != nullptr;
+  uint4 *buf[2] = {reinterpret_cast<uint4 *>(W.scratch),
+                   reinterpret_cast<uint4 *>(W.scratch + W.pass_tiles * kPlainTileScratch)};
   // Pass p counts into scratch buffer p % 2 on `s`; its finish kernel runs on
   // the second stream while `s` counts pass p + 1.  Count p + 2 waits for
   // finish p (same buffer).
@@ -529,7 +577,8 @@ int enqueue_count_mfma(const epi3_dataset &d, bool fp4, float *score, uint32_t *
     if (p >= 2) HIP_OK(hipStreamWaitEvent(s, ev_fin[b], 0));
     HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
     rc = timed(0, s, [&]() {
-      return launch_count_mfma_plain(W.pjob + b, JB, fp4, t0, t1, W.queue, s) == hipSuccess
+      return launch_count_mfma_plain(W.pjobs, W.job_begin, n, JB, fp4, buf[b], t0, t1, W.queue,
+                                     s) == hipSuccess
                  ? EPI3_OK
                  : EPI3_E_HIP;
     });
@@ -537,7 +586,8 @@ int enqueue_count_mfma(const epi3_dataset &d, bool fp4, float *score, uint32_t *
     HIP_OK(hipEventRecord(ev_cnt[b], s));
     HIP_OK(hipStreamWaitEvent(s2, ev_cnt[b], 0));
     rc = timed(3, s2, [&]() {
-      return launch_finish_plain(W.pjob + b, JB, t0, t1, d.lf32, d.n_samples + 2, counts != nullptr, s2) == hipSuccess
+      return launch_finish_plain(W.pjobs, W.job_begin, n, JB, buf[b], t0, t1, lf32, lf_len, counts,
+                                 s2) == hipSuccess
                  ? EPI3_OK
                  : EPI3_E_HIP;
     });
@@ -576,8 +626,8 @@ static int order_scan(const epi3_dataset *d, int order, int32_t k, int64_t cand_
   if (ws_bytes < W.total) return EPI3_E_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t T = order_combos(order, d->n_snps);
-  SelJob S = make_seljob(*d, W.score, T, W.st, W.hist, W.cand, W.rec, nullptr, W.cap, k, W.ckey,
-                         W.crank, W.ccap);
+  SelJob S = make_seljob(*d, W.score, T, W.st, W.hist, W.cand, W.candkey, W.rec, nullptr, W.cap, k,
+                         W.ckey, W.crank, W.ccap);
   S.order = order;
   if (order == 2) S.pair_hits = reinterpret_cast<epi3_pair_hit *>(W.hits);
   else S.quad_hits = reinterpret_cast<epi3_quad_hit *>(W.hits);
@@ -764,10 +814,11 @@ static int enqueue_count(const epi3_dataset &d, int32_t variant, float *score, u
   if (v < 0) return v;
   if (v == EPI3_VARIANT_MFMA || v == EPI3_VARIANT_MFMA_FP4) {
     if (!W.scratch) return EPI3_E_WORKSPACE;
-    const MfmaBufs B{W.scratch, W.pass_tiles, W.pjob, W.jprefix, W.queue, &W.st->kmin};
+    const MfmaBufs B{W.scratch, W.pass_tiles, W.pjob, W.jbegin, W.queue};
     AuxLease lease;
     if (lease.rc != EPI3_OK) return lease.rc;
-    return enqueue_count_mfma(d, v == EPI3_VARIANT_MFMA_FP4, score, counts, B, s, lease.c);
+    const std::vector<MfmaTask> one{{&d, score, counts, W.jprefix, &W.st->kmin}};
+    return enqueue_count_mfma(one, v == EPI3_VARIANT_MFMA_FP4, pick_JB(d, v), B, s, lease.c);
   }
   const int P = pick_P(d);
   Job J = make_job(d, score, counts, W.jprefix, &W.st->kmin, P);
@@ -793,8 +844,8 @@ int epi3_scan(const epi3_dataset *d, int32_t k, int32_t variant, int64_t cand_ca
   if (ws_bytes < W.total) return EPI3_E_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t T = epi3_n_triplets(d->n_snps);
-  SelJob S = make_seljob(*d, W.score, T, W.st, W.hist, W.cand, W.rec, W.hits, W.cap, k, W.ckey,
-                         W.crank, W.ccap);
+  SelJob S = make_seljob(*d, W.score, T, W.st, W.hist, W.cand, W.candkey, W.rec, W.hits, W.cap, k,
+                         W.ckey, W.crank, W.ccap);
   HIP_OK(launch_write_seljobs(&S, 1, W.sel, s));
   HIP_OK(launch_init_select(W.sel, 1, s));
   if (T > 0) {
@@ -920,16 +971,29 @@ struct BatchLayout {
   int64_t *perm_prefix = nullptr; // MASKED: [M + 1]
   uint8_t *perm_scratch = nullptr;// MASKED: counts of one pass of tiles
   int64_t pass_tiles = 0;
+  // MASKED, bounded selection (no score plane): every sample_stride-th tile
+  // is scored first into a sample plane, whose k-th smallest score bounds
+  // what the main pass appends to each job's list
+  bool bounded = false;
+  int64_t sample_stride = 0, sample_tiles = 0, sample_T = 0;
+  float *sample = nullptr;        // [groups * 64][sample_T]
+  SelJob *ssel = nullptr;         // [n] selection of the k-th sample score
+  SelState *sst = nullptr;
+  uint32_t *shist = nullptr;
+  uint32_t *bkey = nullptr;       // [groups * 64][ccap]: the jobs' lists (ckey[x] points in)
+  int64_t *brank = nullptr;
   epi3_hit *hits = nullptr;       // [sum k]
   std::vector<int64_t *> jprefix; // SPLIT, per job
   std::vector<float *> score;
   std::vector<int64_t *> cand;
+  std::vector<uint32_t *> candkey;
   std::vector<CandRec *> rec;
   std::vector<uint32_t *> ckey;
   std::vector<int64_t *> crank;
   std::vector<int64_t> cap, ccap, hit_off, T;
   std::vector<int> vsplit;        // SPLIT: count kernel of each job (EPI3_VARIANT_*)
-  PlainJob *pjobs_plain = nullptr;// SPLIT: two slots per matrix-core job
+  PlainJob *pjobs_plain = nullptr;// SPLIT: one record per matrix-core job
+  int64_t *plain_begin = nullptr; // SPLIT: their global first tiles, per (type, JB) group
   uint8_t *plain_scratch = nullptr;
   int64_t plain_pass_tiles = 0;
   int64_t total_k = 0, total = 0;
@@ -980,10 +1044,11 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
   L.hits = c.take<epi3_hit>(L.total_k);
   if (L.layout == EPI3_LAYOUT_SPLIT) {
     L.jobs = c.take<Job>(n);
-    // per job: the vector-ALU kernel (all such jobs share one launch) or a
-    // matrix-core plain count of its own, sharing one scratch
+    // per job: the vector-ALU kernel (all such jobs share one launch) or the
+    // matrix cores (all jobs of one operand type and tile share one sequence
+    // of launches through one scratch)
     L.vsplit.resize(n);
-    int64_t max_tiles = 0;
+    std::map<std::pair<int, int>, int64_t> group_tiles;
     int n_mfma = 0;
     for (int x = 0; x < n; ++x) {
       const epi3_dataset &d = *jobs[x].d;
@@ -991,11 +1056,15 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
       if ((L.vsplit[x] == EPI3_VARIANT_MFMA || L.vsplit[x] == EPI3_VARIANT_MFMA_FP4) &&
           epi3_n_triplets(d.n_snps) > 0) {
         ++n_mfma;
-        max_tiles = std::max(max_tiles, host_plain_tiles(d.n_snps, pick_JB(d, L.vsplit[x])));
+        const int JB = pick_JB(d, L.vsplit[x]);
+        group_tiles[{L.vsplit[x], JB}] += host_plain_tiles(d.n_snps, JB);
       }
     }
     if (n_mfma > 0) {
-      L.pjobs_plain = c.take<PlainJob>(2 * (int64_t)n);
+      int64_t max_tiles = 0;
+      for (const auto &kv : group_tiles) max_tiles = std::max(max_tiles, kv.second);
+      L.pjobs_plain = c.take<PlainJob>(n);
+      L.plain_begin = c.take<int64_t>((int64_t)n + (int64_t)group_tiles.size());
       L.plain_pass_tiles = std::max<int64_t>(
           1, std::min<int64_t>(max_tiles, pass_bytes(kPlainPassBytes) / kPlainTileScratch));
       L.plain_scratch = c.take<uint8_t>(2 * L.plain_pass_tiles * kPlainTileScratch);
@@ -1016,10 +1085,32 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
         1, std::min<int64_t>(tiles, pass_bytes(kPermPassBytes) / kPermTileScratch));
     // two buffers: the count kernel of pass p + 1 runs while pass p is scored
     L.perm_scratch = c.take<uint8_t>(2 * L.pass_tiles * kPermTileScratch);
+    int32_t max_k = 0;
+    for (int x = 0; x < n; ++x) max_k = std::max(max_k, jobs[x].k);
+    const int64_t T = epi3_n_triplets(d.n_snps);
+    const int mode = batch_select_mode();
+    if (T > 0 && (mode == EPI3_BATCH_SELECT_BOUNDED ||
+                  (mode == EPI3_BATCH_SELECT_AUTO && T >= kBoundedMinTriplets))) {
+      // about max(1024, 64 k) sample tiles (64 scores each), spread evenly
+      // over the tile order
+      const int64_t want = std::max<int64_t>(1024, 64 * (int64_t)max_k);
+      const int64_t stride = std::max<int64_t>(1, tiles / want);
+      if (host_perm_sample_valid(d.n_snps, stride) >= max_k) {
+        L.bounded = true;
+        L.sample_stride = stride;
+        L.sample_tiles = (tiles + stride - 1) / stride;
+        L.sample_T = L.sample_tiles * 64;
+        L.sample = c.take<float>((int64_t)L.groups * kPermGroup * L.sample_T);
+        L.ssel = c.take<SelJob>(n);
+        L.sst = c.take<SelState>(n);
+        L.shist = c.take<uint32_t>((int64_t)n * kHistBins);
+      }
+    }
   }
   L.jprefix.resize(n);
   L.score.resize(n);
   L.cand.resize(n);
+  L.candkey.resize(n);
   L.rec.resize(n);
   L.ckey.resize(n);
   L.crank.resize(n);
@@ -1031,7 +1122,23 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
     L.cap[x] = default_cap(L.T[x], jobs[x].k, cand_cap);
     L.ccap[x] = compact_cap(L.T[x], L.cap[x]);
   }
-  if (L.layout == EPI3_LAYOUT_MASKED) {
+  if (L.bounded) {
+    // one list length for all jobs: the larger of the compacted-list size and
+    // twice the expected count (the sample holds one score in sample_stride,
+    // so about k sample_stride scores lie below its k-th), plus slack
+    // (a size set by epi3_set_compact_cap is taken as it is)
+    const bool fixed = compact_cap_override() > 0;
+    int64_t cc = 0;
+    for (int x = 0; x < n; ++x)
+      cc = std::max(cc, fixed ? L.ccap[x]
+                              : std::max(L.ccap[x], 2 * (int64_t)jobs[x].k * L.sample_stride + 65536));
+    L.bkey = c.take<uint32_t>((int64_t)L.groups * kPermGroup * cc);
+    L.brank = c.take<int64_t>((int64_t)L.groups * kPermGroup * cc);
+    for (int x = 0; x < n; ++x) {
+      L.ccap[x] = cc;
+      L.score[x] = nullptr;
+    }
+  } else if (L.layout == EPI3_LAYOUT_MASKED) {
     // one block [n][T]: the matrix-core kernel addresses phenotype q at q * T
     float *all = c.take<float>((int64_t)n * L.T[0]);
     for (int x = 0; x < n; ++x) L.score[x] = all ? all + (int64_t)x * L.T[0] : nullptr;
@@ -1043,9 +1150,15 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
       L.score[x] = c.take<float>(L.T[x]);
     }
     L.cand[x] = c.take<int64_t>(L.cap[x]);
+    L.candkey[x] = c.take<uint32_t>(L.cap[x]);
     L.rec[x] = c.take<CandRec>(L.cap[x]);
-    L.ckey[x] = c.take<uint32_t>(L.ccap[x]);
-    L.crank[x] = c.take<int64_t>(L.ccap[x]);
+    if (L.bounded) {
+      L.ckey[x] = L.bkey ? L.bkey + (int64_t)x * L.ccap[x] : nullptr;
+      L.crank[x] = L.brank ? L.brank + (int64_t)x * L.ccap[x] : nullptr;
+    } else {
+      L.ckey[x] = c.take<uint32_t>(L.ccap[x]);
+      L.crank[x] = c.take<int64_t>(L.ccap[x]);
+    }
   }
   L.total = c.size();
   return L;
@@ -1063,9 +1176,11 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
   for (int x = 0; x < n; ++x) {
     const epi3_dataset &d = *jobs[x].d;
     sj[x] = make_seljob(d, W.score[x], W.T[x], W.st + x, W.hist + (int64_t)x * kHistBins,
-                        W.cand[x], W.rec[x], W.hits + W.hit_off[x], W.cap[x], jobs[x].k,
-                        W.ckey[x], W.crank[x], W.ccap[x]);
-    any_sample = any_sample || sj[x].sample;
+                        W.cand[x], W.candkey[x], W.rec[x], W.hits + W.hit_off[x], W.cap[x],
+                        jobs[x].k, W.ckey[x], W.crank[x], W.ccap[x]);
+    // bounded jobs have their list before the selection starts (no plane pass)
+    if (W.bounded) sj[x].sample = 1;
+    any_sample = any_sample || (sj[x].sample && sj[x].score);
     if (W.layout == EPI3_LAYOUT_MASKED) {
       const int g = x / kPermGroup, q = x % kPermGroup;
       sj[x].case_mask = jobs[x].case_mask;
@@ -1087,16 +1202,32 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
   }
 
   if (W.layout == EPI3_LAYOUT_SPLIT) {
-    // matrix-core jobs: one plain count each (passes through the shared scratch)
+    // matrix-core jobs: one sequence of passes per (operand type, tile JB)
+    // over all their tiles, the data sets with the most samples per tile
+    // first so the queue ends on the cheapest tiles
+    std::map<std::pair<int, int>, std::vector<int>> groups;
     for (int x = 0; x < n; ++x) {
       const int v = W.vsplit[x];
       if (v < 0) return v;
       if (v == EPI3_VARIANT_VALU || W.T[x] == 0) continue;
-      const MfmaBufs B{W.plain_scratch, W.plain_pass_tiles, W.pjobs_plain + 2 * (int64_t)x,
-                       W.jprefix[x], W.queue, &W.st[x].kmin};
-      const int rc = enqueue_count_mfma(*jobs[x].d, v == EPI3_VARIANT_MFMA_FP4, W.score[x], nullptr,
-                                        B, s, lease.c);
+      groups[{v, pick_JB(*jobs[x].d, v)}].push_back(x);
+    }
+    int64_t rec = 0, beg = 0;
+    for (auto &kv : groups) {
+      std::vector<int> &xs = kv.second;
+      std::stable_sort(xs.begin(), xs.end(), [&](int a, int b) {
+        const epi3_dataset &da = *jobs[a].d, &db = *jobs[b].d;
+        return da.words[0] + da.words[1] > db.words[0] + db.words[1];
+      });
+      std::vector<MfmaTask> tasks;
+      for (int x : xs) tasks.push_back({jobs[x].d, W.score[x], nullptr, W.jprefix[x], &W.st[x].kmin});
+      const MfmaBufs B{W.plain_scratch, W.plain_pass_tiles, W.pjobs_plain + rec,
+                       W.plain_begin + beg, W.queue};
+      const int rc = enqueue_count_mfma(tasks, kv.first.first == EPI3_VARIANT_MFMA_FP4,
+                                        kv.first.second, B, s, lease.c);
       if (rc != EPI3_OK) return rc;
+      rec += (int64_t)xs.size();
+      beg += (int64_t)xs.size() + 1;
     }
     // vector-ALU jobs: one persistent launch over all their tiles; jobs with
     // the most samples per tile first so the queue ends on the cheapest tiles
@@ -1149,6 +1280,17 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
     for (int x = n; x < (int)masks.size(); ++x) masks[x] = jobs[0].case_mask;  // never read
     HIP_OK(launch_write_ptrs(masks.data(), (int32_t)masks.size(), W.masks, s));
     const int64_t tiles = host_perm_tiles(d.n_snps);
+    if (W.bounded) {
+      // selection of each job's k-th smallest sample score
+      std::vector<SelJob> ss(n);
+      for (int x = 0; x < n; ++x)
+        ss[x] = make_seljob(d, W.sample + (int64_t)x * W.sample_T, W.sample_T, W.sst + x,
+                            W.shist + (int64_t)x * kHistBins, nullptr, nullptr, nullptr, nullptr,
+                            1, jobs[x].k, nullptr, nullptr, 0);
+      for (SelJob &j : ss) j.sample = 0;  // read as a whole
+      HIP_OK(launch_write_seljobs(ss.data(), n, W.ssel, s));
+      HIP_OK(launch_init_select(W.ssel, n, s));
+    }
     for (int g = 0; g < W.groups; ++g) {
       const int Q = std::min(kPermGroup, n - g * kPermGroup);
       PermJob pj{};
@@ -1177,51 +1319,87 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
                                W.masks + (int64_t)g * kPermGroup, Q, kPermGroup,
                                const_cast<int32_t *>(pj.case_pairs), s));
       if (g == 0) HIP_OK(launch_perm_prefix(W.pjobs + 0, s));
-      // Pass p counts into scratch buffer p % 2 on `s`; its finish kernel runs on
-      // the second stream while `s` counts pass p + 1.  Count p + 2 waits for
-      // finish p (same buffer).  Events order the two streams (also when captured).
       hipStream_t s2 = lease.c->s2;
-      int rc = EPI3_OK;
       hipEvent_t ev_start = lease.c->ev[0], ev_cnt[2] = {lease.c->ev[1], lease.c->ev[2]},
                  ev_fin[2] = {lease.c->ev[3], lease.c->ev[4]};
-      HIP_OK(hipEventRecord(ev_start, s));
-      HIP_OK(hipStreamWaitEvent(s2, ev_start, 0));
       PermJob pjb[2] = {pj, pj};
       pjb[1].corners = reinterpret_cast<uint4 *>(W.perm_scratch + W.pass_tiles * kPermTileScratch);
       pjb[1].totals = reinterpret_cast<uint4 *>(W.perm_scratch + W.pass_tiles * kPermTileScratch +
                                                 W.pass_tiles * 64 * 64 * 16);
       HIP_OK(launch_write_permjob(pjb[1], W.pjobs_alt + g, s));
       const PermJob *pdev[2] = {W.pjobs + g, W.pjobs_alt + g};
-      int p = 0;
-      for (int64_t t0 = 0; t0 < tiles; t0 += W.pass_tiles, ++p) {
-        const int64_t t1 = std::min(tiles, t0 + W.pass_tiles);
-        const int b = p & 1;
-        if (p >= 2) HIP_OK(hipStreamWaitEvent(s, ev_fin[b], 0));
-        HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
-        rc = timed(0, s, [&]() {
-          return launch_count_mfma_perm(pdev[b], t0, t1, W.queue, fp4, s) == hipSuccess
-                     ? EPI3_OK
-                     : EPI3_E_HIP;
-        });
+      // Passes over the tiles n * stride, n < n_all: pass p counts into scratch
+      // buffer p % 2 on `s`; its finish kernel runs on the second stream while
+      // `s` counts pass p + 1, and count p + 2 waits for finish p (same
+      // buffer).  Events order the two streams (also when captured); the join
+      // at the end puts everything on `s` again.
+      auto passes = [&](int64_t n_all, int64_t stride, SelState *fst, PermOut out) -> int {
+        HIP_OK(hipEventRecord(ev_start, s));
+        HIP_OK(hipStreamWaitEvent(s2, ev_start, 0));
+        int p = 0;
+        for (int64_t n0 = 0; n0 < n_all; n0 += W.pass_tiles, ++p) {
+          const int64_t nn = std::min(W.pass_tiles, n_all - n0);
+          const int b = p & 1;
+          if (p >= 2) HIP_OK(hipStreamWaitEvent(s, ev_fin[b], 0));
+          HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
+          int rc = timed(0, s, [&]() {
+            return launch_count_mfma_perm(pdev[b], n0 * stride, nn, stride, W.queue, fp4, s) ==
+                           hipSuccess
+                       ? EPI3_OK
+                       : EPI3_E_HIP;
+          });
+          if (rc != EPI3_OK) return rc;
+          HIP_OK(hipEventRecord(ev_cnt[b], s));
+          HIP_OK(hipStreamWaitEvent(s2, ev_cnt[b], 0));
+          out.sample_base = n0;
+          rc = timed(3, s2, [&]() {
+            return launch_finish_perm(pdev[b], n0 * stride, nn, stride, fst, d.lf32,
+                                      d.n_samples + 2, out, s2) == hipSuccess
+                       ? EPI3_OK
+                       : EPI3_E_HIP;
+          });
+          if (rc != EPI3_OK) return rc;
+          HIP_OK(hipEventRecord(ev_fin[b], s2));
+        }
+        HIP_OK(hipEventRecord(ev_fin[0], s2));
+        HIP_OK(hipStreamWaitEvent(s, ev_fin[0], 0));
+        return EPI3_OK;
+      };
+      const int64_t x0 = (int64_t)g * kPermGroup;
+      int rc = EPI3_OK;
+      if (W.bounded) {
+        // sample pass: every sample_stride-th tile scored into the sample
+        // plane (slots of no triplet stay +inf), then each job's k-th sample
+        // score sets the bound of its list
+        float *smp = W.sample + x0 * W.sample_T;
+        HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(smp), 0x7f800000u,
+                               (int64_t)kPermGroup * W.sample_T, s));
+        PermOut so{};
+        so.mode = kPermOutSample;
+        so.sample = smp;
+        so.sample_T = W.sample_T;
+        rc = passes(W.sample_tiles, W.sample_stride, W.sst + x0, so);
         if (rc != EPI3_OK) return rc;
-        HIP_OK(hipEventRecord(ev_cnt[b], s));
-        HIP_OK(hipStreamWaitEvent(s2, ev_cnt[b], 0));
-        rc = timed(3, s2, [&]() {
-          return launch_finish_perm(pdev[b], t0, t1, W.st + (int64_t)g * kPermGroup, d.lf32,
-                                    d.n_samples + 2, s2) == hipSuccess
-                     ? EPI3_OK
-                     : EPI3_E_HIP;
-        });
-        if (rc != EPI3_OK) return rc;
-        HIP_OK(hipEventRecord(ev_fin[b], s2));
+        HIP_OK(launch_select_kth(W.ssel + x0, Q, W.sample_T, s));
+        HIP_OK(launch_sample_bound(W.sel + x0, W.ssel + x0, Q, s));
+        PermOut bo{};
+        bo.mode = kPermOutBounded;
+        bo.ckey = W.ckey[x0];
+        bo.crank = W.crank[x0];
+        bo.ccap = W.ccap[x0];
+        rc = passes(tiles, 1, W.st + x0, bo);
+      } else {
+        PermOut po{};
+        po.mode = kPermOutPlane;
+        rc = passes(tiles, 1, W.st + x0, po);
       }
-      // join: everything on the second stream precedes what follows on `s`
-      HIP_OK(hipEventRecord(ev_fin[0], s2));
-      HIP_OK(hipStreamWaitEvent(s, ev_fin[0], 0));
+      if (rc != EPI3_OK) return rc;
     }
   }
+  // bounded jobs' passes read their lists only: size the grids for those
+  const int64_t sel_T = W.bounded ? W.ccap[0] : max_T;
   return timed(1, s, [&]() {
-    return launch_select(W.sel, n, max_T, max_cap, max_k, any_sample, s) == hipSuccess ? EPI3_OK
+    return launch_select(W.sel, n, sel_T, max_cap, max_k, any_sample, s) == hipSuccess ? EPI3_OK
                                                                                     : EPI3_E_HIP;
   });
 }
@@ -1285,6 +1463,26 @@ int epi3_batched_score_plane(const epi3_job *jobs, int32_t n_jobs, int32_t varia
   return EPI3_OK;
 }
 
+int epi3_batched_bound_list(const epi3_job *jobs, int32_t n_jobs, int32_t variant,
+                            int64_t cand_cap, void *ws_dev, int32_t job, uint32_t **keys_dev,
+                            int64_t **ranks_dev, int64_t *count, float *bound, void *stream) {
+  const int rc = check_jobs(jobs, n_jobs, variant);
+  if (rc != EPI3_OK) return rc;
+  if (!ws_dev || !keys_dev || !ranks_dev || !count || !bound || job < 0 || job >= n_jobs)
+    return EPI3_E_INVALID;
+  const BatchLayout W = batch_layout(ws_dev, jobs, n_jobs, cand_cap, variant);
+  if (!W.bounded) return EPI3_E_UNSUPPORTED;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SelState st;
+  HIP_OK(hipMemcpyAsync(&st, W.st + job, sizeof(st), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  *keys_dev = W.ckey[job];
+  *ranks_dev = W.crank[job];
+  *count = std::min<int64_t>((int64_t)st.cn, W.ccap[job]);
+  *bound = st.ub;
+  return EPI3_OK;
+}
+
 int epi3_scan_batched(const epi3_job *jobs, int32_t n_jobs, int32_t variant, int64_t cand_cap,
                       void *ws_dev, int64_t ws_bytes, epi3_hit *hits_host, int32_t *n_out_host,
                       void *stream) {
@@ -1339,6 +1537,11 @@ int epi3_scan_batched(const epi3_job *jobs, int32_t n_jobs, int32_t variant, int
     if (status[x] & 1) {
       n_out_host[x] = 0;
       worst = EPI3_E_GENOTYPE;
+    } else if (st[x].done == 3u) {
+      // the bounded list overflowed: 16 x cand_cap entries hold it on a retry
+      const int64_t need = std::max<int64_t>((int64_t)((st[x].cn + 15) / 16), W.cap[x] + 1);
+      n_out_host[x] = -(int32_t)std::min<int64_t>(need, 0x7fffffff);
+      if (worst == EPI3_OK) worst = EPI3_E_CAPACITY;
     } else if ((int64_t)st[x].ncand > W.cap[x]) {
       n_out_host[x] = -(int32_t)std::min<unsigned long long>(st[x].ncand, 0x7fffffffull);
       if (worst == EPI3_OK) worst = EPI3_E_CAPACITY;
@@ -1429,6 +1632,15 @@ int epi3_set_compact_cap(int64_t n) {
   Tiles &t = tiles();
   std::lock_guard<std::mutex> g(t.mu);
   t.compact_cap = n;
+  ++t.gen;
+  return EPI3_OK;
+}
+
+int epi3_set_batch_select(int32_t mode) {
+  if (mode < EPI3_BATCH_SELECT_AUTO || mode > EPI3_BATCH_SELECT_BOUNDED) return EPI3_E_INVALID;
+  Tiles &t = tiles();
+  std::lock_guard<std::mutex> g(t.mu);
+  t.batch_select = mode;
   ++t.gen;
   return EPI3_OK;
 }

@@ -17,6 +17,8 @@
 // lane l supplies A row l % 32 and B column l % 32 with 16 consecutive K
 // values starting at 16 (l / 32); the result of row r, column c is in lane
 // c + 32 ((r / 4) % 2), register 4 (r / 8) + r % 4.
+#include <algorithm>
+
 #include "epi3_internal.h"
 
 namespace epi3 {
@@ -243,7 +245,7 @@ __device__ __forceinline__ void perm_step_t(v4i p, v4i x, v4i b0, v4i b1, uint32
 
 template <bool FP4>
 __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
-    const PermJob *__restrict__ pjp, int64_t tile_begin, int64_t tile_end,
+    const PermJob *__restrict__ pjp, int64_t tile_begin, int64_t n_tiles, int64_t stride,
     unsigned long long *__restrict__ queue) {
   typedef PermAcc<FP4> Acc;
   __shared__ __attribute__((aligned(16))) unsigned char stage[2 * kStageBytes];
@@ -268,11 +270,11 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
 
   for (;;) {
     __syncthreads();  // previous tile's readers of sTile / stage are done
-    if (tid == 0) sTile[0] = tile_begin + (int64_t)atomicAdd(queue, 1ull);
+    if (tid == 0) sTile[0] = (int64_t)atomicAdd(queue, 1ull);
     __syncthreads();
-    const int64_t t = rfl64p(sTile[0]);
-    if (t >= tile_end) break;
-    const int64_t slot = t - tile_begin;
+    const int64_t slot = rfl64p(sTile[0]);  // scratch slot of this launch
+    if (slot >= n_tiles) break;
+    const int64_t t = tile_begin + slot * stride;
     if (j < 0 || t < jlo || t >= jhi) {
       int lo = 0, hi = M - 1;
       while (lo < hi) {
@@ -434,12 +436,13 @@ __host__ __device__ __forceinline__ int finish_perm_table_bytes(int lf_len) {
   return (lf_len * 4 + 15) / 16 * 16;
 }
 
-template <bool LDS>
+template <bool LDS, int MODE>
 __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restrict__ pjp,
-                                                          int64_t tile_begin, int64_t tile_end,
+                                                          int64_t tile_begin, int64_t n_tiles,
+                                                          int64_t stride,
                                                           SelState *__restrict__ st,
                                                           const float *__restrict__ lf32,
-                                                          int lf_len) {
+                                                          int lf_len, PermOut out) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   const float *sL = lf32;
   FinishPermLds &sh = *reinterpret_cast<FinishPermLds *>(lds + (LDS ? finish_perm_table_bytes(lf_len) : 0));
@@ -468,6 +471,8 @@ __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restr
   gptr<u4e> corners = (gptr<u4e>)pj.corners;
   const int qc = q < Q ? q : 0;  // lanes past Q compute on phenotype 0 and write nothing
   const int n1x4 = pj.n1[qc] << 2;
+  // bounded: this phenotype's append bound (set before the launch)
+  const float ubq = MODE == kPermOutBounded ? st[qc].ub : 0.f;
   uint32_t kmin = 0xffffffffu, kmax = 0u;
   // pivot of tile t
   auto pivot_of = [&](int64_t t) {
@@ -480,14 +485,14 @@ __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restr
   };
   // row of phenotype-major case pair tables for pair (x, y) (uniform)
   auto cp_row = [&](int x, int y) { return cp + ((int64_t)x * Mp + y) * Qp; };
-  for (int64_t t = tile_begin + blockIdx.x; t < tile_end; t += gridDim.x) {
+  for (int64_t slot = blockIdx.x; slot < n_tiles; slot += gridDim.x) {
+    const int64_t t = tile_begin + slot * stride;
     const int j = pivot_of(t);
     const int64_t rr = t - pre[j];
     const int ib = (int)(rr / perm_nkb(M, j)), kbg = perm_kb_lo(j) + (int)(rr % perm_nkb(M, j));
     const int i = 4 * ib + wave;
     const int k0 = kbg * kPermKB;
     if (i >= j) continue;  // wave-uniform
-    const int64_t slot = t - tile_begin;
     gptr<u4e> cor = corners + (slot * 4 + wave) * (int64_t)kPermKB * 64;
     const int64_t tbase = (slot * 4 + wave) * (int64_t)kPermKB;
     const int kk_lo = j + 1 - k0 > 0 ? j + 1 - k0 : 0;
@@ -564,11 +569,22 @@ __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restr
         else
           k2 += l1 - (lf_at(sL, r0) + lf_at(sL, c4[x]));
       }
-      sh.score[wave][kk][q] = k2;
       const uint32_t key = f2key(k2);
       kmin = key < kmin ? key : kmin;
       kmax = key > kmax ? key : kmax;
+      if (MODE == kPermOutPlane) sh.score[wave][kk][q] = k2;
+      if (MODE == kPermOutSample && q < Q)
+        out.sample[(int64_t)q * out.sample_T + (out.sample_base + slot) * 64 + wave * kPermKB + kk] = k2;
+      if (MODE == kPermOutBounded && q < Q && k2 <= ubq) {
+        // rare (a few thousand of the C(M,3) scores per phenotype): one atomic per append
+        const unsigned long long pos = atomicAdd(&st[q].cn, 1ull);
+        if ((int64_t)pos < out.ccap) {
+          out.ckey[(int64_t)q * out.ccap + pos] = key;
+          out.crank[(int64_t)q * out.ccap + pos] = lex_base(M, i, j) + k0 + kk;
+        }
+      }
     }
+    if (MODE != kPermOutPlane) continue;
     // scores of phenotype q at ranks base + k (this wave wrote them)
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -644,10 +660,9 @@ int64_t host_perm_tiles(int64_t M) {
 }
 
 template <bool FP4>
-static hipError_t launch_count_t(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,
-                                 unsigned long long *queue, hipStream_t s) {
-  const int64_t n = tile_end - tile_begin;
-  if (n <= 0) return hipSuccess;
+static hipError_t launch_count_t(const PermJob *pj_dev, int64_t tile_begin, int64_t n_tiles,
+                                 int64_t stride, unsigned long long *queue, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
   int dev = 0, n_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
@@ -658,49 +673,89 @@ static hipError_t launch_count_t(const PermJob *pj_dev, int64_t tile_begin, int6
   if (e != hipSuccess) return e;
   if (per_cu <= 0) per_cu = 1;
   int64_t blocks = (int64_t)n_cu * per_cu;
-  if (blocks > n) blocks = n;
+  if (blocks > n_tiles) blocks = n_tiles;
   hipLaunchKernelGGL(count_mfma_perm_kernel<FP4>, dim3((unsigned)blocks), dim3(256), 0, s, pj_dev,
-                     tile_begin, tile_end, queue);
+                     tile_begin, n_tiles, stride, queue);
   return hipGetLastError();
 }
 
-hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,
-                                  unsigned long long *queue, bool fp4, hipStream_t s) {
-  return fp4 ? launch_count_t<true>(pj_dev, tile_begin, tile_end, queue, s)
-             : launch_count_t<false>(pj_dev, tile_begin, tile_end, queue, s);
+hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t n_tiles,
+                                  int64_t stride, unsigned long long *queue, bool fp4,
+                                  hipStream_t s) {
+  return fp4 ? launch_count_t<true>(pj_dev, tile_begin, n_tiles, stride, queue, s)
+             : launch_count_t<false>(pj_dev, tile_begin, n_tiles, stride, queue, s);
 }
 
-template <bool LDS>
-static hipError_t launch_finish_perm_l(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,
-                                       SelState *st, const float *lf32, int32_t lf_len,
-                                       hipStream_t s) {
-  const int64_t n = tile_end - tile_begin;
-  if (n <= 0) return hipSuccess;
+template <bool LDS, int MODE>
+static hipError_t launch_finish_perm_l(const PermJob *pj_dev, int64_t tile_begin, int64_t n_tiles,
+                                       int64_t stride, SelState *st, const float *lf32,
+                                       int32_t lf_len, const PermOut &out, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
   int dev = 0, n_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
   const size_t lds = (LDS ? (size_t)finish_perm_table_bytes(lf_len) : 0) + sizeof(FinishPermLds);
-  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&finish_perm_kernel<LDS>),
+  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&finish_perm_kernel<LDS, MODE>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, finish_perm_kernel<LDS>, 256, lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, finish_perm_kernel<LDS, MODE>, 256, lds);
   if (e != hipSuccess) return e;
   if (per_cu <= 0) per_cu = 1;
   int64_t blocks = (int64_t)n_cu * per_cu;
-  if (blocks > n) blocks = n;
-  hipLaunchKernelGGL(finish_perm_kernel<LDS>, dim3((unsigned)blocks), dim3(256), lds, s, pj_dev,
-                     tile_begin, tile_end, st, lf32, lf_len);
+  if (blocks > n_tiles) blocks = n_tiles;
+  hipLaunchKernelGGL((finish_perm_kernel<LDS, MODE>), dim3((unsigned)blocks), dim3(256), lds, s,
+                     pj_dev, tile_begin, n_tiles, stride, st, lf32, lf_len, out);
   return hipGetLastError();
 }
 
-hipError_t launch_finish_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,
-                              SelState *st, const float *lf32, int32_t lf_len, hipStream_t s) {
+template <bool LDS>
+static hipError_t launch_finish_perm_m(const PermJob *pj_dev, int64_t tile_begin, int64_t n_tiles,
+                                       int64_t stride, SelState *st, const float *lf32,
+                                       int32_t lf_len, const PermOut &out, hipStream_t s) {
+  switch (out.mode) {
+    case kPermOutPlane:
+      return launch_finish_perm_l<LDS, kPermOutPlane>(pj_dev, tile_begin, n_tiles, stride, st, lf32,
+                                                     lf_len, out, s);
+    case kPermOutSample:
+      return launch_finish_perm_l<LDS, kPermOutSample>(pj_dev, tile_begin, n_tiles, stride, st,
+                                                      lf32, lf_len, out, s);
+    case kPermOutBounded:
+      return launch_finish_perm_l<LDS, kPermOutBounded>(pj_dev, tile_begin, n_tiles, stride, st,
+                                                       lf32, lf_len, out, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_finish_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t n_tiles,
+                              int64_t stride, SelState *st, const float *lf32, int32_t lf_len,
+                              const PermOut &out, hipStream_t s) {
   return lf_in_lds(lf_len)
-             ? launch_finish_perm_l<true>(pj_dev, tile_begin, tile_end, st, lf32, lf_len, s)
-             : launch_finish_perm_l<false>(pj_dev, tile_begin, tile_end, st, lf32, lf_len, s);
+             ? launch_finish_perm_m<true>(pj_dev, tile_begin, n_tiles, stride, st, lf32, lf_len, out, s)
+             : launch_finish_perm_m<false>(pj_dev, tile_begin, n_tiles, stride, st, lf32, lf_len, out, s);
+}
+
+int64_t host_perm_sample_valid(int64_t M, int64_t stride) {
+  int64_t valid = 0, pre = 0;
+  for (int64_t j = 0; j < M; ++j) {
+    const int64_t nt = perm_tiles_of_j(M, j);
+    if (nt > 0) {
+      const int nkb = perm_nkb(M, j);
+      for (int64_t t = (pre + stride - 1) / stride * stride; t < pre + nt; t += stride) {
+        const int64_t rr = t - pre;
+        const int64_t ib = rr / nkb, kb = rr % nkb;
+        const int64_t ni = std::max<int64_t>(0, std::min<int64_t>(4, j - 4 * ib));
+        const int64_t kbase = (perm_kb_lo(j) + kb) * kPermKB;
+        const int64_t nk = std::max<int64_t>(
+            0, std::min<int64_t>(kbase + kPermKB, M) - std::max<int64_t>(kbase, j + 1));
+        valid += ni * nk;
+      }
+    }
+    pre += nt;
+  }
+  return valid;
 }
 
 }  // namespace epi3

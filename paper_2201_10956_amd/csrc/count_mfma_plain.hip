@@ -148,9 +148,29 @@ __device__ __forceinline__ void plain_tile_origin(const TileDecoder &dec, int64_
   k0 = j0 + 1 + kb * KT;
 }
 
+// Finds the job of global tile t: jobs own consecutive ranges of the tile
+// order, job_begin[x] .. job_begin[x + 1] (uniform: scalar loads).
+struct JobDecoder {
+  int x = -1;
+  int64_t lo = 0, hi = 0;
+  __device__ __forceinline__ bool find(cptr<int64_t> job_begin, int n_jobs, int64_t t) {
+    if (x >= 0 && t >= lo && t < hi) return false;
+    int a = 0, b = n_jobs - 1;
+    while (a < b) {
+      const int mid = (a + b + 1) >> 1;
+      if (job_begin[mid] <= t) a = mid; else b = mid - 1;
+    }
+    x = a;
+    lo = job_begin[a];
+    hi = job_begin[a + 1];
+    return true;
+  }
+};
+
 template <bool FP4, int JB>
 __global__ void __launch_bounds__(256, 2) count_mfma_plain_kernel(
-    const PlainJob *__restrict__ pjp, int64_t tile_begin, int64_t tile_end,
+    const PlainJob *__restrict__ jobs, const int64_t *__restrict__ job_begin_p, int n_jobs,
+    uint4 *__restrict__ corners, int64_t tile_begin, int64_t tile_end,
     unsigned long long *__restrict__ queue) {
   typedef PlainAcc<FP4> Acc;
   constexpr int KT = 256 / JB;
@@ -164,14 +184,14 @@ __global__ void __launch_bounds__(256, 2) count_mfma_plain_kernel(
   __shared__ __attribute__((aligned(16))) unsigned char stage[2 * kBuf];
   __shared__ int64_t sTile[2];
 
-  const PlainJob pj = *pjp;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wj = wave / NBP, wb = wave - wj * NBP;
   const int r = lane & 31, g = lane >> 5;
-  const int M = pj.M, Mp = pj.Mp, Sb = pj.Sb;
-  const int nJ = (int)plain_jblocks(M, JB);
-  gptr<uint8_t> gv = (gptr<uint8_t>)pj.vals;
-  cptr<int64_t> pre = as_const(pj.jprefix);
+  cptr<int64_t> job_begin = as_const(job_begin_p);
+  JobDecoder jd;
+  int M = 0, Mp = 0, Sb = 0, Sb0 = 0, Sb1 = 0, nJ = 0;
+  gptr<uint8_t> gv = nullptr;
+  cptr<int64_t> pre = nullptr;
   TileDecoder dec;
   // lane roles: A row r = 4 i8 + 2 a + b; B column r = 2 k16 + g_k
   const int ri8 = r >> 2, ra = (r >> 1) & 1, rb = r & 1;
@@ -184,16 +204,29 @@ __global__ void __launch_bounds__(256, 2) count_mfma_plain_kernel(
     __syncthreads();
     if (tid == 0) sTile[0] = tile_begin + (int64_t)atomicAdd(queue, 1ull);
     __syncthreads();
-    const int64_t t = rfl64q(sTile[0]);
-    if (t >= tile_end) break;
-    const int64_t slot = t - tile_begin;
+    const int64_t tg = rfl64q(sTile[0]);
+    if (tg >= tile_end) break;
+    const int64_t slot = tg - tile_begin;
+    if (jd.find(job_begin, n_jobs, tg)) {
+      const PlainJob &pj = jobs[jd.x];
+      M = pj.M;
+      Mp = pj.Mp;
+      Sb = pj.Sb;
+      Sb0 = pj.Sb0;
+      Sb1 = pj.Sb1;
+      nJ = (int)plain_jblocks(M, JB);
+      gv = (gptr<uint8_t>)pj.vals;
+      pre = as_const(pj.jprefix);
+      dec.J = -1;
+    }
+    const int64_t t = tg - jd.lo;  // tile within its job
     dec.find(pre, nJ, t);
     int i0, j0, k0;
     plain_tile_origin(dec, t, M, JB, i0, j0, k0);
 
     for (int cls = 0; cls < 2; ++cls) {
-      const int nch = (cls ? pj.Sb1 : pj.Sb0) / kPKC;
-      const int64_t cbase = (int64_t)cls * pj.Mp * 2;  // first row of this class
+      const int nch = (cls ? Sb1 : Sb0) / kPKC;
+      const int64_t cbase = (int64_t)cls * Mp * 2;  // first row of this class
       // staging plan: rows [0, 32) X_i (i0 + x / 2, plane x % 2), then 2 JB
       // rows X_j, then 2 KT rows X_k (k0 + x / 2, plane x % 2)
       // 32-bit byte offsets of this thread's 16-byte pieces (the value planes
@@ -273,7 +306,7 @@ __global__ void __launch_bounds__(256, 2) count_mfma_plain_kernel(
       // i8 = 2 u + g with cells (a, b) = w, for its column (k16, plane).
       // Record (i, j, k) of class cls is 16 bytes: plane-0 cells then plane-1
       // cells, each 4 x uint16 in (a, b) order.
-      uint2 *cor = reinterpret_cast<uint2 *>(pj.corners) + ((slot * 2 + cls) * (int64_t)kPI * 256) * 2;
+      uint2 *cor = reinterpret_cast<uint2 *>(corners) + ((slot * 2 + cls) * (int64_t)kPI * 256) * 2;
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -297,41 +330,74 @@ __global__ void __launch_bounds__(256, 2) count_mfma_plain_kernel(
 // are carried as 4 x count (byte offsets into the FP32 log-factorial table,
 // which sits at LDS address 0: the kernel declares no static LDS), so each
 // of the 81 lookups per triplet needs at most one add.
+// Lowest and highest key of the wave's lanes into keyrange[0..1].
+__device__ __forceinline__ void flush_range(uint32_t kmin, uint32_t kmax, uint32_t *keyrange) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const uint32_t a = __shfl_xor(kmin, off), b = __shfl_xor(kmax, off);
+    kmin = a < kmin ? a : kmin;
+    kmax = b > kmax ? b : kmax;
+  }
+  if ((threadIdx.x & 63) == 0 && kmax != 0u) {
+    atomicMin(keyrange, kmin);
+    atomicMax(keyrange + 1, kmax);
+  }
+}
+
 template <int JB, bool LDS, bool COUNTS>
-__global__ void __launch_bounds__(256) finish_plain_kernel(const PlainJob *__restrict__ pjp,
+__global__ void __launch_bounds__(256) finish_plain_kernel(const PlainJob *__restrict__ jobs,
+                                                           const int64_t *__restrict__ job_begin_p,
+                                                           int n_jobs,
+                                                           const uint4 *__restrict__ corners,
                                                            int64_t tile_begin, int64_t tile_end,
                                                            const float *__restrict__ lf32,
                                                            int lf_len) {
   constexpr int KT = 256 / JB;
   constexpr int kTile = kPI * JB * KT;  // 4096 triplets
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-  uint32_t *sRange = reinterpret_cast<uint32_t *>(lds + (LDS ? (lf_len * 4 + 15) / 16 * 16 : 0));
   if (LDS) {
     float *tab = reinterpret_cast<float *>(lds);
     for (int x = threadIdx.x; x < lf_len; x += blockDim.x) tab[x] = lf32[x];
   }
-  if (threadIdx.x == 0) {
-    sRange[0] = 0xffffffffu;
-    sRange[1] = 0u;
-  }
   __syncthreads();
-  const PlainJob pj = *pjp;
-  const int M = pj.M, Mp = pj.Mp;
-  const int nJ = (int)plain_jblocks(M, JB);
-  cptr<int64_t> pre = as_const(pj.jprefix);
   typedef int i4e __attribute__((ext_vector_type(4)));
   typedef unsigned u4e __attribute__((ext_vector_type(4)));
-  gptr<i4e> pr = (gptr<i4e>)pj.pairs;
-  const uint32_t MpMp = (uint32_t)Mp * (uint32_t)Mp;  // pair tables < 4 G entries
-  const int N0x4 = pj.N0 << 2, N1x4 = pj.N1 << 2;
+  cptr<int64_t> job_begin = as_const(job_begin_p);
+  JobDecoder jd;
+  int M = 0, Mp = 0, nJ = 0, N0x4 = 0, N1x4 = 0;
+  uint32_t MpMp = 0;  // pair tables < 4 G entries
+  cptr<int64_t> pre = nullptr;
+  gptr<i4e> pr = nullptr;
+  float *score = nullptr;
+  uint32_t *counts = nullptr, *keyrange = nullptr;
+  // key range of this thread's scores of the current job (flushed per job)
   uint32_t kmin = 0xffffffffu, kmax = 0u;
   TileDecoder dec;
-  for (int64_t t = tile_begin + blockIdx.x; t < tile_end; t += gridDim.x) {
+  for (int64_t tg = tile_begin + blockIdx.x; tg < tile_end; tg += gridDim.x) {
+    if (jd.find(job_begin, n_jobs, tg)) {
+      if (keyrange) flush_range(kmin, kmax, keyrange);
+      kmin = 0xffffffffu;
+      kmax = 0u;
+      const PlainJob &pj = jobs[jd.x];
+      M = pj.M;
+      Mp = pj.Mp;
+      nJ = (int)plain_jblocks(M, JB);
+      N0x4 = pj.N0 << 2;
+      N1x4 = pj.N1 << 2;
+      MpMp = (uint32_t)Mp * (uint32_t)Mp;
+      pre = as_const(pj.jprefix);
+      pr = (gptr<i4e>)pj.pairs;
+      score = pj.score;
+      counts = pj.counts;
+      keyrange = pj.keyrange;
+      dec.J = -1;
+    }
+    const int64_t t = tg - jd.lo;  // tile within its job
     dec.find(pre, nJ, t);
     int i0, j0, k0;
     plain_tile_origin(dec, t, M, JB, i0, j0, k0);
-    const int64_t slot = t - tile_begin;
-    gptr<u4e> cor = (gptr<u4e>)(pj.corners + slot * 2 * (int64_t)kTile);
+    const int64_t slot = tg - tile_begin;
+    gptr<u4e> cor = (gptr<u4e>)(corners + slot * 2 * (int64_t)kTile);
     for (int x = threadIdx.x; x < kTile; x += blockDim.x) {
       const int il = x / (JB * KT), jl = (x / KT) % JB, kl = x % KT;
       const int i = i0 + il, j = j0 + jl, k = k0 + kl;
@@ -367,9 +433,9 @@ __global__ void __launch_bounds__(256) finish_plain_kernel(const PlainJob *__res
           k2 += lf_at(lf32, b0 + b1 + 4) - (lf_at(lf32, b0) + lf_at(lf32, b1));
       }
       const int64_t rank = lex_base(M, i, j) + k;
-      pj.score[rank] = k2;
+      score[rank] = k2;
       if (COUNTS) {
-        uint32_t *o = pj.counts + rank * 54;
+        uint32_t *o = counts + rank * 54;
         for (int x2 = 0; x2 < 27; ++x2) {
           o[x2] = (uint32_t)tab[0][x2] >> 2;
           o[27 + x2] = (uint32_t)tab[1][x2] >> 2;
@@ -380,15 +446,7 @@ __global__ void __launch_bounds__(256) finish_plain_kernel(const PlainJob *__res
       kmax = key > kmax ? key : kmax;
     }
   }
-  if (kmax != 0u) {
-    atomicMin(&sRange[0], kmin);
-    atomicMax(&sRange[1], kmax);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0 && sRange[1] != 0u) {
-    atomicMin(pj.keyrange, sRange[0]);
-    atomicMax(pj.keyrange + 1, sRange[1]);
-  }
+  if (keyrange) flush_range(kmin, kmax, keyrange);
 }
 
 __global__ void write_plainjob_kernel(PlainJob h, PlainJob *dst) { if (threadIdx.x == 0) *dst = h; }
@@ -420,8 +478,9 @@ static hipError_t cu_count(int *n_cu) {
 }
 
 template <bool FP4, int JB>
-static hipError_t launch_plain_count_t(const PlainJob *pj_dev, int64_t tile_begin,
-                                       int64_t tile_end, unsigned long long *queue, hipStream_t s) {
+static hipError_t launch_plain_count_t(const PlainJob *jobs, const int64_t *job_begin, int n_jobs,
+                                       uint4 *corners, int64_t tile_begin, int64_t tile_end,
+                                       unsigned long long *queue, hipStream_t s) {
   const int64_t n = tile_end - tile_begin;
   if (n <= 0) return hipSuccess;
   int n_cu = 0;
@@ -434,36 +493,37 @@ static hipError_t launch_plain_count_t(const PlainJob *pj_dev, int64_t tile_begi
   int64_t blocks = (int64_t)n_cu * per_cu;
   if (blocks > n) blocks = n;
   hipLaunchKernelGGL((count_mfma_plain_kernel<FP4, JB>), dim3((unsigned)blocks), dim3(256), 0, s,
-                     pj_dev, tile_begin, tile_end, queue);
+                     jobs, job_begin, n_jobs, corners, tile_begin, tile_end, queue);
   return hipGetLastError();
 }
 
-hipError_t launch_count_mfma_plain(const PlainJob *pj_dev, int JB, bool fp4, int64_t tile_begin,
+hipError_t launch_count_mfma_plain(const PlainJob *jobs, const int64_t *job_begin, int32_t n_jobs,
+                                   int JB, bool fp4, uint4 *corners, int64_t tile_begin,
                                    int64_t tile_end, unsigned long long *queue, hipStream_t s) {
   switch (JB) {
     case 2:
-      return fp4 ? launch_plain_count_t<true, 2>(pj_dev, tile_begin, tile_end, queue, s)
-                 : launch_plain_count_t<false, 2>(pj_dev, tile_begin, tile_end, queue, s);
+      return fp4 ? launch_plain_count_t<true, 2>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, queue, s)
+                 : launch_plain_count_t<false, 2>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, queue, s);
     case 4:
-      return fp4 ? launch_plain_count_t<true, 4>(pj_dev, tile_begin, tile_end, queue, s)
-                 : launch_plain_count_t<false, 4>(pj_dev, tile_begin, tile_end, queue, s);
+      return fp4 ? launch_plain_count_t<true, 4>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, queue, s)
+                 : launch_plain_count_t<false, 4>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, queue, s);
     case 8:
-      return fp4 ? launch_plain_count_t<true, 8>(pj_dev, tile_begin, tile_end, queue, s)
-                 : launch_plain_count_t<false, 8>(pj_dev, tile_begin, tile_end, queue, s);
+      return fp4 ? launch_plain_count_t<true, 8>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, queue, s)
+                 : launch_plain_count_t<false, 8>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, queue, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <int JB, bool LDS, bool COUNTS>
-static hipError_t launch_finish_plain_t(const PlainJob *pj_dev, int64_t tile_begin,
-                                        int64_t tile_end, const float *lf32, int32_t lf_len,
-                                        hipStream_t s) {
+static hipError_t launch_finish_plain_t(const PlainJob *jobs, const int64_t *job_begin, int n_jobs,
+                                        const uint4 *corners, int64_t tile_begin, int64_t tile_end,
+                                        const float *lf32, int32_t lf_len, hipStream_t s) {
   const int64_t n = tile_end - tile_begin;
   if (n <= 0) return hipSuccess;
   int n_cu = 0;
   hipError_t e = cu_count(&n_cu);
   if (e != hipSuccess) return e;
-  const size_t lds = (LDS ? (size_t)(lf_len * 4 + 15) / 16 * 16 : 0) + 16;  // table + key range
+  const size_t lds = (LDS ? (size_t)(lf_len * 4 + 15) / 16 * 16 : 0) + 16;  // table
   e = hipFuncSetAttribute(reinterpret_cast<const void *>(&finish_plain_kernel<JB, LDS, COUNTS>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -475,32 +535,50 @@ static hipError_t launch_finish_plain_t(const PlainJob *pj_dev, int64_t tile_beg
   int64_t blocks = (int64_t)n_cu * per_cu;
   if (blocks > n) blocks = n;
   hipLaunchKernelGGL((finish_plain_kernel<JB, LDS, COUNTS>), dim3((unsigned)blocks), dim3(256), lds,
-                     s, pj_dev, tile_begin, tile_end, lf32, lf_len);
+                     s, jobs, job_begin, n_jobs, corners, tile_begin, tile_end, lf32, lf_len);
   return hipGetLastError();
 }
 
 template <int JB>
-static hipError_t launch_finish_plain_j(const PlainJob *pj_dev, int64_t tile_begin,
-                                        int64_t tile_end, const float *lf32, int32_t lf_len,
-                                        bool counts, hipStream_t s) {
+static hipError_t launch_finish_plain_j(const PlainJob *jobs, const int64_t *job_begin, int n_jobs,
+                                        const uint4 *corners, int64_t tile_begin, int64_t tile_end,
+                                        const float *lf32, int32_t lf_len, bool counts,
+                                        hipStream_t s) {
   if (counts)
     return lf_in_lds(lf_len)
-               ? launch_finish_plain_t<JB, true, true>(pj_dev, tile_begin, tile_end, lf32, lf_len, s)
-               : launch_finish_plain_t<JB, false, true>(pj_dev, tile_begin, tile_end, lf32, lf_len, s);
+               ? launch_finish_plain_t<JB, true, true>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, lf32, lf_len, s)
+               : launch_finish_plain_t<JB, false, true>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, lf32, lf_len, s);
   return lf_in_lds(lf_len)
-             ? launch_finish_plain_t<JB, true, false>(pj_dev, tile_begin, tile_end, lf32, lf_len, s)
-             : launch_finish_plain_t<JB, false, false>(pj_dev, tile_begin, tile_end, lf32, lf_len, s);
+             ? launch_finish_plain_t<JB, true, false>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, lf32, lf_len, s)
+             : launch_finish_plain_t<JB, false, false>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, lf32, lf_len, s);
 }
 
-hipError_t launch_finish_plain(const PlainJob *pj_dev, int JB, int64_t tile_begin,
-                               int64_t tile_end, const float *lf32, int32_t lf_len, bool counts,
-                               hipStream_t s) {
+hipError_t launch_finish_plain(const PlainJob *jobs, const int64_t *job_begin, int32_t n_jobs,
+                               int JB, const uint4 *corners, int64_t tile_begin, int64_t tile_end,
+                               const float *lf32, int32_t lf_len, bool counts, hipStream_t s) {
   switch (JB) {
-    case 2: return launch_finish_plain_j<2>(pj_dev, tile_begin, tile_end, lf32, lf_len, counts, s);
-    case 4: return launch_finish_plain_j<4>(pj_dev, tile_begin, tile_end, lf32, lf_len, counts, s);
-    case 8: return launch_finish_plain_j<8>(pj_dev, tile_begin, tile_end, lf32, lf_len, counts, s);
+    case 2: return launch_finish_plain_j<2>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, lf32, lf_len, counts, s);
+    case 4: return launch_finish_plain_j<4>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, lf32, lf_len, counts, s);
+    case 8: return launch_finish_plain_j<8>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, lf32, lf_len, counts, s);
   }
   return hipErrorInvalidValue;
+}
+
+struct I64Pack {
+  int64_t v[32];
+};
+__global__ void write_i64_kernel(I64Pack h, int n, int64_t *dst) {
+  if ((int)threadIdx.x < n) dst[threadIdx.x] = h.v[threadIdx.x];
+}
+
+hipError_t launch_write_i64(const int64_t *h, int32_t n, int64_t *dst_dev, hipStream_t s) {
+  for (int32_t base = 0; base < n; base += 32) {
+    I64Pack pk{};
+    const int m = n - base < 32 ? n - base : 32;
+    for (int x = 0; x < m; ++x) pk.v[x] = h[base + x];
+    hipLaunchKernelGGL(write_i64_kernel, dim3(1), dim3(64), 0, s, pk, m, dst_dev + base);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace epi3

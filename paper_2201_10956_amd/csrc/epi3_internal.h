@@ -121,8 +121,27 @@ struct PermJob {
   int32_t M, Mp, S, N, Q, Qp;  // S: bytes per staged row (samples for bytes, samples / 2 for nibbles)
 };
 
+// Where the phenotype-batch finish kernel puts its FP32 scores.
+enum { kPermOutPlane = 0, kPermOutSample = 1, kPermOutBounded = 2 };
+struct PermOut {
+  int32_t mode;          // kPermOut*
+  int32_t pad;
+  // sample: the launch's tiles are sample tiles sample_base + n; the score of
+  // slot s (= 16 wave + kk) of sample tile m of phenotype q goes to
+  // sample[q * sample_T + 64 m + s] (invalid slots keep what the buffer held)
+  float *sample;
+  int64_t sample_T;
+  int64_t sample_base;
+  // bounded: phenotype q appends (key, rank) of every score <= st[q].ub to
+  // ckey / crank [q * ccap + pos], pos from st[q].cn
+  uint32_t *ckey;
+  int64_t *crank;
+  int64_t ccap;
+};
+
 // Plain two-class scan on the matrix cores: one SPLIT data set, counted in
-// passes of tiles whose corner cells go through a scratch buffer.
+// passes of tiles whose corner cells go through a scratch buffer
+// ([pass tile][class][16 i][JB j][256 / JB k] 8 x uint16 cells).
 struct PlainJob {
   const uint8_t *vals;     // [2][Mp][2][Sb] 0/1 values per class (bytes, or E2M1 nibbles)
   const int32_t *pairs;    // [2][Mp][Mp][4]
@@ -130,7 +149,6 @@ struct PlainJob {
   uint32_t *counts;        // optional [T][2][27]
   uint32_t *keyrange;      // [2] atomic min / max of f2key(score)
   const int64_t *jprefix;  // [M + 1] tiles before pivot j
-  uint4 *corners;          // scratch: [pass tile][class][16 i][JB j][256 / JB k] 8 x uint16 cells
   int64_t n_tiles, T;
   int32_t M, Mp, Sb, Sb0, Sb1, N0, N1, JB;  // Sb: bytes per row; Sb0 / Sb1: bytes holding each class
 };
@@ -142,6 +160,7 @@ struct SelJob {
   SelState *st;
   uint32_t *hist;          // [kHistBins]
   int64_t *cand;           // [cap] ranks
+  uint32_t *candkey;       // [cap] their FP32 score keys
   CandRec *rec;            // [cap]
   epi3_hit *hits;          // [k]
   int64_t cap;
@@ -161,7 +180,8 @@ struct SelJob {
   int32_t M, Mp, W0, W1, N0, N1;
   int32_t layout;
   int32_t k;
-  int32_t sample;          // 1: the first bound comes from a radix select on a sample (sample_select)
+  int32_t sample;          // 1: the first bound comes from a radix select on a sample (sample_select),
+                           // or (score == NULL) from the batch's sample pass with the list already built
   int32_t order;           // 2: pairs (9-row tables, pair_hits); 4: quads (81 rows, quad_hits);
                            // else triplets
   epi3_pair_hit *pair_hits;  // [k] (order 2)
@@ -467,6 +487,13 @@ hipError_t launch_count_valu(const Job *jobs_dev, int32_t n_jobs, int64_t total_
 hipError_t launch_select(SelJob *sel_dev, int32_t n_jobs, int64_t max_T, int64_t max_cap,
                          int32_t max_k, bool sampled, hipStream_t s);
 hipError_t launch_write_seljobs(const SelJob *h, int32_t n, SelJob *dst_dev, hipStream_t s);
+// The k-th smallest key of each job's plane only (st->kth, done = 1; jobs
+// with fewer than k keys in their key range end with done = 0).
+hipError_t launch_select_kth(SelJob *sel_dev, int32_t n_jobs, int64_t max_T, hipStream_t s);
+// After a sample pass: main job x's compacted list bound = the sample's k-th
+// score + 2 e(N) (rounded up; +inf if the sample had no k-th score), empty list.
+hipError_t launch_sample_bound(SelJob *main_dev, const SelJob *sample_dev, int32_t n_jobs,
+                               hipStream_t s);
 hipError_t launch_init_select(SelJob *sel_dev, int32_t n_jobs, hipStream_t s);
 hipError_t launch_score_triplets(const epi3_dataset &d, const uint32_t *ijk, int64_t n,
                                  uint32_t *counts, float *k2f, double *k2, hipStream_t s);
@@ -488,10 +515,16 @@ inline int64_t quad_triplet_table_bytes(int64_t M) { return 2 * 16 * (M < 3 ? 0 
 hipError_t launch_quad_scores(const epi3_dataset &d, void *t3, float *score, uint32_t *keyrange,
                               hipStream_t s);
 int64_t host_perm_tiles(int64_t M);
-hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,
-                                  unsigned long long *queue, bool fp4, hipStream_t s);
-hipError_t launch_finish_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t tile_end,
-                              SelState *st, const float *lf32, int32_t lf_len, hipStream_t s);
+// Count / finish the tiles tile_begin + n * stride, n in [0, n_tiles); their
+// corner cells go to scratch slot n.
+hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t n_tiles,
+                                  int64_t stride, unsigned long long *queue, bool fp4,
+                                  hipStream_t s);
+hipError_t launch_finish_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t n_tiles,
+                              int64_t stride, SelState *st, const float *lf32, int32_t lf_len,
+                              const PermOut &out, hipStream_t s);
+// Triplets (i < j < k < M) in the phenotype-batch tiles 0, stride, 2 stride, ...
+int64_t host_perm_sample_valid(int64_t M, int64_t stride);
 constexpr int64_t kPermTileScratch = 64 * 64 * 16 + 64 * 16;  // bytes per tile (corners + totals)
 hipError_t launch_write_permjob(const PermJob &h, PermJob *dst_dev, hipStream_t s);
 hipError_t launch_write_ptrs(const uint32_t *const *h, int32_t n, const uint32_t **dst_dev,
@@ -502,11 +535,17 @@ constexpr int kPlainI = 16;  // pivots i per plain matrix-core tile (x JB j x 25
 constexpr int64_t kPlainTileScratch = 2ll * kPlainI * 256 * 16;  // bytes per tile, both classes
 hipError_t launch_write_plainjob(const PlainJob &h, PlainJob *dst_dev, hipStream_t s);
 hipError_t launch_plain_prefix(PlainJob *pj_dev, hipStream_t s);
-hipError_t launch_count_mfma_plain(const PlainJob *pj_dev, int JB, bool fp4, int64_t tile_begin,
+// Plain matrix-core count / finish of global tiles [tile_begin, tile_end) of
+// n_jobs data sets (same JB and operand type): job x owns global tiles
+// job_begin[x] .. job_begin[x + 1] (device int64 [n_jobs + 1]); tile t's
+// corner cells sit in scratch slot t - tile_begin of `corners`.
+hipError_t launch_count_mfma_plain(const PlainJob *jobs, const int64_t *job_begin, int32_t n_jobs,
+                                   int JB, bool fp4, uint4 *corners, int64_t tile_begin,
                                    int64_t tile_end, unsigned long long *queue, hipStream_t s);
-hipError_t launch_finish_plain(const PlainJob *pj_dev, int JB, int64_t tile_begin,
-                               int64_t tile_end, const float *lf32, int32_t lf_len, bool counts,
-                               hipStream_t s);
+hipError_t launch_finish_plain(const PlainJob *jobs, const int64_t *job_begin, int32_t n_jobs,
+                               int JB, const uint4 *corners, int64_t tile_begin, int64_t tile_end,
+                               const float *lf32, int32_t lf_len, bool counts, hipStream_t s);
+hipError_t launch_write_i64(const int64_t *h, int32_t n, int64_t *dst_dev, hipStream_t s);
 
 int tile_P_default(int32_t M, int32_t N);
 

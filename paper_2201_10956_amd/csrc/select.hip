@@ -59,6 +59,12 @@ __global__ void window_kernel(SelJob *sj, int n) {
     st->done = 2u;  // nothing to select
     return;
   }
+  if (!sj[x].score && !(st->cmode == 1u && st->cn <= (unsigned long long)sj[x].ccap)) {
+    // no plane to fall back on: the bounded list overflowed (reported as a
+    // capacity error; every later kernel skips the job)
+    st->done = 3u;
+    return;
+  }
   const uint32_t range = st->kmax - st->kmin;
   st->lo = st->kmin;
   st->krem = (uint64_t)st->keff;
@@ -274,7 +280,10 @@ __global__ void __launch_bounds__(256) collect_kernel(const SelJob *__restrict__
     if (lane == 0) pos0 = atomicAdd(&st->ncand, (unsigned long long)__popcll(m));
     pos0 = __shfl(pos0, 0);
     const unsigned long long pos = pos0 + __popcll(m & ((1ull << lane) - 1ull));
-    if (pred && (int64_t)pos < cap) J.cand[pos] = compact ? J.crank[x] : x;
+    if (pred && (int64_t)pos < cap) {
+      J.cand[pos] = compact ? J.crank[x] : x;
+      J.candkey[pos] = compact ? J.ckey[x] : f2key(score[x]);
+    }
   }
 }
 
@@ -452,7 +461,7 @@ __global__ void __launch_bounds__(256) rescore_kernel(const SelJob *__restrict__
         R.key = (uint64_t)__double_as_longlong(k2);
         R.rank = rank;
         R.i = i; R.j = j; R.k = k; R.l = l;
-        R.k2f = J.score[rank];
+        R.k2f = key2f(J.candkey[c]);
         R.k2 = k2;
         for (int x = 0; x < 81; ++x) {
           R.counts[x] = (uint32_t)q[0][x];
@@ -471,7 +480,7 @@ __global__ void __launch_bounds__(256) rescore_kernel(const SelJob *__restrict__
         R.key = (uint64_t)__double_as_longlong(k2);
         R.rank = rank;
         R.i = i; R.j = j; R.k = 0;
-        R.k2f = J.score[rank];
+        R.k2f = key2f(J.candkey[c]);
         R.k2 = k2;
         for (int x = 0; x < 9; ++x) {
           R.counts[x] = (uint32_t)tab[0][x];
@@ -495,7 +504,7 @@ __global__ void __launch_bounds__(256) rescore_kernel(const SelJob *__restrict__
       R.key = (uint64_t)__double_as_longlong(k2);
       R.rank = rank;
       R.i = i; R.j = j; R.k = k;
-      R.k2f = J.score[rank];
+      R.k2f = key2f(J.candkey[c]);
       R.k2 = k2;
       for (int x = 0; x < 27; ++x) {
         R.counts[x] = (uint32_t)tab[0][x];
@@ -597,6 +606,49 @@ hipError_t launch_write_seljobs(const SelJob *h, int32_t n, SelJob *dst_dev, hip
 hipError_t launch_init_select(SelJob *sel_dev, int32_t n_jobs, hipStream_t s) {
   hipLaunchKernelGGL(init_select_kernel, dim3((n_jobs + 63) / 64), dim3(64), 0, s, sel_dev,
                      n_jobs);
+  return hipGetLastError();
+}
+
+// After a batch's sample pass (see launch_sample_bound in the header).
+__global__ void sample_bound_kernel(SelJob *main, const SelJob *smp, int n) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  SelState *st = main[x].st;
+  const SelState *ss = smp[x].st;
+  float ub = __builtin_inff();
+  uint32_t whi = 0xffffffffu;
+  if (ss->done == 1u) {
+    // the sample's k smallest are k scores of the whole set, so its k-th
+    // smallest is at least the whole set's: every member of the FP64 top-k
+    // has an FP32 score <= that + 2 e(N)
+    const double u = (double)key2f(ss->kth) + main[x].err2;
+    ub = (float)u;
+    if ((double)ub < u) ub = __uint_as_float(__float_as_uint(ub) + 1u);  // ub >= 0: next float up
+    whi = ss->kth;
+  }
+  st->ub = ub;
+  st->whi = whi;
+  st->cmode = 1u;
+  st->cn = 0ull;
+}
+
+hipError_t launch_sample_bound(SelJob *main_dev, const SelJob *sample_dev, int32_t n_jobs,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(sample_bound_kernel, dim3((n_jobs + 63) / 64), dim3(64), 0, s, main_dev,
+                     sample_dev, n_jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_kth(SelJob *sel_dev, int32_t n_jobs, int64_t max_T, hipStream_t s) {
+  const unsigned nj = (unsigned)n_jobs;
+  hipLaunchKernelGGL(window_kernel, dim3((n_jobs + 63) / 64), dim3(64), 0, s, sel_dev, n_jobs);
+  int64_t hb = (max_T + 256 * 16 - 1) / (256 * 16);
+  if (hb > 2048) hb = 2048;
+  if (hb < 1) hb = 1;
+  for (int p = 0; p < kHistPasses; ++p) {
+    hipLaunchKernelGGL(hist_kernel, dim3((unsigned)hb, nj), dim3(256), 0, s, sel_dev, 0);
+    hipLaunchKernelGGL(find_kernel, dim3(nj), dim3(1024), 0, s, sel_dev, 0);
+  }
   return hipGetLastError();
 }
 

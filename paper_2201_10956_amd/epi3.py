@@ -100,6 +100,9 @@ def _load():
         "epi3_scan_batched": (ctypes.c_int, [P(CJob), i32, i32, i64, vp, i64, vp, vp, vp]),
         "epi3_batched_score_plane": (ctypes.c_int, [P(CJob), i32, i32, i64, vp, i32, P(vp)]),
         "epi3_init": (ctypes.c_int, []),
+        "epi3_batched_bound_list": (ctypes.c_int, [P(CJob), i32, i32, i64, vp, i32, P(vp), P(vp),
+                                                   P(i64), P(ctypes.c_float), vp]),
+        "epi3_set_batch_select": (ctypes.c_int, [i32]),
         "epi3_scan_tables": (ctypes.c_int, [P(CDataset), i32, vp, vp, vp, i64, vp]),
         "epi3_score_triplets": (ctypes.c_int, [P(CDataset), vp, i64, vp, vp, vp, vp]),
         "epi3_score_plane": (ctypes.c_int, [P(CDataset), i32, i64, vp, P(vp)]),
@@ -139,7 +142,8 @@ def _load():
 _lib = _load()
 EXPORTS = ("epi3_encode_bytes", "epi3_encode", "epi3_workspace_bytes", "epi3_scan", "epi3_topk",
            "epi3_batched_workspace_bytes", "epi3_scan_batched", "epi3_batched_score_plane",
-           "epi3_init", "epi3_scan_tables",
+           "epi3_init", "epi3_scan_tables", "epi3_batched_bound_list",
+           "epi3_set_batch_select",
            "epi3_score_triplets", "epi3_score_plane", "epi3_k2_error_bound", "epi3_n_triplets", "epi3_release",
            "epi3_version", "epi3_timing_enable", "epi3_timing_query", "epi3_timing_reset",
            "epi3_tile_rule", "epi3_tile_rules_clear", "epi3_tile_for", "epi3_set_pass_bytes",
@@ -218,6 +222,15 @@ def tile_for(ds: "Dataset", variant: str):
 def set_pass_bytes(nbytes: int) -> None:
     """Scratch bytes per pass buffer of the matrix-core paths (0: default)."""
     _check(_lib.epi3_set_pass_bytes(int(nbytes)), "epi3_set_pass_bytes")
+
+
+BATCH_SELECT = {"auto": 0, "plane": 1, "bounded": 2}
+
+
+def set_batch_select(mode: str) -> None:
+    """How phenotype batches select: "auto", "plane" (score plane per job) or
+    "bounded" (sample pass + bounded list, no plane)."""
+    _check(_lib.epi3_set_batch_select(BATCH_SELECT[mode]), "epi3_set_batch_select")
 
 
 def set_compact_cap(n: int) -> None:
@@ -575,6 +588,24 @@ class BatchScanner:
             out.append(allh[off: off + int(self.n_out[x])].copy())
             off += kk
         return out
+
+    def bound_list(self, job: int, stream=None):
+        """(FP32 scores, lexicographic ranks, bound) of job `job`'s list in a
+        batch selected by bound, as numpy arrays in list order."""
+        torch = _torch()
+        kp, rp = ctypes.c_void_p(0), ctypes.c_void_p(0)
+        n, b = ctypes.c_int64(0), ctypes.c_float(0.0)
+        rc = _lib.epi3_batched_bound_list(self.jobs, len(self.jobs), self.variant, self.cand_cap,
+                                          ctypes.c_void_p(self.ws.data_ptr()), int(job),
+                                          ctypes.byref(kp), ctypes.byref(rp), ctypes.byref(n),
+                                          ctypes.byref(b), _stream(stream))
+        _check(rc, "epi3_batched_bound_list")
+        base = self.ws.data_ptr()
+        ko, ro, cnt = (kp.value or base) - base, (rp.value or base) - base, int(n.value)
+        keys = self.ws[ko: ko + 4 * cnt].view(torch.int32).cpu().numpy().view(np.uint32)
+        ranks = self.ws[ro: ro + 8 * cnt].view(torch.int64).cpu().numpy()
+        scores = (keys & np.uint32(0x7fffffff)).view(np.float32)
+        return scores, ranks, float(b.value)
 
     def score_plane(self, job: int):
         """FP32 K2 of every triplet of job `job` (lexicographic order): a torch

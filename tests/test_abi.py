@@ -241,3 +241,32 @@ def test_phenotype_batches_limit_sample_count(epi3):
             jobs[q].k = 5
         r = lib.epi3_batched_workspace_bytes(jobs, 2, epi3.VARIANT_MFMA_FP4, 0)
         assert (r > 0) if want_ok else (r == epi3.E_UNSUPPORTED), r
+
+
+def test_bounded_batches_need_no_plane(epi3):
+    """A phenotype batch of 1024 SNPs x 8192 samples x 64 masks: selected by
+    bound (the default at this size) its workspace does not hold the
+    64 x C(1024,3) score plane that plane selection needs; invalid modes are
+    refused."""
+    lib = epi3._lib
+    d = _fake_dataset(epi3, 1024, 8192, 0, layout=1)
+    d.byte_stride = 8192
+    jobs = (epi3.CJob * 64)()
+    for q in range(64):
+        jobs[q].d = ctypes.pointer(d)
+        jobs[q].case_mask = ctypes.c_void_p(4096)
+        jobs[q].k = 10
+    T = math.comb(1024, 3)
+    try:
+        auto = lib.epi3_batched_workspace_bytes(jobs, 64, epi3.VARIANT_MFMA_FP4, 0)
+        epi3.set_batch_select("plane")
+        plane = lib.epi3_batched_workspace_bytes(jobs, 64, epi3.VARIANT_MFMA_FP4, 0)
+        epi3.set_batch_select("bounded")
+        bounded = lib.epi3_batched_workspace_bytes(jobs, 64, epi3.VARIANT_MFMA_FP4, 0)
+    finally:
+        epi3.set_batch_select("auto")
+    assert auto == bounded
+    assert plane - bounded > 64 * T * 4 * 0.99
+    assert bounded < 10 * (1 << 30)  # the pass scratch (2 x 4 GiB) dominates
+    assert lib.epi3_set_batch_select(3) == epi3.E_INVALID
+    assert lib.epi3_set_batch_select(-1) == epi3.E_INVALID

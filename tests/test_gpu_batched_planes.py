@@ -52,11 +52,13 @@ def test_perm_score_block_every_score(env, M, N, Q, pass_tiles, variant):
     ds = epi3.encode(g, d.pheno, layout="masked")
     try:
         epi3.set_pass_bytes(pass_tiles * TILE_SCRATCH)
+        epi3.set_batch_select("plane")
         bs = epi3.BatchScanner(ds, 5, masks=_masks(epi3, perms), variant=variant)
         res = bs.run()
         planes = [bs.score_plane(q).clone() for q in range(Q)]
     finally:
         epi3.set_pass_bytes(0)
+        epi3.set_batch_select("auto")
     worst = 0.0
     for q in range(Q):
         ref = _valu_plane(epi3, g, perms[q])
@@ -71,7 +73,8 @@ def test_perm_score_block_every_score(env, M, N, Q, pass_tiles, variant):
 
 @pytest.mark.parametrize("variant", ["mfma_fp4", "mfma"])
 def test_cfg4_score_block_full_size(env, variant):
-    """1024 SNPs x 8192 samples x 64 phenotypes with the score plane kept:
+    """1024 SNPs x 8192 samples x 64 phenotypes with the score plane kept
+    (the default for this size selects by bound and keeps none):
     every phenotype's whole FP32 plane equals its vector-ALU plain scan's bit
     for bit, 10^4 sampled ranks per phenotype equal the oracle's FP64 K2
     within e(N), and each top-10 equals the stored oracle result."""
@@ -81,12 +84,17 @@ def test_cfg4_score_block_full_size(env, variant):
     d, perms = make_config(4)
     g = to_dev(d.geno)
     ds = epi3.encode(g, d.pheno, layout="masked")
-    bs = epi3.BatchScanner(ds, c["k"], masks=_masks(epi3, perms), variant=variant)
-    res = bs.run()
+    try:
+        epi3.set_batch_select("plane")  # kept while the planes are read
+        bs = epi3.BatchScanner(ds, c["k"], masks=_masks(epi3, perms), variant=variant)
+        res = bs.run()
+        planes = [bs.score_plane(q) for q in range(c["n_perm"])]
+    finally:
+        epi3.set_batch_select("auto")
     T = epi3.n_triplets(d.n_snps)
     worst_abs = worst_rel = 0.0
     for q in range(c["n_perm"]):
-        plane = bs.score_plane(q)
+        plane = planes[q]
         assert torch.equal(plane, _valu_plane(epi3, g, perms[q])), q
         ranks = np.unique((SplitMix64(4000 + q, 0).uniform(0, 10000) * T).astype(np.int64))
         _, rk = oracle.score_list(d.geno, perms[q], lex_unrank(d.n_snps, ranks))
