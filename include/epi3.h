@@ -190,6 +190,36 @@ int epi3_score_plane(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *w
                      float **plane_dev);
 
 /* ---------------------------------------------------------------------------
+ * Allocation-free plain scan, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Not a step of the paper's method: the same vector-ALU count
+ * kernel and selection as epi3_scan + epi3_topk with EPI3_VARIANT_VALU, whose
+ * workspace is a device array of EPI3_STATIC_SCRATCH_BYTES inside the library
+ * instead of a caller buffer (each GPU the library runs on holds its own copy
+ * from the first call on it, or from epi3_init, until the process ends).
+ * ------------------------------------------------------------------------ */
+
+/* Size of the library's static workspace: the FP32 score plane of the data
+ * set (4 C(M,3) bytes) plus about 1 MB of selection buffers must fit, so M is
+ * limited to about 580 SNPs (C(M,3) up to about 33 million triplets). */
+#define EPI3_STATIC_SCRATCH_BYTES (128ll << 20)
+
+/* epi3_scan + epi3_topk (variant EPI3_VARIANT_VALU, default candidate
+ * capacity) with the static workspace: copies min(k, C(M,3)) hits to
+ * hits_host [k] and their number to *n_out; synchronises `stream`.  Calls no
+ * device or host allocator.  Returns EPI3_E_WORKSPACE (nothing enqueued) when
+ * epi3_workspace_bytes(d, k, EPI3_VARIANT_VALU, 0) exceeds
+ * EPI3_STATIC_SCRATCH_BYTES, EPI3_E_CAPACITY when more candidates pass the
+ * FP32 screen than the default capacity holds (*n_out = candidates needed;
+ * use epi3_scan with a larger cand_cap), and the other codes of epi3_scan /
+ * epi3_topk.  Every call on one GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (two host threads, or two streams) race and
+ * must not be made; each call initialises every part of the array it reads,
+ * so what a previous call left there does not matter. */
+int epi3_scan_topk_static(const epi3_dataset *d, int32_t k, epi3_hit *hits_host,
+                          int32_t *n_out, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Batched scans in one persistent launch, captured into a HIP graph that is
  * cached per job signature (released by epi3_release).  Not in the paper,
  * which scans one data set per run.
@@ -368,8 +398,9 @@ int64_t epi3_n_triplets(int32_t n_snps);
 
 /* Optional set-up on the current device: creates the library's second
  * stream and events of the matrix-core paths and the stream batched scans
- * are captured on, which the first call that needs them would otherwise
- * create.  Returns EPI3_E_HIP if the runtime refuses. */
+ * are captured on, and looks up the device address of the static workspace
+ * of epi3_scan_topk_static, which the first call that needs them would
+ * otherwise do.  Returns EPI3_E_HIP if the runtime refuses. */
 int epi3_init(void);
 
 /* Release cached graphs and the library's idle streams and events.  Must not

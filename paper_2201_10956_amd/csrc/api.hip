@@ -1555,6 +1555,10 @@ int epi3_init(void) {
     AuxLease lease;  // one idle context in the pool from now on
     if (lease.rc != EPI3_OK) return lease.rc;
   }
+  {
+    const int rc = static_scratch_ptr(nullptr);  // epi3_scan_topk_static's workspace
+    if (rc != EPI3_OK) return rc;
+  }
   GraphCache &G = graphs();
   std::lock_guard<std::mutex> lk(G.mu);
   if (!G.capture) HIP_OK(hipStreamCreateWithFlags(&G.capture, hipStreamNonBlocking));

@@ -549,4 +549,8 @@ hipError_t launch_write_i64(const int64_t *h, int32_t n, int64_t *dst_dev, hipSt
 
 int tile_P_default(int32_t M, int32_t N);
 
+// Device address of the current device's copy of the static scan workspace
+// (looked up once per device; out may be NULL to only set it up).
+int static_scratch_ptr(void **out);
+
 }  // namespace epi3

@@ -100,6 +100,7 @@ def _load():
         "epi3_scan_batched": (ctypes.c_int, [P(CJob), i32, i32, i64, vp, i64, vp, vp, vp]),
         "epi3_batched_score_plane": (ctypes.c_int, [P(CJob), i32, i32, i64, vp, i32, P(vp)]),
         "epi3_init": (ctypes.c_int, []),
+        "epi3_scan_topk_static": (ctypes.c_int, [P(CDataset), i32, vp, P(i32), vp]),
         "epi3_batched_bound_list": (ctypes.c_int, [P(CJob), i32, i32, i64, vp, i32, P(vp), P(vp),
                                                    P(i64), P(ctypes.c_float), vp]),
         "epi3_set_batch_select": (ctypes.c_int, [i32]),
@@ -142,7 +143,7 @@ def _load():
 _lib = _load()
 EXPORTS = ("epi3_encode_bytes", "epi3_encode", "epi3_workspace_bytes", "epi3_scan", "epi3_topk",
            "epi3_batched_workspace_bytes", "epi3_scan_batched", "epi3_batched_score_plane",
-           "epi3_init", "epi3_scan_tables", "epi3_batched_bound_list",
+           "epi3_init", "epi3_scan_topk_static", "epi3_scan_tables", "epi3_batched_bound_list",
            "epi3_set_batch_select",
            "epi3_score_triplets", "epi3_score_plane", "epi3_k2_error_bound", "epi3_n_triplets", "epi3_release",
            "epi3_version", "epi3_timing_enable", "epi3_timing_query", "epi3_timing_reset",
@@ -474,6 +475,21 @@ def scan_pairs(ds: Dataset, k: int, cand_cap: int = 0, stream=None) -> np.ndarra
 
 def scan_topk(ds: Dataset, k: int, variant: str = "auto", cand_cap: int = 0, stream=None):
     return Scanner(ds, k, variant, cand_cap).run(stream)
+
+
+STATIC_SCRATCH_BYTES = 128 << 20  # EPI3_STATIC_SCRATCH_BYTES
+
+
+def scan_topk_static(ds: Dataset, k: int, stream=None) -> np.ndarray:
+    """Plain vector-ALU scan + top-k in the library's static workspace
+    (epi3_scan_topk_static: no device buffer is allocated for the call)."""
+    hits = (CHit * max(int(k), 1))()
+    n = ctypes.c_int32(0)
+    rc = _lib.epi3_scan_topk_static(ctypes.byref(ds.c), int(k), ctypes.cast(hits, ctypes.c_void_p),
+                                    ctypes.byref(n), _stream(stream))
+    _check(rc, "epi3_scan_topk_static")
+    raw = np.frombuffer(hits, dtype=HIT_DTYPE, count=len(hits))
+    return raw[:n.value].copy()
 
 
 def scan_tables(ds: Dataset, variant: str = "auto", counts: bool = True, stream=None):

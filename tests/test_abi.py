@@ -270,3 +270,25 @@ def test_bounded_batches_need_no_plane(epi3):
     assert bounded < 10 * (1 << 30)  # the pass scratch (2 x 4 GiB) dominates
     assert lib.epi3_set_batch_select(3) == epi3.E_INVALID
     assert lib.epi3_set_batch_select(-1) == epi3.E_INVALID
+
+
+def test_static_scan_refuses_what_does_not_fit(epi3):
+    """epi3_scan_topk_static checks its sizes on the host before it touches a
+    device: the score plane of 700 SNPs (57 M triplets) exceeds the static
+    workspace; 580 SNPs fit; bad arguments are refused."""
+    lib = epi3._lib
+    hits = (epi3.CHit * 10)()
+    n = ctypes.c_int32(0)
+    big = _fake_dataset(epi3, 700, 200, 200)
+    rc = lib.epi3_scan_topk_static(ctypes.byref(big), 10, ctypes.cast(hits, ctypes.c_void_p),
+                                   ctypes.byref(n), None)
+    assert rc == epi3.E_WORKSPACE
+    fits = _fake_dataset(epi3, 580, 200, 200)
+    assert 0 < lib.epi3_workspace_bytes(ctypes.byref(fits), 10, epi3.VARIANT_VALU, 0) \
+        <= epi3.STATIC_SCRATCH_BYTES
+    assert lib.epi3_scan_topk_static(ctypes.byref(big), 0, ctypes.cast(hits, ctypes.c_void_p),
+                                     ctypes.byref(n), None) == epi3.E_INVALID
+    assert lib.epi3_scan_topk_static(ctypes.byref(big), 10, None, ctypes.byref(n), None) == \
+        epi3.E_INVALID
+    assert "#define EPI3_STATIC_SCRATCH_BYTES (128ll << 20)" in open(HEADER).read()
+    assert epi3.STATIC_SCRATCH_BYTES == 128 << 20
