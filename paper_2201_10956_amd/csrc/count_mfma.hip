@@ -231,18 +231,6 @@ __device__ __forceinline__ v4i quad_bcast(v4i x) {
   return y;
 }
 
-// One 32-sample (int8) or 64-sample (FP4) step of row tile TT: A rows
-// X_i[a] & X_j[b] & X_k[c] for the tile's 4 triplets, the all-sample count of
-// each row, and the products with both 32-phenotype column tiles.
-template <int TT, typename Acc>
-__device__ __forceinline__ void perm_step_t(v4i p, v4i x, v4i b0, v4i b1, uint32_t &tot,
-                                            typename Acc::type (&acc)[2]) {
-  const v4i a = p & quad_bcast<TT>(x);
-  tot = popc4_acc(a, tot);
-  acc[0] = Acc::mma(a, b0, acc[0]);
-  acc[1] = Acc::mma(a, b1, acc[1]);
-}
-
 template <bool FP4>
 __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
     const PermJob *__restrict__ pjp, int64_t tile_begin, int64_t n_tiles, int64_t stride,
@@ -363,24 +351,84 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
     __syncthreads();
     const int prow = kRowsPH + kRowsXK + wave * 4 + (ra * 2 + rb);
     const int xrow = kRowsPH + (4 * (r & 3) + ta) * 2 + rc;  // k row of row tile r % 4
-    for (int ch = 0; ch < nch; ++ch) {
-      if (ch + 1 < nch) fetch(ch + 1);
-      const uint8_t *buf = stage + (ch & 1) * kStageBytes;
-#pragma unroll 1  // one step at a time keeps the operands of a single step live (no spills)
-      for (int stp = 0; stp < kKC / 32; ++stp) {
-        const int off = stp * 32 + 16 * g;
-        const v4i p = *reinterpret_cast<const v4i *>(buf + prow * kRow + off);
-        const v4i x = *reinterpret_cast<const v4i *>(buf + xrow * kRow + off);
-        const v4i b0 = *reinterpret_cast<const v4i *>(buf + r * kRow + off);
-        const v4i b1 = *reinterpret_cast<const v4i *>(buf + (32 + r) * kRow + off);
-        perm_step_t<0, Acc>(p, x, b0, b1, tot[0], acc[0]);
-        perm_step_t<1, Acc>(p, x, b0, b1, tot[1], acc[1]);
-        perm_step_t<2, Acc>(p, x, b0, b1, tot[2], acc[2]);
-        perm_step_t<3, Acc>(p, x, b0, b1, tot[3], acc[3]);
-      }
-      if (ch + 1 < nch) store((ch + 1) & 1);
-      __syncthreads();
+    // Software pipeline over the steps of a chunk: while the matrix products
+    // of step s run, the operands of step s + 1 are read from LDS (two
+    // register sets, X and Y, taken in turn), and each row tile's A rows are
+    // formed between the products of the previous row tile.  The next chunk
+    // is stored to the other LDS buffer before the last step of a chunk and
+    // one barrier follows, so the last step already reads the first operands
+    // of the next chunk and the pipeline does not drain between chunks.
+    static_assert(kKC / 32 == 4, "four steps per chunk");
+    const int o_p = prow * kRow + 16 * g, o_x = xrow * kRow + 16 * g;
+    const int o_b0 = r * kRow + 16 * g, o_b1 = (32 + r) * kRow + 16 * g;
+#define EPI3_LD(BB, STP, P, X, B0, B1)                                              \
+    P = *reinterpret_cast<const v4i *>((BB) + o_p + 32 * (STP));                  \
+    X = *reinterpret_cast<const v4i *>((BB) + o_x + 32 * (STP));                  \
+    B0 = *reinterpret_cast<const v4i *>((BB) + o_b0 + 32 * (STP));                \
+    B1 = *reinterpret_cast<const v4i *>((BB) + o_b1 + 32 * (STP));
+#define EPI3_TILE(TT, P, X, B0, B1)                                                 \
+    {                                                                             \
+      const v4i a_ = (P) & quad_bcast<TT>(X);                                     \
+      acc[TT][0] = Acc::mma(a_, B0, acc[TT][0]);                                  \
+      acc[TT][1] = Acc::mma(a_, B1, acc[TT][1]);                                  \
+      tot[TT] = popc4_acc(a_, tot[TT]);                                           \
     }
+#define EPI3_SCHED                                                                  \
+    __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);                            \
+    __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);                            \
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
+    __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);                            \
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
+    __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);                            \
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
+    __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);                            \
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
+    __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);                            \
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
+    __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);                            \
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
+    __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);                            \
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
+    __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);                            \
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
+    __builtin_amdgcn_sched_barrier(0);
+#define EPI3_STEP(P, X, B0, B1)                                                     \
+    EPI3_TILE(0, P, X, B0, B1)                                                    \
+    EPI3_TILE(1, P, X, B0, B1)                                                    \
+    EPI3_TILE(2, P, X, B0, B1)                                                    \
+    EPI3_TILE(3, P, X, B0, B1)
+    v4i pX, xX, b0X, b1X, pY, xY, b0Y, b1Y;
+    EPI3_LD(stage, 0, pX, xX, b0X, b1X)
+    for (int ch = 0; ch < nch; ++ch) {
+      const bool more = ch + 1 < nch;
+      if (more) fetch(ch + 1);
+      const uint8_t *buf = stage + (ch & 1) * kStageBytes;
+      const uint8_t *nbuf = stage + ((ch + 1) & 1) * kStageBytes;
+      EPI3_LD(buf, 1, pY, xY, b0Y, b1Y)
+      EPI3_STEP(pX, xX, b0X, b1X)
+      EPI3_SCHED
+      EPI3_LD(buf, 2, pX, xX, b0X, b1X)
+      EPI3_STEP(pY, xY, b0Y, b1Y)
+      EPI3_SCHED
+      EPI3_LD(buf, 3, pY, xY, b0Y, b1Y)
+      EPI3_STEP(pX, xX, b0X, b1X)
+      EPI3_SCHED
+      // the products above stay before the branch (they would otherwise be
+      // sunk to their first use below it)
+#pragma unroll
+      for (int tt = 0; tt < kPermT; ++tt) asm volatile("" : "+v"(acc[tt][0]), "+v"(acc[tt][1]));
+      if (more) store((ch + 1) & 1);
+      __syncthreads();
+      // after the last chunk this reads the other buffer's stale contents,
+      // which no product uses
+      EPI3_LD(nbuf, 0, pX, xX, b0X, b1X)
+      EPI3_STEP(pY, xY, b0Y, b1Y)
+      EPI3_SCHED
+    }
+#undef EPI3_LD
+#undef EPI3_TILE
+#undef EPI3_SCHED
+#undef EPI3_STEP
 
     if (i >= j) continue;  // padding pivot of the last i-block: nothing to write
 
