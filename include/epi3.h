@@ -327,10 +327,14 @@ int epi3_pairs_score_plane(const epi3_dataset *d, int32_t k, int64_t cand_cap, v
  * Fourth-order scan: quads of SNPs (SPLIT data sets), Eq. 1 with I = 81
  * rows.  A quad is (i, j, k, l), i < j < k < l < M; the table row of
  * (g_i, g_j, g_k, g_l) is 27 g_i + 9 g_j + 3 g_k + g_l.  Per class, the 16
- * cells with all four genotypes in {0, 1} and the corner cells of the four
- * sub-triplets are counted by AND + POPCNT over the bit planes; every other
- * cell follows by inclusion-exclusion from those, the pairwise tables of
- * epi3_encode and the class size.  Hits are the k lowest under
+ * cells with all four genotypes in {0, 1} are counted on the matrix cores
+ * (0/1 FP4 products, exact FP32 accumulation) when the data set has value
+ * planes and classes of at most 65535 samples, else by AND + POPCNT over the
+ * bit planes (a data set encoded with EPI3_ENCODE_BITS_ONLY); the corner
+ * cells of the four sub-triplets are counted by AND + POPCNT once per
+ * triplet, and every other cell follows by inclusion-exclusion from those,
+ * the pairwise tables of epi3_encode and the class size.  Both count paths
+ * give the same FP32 scores.  Hits are the k lowest under
  * (K2, i, j, k, l) with the same FP32 screen and FP64 re-score as the other
  * orders.  The score plane holds C(M,4) floats, so M is limited by memory
  * (M = 256: 0.7 GB; M = 512: 11 GB); M > 4096 is EPI3_E_UNSUPPORTED.
@@ -411,7 +415,7 @@ void epi3_release(void);
  * event pair on the call's stream around each launch of the count stage
  * (which = 0), of the selection pipeline (which = 1), of a whole batched
  * scan (which = 2), of the table-completion/scoring kernel that follows the
- * matrix-core count of phenotype batches (which = 3) and of the pairwise-table
+ * matrix-core count of phenotype batches and of quad scans (which = 3) and of the pairwise-table
  * kernel of epi3_encode (which = 4); batched scans run without graph capture while timing is
  * enabled so that their kernels can be timed.  epi3_timing_query waits for the
  * recorded events and returns the summed milliseconds and the number of

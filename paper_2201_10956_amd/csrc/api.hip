@@ -281,10 +281,17 @@ struct OrderLayout {
   int64_t ccap;
   int64_t cap;
   uint8_t *t3;  // quads: triplet corner table (NULL: counted per quad)
+  // quads on the matrix cores (data sets with FP4 value planes)
+  bool qmfma;
+  int64_t *qprefix;           // [M + 1] tiles before each pivot j
+  unsigned long long *queue;  // tile queue
+  uint8_t *qscratch;          // pass_tiles tiles of corner cells
+  int64_t pass_tiles;
   int64_t total;
 };
 
 constexpr int32_t kQuadMaxSnps = 4096;
+constexpr int64_t kQuadPassBytes = 1ll << 30;  // corner scratch of the matrix-core quad scan
 
 int64_t order_combos(int order, int32_t M) { return order == 2 ? c2(M) : c4(M); }
 int64_t order_hit_bytes(int order) {
@@ -309,6 +316,15 @@ OrderLayout order_layout(void *ws, const epi3_dataset &d, int order, int32_t k, 
   L.crank = c.take<int64_t>(L.ccap);
   if (order == 4 && d.n_cases <= 65535 && d.n_controls <= 65535)
     L.t3 = c.take<uint8_t>(quad_triplet_table_bytes(d.n_snps));
+  if (order == 4 && T > 0 && mfma_supported(d)) {
+    L.qmfma = true;
+    L.qprefix = c.take<int64_t>((int64_t)d.n_snps + 1);
+    L.queue = c.take<unsigned long long>(4);
+    const int64_t tiles = host_quad_tiles(d.n_snps);
+    L.pass_tiles = std::max<int64_t>(
+        1, std::min<int64_t>(tiles, pass_bytes(kQuadPassBytes) / kQuadTileScratch));
+    L.qscratch = c.take<uint8_t>(L.pass_tiles * kQuadTileScratch);
+  }
   L.total = c.size();
   return L;
 }
@@ -634,7 +650,31 @@ static int order_scan(const epi3_dataset *d, int order, int32_t k, int64_t cand_
   S.err2 = 2.0 * order_error_bound(order, d->n_samples);
   HIP_OK(launch_write_seljobs(&S, 1, W.sel, s));
   HIP_OK(launch_init_select(W.sel, 1, s));
-  if (T > 0) {
+  if (T > 0 && W.qmfma) {
+    // quads on the matrix cores: per pass of tiles, the count kernel (timed as
+    // the count stage) fills the scratch, then the finish kernel (timed as
+    // table completion) scores its quads; one stream, one scratch buffer
+    HIP_OK(launch_triplet_corners(*d, W.t3, s));
+    HIP_OK(launch_quad_prefix(d->n_snps, W.qprefix, s));
+    const int64_t tiles = host_quad_tiles(d->n_snps);
+    for (int64_t t0 = 0; t0 < tiles; t0 += W.pass_tiles) {
+      const int64_t nn = std::min(W.pass_tiles, tiles - t0);
+      HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
+      rc = timed(0, s, [&]() {
+        return launch_count_mfma_quad(*d, W.qprefix, W.queue, t0, nn, W.qscratch, s) == hipSuccess
+                   ? EPI3_OK
+                   : EPI3_E_HIP;
+      });
+      if (rc != EPI3_OK) return rc;
+      rc = timed(3, s, [&]() {
+        return launch_finish_quad(*d, W.qscratch, W.qprefix, W.t3, t0, nn, W.score, &W.st->kmin,
+                                  s) == hipSuccess
+                   ? EPI3_OK
+                   : EPI3_E_HIP;
+      });
+      if (rc != EPI3_OK) return rc;
+    }
+  } else if (T > 0) {
     rc = timed(0, s, [&]() {
       const hipError_t e = order == 2 ? launch_pair_scores(*d, W.score, &W.st->kmin, s)
                                       : launch_quad_scores(*d, W.t3, W.score, &W.st->kmin, s);

@@ -512,6 +512,22 @@ hipError_t launch_pair_scores(const epi3_dataset &d, float *score, uint32_t *key
 // quad_triplet_table_bytes for the triplet corner table (classes of at most
 // 65535 samples), or NULL to count the sub-triplet corners per quad.
 inline int64_t quad_triplet_table_bytes(int64_t M) { return 2 * 16 * (M < 3 ? 0 : M * (M - 1) / 2 * (M - 2) / 3); }
+// Corner cells of every triplet per class into t3 (quad_triplet_table_bytes).
+hipError_t launch_triplet_corners(const epi3_dataset &d, void *t3, hipStream_t s);
+// Quad scan with the counts on the matrix cores (FP4 value planes, classes of
+// at most 65535 samples): tiles of 4 i x 1 j x 16 k x 32 l, counted and
+// scored pass by pass through a scratch buffer of pass_tiles tiles.
+constexpr int64_t kQuadTileScratch = 128 * 1024;  // bytes per tile, both classes
+int64_t host_quad_tiles(int32_t M);
+hipError_t launch_quad_prefix(int32_t M, int64_t *jprefix, hipStream_t s);
+// counts tiles [tile_begin, tile_begin + n_tiles) into scratch slots from 0
+hipError_t launch_count_mfma_quad(const epi3_dataset &d, const int64_t *jprefix,
+                                  unsigned long long *queue, int64_t tile_begin, int64_t n_tiles,
+                                  void *scratch, hipStream_t s);
+// completes and scores the quads of those tiles (t3: launch_triplet_corners)
+hipError_t launch_finish_quad(const epi3_dataset &d, const void *scratch, const int64_t *jprefix,
+                              const void *t3, int64_t tile_begin, int64_t n_tiles, float *score,
+                              uint32_t *keyrange, hipStream_t s);
 hipError_t launch_quad_scores(const epi3_dataset &d, void *t3, float *score, uint32_t *keyrange,
                               hipStream_t s);
 int64_t host_perm_tiles(int64_t M);

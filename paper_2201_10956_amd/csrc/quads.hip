@@ -151,6 +151,23 @@ hipError_t launch_quad_scores_t(const epi3_dataset &d, const uint4 *t3, float *s
 
 }  // namespace
 
+hipError_t launch_triplet_corners(const epi3_dataset &d, void *t3, hipStream_t s) {
+  const int M = d.n_snps;
+  const int64_t T = c3(M);
+  if (T == 0) return hipSuccess;
+  int dev = 0, n_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  int64_t tb = (T + 255) / 256;
+  if (tb > (int64_t)n_cu * 16) tb = (int64_t)n_cu * 16;
+  hipLaunchKernelGGL(triplet_corners_kernel, dim3((unsigned)tb), dim3(256), 0, s,
+                     static_cast<const uint32_t *>(d.planes), M, d.snp_stride, d.words[0],
+                     d.words[1], T, static_cast<uint4 *>(t3));
+  return hipGetLastError();
+}
+
 hipError_t launch_quad_scores(const epi3_dataset &d, void *t3, float *score, uint32_t *keyrange,
                               hipStream_t s) {
   if (d.n_snps < 4) return hipSuccess;

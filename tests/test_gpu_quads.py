@@ -1,6 +1,8 @@
 """GPU parity of the fourth-order (quad) scan against the oracle's quad scan:
 every quad's FP32 score within the 81-row error bound, and hits (quad, FP64
-K2 bit for bit, both 81-row tables) equal to the oracle's top-k."""
+K2 bit for bit, both 81-row tables) equal to the oracle's top-k.  Each case
+runs on a data set with FP4 value planes (counts on the matrix cores) and on
+one encoded without them (counts by popcount)."""
 import numpy as np
 import pytest
 
@@ -53,14 +55,18 @@ def assert_quad_k2_close(got32, ref64, N, epi3):
     assert np.all(diff / np.maximum(np.abs(ref64), 1e-30) <= 1e-4)
 
 
+VALUES = [pytest.param(True, id="mfma"), pytest.param(False, id="popcount")]
+
+
+@pytest.mark.parametrize("values", VALUES)
 @pytest.mark.parametrize("M,N,p", [(4, 1, 0.5), (4, 64, 0.0), (5, 33, 1.0), (7, 31, 0.3),
                                    (12, 95, 0.5), (20, 129, 0.45), (40, 300, 0.2),
-                                   (33, 2000, 0.5)])
-def test_every_quad_score_and_topk(env, M, N, p):
+                                   (33, 2000, 0.5), (70, 333, 0.4)])
+def test_every_quad_score_and_topk(env, M, N, p, values):
     torch, epi3 = env
-    print(f"[case] quads M={M} N={N} p={p}", flush=True)
+    print(f"[case] quads M={M} N={N} p={p} values={values}", flush=True)
     geno, pheno = _tiny(100 * M + N, M, N, p)
-    ds = epi3.encode(to_dev(geno), pheno)
+    ds = epi3.encode(to_dev(geno), pheno, values=values)
     k = min(30, M * (M - 1) * (M - 2) * (M - 3) // 24)
     sc = epi3.QuadScanner(ds, k)
     h = sc.run()
@@ -70,13 +76,14 @@ def test_every_quad_score_and_topk(env, M, N, p):
     assert_quad_hits_equal_oracle(h, q, rk2, rcc)
 
 
-def test_quads_128_snps(env):
+@pytest.mark.parametrize("values", VALUES)
+def test_quads_128_snps(env, values):
     """128 SNPs x 4096 samples (10.7 M quads), top-100 equal to the oracle's;
     sampled FP32 scores within the bound."""
     torch, epi3 = env
-    print("[case] quads 128 x 4096", flush=True)
+    print(f"[case] quads 128 x 4096 values={values}", flush=True)
     d = make_dataset(128, 4096, 0.5, 0.05, seed=44)
-    ds = epi3.encode(to_dev(d.geno), d.pheno)
+    ds = epi3.encode(to_dev(d.geno), d.pheno, values=values)
     sc = epi3.QuadScanner(ds, 100)
     h = sc.run()
     q, rk2, rcc = oracle.scan_quads_topk(d.geno, d.pheno, 100)
@@ -90,11 +97,12 @@ def test_quads_128_snps(env):
     assert_quad_k2_close(got, ref, d.n_samples, epi3)
 
 
-def test_quads_large_sample_count(env):
+@pytest.mark.parametrize("values", VALUES)
+def test_quads_large_sample_count(env, values):
     """50000 samples: the log-factorial table is read from global memory."""
     torch, epi3 = env
     geno, pheno = _tiny(71, 9, 50000, 0.45)
-    ds = epi3.encode(to_dev(geno), pheno)
+    ds = epi3.encode(to_dev(geno), pheno, values=values)
     sc = epi3.QuadScanner(ds, 12)
     h = sc.run()
     ref_k2, _ = oracle.scan_quads_all(geno, pheno, counts=False)
@@ -103,12 +111,13 @@ def test_quads_large_sample_count(env):
     assert_quad_hits_equal_oracle(h, q, rk2, rcc)
 
 
-def test_quads_edge_cases(env):
+@pytest.mark.parametrize("values", VALUES)
+def test_quads_edge_cases(env, values):
     torch, epi3 = env
     base, _ = _tiny(3, 1, 150, 0.5)
     geno = np.repeat(base, 6, axis=0)           # identical rows: ties broken by index
-    for ph in (np.zeros(150, np.uint8), np.ones(150, np.uint8)):
-        ds = epi3.encode(to_dev(geno), ph)
+    for ph in (np.zeros(150, np.uint8), np.ones(150, np.uint8)):  # one class empty
+        ds = epi3.encode(to_dev(geno), ph, values=values)
         h = epi3.scan_quads(ds, 40)
         q, rk2, rcc = oracle.scan_quads_topk(geno, ph, 40)
         assert len(h) == 15
@@ -121,10 +130,11 @@ def test_quads_edge_cases(env):
     assert e.value.code == epi3.E_UNSUPPORTED
 
 
-def test_quads_candidate_capacity_retry(env):
+@pytest.mark.parametrize("values", VALUES)
+def test_quads_candidate_capacity_retry(env, values):
     torch, epi3 = env
     d = make_dataset(30, 2000, 0.5, 0.05, seed=45)
-    ds = epi3.encode(to_dev(d.geno), d.pheno)
+    ds = epi3.encode(to_dev(d.geno), d.pheno, values=values)
     sc = epi3.QuadScanner(ds, 20, cand_cap=5)
     sc.scan()
     rc, need = sc.topk()
@@ -134,17 +144,18 @@ def test_quads_candidate_capacity_retry(env):
     assert_quad_hits_equal_oracle(h, q, rk2, rcc)
 
 
-def test_quads_256_snps_bench_workload(env):
+@pytest.mark.parametrize("values", VALUES)
+def test_quads_256_snps_bench_workload(env, values):
     """The benchmark's fourth-order workload, the first 256 SNPs of the
     512 x 4096 data set (174 M quads): top-100 equal to the stored oracle
     result, 2000 sampled FP32 scores within the bound."""
     import os
     from synth import CONFIGS, make_config, manifest_sha256
     torch, epi3 = env
-    print("[case] quads 256 x 4096", flush=True)
+    print(f"[case] quads 256 x 4096 values={values}", flush=True)
     d = make_config(2)
     g = np.ascontiguousarray(d.geno[:256])
-    ds = epi3.encode(to_dev(g), d.pheno, values=False)
+    ds = epi3.encode(to_dev(g), d.pheno, values=values)
     sc = epi3.QuadScanner(ds, 100)
     h = sc.run()
     z = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
@@ -158,3 +169,29 @@ def test_quads_256_snps_bench_workload(env):
     ref = np.array([oracle.k2_rows(oracle.quad_table(g, d.pheno, *map(int, x)), L) for x in lex])
     got = sc.score_plane()[torch.as_tensor(ranks, device="cuda")].cpu().numpy()
     assert_quad_k2_close(got, ref, d.n_samples, epi3)
+
+
+@pytest.mark.parametrize("M,N,p,pass_tiles", [(70, 700, 0.45, 3), (97, 513, 0.3, 0), (131, 260, 0.6, 7)])
+def test_matrix_core_quads_equal_popcount_quads(env, M, N, p, pass_tiles):
+    """Every FP32 score of the matrix-core quad scan equals the popcount quad
+    scan's bit for bit (same cells, same expression and row order), over M
+    not a multiple of the 16 x 32 tile blocks, ragged class sizes and many
+    scratch passes; hits equal the oracle's."""
+    torch, epi3 = env
+    print(f"[case] quads mfma vs popcount M={M} N={N} pass_tiles={pass_tiles}", flush=True)
+    geno, pheno = _tiny(7 * M + N, M, N, p)
+    dv = epi3.encode(to_dev(geno), pheno, values=True)
+    db = epi3.encode(to_dev(geno), pheno, values=False)
+    try:
+        if pass_tiles:
+            epi3.set_pass_bytes(pass_tiles * 128 * 1024)
+        sv = epi3.QuadScanner(dv, 25)
+        hv = sv.run()
+    finally:
+        epi3.set_pass_bytes(0)
+    sb = epi3.QuadScanner(db, 25)
+    hb = sb.run()
+    assert torch.equal(sv.score_plane(), sb.score_plane())
+    q, rk2, rcc = oracle.scan_quads_topk(geno, pheno, 25)
+    assert_quad_hits_equal_oracle(hv, q, rk2, rcc)
+    assert_quad_hits_equal_oracle(hb, q, rk2, rcc)
