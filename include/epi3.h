@@ -444,7 +444,8 @@ void epi3_tile_rules_clear(void);
 /* The tile (or, for AUTO, the variant) a scan of d with `variant` uses. */
 int32_t epi3_tile_for(const epi3_dataset *d, int32_t variant);
 /* Scratch bytes per pass buffer of the matrix-core paths (0: default 1 GiB
- * for plain scans, 4 GiB for phenotype batches).  Same rules as above. */
+ * for plain scans, 4 GiB for phenotype batches, 2 GiB for quad scans; each
+ * path keeps two buffers).  Same rules as above. */
 int epi3_set_pass_bytes(int64_t bytes);
 /* Entries of the compacted low end of a score plane that the selection keeps
  * after its first histogram pass (0: default max(65536, 16 x candidate

@@ -291,7 +291,7 @@ struct OrderLayout {
 };
 
 constexpr int32_t kQuadMaxSnps = 4096;
-constexpr int64_t kQuadPassBytes = 1ll << 30;  // corner scratch of the matrix-core quad scan
+constexpr int64_t kQuadPassBytes = 2ll << 30;  // per corner scratch buffer of the matrix-core quad scan
 
 int64_t order_combos(int order, int32_t M) { return order == 2 ? c2(M) : c4(M); }
 int64_t order_hit_bytes(int order) {
@@ -323,7 +323,7 @@ OrderLayout order_layout(void *ws, const epi3_dataset &d, int order, int32_t k, 
     const int64_t tiles = host_quad_tiles(d.n_snps);
     L.pass_tiles = std::max<int64_t>(
         1, std::min<int64_t>(tiles, pass_bytes(kQuadPassBytes) / kQuadTileScratch));
-    L.qscratch = c.take<uint8_t>(L.pass_tiles * kQuadTileScratch);
+    L.qscratch = c.take<uint8_t>(2 * L.pass_tiles * kQuadTileScratch);  // two buffers
   }
   L.total = c.size();
   return L;
@@ -651,29 +651,47 @@ static int order_scan(const epi3_dataset *d, int order, int32_t k, int64_t cand_
   HIP_OK(launch_write_seljobs(&S, 1, W.sel, s));
   HIP_OK(launch_init_select(W.sel, 1, s));
   if (T > 0 && W.qmfma) {
-    // quads on the matrix cores: per pass of tiles, the count kernel (timed as
-    // the count stage) fills the scratch, then the finish kernel (timed as
-    // table completion) scores its quads; one stream, one scratch buffer
+    // quads on the matrix cores: pass p of tiles is counted (timed as the
+    // count stage) into scratch buffer p % 2 on `s`; its finish kernel (timed
+    // as table completion) runs on the library's second stream while `s`
+    // counts pass p + 1, and count p + 2 waits for finish p (same buffer)
     HIP_OK(launch_triplet_corners(*d, W.t3, s));
     HIP_OK(launch_quad_prefix(d->n_snps, W.qprefix, s));
+    AuxLease lease;
+    if (lease.rc != EPI3_OK) return lease.rc;
+    hipStream_t s2 = lease.c->s2;
+    hipEvent_t ev_start = lease.c->ev[0], ev_cnt[2] = {lease.c->ev[1], lease.c->ev[2]},
+               ev_fin[2] = {lease.c->ev[3], lease.c->ev[4]};
+    uint8_t *buf[2] = {W.qscratch, W.qscratch + W.pass_tiles * kQuadTileScratch};
+    HIP_OK(hipEventRecord(ev_start, s));
+    HIP_OK(hipStreamWaitEvent(s2, ev_start, 0));
     const int64_t tiles = host_quad_tiles(d->n_snps);
-    for (int64_t t0 = 0; t0 < tiles; t0 += W.pass_tiles) {
+    int p = 0;
+    for (int64_t t0 = 0; t0 < tiles; t0 += W.pass_tiles, ++p) {
       const int64_t nn = std::min(W.pass_tiles, tiles - t0);
+      const int b = p & 1;
+      if (p >= 2) HIP_OK(hipStreamWaitEvent(s, ev_fin[b], 0));
       HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
       rc = timed(0, s, [&]() {
-        return launch_count_mfma_quad(*d, W.qprefix, W.queue, t0, nn, W.qscratch, s) == hipSuccess
+        return launch_count_mfma_quad(*d, W.qprefix, W.queue, t0, nn, buf[b], s) == hipSuccess
                    ? EPI3_OK
                    : EPI3_E_HIP;
       });
       if (rc != EPI3_OK) return rc;
-      rc = timed(3, s, [&]() {
-        return launch_finish_quad(*d, W.qscratch, W.qprefix, W.t3, t0, nn, W.score, &W.st->kmin,
-                                  s) == hipSuccess
+      HIP_OK(hipEventRecord(ev_cnt[b], s));
+      HIP_OK(hipStreamWaitEvent(s2, ev_cnt[b], 0));
+      rc = timed(3, s2, [&]() {
+        return launch_finish_quad(*d, buf[b], W.qprefix, W.t3, t0, nn, W.score, &W.st->kmin,
+                                  s2) == hipSuccess
                    ? EPI3_OK
                    : EPI3_E_HIP;
       });
       if (rc != EPI3_OK) return rc;
+      HIP_OK(hipEventRecord(ev_fin[b], s2));
     }
+    // everything back on `s` before the selection reads the plane
+    HIP_OK(hipEventRecord(ev_fin[0], s2));
+    HIP_OK(hipStreamWaitEvent(s, ev_fin[0], 0));
   } else if (T > 0) {
     rc = timed(0, s, [&]() {
       const hipError_t e = order == 2 ? launch_pair_scores(*d, W.score, &W.st->kmin, s)

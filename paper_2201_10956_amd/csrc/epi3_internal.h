@@ -326,16 +326,19 @@ __device__ __forceinline__ void quad_corner_counts(const uint32_t *planes, int64
 // (complete_table); then the rows with a 2 at SNP i, j, k, l in turn: a count
 // with a 2 at one SNP is the sub-triplet table without that SNP minus the
 // rows with 0 and 1 there (every sample of the class is in one row).
+// SH scales every count by 2^SH (SH = 2: cells as byte offsets into an FP32
+// table); cnt and Nc must come scaled alike, the pairwise tables are scaled here.
+template <int SH = 0>
 __device__ __forceinline__ void quad_cells(const uint32_t cnt[48], const int32_t *pairs, int64_t Mp,
                                            int i, int j, int k, int l, int Nc, int t[81]) {
   const int4 *pr = reinterpret_cast<const int4 *>(pairs);
   auto pair = [&](int x, int y, int v[4]) {
     const int4 p = pr[(int64_t)x * Mp + y];
-    v[0] = p.x; v[1] = p.y; v[2] = p.z; v[3] = p.w;
+    v[0] = p.x << SH; v[1] = p.y << SH; v[2] = p.z << SH; v[3] = p.w << SH;
   };
   auto marg = [&](int x, int v[2]) {
     const int4 p = pr[(int64_t)x * Mp + x];
-    v[0] = p.x; v[1] = p.w;
+    v[0] = p.x << SH; v[1] = p.w << SH;
   };
   int pij[4], pik[4], pil[4], pjk[4], pjl[4], pkl[4], mi[2], mj[2], mk[2], ml[2];
   pair(i, j, pij); pair(i, k, pik); pair(i, l, pil);

@@ -323,9 +323,10 @@ __global__ void __launch_bounds__(256, 2) count_mfma_quad_kernel(
   }
 }
 
+// the 8 corner cells of a triplet-table entry, each x 4
 __device__ __forceinline__ void unpack8q(uint4 v, uint32_t *n) {
-  n[0] = v.x & 0xffffu; n[1] = v.x >> 16; n[2] = v.y & 0xffffu; n[3] = v.y >> 16;
-  n[4] = v.z & 0xffffu; n[5] = v.z >> 16; n[6] = v.w & 0xffffu; n[7] = v.w >> 16;
+  n[0] = (v.x & 0xffffu) << 2; n[1] = (v.x >> 16) << 2; n[2] = (v.y & 0xffffu) << 2; n[3] = (v.y >> 16) << 2;
+  n[4] = (v.z & 0xffffu) << 2; n[5] = (v.z >> 16) << 2; n[6] = (v.w & 0xffffu) << 2; n[7] = (v.w >> 16) << 2;
 }
 
 // Completes both 81-row tables of every quad of the pass's tiles and scores
@@ -336,12 +337,13 @@ __global__ void __launch_bounds__(256) finish_quad_kernel(
     const uint4 *__restrict__ t3, const int32_t *__restrict__ pairs, int M, int Mp, int N0,
     int N1, int64_t T, int64_t tile_begin, int64_t n_tiles, const float *__restrict__ lf32,
     int lf_len, float *__restrict__ score, uint32_t *__restrict__ keyrange) {
+  // the LDS table is the kernel's whole dynamic LDS block, at LDS address 0
+  // (no static LDS), so a lookup is one ds_read at the byte offset
   extern __shared__ float qtab[];
   const float *L = lf32;
   if (LDS) {
     for (int x = threadIdx.x; x < lf_len; x += blockDim.x) qtab[x] = lf32[x];
     __syncthreads();
-    L = qtab;
   }
   cptr<int64_t> pre = as_const(pre_p);
   const int64_t MpMp4 = (int64_t)Mp * Mp * 4;
@@ -376,21 +378,25 @@ __global__ void __launch_bounds__(256) finish_quad_kernel(
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
               const uint32_t wd = a ? (cc ? v[d].w : v[d].y) : (cc ? v[d].z : v[d].x);
-              cnt[8 * a + 2 * cc + d] = wd & 0xffffu;
-              cnt[8 * a + 4 + 2 * cc + d] = wd >> 16;
+              cnt[8 * a + 2 * cc + d] = (wd & 0xffffu) << 2;
+              cnt[8 * a + 4 + 2 * cc + d] = (wd >> 16) << 2;
             }
         const uint4 *tcl = t3 + c * T;
         unpack8q(tcl[lex_base(M, i, j) + k], cnt + 16);
         unpack8q(tcl[lex_base(M, i, j) + l], cnt + 24);
         unpack8q(tcl[lex_base(M, i, k) + l], cnt + 32);
         unpack8q(tcl[lex_base(M, j, k) + l], cnt + 40);
-        quad_cells(cnt, pairs + c * MpMp4, Mp, i, j, k, l, c ? N1 : N0, tc[c]);
+        // cells as byte offsets into the FP32 table (x 4)
+        quad_cells<2>(cnt, pairs + c * MpMp4, Mp, i, j, k, l, (c ? N1 : N0) << 2, tc[c]);
       }
       float k2 = 0.f;  // rows in order: L[r + 1] - (L[r_0] + L[r_1])
 #pragma unroll
       for (int y = 0; y < 81; ++y) {
-        const int r0 = tc[0][y], r1 = tc[1][y];
-        k2 += L[r0 + r1 + 1] - (L[r0] + L[r1]);
+        const int b0 = tc[0][y], b1 = tc[1][y];
+        if (LDS)
+          k2 += lf_at_lds0(b0 + b1 + 4) - (lf_at_lds0(b0) + lf_at_lds0(b1));
+        else
+          k2 += lf_at(L, b0 + b1 + 4) - (lf_at(L, b0) + lf_at(L, b1));
       }
       score[quad_rank(M, i, j, k, l)] = k2;
       const uint32_t key = f2key(k2);
