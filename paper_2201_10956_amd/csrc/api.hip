@@ -131,6 +131,8 @@ struct ScanLayout {
   int64_t *cand;
   uint32_t *candkey;
   CandRec *rec;
+  uint64_t *skey;         // sort buffers (candidate capacities above kRankDirectMax)
+  uint32_t *sidx;
   epi3_hit *hits;
   uint32_t *ckey;         // compacted low end of the plane
   int64_t *crank;
@@ -249,6 +251,8 @@ ScanLayout scan_layout(void *ws, const epi3_dataset &d, int32_t k, int64_t cand_
   L.cand = c.take<int64_t>(L.cap);
   L.candkey = c.take<uint32_t>(L.cap);
   L.rec = c.take<CandRec>(L.cap);
+  L.skey = c.take<uint64_t>(sort_len(L.cap));
+  L.sidx = c.take<uint32_t>(sort_len(L.cap));
   L.hits = c.take<epi3_hit>(std::max<int32_t>(k, 1));
   L.ccap = compact_cap(T, L.cap);
   L.ckey = c.take<uint32_t>(L.ccap);
@@ -275,6 +279,8 @@ struct OrderLayout {
   int64_t *cand;
   uint32_t *candkey;
   CandRec *rec;
+  uint64_t *skey;
+  uint32_t *sidx;
   uint8_t *hits;
   uint32_t *ckey;
   int64_t *crank;
@@ -310,6 +316,8 @@ OrderLayout order_layout(void *ws, const epi3_dataset &d, int order, int32_t k, 
   L.cand = c.take<int64_t>(L.cap);
   L.candkey = c.take<uint32_t>(L.cap);
   L.rec = c.take<CandRec>(L.cap);
+  L.skey = c.take<uint64_t>(sort_len(L.cap));
+  L.sidx = c.take<uint32_t>(sort_len(L.cap));
   L.hits = c.take<uint8_t>(std::max<int32_t>(k, 1) * order_hit_bytes(order));
   L.ccap = compact_cap(T, L.cap);
   L.ckey = c.take<uint32_t>(L.ccap);
@@ -645,6 +653,9 @@ static int order_scan(const epi3_dataset *d, int order, int32_t k, int64_t cand_
   SelJob S = make_seljob(*d, W.score, T, W.st, W.hist, W.cand, W.candkey, W.rec, nullptr, W.cap, k,
                          W.ckey, W.crank, W.ccap);
   S.order = order;
+  S.skey = W.skey;
+  S.sidx = W.sidx;
+  S.sortP = sort_len(W.cap);
   if (order == 2) S.pair_hits = reinterpret_cast<epi3_pair_hit *>(W.hits);
   else S.quad_hits = reinterpret_cast<epi3_quad_hit *>(W.hits);
   S.err2 = 2.0 * order_error_bound(order, d->n_samples);
@@ -904,6 +915,9 @@ int epi3_scan(const epi3_dataset *d, int32_t k, int32_t variant, int64_t cand_ca
   const int64_t T = epi3_n_triplets(d->n_snps);
   SelJob S = make_seljob(*d, W.score, T, W.st, W.hist, W.cand, W.candkey, W.rec, W.hits, W.cap, k,
                          W.ckey, W.crank, W.ccap);
+  S.skey = W.skey;
+  S.sidx = W.sidx;
+  S.sortP = sort_len(W.cap);
   HIP_OK(launch_write_seljobs(&S, 1, W.sel, s));
   HIP_OK(launch_init_select(W.sel, 1, s));
   if (T > 0) {
@@ -1046,6 +1060,8 @@ struct BatchLayout {
   std::vector<int64_t *> cand;
   std::vector<uint32_t *> candkey;
   std::vector<CandRec *> rec;
+  std::vector<uint64_t *> skey;   // sort buffers of jobs with capacities above kRankDirectMax
+  std::vector<uint32_t *> sidx;
   std::vector<uint32_t *> ckey;
   std::vector<int64_t *> crank;
   std::vector<int64_t> cap, ccap, hit_off, T;
@@ -1170,6 +1186,8 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
   L.cand.resize(n);
   L.candkey.resize(n);
   L.rec.resize(n);
+  L.skey.resize(n);
+  L.sidx.resize(n);
   L.ckey.resize(n);
   L.crank.resize(n);
   L.cap.resize(n);
@@ -1210,6 +1228,8 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
     L.cand[x] = c.take<int64_t>(L.cap[x]);
     L.candkey[x] = c.take<uint32_t>(L.cap[x]);
     L.rec[x] = c.take<CandRec>(L.cap[x]);
+    L.skey[x] = c.take<uint64_t>(sort_len(L.cap[x]));
+    L.sidx[x] = c.take<uint32_t>(sort_len(L.cap[x]));
     if (L.bounded) {
       L.ckey[x] = L.bkey ? L.bkey + (int64_t)x * L.ccap[x] : nullptr;
       L.crank[x] = L.brank ? L.brank + (int64_t)x * L.ccap[x] : nullptr;
@@ -1236,6 +1256,9 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
     sj[x] = make_seljob(d, W.score[x], W.T[x], W.st + x, W.hist + (int64_t)x * kHistBins,
                         W.cand[x], W.candkey[x], W.rec[x], W.hits + W.hit_off[x], W.cap[x],
                         jobs[x].k, W.ckey[x], W.crank[x], W.ccap[x]);
+    sj[x].skey = W.skey[x];
+    sj[x].sidx = W.sidx[x];
+    sj[x].sortP = sort_len(W.cap[x]);
     // bounded jobs have their list before the selection starts (no plane pass)
     if (W.bounded) sj[x].sample = 1;
     any_sample = any_sample || (sj[x].sample && sj[x].score);

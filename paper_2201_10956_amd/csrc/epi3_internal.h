@@ -186,7 +186,22 @@ struct SelJob {
                            // else triplets
   epi3_pair_hit *pair_hits;  // [k] (order 2)
   epi3_quad_hit *quad_hits;  // [k] (order 4)
+  // candidate capacities above kRankDirectMax order the candidates by a
+  // bitonic sort of (FP64 key, index) pairs in these buffers of sortP entries
+  // (a power of two >= cap) instead of counting, for each, the candidates
+  // before it; sortP = 0 otherwise
+  uint64_t *skey;
+  uint32_t *sidx;
+  int64_t sortP;
 };
+
+constexpr int64_t kRankDirectMax = 16384;
+inline int64_t sort_len(int64_t cap) {
+  if (cap <= kRankDirectMax) return 0;
+  int64_t p = 1;
+  while (p < cap) p <<= 1;
+  return p;
+}
 
 // The 27 cells of one class from the 8 counted corner cells n[4a + 2b + c]
 // (a, b, c in {0, 1}), the pairwise tables pij[2a + b], pik[2a + c],

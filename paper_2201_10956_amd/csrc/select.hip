@@ -21,6 +21,8 @@
 //      Eq. 1's bracketing, rows summed in row order;
 //   4. each candidate's position under (K2_fp64, i, j, k) is counted against
 //      all others and the first k are written out.
+#include <algorithm>
+
 #include "epi3_internal.h"
 
 namespace epi3 {
@@ -516,15 +518,51 @@ __global__ void __launch_bounds__(256) rescore_kernel(const SelJob *__restrict__
 }
 
 // Position of each candidate under (key, rank); the first keff go out.
+// Hit `pos` of the job's list from candidate record x.
+__device__ __forceinline__ void emit_hit(const SelJob &J, int64_t x, int64_t pos) {
+  const CandRec &R = J.rec[x];
+  if (J.order == 4) {
+    epi3_quad_hit &H = J.quad_hits[pos];
+    H.i = R.i; H.j = R.j; H.k = R.k; H.l = R.l;
+    H.k2_f32 = R.k2f;
+    H.reserved = 0u;
+    H.k2 = R.k2;
+    for (int q = 0; q < 81; ++q) {
+      H.counts[0][q] = R.counts[q];
+      H.counts[1][q] = R.counts[81 + q];
+    }
+  } else if (J.order == 2) {
+    epi3_pair_hit &H = J.pair_hits[pos];
+    H.i = R.i; H.j = R.j;
+    H.k2_f32 = R.k2f;
+    H.reserved = 0u;
+    H.k2 = R.k2;
+    for (int q = 0; q < 9; ++q) {
+      H.counts[0][q] = R.counts[q];
+      H.counts[1][q] = R.counts[27 + q];
+    }
+  } else {
+    epi3_hit &H = J.hits[pos];
+    H.i = R.i; H.j = R.j; H.k = R.k;
+    H.k2_f32 = R.k2f;
+    H.k2 = R.k2;
+    for (int q = 0; q < 27; ++q) {
+      H.counts[0][q] = R.counts[q];
+      H.counts[1][q] = R.counts[27 + q];
+    }
+  }
+}
+
 // Rank of every candidate = number of candidates before it under
 // (K2_fp64, rank); each workgroup takes 64 candidates (one per lane) and its
 // 16 waves split the comparisons, so chains stay short for a few thousand
-// candidates.
+// candidates.  Jobs with sort buffers (sortP > 0) are ordered by the sort
+// kernels below instead.
 constexpr int kRankThreads = 1024;
 __global__ void __launch_bounds__(kRankThreads) rank_kernel(const SelJob *__restrict__ sj) {
   const SelJob &J = sj[blockIdx.y];
   SelState *st = J.st;
-  if (st->done != 1u) return;
+  if (st->done != 1u || J.sortP > 0) return;
   const int64_t n = (int64_t)st->ncand < J.cap ? (int64_t)st->ncand : J.cap;
   const int64_t keff = st->keff;
   __shared__ uint64_t skey[kRankThreads];
@@ -559,40 +597,95 @@ __global__ void __launch_bounds__(kRankThreads) rank_kernel(const SelJob *__rest
     if (wave != 0) continue;
     int64_t pos = 0;
     for (int w = 0; w < kRankThreads / 64; ++w) pos += spos[w][lane];
-    if (x < n && pos < keff && J.order == 4) {
-      const CandRec &R = J.rec[x];
-      epi3_quad_hit &H = J.quad_hits[pos];
-      H.i = R.i; H.j = R.j; H.k = R.k; H.l = R.l;
-      H.k2_f32 = R.k2f;
-      H.reserved = 0u;
-      H.k2 = R.k2;
-      for (int q = 0; q < 81; ++q) {
-        H.counts[0][q] = R.counts[q];
-        H.counts[1][q] = R.counts[81 + q];
-      }
-    } else if (x < n && pos < keff && J.order == 2) {
-      const CandRec &R = J.rec[x];
-      epi3_pair_hit &H = J.pair_hits[pos];
-      H.i = R.i; H.j = R.j;
-      H.k2_f32 = R.k2f;
-      H.reserved = 0u;
-      H.k2 = R.k2;
-      for (int q = 0; q < 9; ++q) {
-        H.counts[0][q] = R.counts[q];
-        H.counts[1][q] = R.counts[27 + q];
-      }
-    } else if (x < n && pos < keff) {
-      const CandRec &R = J.rec[x];
-      epi3_hit &H = J.hits[pos];
-      H.i = R.i; H.j = R.j; H.k = R.k;
-      H.k2_f32 = R.k2f;
-      H.k2 = R.k2;
-      for (int q = 0; q < 27; ++q) {
-        H.counts[0][q] = R.counts[q];
-        H.counts[1][q] = R.counts[27 + q];
-      }
+    if (x < n && pos < keff) emit_hit(J, x, pos);
+  }
+}
+
+// ---- ordering of large candidate sets: bitonic sort of (key, index) ----
+// Entries past the candidate count carry key ~0 (above every FP64 key, which
+// is the bit pattern of a non-negative double); equal keys of candidates are
+// ordered by their lexicographic rank, equal padding keys by index.
+__device__ __forceinline__ bool sort_before(const SelJob &J, uint64_t ka, uint32_t ia, uint64_t kb,
+                                            uint32_t ib) {
+  if (ka != kb) return ka < kb;
+  if (ka == ~0ull) return ia < ib;
+  return J.rec[ia].rank < J.rec[ib].rank;
+}
+
+__global__ void __launch_bounds__(256) sort_init_kernel(const SelJob *__restrict__ sj) {
+  const SelJob &J = sj[blockIdx.y];
+  const SelState *st = J.st;
+  if (J.sortP == 0 || st->done != 1u) return;
+  const int64_t n = (int64_t)st->ncand < J.cap ? (int64_t)st->ncand : J.cap;
+  for (int64_t x = blockIdx.x * 256 + threadIdx.x; x < J.sortP; x += (int64_t)gridDim.x * 256) {
+    J.skey[x] = x < n ? J.rec[x].key : ~0ull;
+    J.sidx[x] = (uint32_t)x;
+  }
+}
+
+// One compare-exchange stage (block size k, distance j >= kSortLocal) over
+// global memory: thread t handles the pair (lo, lo + j).
+__global__ void __launch_bounds__(256) sort_global_kernel(const SelJob *__restrict__ sj, int64_t k,
+                                                          int64_t j) {
+  const SelJob &J = sj[blockIdx.y];
+  if (J.sortP == 0 || J.st->done != 1u) return;
+  for (int64_t t = blockIdx.x * 256 + threadIdx.x; t < J.sortP / 2; t += (int64_t)gridDim.x * 256) {
+    const int64_t lo = ((t & ~(j - 1)) << 1) | (t & (j - 1)), hi = lo + j;
+    const bool asc = (lo & k) == 0;
+    const uint64_t ka = J.skey[lo], kb = J.skey[hi];
+    const uint32_t ia = J.sidx[lo], ib = J.sidx[hi];
+    if (asc ? sort_before(J, kb, ib, ka, ia) : sort_before(J, ka, ia, kb, ib)) {
+      J.skey[lo] = kb; J.skey[hi] = ka;
+      J.sidx[lo] = ib; J.sidx[hi] = ia;
     }
   }
+}
+
+// The stages of distance j < kSortLocal inside blocks of kSortLocal entries
+// in LDS: every block size from 2 up (full = 1), or only block size k.
+constexpr int kSortLocal = 2048;
+__global__ void __launch_bounds__(1024) sort_local_kernel(const SelJob *__restrict__ sj, int64_t k,
+                                                          int full) {
+  const SelJob &J = sj[blockIdx.y];
+  if (J.sortP == 0 || J.st->done != 1u) return;
+  __shared__ uint64_t lk[kSortLocal];
+  __shared__ uint32_t li[kSortLocal];
+  for (int64_t base = (int64_t)blockIdx.x * kSortLocal; base < J.sortP;
+       base += (int64_t)gridDim.x * kSortLocal) {
+    __syncthreads();
+    for (int x = threadIdx.x; x < kSortLocal; x += 1024) {
+      lk[x] = J.skey[base + x];
+      li[x] = J.sidx[base + x];
+    }
+    __syncthreads();
+    for (int64_t kk = full ? 2 : k; kk <= (full ? (int64_t)kSortLocal : k); kk <<= 1) {
+      for (int jj = (int)((kk < kSortLocal ? kk : kSortLocal) >> 1); jj > 0; jj >>= 1) {
+        const int t = threadIdx.x;  // pair t of the block
+        const int lo = ((t & ~(jj - 1)) << 1) | (t & (jj - 1)), hi = lo + jj;
+        const bool asc = ((base + lo) & kk) == 0;
+        const uint64_t ka = lk[lo], kb = lk[hi];
+        const uint32_t ia = li[lo], ib = li[hi];
+        if (asc ? sort_before(J, kb, ib, ka, ia) : sort_before(J, ka, ia, kb, ib)) {
+          lk[lo] = kb; lk[hi] = ka;
+          li[lo] = ib; li[hi] = ia;
+        }
+        __syncthreads();
+      }
+    }
+    for (int x = threadIdx.x; x < kSortLocal; x += 1024) {
+      J.skey[base + x] = lk[x];
+      J.sidx[base + x] = li[x];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) sort_emit_kernel(const SelJob *__restrict__ sj) {
+  const SelJob &J = sj[blockIdx.y];
+  const SelState *st = J.st;
+  if (J.sortP == 0 || st->done != 1u) return;
+  const int64_t keff = st->keff;
+  for (int64_t pos = blockIdx.x * 256 + threadIdx.x; pos < keff; pos += (int64_t)gridDim.x * 256)
+    emit_hit(J, J.sidx[pos], pos);
 }
 
 __global__ void write_seljob_kernel(SelJob j0, SelJob *dst) { if (threadIdx.x == 0) *dst = j0; }
@@ -654,7 +747,6 @@ hipError_t launch_select_kth(SelJob *sel_dev, int32_t n_jobs, int64_t max_T, hip
 
 hipError_t launch_select(SelJob *sel_dev, int32_t n_jobs, int64_t max_T, int64_t max_cap,
                          int32_t max_k, bool sampled, hipStream_t s) {
-  (void)max_k;
   const unsigned nj = (unsigned)n_jobs;
   hipLaunchKernelGGL(window_kernel, dim3((n_jobs + 63) / 64), dim3(64), 0, s, sel_dev, n_jobs);
   int64_t hb = (max_T + 256 * 16 - 1) / (256 * 16);
@@ -687,6 +779,20 @@ hipError_t launch_select(SelJob *sel_dev, int32_t n_jobs, int64_t max_T, int64_t
   if (kb > 1024) kb = 1024;
   if (kb < 1) kb = 1;
   hipLaunchKernelGGL(rank_kernel, dim3((unsigned)kb, nj), dim3(kRankThreads), 0, s, sel_dev);
+  const int64_t P = sort_len(max_cap);  // jobs with sort buffers (each skips the other path)
+  if (P > 0) {
+    const unsigned gb = (unsigned)std::min<int64_t>(P / 512, 4096);
+    const unsigned lb = (unsigned)std::min<int64_t>(P / kSortLocal, 1024);
+    hipLaunchKernelGGL(sort_init_kernel, dim3(gb, nj), dim3(256), 0, s, sel_dev);
+    hipLaunchKernelGGL(sort_local_kernel, dim3(lb, nj), dim3(1024), 0, s, sel_dev, (int64_t)0, 1);
+    for (int64_t k2 = 2 * kSortLocal; k2 <= P; k2 <<= 1) {
+      for (int64_t j = k2 >> 1; j >= kSortLocal; j >>= 1)
+        hipLaunchKernelGGL(sort_global_kernel, dim3(gb, nj), dim3(256), 0, s, sel_dev, k2, j);
+      hipLaunchKernelGGL(sort_local_kernel, dim3(lb, nj), dim3(1024), 0, s, sel_dev, k2, 0);
+    }
+    const unsigned eb = (unsigned)std::min<int64_t>((max_k + 255) / 256, 1024);
+    hipLaunchKernelGGL(sort_emit_kernel, dim3(eb > 0 ? eb : 1, nj), dim3(256), 0, s, sel_dev);
+  }
   return hipGetLastError();
 }
 
