@@ -355,6 +355,8 @@ __global__ void __launch_bounds__(256) finish_plain_kernel(const PlainJob *__res
   constexpr int KT = 256 / JB;
   constexpr int kTile = kPI * JB * KT;  // 4096 triplets
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  // after the table (its dynamic block starts at LDS address 0)
+  int2(*smk)[KT] = reinterpret_cast<int2(*)[KT]>(lds + (LDS ? (lf_len * 4 + 15) / 16 * 16 : 0));
   if (LDS) {
     float *tab = reinterpret_cast<float *>(lds);
     for (int x = threadIdx.x; x < lf_len; x += blockDim.x) tab[x] = lf32[x];
@@ -398,6 +400,17 @@ __global__ void __launch_bounds__(256) finish_plain_kernel(const PlainJob *__res
     plain_tile_origin(dec, t, M, JB, i0, j0, k0);
     const int64_t slot = tg - tile_begin;
     gptr<u4e> cor = (gptr<u4e>)(corners + slot * 2 * (int64_t)kTile);
+    // per-SNP counts (the pair tables' diagonals) of the tile's k range in
+    // LDS, so each lane's k margin is one conflict-free LDS read instead of a
+    // strided global load
+    __syncthreads();  // previous tile's readers are done
+    if (threadIdx.x < 2 * KT) {
+      const int c = threadIdx.x / KT, kl = threadIdx.x % KT;
+      const int k = k0 + kl < Mp ? k0 + kl : Mp - 1;
+      const i4e v = pr[(uint32_t)c * MpMp + (uint32_t)k * Mp + k];
+      smk[c][kl] = make_int2(v.x << 2, v.w << 2);
+    }
+    __syncthreads();
     for (int x = threadIdx.x; x < kTile; x += blockDim.x) {
       const int il = x / (JB * KT), jl = (x / KT) % JB, kl = x % KT;
       const int i = i0 + il, j = j0 + jl, k = k0 + kl;
@@ -415,12 +428,12 @@ __global__ void __launch_bounds__(256) finish_plain_kernel(const PlainJob *__res
         const i4e a4 = pr[cb + (uint32_t)i * Mp + j], b4 = pr[cb + (uint32_t)i * Mp + k];
         const i4e c4 = pr[cb + (uint32_t)j * Mp + k];
         const i4e ii = pr[cb + (uint32_t)i * Mp + i], jj = pr[cb + (uint32_t)j * Mp + j];
-        const i4e kk = pr[cb + (uint32_t)k * Mp + k];
+        const int2 kk2 = smk[c][kl];
         const int pij[4] = {a4.x << 2, a4.y << 2, a4.z << 2, a4.w << 2};
         const int pik[4] = {b4.x << 2, b4.y << 2, b4.z << 2, b4.w << 2};
         const int pjk[4] = {c4.x << 2, c4.y << 2, c4.z << 2, c4.w << 2};
         const int mi[2] = {ii.x << 2, ii.w << 2}, mj[2] = {jj.x << 2, jj.w << 2};
-        const int mk[2] = {kk.x << 2, kk.w << 2};
+        const int mk[2] = {kk2.x, kk2.y};
         complete_table(n, pij, pik, pjk, mi, mj, mk, c ? N1x4 : N0x4, tab[c]);
       }
       float k2 = 0.f;  // rows in order, each L[r + 1] - (L[r_0] + L[r_1])
@@ -523,7 +536,8 @@ static hipError_t launch_finish_plain_t(const PlainJob *jobs, const int64_t *job
   int n_cu = 0;
   hipError_t e = cu_count(&n_cu);
   if (e != hipSuccess) return e;
-  const size_t lds = (LDS ? (size_t)(lf_len * 4 + 15) / 16 * 16 : 0) + 16;  // table
+  const size_t lds = (LDS ? (size_t)(lf_len * 4 + 15) / 16 * 16 : 0) +
+                     2 * (256 / JB) * sizeof(int2);  // table, then the tile's k margins
   e = hipFuncSetAttribute(reinterpret_cast<const void *>(&finish_plain_kernel<JB, LDS, COUNTS>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;

@@ -343,9 +343,12 @@ __device__ __forceinline__ void quad_corner_counts(const uint32_t *planes, int64
 // rows with 0 and 1 there (every sample of the class is in one row).
 // SH scales every count by 2^SH (SH = 2: cells as byte offsets into an FP32
 // table); cnt and Nc must come scaled alike, the pairwise tables are scaled here.
+// ml_in: the per-SNP counts of SNP l already scaled (NULL: read from the
+// pairwise table's diagonal).
 template <int SH = 0>
 __device__ __forceinline__ void quad_cells(const uint32_t cnt[48], const int32_t *pairs, int64_t Mp,
-                                           int i, int j, int k, int l, int Nc, int t[81]) {
+                                           int i, int j, int k, int l, int Nc, int t[81],
+                                           const int *ml_in = nullptr) {
   const int4 *pr = reinterpret_cast<const int4 *>(pairs);
   auto pair = [&](int x, int y, int v[4]) {
     const int4 p = pr[(int64_t)x * Mp + y];
@@ -358,7 +361,13 @@ __device__ __forceinline__ void quad_cells(const uint32_t cnt[48], const int32_t
   int pij[4], pik[4], pil[4], pjk[4], pjl[4], pkl[4], mi[2], mj[2], mk[2], ml[2];
   pair(i, j, pij); pair(i, k, pik); pair(i, l, pil);
   pair(j, k, pjk); pair(j, l, pjl); pair(k, l, pkl);
-  marg(i, mi); marg(j, mj); marg(k, mk); marg(l, ml);
+  marg(i, mi); marg(j, mj); marg(k, mk);
+  if (ml_in) {
+    ml[0] = ml_in[0];
+    ml[1] = ml_in[1];
+  } else {
+    marg(l, ml);
+  }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll

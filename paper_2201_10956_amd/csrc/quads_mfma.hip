@@ -337,14 +337,16 @@ __global__ void __launch_bounds__(256) finish_quad_kernel(
     const uint4 *__restrict__ t3, const int32_t *__restrict__ pairs, int M, int Mp, int N0,
     int N1, int64_t T, int64_t tile_begin, int64_t n_tiles, const float *__restrict__ lf32,
     int lf_len, float *__restrict__ score, uint32_t *__restrict__ keyrange) {
-  // the LDS table is the kernel's whole dynamic LDS block, at LDS address 0
-  // (no static LDS), so a lookup is one ds_read at the byte offset
+  // the LDS table starts the kernel's dynamic LDS block, at LDS address 0
+  // (no static LDS), so a lookup is one ds_read at the byte offset; the
+  // per-SNP counts of the tile's l range follow it
   extern __shared__ float qtab[];
   const float *L = lf32;
   if (LDS) {
     for (int x = threadIdx.x; x < lf_len; x += blockDim.x) qtab[x] = lf32[x];
-    __syncthreads();
   }
+  int2(*sml)[kQLB] = reinterpret_cast<int2(*)[kQLB]>(
+      reinterpret_cast<unsigned char *>(qtab) + (LDS ? (lf_len * 4 + 15) / 16 * 16 : 0));
   cptr<int64_t> pre = as_const(pre_p);
   const int64_t MpMp4 = (int64_t)Mp * Mp * 4;
   uint32_t kmin = 0xffffffffu, kmax = 0u;
@@ -359,6 +361,16 @@ __global__ void __launch_bounds__(256) finish_quad_kernel(
     }
     int ib, kb, lb;
     q_decode(M, j, t - jlo, ib, kb, lb);
+    // per-SNP counts of the tile's 32 l (pair-table diagonals) into LDS: one
+    // conflict-free LDS read per lane instead of a strided global load
+    __syncthreads();  // previous tile's readers are done (and the table is in)
+    if (threadIdx.x < 2 * kQLB) {
+      const int c = threadIdx.x / kQLB, ll = threadIdx.x % kQLB;
+      const int l = lb * kQLB + ll < Mp ? lb * kQLB + ll : Mp - 1;
+      const int4 v = reinterpret_cast<const int4 *>(pairs + c * MpMp4)[(int64_t)l * Mp + l];
+      sml[c][ll] = make_int2(v.x << 2, v.w << 2);
+    }
+    __syncthreads();
     for (int x = threadIdx.x; x < 4 * kQKB * kQLB; x += blockDim.x) {
       const int ll = x & (kQLB - 1), kk = (x / kQLB) & (kQKB - 1), w = x / (kQLB * kQKB);
       const int i = 4 * ib + w, k = kb * kQKB + kk, l = lb * kQLB + ll;
@@ -387,7 +399,9 @@ __global__ void __launch_bounds__(256) finish_quad_kernel(
         unpack8q(tcl[lex_base(M, i, k) + l], cnt + 32);
         unpack8q(tcl[lex_base(M, j, k) + l], cnt + 40);
         // cells as byte offsets into the FP32 table (x 4)
-        quad_cells<2>(cnt, pairs + c * MpMp4, Mp, i, j, k, l, (c ? N1 : N0) << 2, tc[c]);
+        const int2 mlv = sml[c][ll];
+        const int ml[2] = {mlv.x, mlv.y};
+        quad_cells<2>(cnt, pairs + c * MpMp4, Mp, i, j, k, l, (c ? N1 : N0) << 2, tc[c], ml);
       }
       float k2 = 0.f;  // rows in order: L[r + 1] - (L[r_0] + L[r_1])
 #pragma unroll
@@ -421,7 +435,7 @@ hipError_t launch_finish_quad_t(const epi3_dataset &d, const uint2 *corners, con
                                 const uint4 *t3, int64_t tile_begin, int64_t n_tiles,
                                 float *score, uint32_t *keyrange, int n_cu, hipStream_t s) {
   const int lf_len = d.n_samples + 2;
-  const int lds = LDS ? lf_len * 4 : 0;
+  const int lds = (LDS ? (lf_len * 4 + 15) / 16 * 16 : 0) + 2 * kQLB * (int)sizeof(int2);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&finish_quad_kernel<LDS>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e != hipSuccess) return e;
