@@ -513,9 +513,7 @@ def run_perm(args, wl):
                        "traffic_unit": "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
                        "kernel": "count_mfma_perm_kernel", "kernel_ms": round(k_ms / max(k_n, 1), 4),
                        "launches_per_step": k_n,
-                       "ops_per_launch": MFMA_OPS_PER_STQ * T * N * Q / max(k_n, 1),
-                       "measured_peak_note": "register-only chains sustain 4.6 POP/s (int8 32x32x32) "
-                                             "and 9.0 PFLOP/s (fp4 32x32x64)"}
+                       "ops_per_launch": MFMA_OPS_PER_STQ * T * N * Q / max(k_n, 1)}
     out["breakdown_ms"] = {"count_kernels": round(k_ms, 3), "finish_kernels": round(fin_ms, 3),
                            "selection": round(sel_ms, 3)}
     out["min_k2_per_phenotype"] = [round(float(h["k2"][0]), 6) for h in res[:4]] + ["..."]
@@ -580,7 +578,10 @@ def run_uneven(args, wl):
         achieved = MFMA_OPS_PER_ST * w_mfma / (m_ms / 1e3) / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                 "unit": "TFLOP/s (fp4)" if fp4 else "TOP/s (int8)", "frac": round(achieved / peak, 4),
-                "traffic": None, "kernel": "count_mfma_plain_kernel",
+                "traffic": recorded_traffic(f"{args.workload}|{'mfma_fp4' if fp4 else 'mfma'}"),
+                "traffic_unit": "bytes per launch of the matrix-core subset's count kernel "
+                                "(FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
+                "kernel": "count_mfma_plain_kernel",
                 "kernel_ms": round(m_ms / max(m_n, 1), 4), "launches": m_n,
                 "datasets_timed": len(on_mfma), "ops": MFMA_OPS_PER_ST * w_mfma}
     else:
