@@ -194,9 +194,20 @@ using gptr = const __attribute__((address_space(1))) T *;
 // corner cells, 2 column tiles of 32 phenotypes).
 // FP4: operands are E2M1 nibbles (each staged byte holds two samples, so a
 // 32-byte step covers 64 samples) on v_mfma_scale_f32_32x32x64_f8f6f4 with
-// unit scales; accumulation in FP32 is exact for counts below 2^24.
+// unit scales; accumulation in FP32 is exact for counts below 2^24.  The
+// all-sample corner counts (the phenotype-independent column) come from one
+// 16 x 16 x 128 product per wave and chunk over the staged pair and k rows;
+// int8 operands count them by popcounts of the A rows.
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+// 16 x 16 x 128 FP4 product with unit scales (all-sample corner counts)
+__device__ __forceinline__ v4f tot_mma(v4i a, v4i b, v4f c) {
+  const v8i a8 = {a.x, a.y, a.z, a.w, 0, 0, 0, 0};
+  const v8i b8 = {b.x, b.y, b.z, b.w, 0, 0, 0, 0};
+  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a8, b8, c, 4, 4, 0, 127, 0, 127);
+}
 
 template <bool FP4>
 struct PermAcc {
@@ -238,6 +249,9 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
   typedef PermAcc<FP4> Acc;
   __shared__ __attribute__((aligned(16))) unsigned char stage[2 * kStageBytes];
   __shared__ int64_t sTile[2];
+  // FP4: all-sample corner counts of half the samples from the waves of the
+  // second half, added by the waves of the first half
+  __shared__ float sTot[2][64][4];
 
   const PermJob pj = *pjp;
   const int tid = threadIdx.x;
@@ -346,6 +360,15 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[tt][0][v] = acc[tt][1][v] = 0;
     }
+    // FP4: the all-sample corner counts of the tile are one 16 x 16 product
+    // per k half: rows = the 16 pair rows (4 pivots x (a, b)), columns = 8 k
+    // x c, K = 128 samples; wave w takes k half w % 2 and the chunk's sample
+    // half w / 2 (one product per chunk)
+    v4f tacc = {0.f, 0.f, 0.f, 0.f};
+    const int tkh = wave & 1, tsh = wave >> 1;
+    const int o_ta = (kRowsPH + kRowsXK + (lane & 15)) * kRow + 64 * tsh + 16 * (lane >> 4);
+    const int o_tb = (kRowsPH + 16 * tkh + (lane & 15)) * kRow + 64 * tsh + 16 * (lane >> 4);
+    v4i tA, tB;
     fetch(0);
     store(0);
     __syncthreads();
@@ -354,7 +377,9 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
     // Software pipeline over the steps of a chunk: while the matrix products
     // of step s run, the operands of step s + 1 are read from LDS (two
     // register sets, X and Y, taken in turn), and each row tile's A rows are
-    // formed between the products of the previous row tile.  The next chunk
+    // formed between the products of the previous row tile (int8: four
+    // vector instructions between products, with the popcounts, by
+    // scheduling-group hints; FP4 schedules better without them).  The next chunk
     // is stored to the other LDS buffer before the last step of a chunk and
     // one barrier follows, so the last step already reads the first operands
     // of the next chunk and the pipeline does not drain between chunks.
@@ -371,7 +396,7 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
       const v4i a_ = (P) & quad_bcast<TT>(X);                                     \
       acc[TT][0] = Acc::mma(a_, B0, acc[TT][0]);                                  \
       acc[TT][1] = Acc::mma(a_, B1, acc[TT][1]);                                  \
-      tot[TT] = popc4_acc(a_, tot[TT]);                                           \
+      if constexpr (!FP4) tot[TT] = popc4_acc(a_, tot[TT]);                       \
     }
 #define EPI3_SCHED                                                                  \
     __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);                            \
@@ -392,6 +417,9 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
     __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);                            \
     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
     __builtin_amdgcn_sched_barrier(0);
+// FP4: a scheduling barrier between steps only; the compiler interleaves
+// the four A-row ANDs of each row tile with the products itself
+#define EPI3_SCHED4 __builtin_amdgcn_sched_barrier(0);
 #define EPI3_STEP(P, X, B0, B1)                                                     \
     EPI3_TILE(0, P, X, B0, B1)                                                    \
     EPI3_TILE(1, P, X, B0, B1)                                                    \
@@ -404,42 +432,84 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
       if (more) fetch(ch + 1);
       const uint8_t *buf = stage + (ch & 1) * kStageBytes;
       const uint8_t *nbuf = stage + ((ch + 1) & 1) * kStageBytes;
-      EPI3_LD(buf, 1, pY, xY, b0Y, b1Y)
-      EPI3_STEP(pX, xX, b0X, b1X)
-      EPI3_SCHED
-      EPI3_LD(buf, 2, pX, xX, b0X, b1X)
-      EPI3_STEP(pY, xY, b0Y, b1Y)
-      EPI3_SCHED
-      EPI3_LD(buf, 3, pY, xY, b0Y, b1Y)
-      EPI3_STEP(pX, xX, b0X, b1X)
-      EPI3_SCHED
+      if constexpr (FP4) {
+        EPI3_LD(buf, 1, pY, xY, b0Y, b1Y)
+        EPI3_STEP(pX, xX, b0X, b1X)
+        EPI3_SCHED4
+        EPI3_LD(buf, 2, pX, xX, b0X, b1X)
+        EPI3_STEP(pY, xY, b0Y, b1Y)
+        EPI3_SCHED4
+        EPI3_LD(buf, 3, pY, xY, b0Y, b1Y)
+        tA = *reinterpret_cast<const v4i *>(buf + o_ta);
+        tB = *reinterpret_cast<const v4i *>(buf + o_tb);
+        EPI3_STEP(pX, xX, b0X, b1X)
+        tacc = tot_mma(tA, tB, tacc);
+        EPI3_SCHED4
+      } else {
+        EPI3_LD(buf, 1, pY, xY, b0Y, b1Y)
+        EPI3_STEP(pX, xX, b0X, b1X)
+        EPI3_SCHED
+        EPI3_LD(buf, 2, pX, xX, b0X, b1X)
+        EPI3_STEP(pY, xY, b0Y, b1Y)
+        EPI3_SCHED
+        EPI3_LD(buf, 3, pY, xY, b0Y, b1Y)
+        EPI3_STEP(pX, xX, b0X, b1X)
+        EPI3_SCHED
+      }
       // the products above stay before the branch (they would otherwise be
       // sunk to their first use below it)
 #pragma unroll
       for (int tt = 0; tt < kPermT; ++tt) asm volatile("" : "+v"(acc[tt][0]), "+v"(acc[tt][1]));
+      if constexpr (FP4) asm volatile("" : "+v"(tacc));
       if (more) store((ch + 1) & 1);
       __syncthreads();
       // after the last chunk this reads the other buffer's stale contents,
       // which no product uses
       EPI3_LD(nbuf, 0, pX, xX, b0X, b1X)
       EPI3_STEP(pY, xY, b0Y, b1Y)
-      EPI3_SCHED
+      if constexpr (FP4) {
+        EPI3_SCHED4
+      } else {
+        EPI3_SCHED
+      }
     }
 #undef EPI3_LD
 #undef EPI3_TILE
 #undef EPI3_SCHED
+#undef EPI3_SCHED4
 #undef EPI3_STEP
 
+    if constexpr (FP4) {
+      // lane l holds column l % 16 = (k = 8 tkh + (l % 16) / 2, c = l % 2) and
+      // rows 4 (l / 16) + v = (pivot l / 16, (a, b) = v)
+      if (tsh == 1) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sTot[tkh][lane][v] = tacc[v];
+      }
+      __syncthreads();
+      if (tsh == 0) {
+        const int p = lane >> 4;
+        if (4 * ib + p < j) {
+          uint16_t *t16 = reinterpret_cast<uint16_t *>(pj.totals + (slot * 4 + p) * (int64_t)kPermKB);
+          const int kl = 8 * tkh + ((lane & 15) >> 1), c = lane & 1;
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            t16[kl * 8 + 2 * v + c] = (uint16_t)(uint32_t)(tacc[v] + sTot[tkh][lane][v]);
+        }
+      }
+    }
     if (i >= j) continue;  // padding pivot of the last i-block: nothing to write
 
     // ---- counts out: all-sample corner cells per triplet, case corner cells
     // per (triplet, phenotype); the finish kernel completes tables and scores.
     uint4 *cor = pj.corners + (slot * 4 + wave) * (int64_t)kPermKB * 64;
-    uint16_t *tot16 = reinterpret_cast<uint16_t *>(pj.totals + (slot * 4 + wave) * (int64_t)kPermKB);
+    if constexpr (!FP4) {
+      uint16_t *tot16 = reinterpret_cast<uint16_t *>(pj.totals + (slot * 4 + wave) * (int64_t)kPermKB);
 #pragma unroll
-    for (int tt = 0; tt < kPermT; ++tt) {
-      const uint32_t full = tot[tt] + __shfl_xor(tot[tt], 32);
-      if (g == 0) tot16[(4 * tt + ta) * 8 + 4 * ra + 2 * rb + rc] = (uint16_t)full;
+      for (int tt = 0; tt < kPermT; ++tt) {
+        const uint32_t full = tot[tt] + __shfl_xor(tot[tt], 32);
+        if (g == 0) tot16[(4 * tt + ta) * 8 + 4 * ra + 2 * rb + rc] = (uint16_t)full;
+      }
     }
     // lane (q, h) holds, for each of the 4 triplets of a row tile, the 4 case
     // cells with genotype c = h at SNP k: registers 4 t + (2 a + b).  Each lane

@@ -249,24 +249,9 @@ __global__ void __launch_bounds__(256, 2) count_mfma_quad_kernel(
         acc[TT][0] = qmma(a_, B0, acc[TT][0]);                                      \
         acc[TT][1] = qmma(a_, B1, acc[TT][1]);                                      \
       }
-#define EPI3_QSCHED                                                                   \
-      __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);                            \
-      __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);                            \
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
-      __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);                            \
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
-      __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);                            \
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
-      __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);                            \
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
-      __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);                            \
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
-      __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);                            \
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
-      __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);                            \
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
-      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                            \
-      __builtin_amdgcn_sched_barrier(0);
+// a scheduling barrier between steps; the compiler interleaves each row
+// tile's A-row ANDs with the products itself
+#define EPI3_QSCHED __builtin_amdgcn_sched_barrier(0);
 #define EPI3_QSTEP(P, X, B0, B1)                                                      \
       EPI3_QTILE(0, P, X, B0, B1)                                                   \
       EPI3_QTILE(1, P, X, B0, B1)                                                   \
