@@ -16,8 +16,8 @@
 // SNPs instead of the 161 of a (32 i, one j, 128 k) slab.  Each of the 4
 // waves owns 2 i-blocks of 8 x 2 j (four 32-row A tiles: 8 i x (a, b), the
 // rows X_i[a] & X_j[b] formed in registers) and two 32-column B tiles
-// (16 k x g).  Operand rows are staged per 64-byte chunk in double-buffered
-// LDS.
+// (16 k x g).  Operand rows are staged per chunk of 128 bytes (64 for
+// JB = 2) in double-buffered LDS.
 #include "epi3_internal.h"
 
 namespace epi3 {
@@ -32,8 +32,11 @@ template <typename T>
 using gptr = const __attribute__((address_space(1))) T *;
 
 constexpr int kPI = kPlainI;   // i per workgroup tile
-constexpr int kPKC = 64;       // bytes per staged chunk of a row
-constexpr int kPRow = kPKC + 16;
+
+// Bytes per staged chunk of a row: 128 (four steps per barrier), 64 for
+// JB = 2, whose 176 rows would otherwise take more than half of the LDS.
+// Rows are padded by 16 bytes against bank conflicts.
+__host__ __device__ constexpr int plain_chunk(int JB) { return JB == 2 ? 64 : 128; }
 
 __host__ __device__ __forceinline__ int plain_kt(int JB) { return 256 / JB; }
 
@@ -174,6 +177,7 @@ __global__ void __launch_bounds__(256, 2) count_mfma_plain_kernel(
     unsigned long long *__restrict__ queue) {
   typedef PlainAcc<FP4> Acc;
   constexpr int KT = 256 / JB;
+  constexpr int kPKC = plain_chunk(JB), kPRow = kPKC + 16;
   constexpr int kRowsI = 2 * kPI, kRowsJ = 2 * JB, kRowsK = 2 * KT;
   constexpr int kRows = kRowsI + kRowsJ + kRowsK;
   constexpr int kBuf = kRows * kPRow;
@@ -184,7 +188,7 @@ __global__ void __launch_bounds__(256, 2) count_mfma_plain_kernel(
   __shared__ __attribute__((aligned(16))) unsigned char stage[2 * kBuf];
   __shared__ int64_t sTile[2];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wj = wave / NBP, wb = wave - wj * NBP;
   const int r = lane & 31, g = lane >> 5;
   cptr<int64_t> job_begin = as_const(job_begin_p);
@@ -225,7 +229,9 @@ __global__ void __launch_bounds__(256, 2) count_mfma_plain_kernel(
     plain_tile_origin(dec, t, M, JB, i0, j0, k0);
 
     for (int cls = 0; cls < 2; ++cls) {
-      const int nch = (cls ? Sb1 : Sb0) / kPKC;
+      // the class's bytes rounded up to whole chunks (rows are zero-padded
+      // to a multiple of 128 bytes)
+      const int nch = ((cls ? Sb1 : Sb0) + kPKC - 1) / kPKC;
       const int64_t cbase = (int64_t)cls * Mp * 2;  // first row of this class
       // staging plan: rows [0, 32) X_i (i0 + x / 2, plane x % 2), then 2 JB
       // rows X_j, then 2 KT rows X_k (k0 + x / 2, plane x % 2)
@@ -307,6 +313,12 @@ __global__ void __launch_bounds__(256, 2) count_mfma_plain_kernel(
       // Record (i, j, k) of class cls is 16 bytes: plane-0 cells then plane-1
       // cells, each 4 x uint16 in (a, b) order.
       uint2 *cor = reinterpret_cast<uint2 *>(corners) + ((slot * 2 + cls) * (int64_t)kPI * 256) * 2;
+      // record (il, jl, kl) = (8 x + 2 u + g, 2 wj + y, 16 (2 wb + z) + ck16)
+      // sits at a constant per (x, y, z, u) plus one lane offset; the offset
+      // is made opaque here so the 32 addresses are formed at the stores
+      // instead of being held in registers through the tile
+      uint32_t lo = (uint32_t)(((g * JB + 2 * wj) * KT + 32 * wb + ck16) * 2 + cpl);
+      asm volatile("" : "+v"(lo));
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -315,11 +327,10 @@ __global__ void __launch_bounds__(256, 2) count_mfma_plain_kernel(
           for (int z = 0; z < 2; ++z)
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-              const int il = 8 * x + 2 * u + g, jl = 2 * wj + y, kl = 16 * (2 * wb + z) + ck16;
+              const int c_off = (((8 * x + 2 * u) * JB + y) * KT + 16 * z) * 2;
               const uint32_t c0 = Acc::get(acc[x][y][z], 4 * u + 0), c1 = Acc::get(acc[x][y][z], 4 * u + 1);
               const uint32_t c2 = Acc::get(acc[x][y][z], 4 * u + 2), c3 = Acc::get(acc[x][y][z], 4 * u + 3);
-              cor[(((int64_t)il * JB + jl) * KT + kl) * 2 + cpl] =
-                  make_uint2(c0 | (c1 << 16), c2 | (c3 << 16));
+              (cor + c_off)[lo] = make_uint2(c0 | (c1 << 16), c2 | (c3 << 16));
             }
     }
   }
