@@ -279,35 +279,87 @@ __global__ void __launch_bounds__(256, 2) count_mfma_plain_kernel(
         store(0);
       }
       __syncthreads();
-      for (int ch = 0; ch < nch; ++ch) {
-        if (ch + 1 < nch) fetch(ch + 1);
-        const uint8_t *buf = stage + (ch & 1) * kBuf;
-#pragma unroll 1
-        for (int stp = 0; stp < kPKC / 32; ++stp) {
-          const int off = stp * 32 + 16 * g;
-          // the quad (a, b) loads X_i[a] of i-block b and X_j[b] of pivot a;
-          // DPP hands each lane the two rows its A rows need
-          const v4i xiq = *reinterpret_cast<const v4i *>(buf + xi_off + off);
-          const v4i xjq = *reinterpret_cast<const v4i *>(buf + xj_off + off);
-          v4i b[2];
+      const int o_xi = xi_off + 16 * g, o_xj = xj_off + 16 * g;
+      const int o_b0 = (kRowsI + kRowsJ + 2 * (16 * (2 * wb) + ck16) + cpl) * kPRow + 16 * g;
+      const int o_b1 = (kRowsI + kRowsJ + 2 * (16 * (2 * wb + 1) + ck16) + cpl) * kPRow + 16 * g;
+#define EPI3_PLD(BB, STP, XI, XJ, B0, B1)                                           \
+      XI = *reinterpret_cast<const v4i *>((BB) + o_xi + 32 * (STP));              \
+      XJ = *reinterpret_cast<const v4i *>((BB) + o_xj + 32 * (STP));              \
+      B0 = *reinterpret_cast<const v4i *>((BB) + o_b0 + 32 * (STP));              \
+      B1 = *reinterpret_cast<const v4i *>((BB) + o_b1 + 32 * (STP));
+#define EPI3_PSTEP(XI, XJ, B0, B1)                                                  \
+      {                                                                           \
+        const v4i xi_[2] = {quad_perm<0xA0>(XI), quad_perm<0xF5>(XI)};            \
+        _Pragma("unroll") for (int x = 0; x < 2; ++x) {                           \
+          const v4i a0 = xi_[x] & quad_perm<0x44>(XJ);                            \
+          acc[x][0][0] = Acc::mma(a0, B0, acc[x][0][0]);                          \
+          acc[x][0][1] = Acc::mma(a0, B1, acc[x][0][1]);                          \
+          const v4i a1 = xi_[x] & quad_perm<0xEE>(XJ);                            \
+          acc[x][1][0] = Acc::mma(a1, B0, acc[x][1][0]);                          \
+          acc[x][1][1] = Acc::mma(a1, B1, acc[x][1][1]);                          \
+        }                                                                         \
+      }                                                                           \
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (kPKC == 128) {
+        // software pipeline over the four steps of a chunk (operand sets X
+        // and Y in turn; the next chunk is stored before the last step)
+        v4i xiX, xjX, b0X, b1X, xiY, xjY, b0Y, b1Y;
+        EPI3_PLD(stage, 0, xiX, xjX, b0X, b1X)
+        for (int ch = 0; ch < nch; ++ch) {
+          const bool more = ch + 1 < nch;
+          if (more) fetch(ch + 1);
+          const uint8_t *buf = stage + (ch & 1) * kBuf;
+          const uint8_t *nbuf = stage + ((ch + 1) & 1) * kBuf;
+          EPI3_PLD(buf, 1, xiY, xjY, b0Y, b1Y)
+          EPI3_PSTEP(xiX, xjX, b0X, b1X)
+          EPI3_PLD(buf, 2, xiX, xjX, b0X, b1X)
+          EPI3_PSTEP(xiY, xjY, b0Y, b1Y)
+          EPI3_PLD(buf, 3, xiY, xjY, b0Y, b1Y)
+          EPI3_PSTEP(xiX, xjX, b0X, b1X)
 #pragma unroll
           for (int x = 0; x < 2; ++x)
-            b[x] = *reinterpret_cast<const v4i *>(
-                buf + (kRowsI + kRowsJ + 2 * (16 * (2 * wb + x) + ck16) + cpl) * kPRow + off);
-          const v4i xi[2] = {quad_perm<0xA0>(xiq), quad_perm<0xF5>(xiq)};  // [0,0,2,2], [1,1,3,3]
 #pragma unroll
-          for (int x = 0; x < 2; ++x) {
-            const v4i a0 = xi[x] & quad_perm<0x44>(xjq);  // [0,1,0,1]: X_j[b] of pivot 0
-            acc[x][0][0] = Acc::mma(a0, b[0], acc[x][0][0]);
-            acc[x][0][1] = Acc::mma(a0, b[1], acc[x][0][1]);
-            const v4i a1 = xi[x] & quad_perm<0xEE>(xjq);  // [2,3,2,3]: X_j[b] of pivot 1
-            acc[x][1][0] = Acc::mma(a1, b[0], acc[x][1][0]);
-            acc[x][1][1] = Acc::mma(a1, b[1], acc[x][1][1]);
-          }
+            for (int y = 0; y < 2; ++y) asm volatile("" : "+v"(acc[x][y][0]), "+v"(acc[x][y][1]));
+          if (more) store((ch + 1) & 1);
+          __syncthreads();
+          // after the last chunk this reads the other buffer's stale
+          // contents, which no product uses
+          EPI3_PLD(nbuf, 0, xiX, xjX, b0X, b1X)
+          EPI3_PSTEP(xiY, xjY, b0Y, b1Y)
         }
-        if (ch + 1 < nch) store((ch + 1) & 1);
-        __syncthreads();
+      } else {
+        for (int ch = 0; ch < nch; ++ch) {
+          if (ch + 1 < nch) fetch(ch + 1);
+          const uint8_t *buf = stage + (ch & 1) * kBuf;
+  #pragma unroll 1
+          for (int stp = 0; stp < kPKC / 32; ++stp) {
+            const int off = stp * 32 + 16 * g;
+            // the quad (a, b) loads X_i[a] of i-block b and X_j[b] of pivot a;
+            // DPP hands each lane the two rows its A rows need
+            const v4i xiq = *reinterpret_cast<const v4i *>(buf + xi_off + off);
+            const v4i xjq = *reinterpret_cast<const v4i *>(buf + xj_off + off);
+            v4i b[2];
+  #pragma unroll
+            for (int x = 0; x < 2; ++x)
+              b[x] = *reinterpret_cast<const v4i *>(
+                  buf + (kRowsI + kRowsJ + 2 * (16 * (2 * wb + x) + ck16) + cpl) * kPRow + off);
+            const v4i xi[2] = {quad_perm<0xA0>(xiq), quad_perm<0xF5>(xiq)};  // [0,0,2,2], [1,1,3,3]
+  #pragma unroll
+            for (int x = 0; x < 2; ++x) {
+              const v4i a0 = xi[x] & quad_perm<0x44>(xjq);  // [0,1,0,1]: X_j[b] of pivot 0
+              acc[x][0][0] = Acc::mma(a0, b[0], acc[x][0][0]);
+              acc[x][0][1] = Acc::mma(a0, b[1], acc[x][0][1]);
+              const v4i a1 = xi[x] & quad_perm<0xEE>(xjq);  // [2,3,2,3]: X_j[b] of pivot 1
+              acc[x][1][0] = Acc::mma(a1, b[0], acc[x][1][0]);
+              acc[x][1][1] = Acc::mma(a1, b[1], acc[x][1][1]);
+            }
+          }
+          if (ch + 1 < nch) store((ch + 1) & 1);
+          __syncthreads();
+        }
       }
+#undef EPI3_PLD
+#undef EPI3_PSTEP
       // corners out: lane (column, g) holds rows 8 u + 4 g + w, i.e. pivot
       // i8 = 2 u + g with cells (a, b) = w, for its column (k16, plane).
       // Record (i, j, k) of class cls is 16 bytes: plane-0 cells then plane-1
