@@ -547,9 +547,14 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
 // declares no static LDS, so the dynamic block and with it the table start at
 // LDS address 0 and a lookup is one ds_read at the byte offset.
 struct FinishPermLds {
-  float score[4][kPermKB][64];
   uint32_t range[64][2];
+  float score[4][kPermKB][64];  // staged scores (score-plane mode only)
 };
+// Bytes of the block after the table: the sample and bounded modes leave the
+// score staging out (more workgroups per CU).
+__host__ __device__ constexpr size_t finish_perm_lds_bytes(int mode) {
+  return mode == kPermOutPlane ? sizeof(FinishPermLds) : offsetof(FinishPermLds, score);
+}
 __host__ __device__ __forceinline__ int finish_perm_table_bytes(int lf_len) {
   return (lf_len * 4 + 15) / 16 * 16;
 }
@@ -575,7 +580,7 @@ __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restr
   }
   __syncthreads();
   const PermJob pj = *pjp;
-  const int q = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int q = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int M = pj.M, Mp = pj.Mp, Q = pj.Q, Qp = pj.Qp;
   const int64_t T = pj.T;
   cptr<int64_t> pre = as_const(pj.jprefix);
@@ -607,7 +612,11 @@ __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restr
     const int64_t t = tile_begin + slot * stride;
     const int j = pivot_of(t);
     const int64_t rr = t - pre[j];
-    const int ib = (int)(rr / perm_nkb(M, j)), kbg = perm_kb_lo(j) + (int)(rr % perm_nkb(M, j));
+    // the quotient comes out of vector instructions: taken back to a scalar
+    // register, so the row addresses below are formed by scalar arithmetic
+    const int nkb_j = perm_nkb(M, j);
+    const int ib = __builtin_amdgcn_readfirstlane((int)rr / nkb_j);
+    const int kbg = perm_kb_lo(j) + ((int)rr - ib * nkb_j);
     const int i = 4 * ib + wave;
     const int k0 = kbg * kPermKB;
     if (i >= j) continue;  // wave-uniform
@@ -646,19 +655,27 @@ __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restr
     const u2e cii = cp_row(i, i)[qc], cjj = cp_row(j, j)[qc];
     const int aij[4] = {lo4(cij.x), hi4(cij.x), lo4(cij.y), hi4(cij.y)};
     const int mi[2] = {lo4(cii.x), hi4(cii.y)}, mj[2] = {lo4(cjj.x), hi4(cjj.y)};
-    // loads of the next k are issued before the current k is scored
-    u4e cq_n = cor[kk_lo * 64 + qc];
-    u2e cik_n = cp_row(i, k0 + kk_lo)[qc], cjk_n = cp_row(j, k0 + kk_lo)[qc];
-    u2e ckk_n = cp_row(k0 + kk_lo, k0 + kk_lo)[qc];
+    // loads of the next k are issued before the current k is scored; the
+    // (uniform) row pointers advance by one k per step, each load being a
+    // scalar base plus the lane's phenotype offset
+    gptr<u4e> pq = cor + kk_lo * 64;
+    gptr<u2e> pik = cp_row(i, k0 + kk_lo), pjk = cp_row(j, k0 + kk_lo);
+    gptr<u2e> pkk = cp_row(k0 + kk_lo, k0 + kk_lo);
+    const int64_t dkk = (int64_t)(Mp + 1) * Qp;
+    u4e cq_n = pq[qc];
+    u2e cik_n = pik[qc], cjk_n = pjk[qc], ckk_n = pkk[qc];
     for (int kk = kk_lo; kk < kk_hi; ++kk) {
       const u4e cq = cq_n;
       const u2e cik = cik_n, cjk = cjk_n, ckk = ckk_n;
       if (kk + 1 < kk_hi) {
-        const int kn = k0 + kk + 1;
-        cq_n = cor[(kk + 1) * 64 + qc];
-        cik_n = cp_row(i, kn)[qc];
-        cjk_n = cp_row(j, kn)[qc];
-        ckk_n = cp_row(kn, kn)[qc];
+        pq += 64;
+        pik += Qp;
+        pjk += Qp;
+        pkk += dkk;
+        cq_n = pq[qc];
+        cik_n = pik[qc];
+        cjk_n = pjk[qc];
+        ckk_n = pkk[qc];
       }
       int c4[27];
       {
@@ -814,7 +831,7 @@ static hipError_t launch_finish_perm_l(const PermJob *pj_dev, int64_t tile_begin
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  const size_t lds = (LDS ? (size_t)finish_perm_table_bytes(lf_len) : 0) + sizeof(FinishPermLds);
+  const size_t lds = (LDS ? (size_t)finish_perm_table_bytes(lf_len) : 0) + finish_perm_lds_bytes(MODE);
   e = hipFuncSetAttribute(reinterpret_cast<const void *>(&finish_perm_kernel<LDS, MODE>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
