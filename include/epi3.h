@@ -164,13 +164,17 @@ int epi3_encode(const uint8_t *geno_dev, int64_t ld, const uint8_t *pheno_host,
 /* Workspace bytes for epi3_scan + epi3_topk with count kernel `variant`.
  * cand_cap <= 0 picks a default capacity for FP32-screen candidates.  The
  * matrix-core variants add a scratch buffer for counted corner cells at the
- * end of the workspace; every other part sits at the same offset for all
- * variants. */
+ * end of the workspace (and, selecting by bound, a sample plane); the
+ * selection state and the hits sit at the same offset for all variants.
+ * The FP32 score plane (4 C(M,3) bytes) is part of it unless the scan selects
+ * by bound (epi3_set_scan_select). */
 int64_t epi3_workspace_bytes(const epi3_dataset *d, int32_t k, int32_t variant, int64_t cand_cap);
 
 /* Count + score every triplet and select candidates; asynchronous.
  * variant: EPI3_VARIANT_*.  EPI3_VARIANT_MFMA and _MFMA_FP4 need class sizes
- * of at most 65535 samples (EPI3_E_UNSUPPORTED otherwise).
+ * of at most 65535 samples (EPI3_E_UNSUPPORTED otherwise).  Selecting by
+ * bound (epi3_set_scan_select) needs a matrix-core variant
+ * (EPI3_E_UNSUPPORTED for EPI3_VARIANT_VALU).
  * ws_dev: device workspace of epi3_workspace_bytes(d, k, variant, cand_cap)
  * bytes (256-byte aligned). */
 int epi3_scan(const epi3_dataset *d, int32_t k, int32_t variant, int64_t cand_cap,
@@ -178,14 +182,16 @@ int epi3_scan(const epi3_dataset *d, int32_t k, int32_t variant, int64_t cand_ca
 
 /* Re-score candidates in FP64, order them and copy min(k, C(M,3)) hits to
  * hits_host [k]; *n_out receives the count.  Synchronises `stream`.
- * EPI3_E_CAPACITY: *n_out receives the candidate count needed; retry with
- * cand_cap >= that value. */
+ * EPI3_E_CAPACITY: *n_out receives the candidate count needed (selecting by
+ * bound: the cand_cap whose list, 16 x cand_cap entries, holds every score
+ * under the bound); retry with cand_cap >= that value. */
 int epi3_topk(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
               epi3_hit *hits_host, int32_t *n_out, void *stream);
 
 /* Device address of the FP32 score plane inside a plain-scan workspace:
  * K2_fp32 of every triplet in lexicographic (i, j, k) order, C(M,3) floats,
- * valid once the stream has run epi3_scan (and until the workspace is reused). */
+ * valid once the stream has run epi3_scan (and until the workspace is reused).
+ * EPI3_E_UNSUPPORTED when the scan selects by bound (no plane). */
 int epi3_score_plane(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
                      float **plane_dev);
 
@@ -470,6 +476,23 @@ int epi3_set_compact_cap(int64_t n);
  * EPI3_E_INVALID for another value. */
 enum { EPI3_BATCH_SELECT_AUTO = 0, EPI3_BATCH_SELECT_PLANE = 1, EPI3_BATCH_SELECT_BOUNDED = 2 };
 int epi3_set_batch_select(int32_t mode);
+
+/* The same choice for plain scans (epi3_scan), process-wide (same rules as
+ * epi3_set_pass_bytes; it sizes the workspaces):
+ *   PLANE    every FP32 score goes to the score plane (4 C(M,3) bytes);
+ *   BOUNDED  no plane (matrix-core variants): every sample_stride-th tile
+ *            (about max(1024, 8 k) tiles of 4096 triplets) is scored first,
+ *            the sample's k-th smallest score plus 2 e(N) bounds the FP32
+ *            score of every member of the exact top-k, and the full pass
+ *            appends only the scores under that bound to a list of
+ *            max(16 cand_cap, 2 k sample_stride + 65536) entries.  The
+ *            workspace no longer grows with C(M,3), so one GPU scans data
+ *            sets whose plane would not fit in its memory;
+ *   AUTO     (default) BOUNDED when the plane would take more than 16 GiB
+ *            (beyond about 2900 SNPs).
+ * EPI3_E_INVALID for another value. */
+enum { EPI3_SCAN_SELECT_AUTO = 0, EPI3_SCAN_SELECT_PLANE = 1, EPI3_SCAN_SELECT_BOUNDED = 2 };
+int epi3_set_scan_select(int32_t mode);
 
 /* Library version string. */
 const char *epi3_version(void);

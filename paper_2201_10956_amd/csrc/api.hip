@@ -142,6 +142,15 @@ struct ScanLayout {
   uint8_t *scratch;       // matrix-core variants: two buffers of pass_tiles tiles
   int64_t pass_tiles;
   int64_t cap;
+  // bounded selection (no score plane; matrix-core variants): every
+  // sample_stride-th tile is scored first into a sample plane, whose k-th
+  // smallest score bounds what the full pass appends to the list ckey / crank
+  bool bounded;
+  int64_t sample_stride, sample_tiles;
+  float *sample;          // [sample_tiles][4096]
+  SelJob *ssel;           // selection of the k-th sample score
+  SelState *sst;
+  uint32_t *shist;
   int64_t total;
 };
 
@@ -163,6 +172,7 @@ struct Tiles {
   int64_t pass_bytes = 0;
   int64_t compact_cap = 0;
   int32_t batch_select = EPI3_BATCH_SELECT_AUTO;
+  int32_t scan_select = EPI3_SCAN_SELECT_AUTO;
   uint64_t gen = 0;  // bumped by every setter: part of the cached graphs' key
 };
 Tiles &tiles() {
@@ -189,6 +199,15 @@ int batch_select_mode() {
 }
 // Phenotype batches of at least this many triplets select by bound (AUTO).
 constexpr int64_t kBoundedMinTriplets = 1ll << 22;
+
+int scan_select_mode() {
+  Tiles &t = tiles();
+  std::lock_guard<std::mutex> g(t.mu);
+  return t.scan_select;
+}
+// Plain scans whose FP32 score plane would exceed this many bytes select by
+// bound (AUTO): beyond about 2900 SNPs.
+constexpr int64_t kPlainPlaneMaxBytes = 16ll << 30;
 
 uint64_t settings_gen() {
   Tiles &t = tiles();
@@ -247,21 +266,49 @@ ScanLayout scan_layout(void *ws, const epi3_dataset &d, int32_t k, int64_t cand_
   L.sel = c.take<SelJob>(1);
   L.st = c.take<SelState>(1);
   L.hist = c.take<uint32_t>(kHistBins);
-  L.score = c.take<float>(T);
+  const int smode = scan_select_mode();
+  L.bounded = T > 0 && (smode == EPI3_SCAN_SELECT_BOUNDED ||
+                        (smode == EPI3_SCAN_SELECT_AUTO && 4 * T > kPlainPlaneMaxBytes));
+  // (epi3_topk reads the state and the hits: their places depend on k,
+  // cand_cap and the selection mode only, not on the variant)
+  if (!L.bounded) L.score = c.take<float>(T);
   L.cand = c.take<int64_t>(L.cap);
   L.candkey = c.take<uint32_t>(L.cap);
   L.rec = c.take<CandRec>(L.cap);
   L.skey = c.take<uint64_t>(sort_len(L.cap));
   L.sidx = c.take<uint32_t>(sort_len(L.cap));
   L.hits = c.take<epi3_hit>(std::max<int32_t>(k, 1));
+  const int v = plain_variant(d, variant);
+  const bool mfma = v == EPI3_VARIANT_MFMA || v == EPI3_VARIANT_MFMA_FP4;
+  const int JB = mfma ? pick_JB(d, v) : 0;
+  if (L.bounded && mfma) {
+    // about max(1024, 8 k) sample tiles (4096 scores each) spread evenly over
+    // the tile order, enough of them to hold k triplets
+    const int64_t tiles = host_plain_tiles(d.n_snps, JB);
+    const int64_t want = std::max<int64_t>(1024, 8 * (int64_t)k);
+    int64_t stride = std::max<int64_t>(1, tiles / want), ns = 0;
+    while (stride > 1 && host_plain_sample_valid(d.n_snps, JB, stride, &ns) < k) stride /= 2;
+    host_plain_sample_valid(d.n_snps, JB, stride, &ns);
+    L.sample_stride = stride;
+    L.sample_tiles = ns;
+    L.sample = c.take<float>(ns * 4096);
+    L.ssel = c.take<SelJob>(1);
+    L.sst = c.take<SelState>(1);
+    L.shist = c.take<uint32_t>(kHistBins);
+  }
   L.ccap = compact_cap(T, L.cap);
+  if (L.bounded && mfma && compact_cap_override() <= 0) {
+    // the list: twice the expected count (the sample holds one tile in
+    // sample_stride, so about k sample_stride scores lie below its k-th),
+    // plus slack; a size set by epi3_set_compact_cap is taken as it is
+    L.ccap = std::max(L.ccap, std::min<int64_t>(T, 2 * (int64_t)k * L.sample_stride + 65536));
+  }
   L.ckey = c.take<uint32_t>(L.ccap);
   L.crank = c.take<int64_t>(L.ccap);
   L.pjob = c.take<PlainJob>(1);
   L.jbegin = c.take<int64_t>(2);
-  const int v = plain_variant(d, variant);
-  if (T > 0 && (v == EPI3_VARIANT_MFMA || v == EPI3_VARIANT_MFMA_FP4)) {
-    const int64_t tiles = host_plain_tiles(d.n_snps, pick_JB(d, v));
+  if (T > 0 && mfma) {
+    const int64_t tiles = host_plain_tiles(d.n_snps, JB);
     L.pass_tiles = std::max<int64_t>(
         1, std::min<int64_t>(tiles, pass_bytes(kPlainPassBytes) / kPlainTileScratch));
     L.scratch = c.take<uint8_t>(2 * L.pass_tiles * kPlainTileScratch);
@@ -538,13 +585,28 @@ struct MfmaTask {
   uint32_t *keyrange;         // [2]
 };
 
+// Bounded selection of a single-task matrix-core count (see ScanLayout).
+struct PlainBound {
+  int64_t stride, sample_tiles;
+  float *sample;
+  SelJob *ssel, *sel;  // device: selection of the sample's k-th score, the main selection
+  SelState *sst, *st;
+  uint32_t *ckey;
+  int64_t *crank;
+  int64_t ccap;
+};
+
 // Counts and scores every triplet of the tasks' data sets (all with the same
 // operand type and tile JB) in one sequence of passes over their tiles taken
 // in task order: data set x owns global tiles job_begin[x] .. job_begin[x + 1]
 // and the persistent count and finish kernels walk the global tile order, so
-// one data set's last tiles share a launch with the next one's first.
+// one data set's last tiles share a launch with the next one's first.  With
+// `bd` (one task): a sample pass over every bd->stride-th tile first, its k-th
+// smallest score + 2 e(N) as the bound, then the full pass appending only the
+// scores under the bound to the list (no score plane).
 int enqueue_count_mfma(const std::vector<MfmaTask> &tasks, bool fp4, int JB, const MfmaBufs &W,
-                       hipStream_t s, AuxCtx *ctx) {
+                       hipStream_t s, AuxCtx *ctx, const PlainBound *bd = nullptr) {
+  if (bd && tasks.size() != 1) return EPI3_E_INVALID;
   const int32_t unit = fp4 ? 128 : 64;  // samples per 64-byte staged chunk
   const int n = (int)tasks.size();
   std::vector<int64_t> begin(n + 1, 0);
@@ -587,40 +649,67 @@ int enqueue_count_mfma(const std::vector<MfmaTask> &tasks, bool fp4, int JB, con
                    reinterpret_cast<uint4 *>(W.scratch + W.pass_tiles * kPlainTileScratch)};
   // Pass p counts into scratch buffer p % 2 on `s`; its finish kernel runs on
   // the second stream while `s` counts pass p + 1.  Count p + 2 waits for
-  // finish p (same buffer).
+  // finish p (same buffer).  The slots of a pass are the tiles n0 + q of a
+  // sequence of n_all tiles 0, stride, 2 stride, ...
   hipStream_t s2 = ctx->s2;
-  int rc = EPI3_OK;
   hipEvent_t ev_start = ctx->ev[0], ev_cnt[2] = {ctx->ev[1], ctx->ev[2]},
              ev_fin[2] = {ctx->ev[3], ctx->ev[4]};
-  HIP_OK(hipEventRecord(ev_start, s));
-  HIP_OK(hipStreamWaitEvent(s2, ev_start, 0));
-  int p = 0;
-  for (int64_t t0 = 0; t0 < tiles; t0 += W.pass_tiles, ++p) {
-    const int64_t t1 = std::min(tiles, t0 + W.pass_tiles);
-    const int b = p & 1;
-    if (p >= 2) HIP_OK(hipStreamWaitEvent(s, ev_fin[b], 0));
-    HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
-    rc = timed(0, s, [&]() {
-      return launch_count_mfma_plain(W.pjobs, W.job_begin, n, JB, fp4, buf[b], t0, t1, W.queue,
-                                     s) == hipSuccess
-                 ? EPI3_OK
-                 : EPI3_E_HIP;
-    });
-    if (rc != EPI3_OK) return rc;
-    HIP_OK(hipEventRecord(ev_cnt[b], s));
-    HIP_OK(hipStreamWaitEvent(s2, ev_cnt[b], 0));
-    rc = timed(3, s2, [&]() {
-      return launch_finish_plain(W.pjobs, W.job_begin, n, JB, buf[b], t0, t1, lf32, lf_len, counts,
-                                 s2) == hipSuccess
-                 ? EPI3_OK
-                 : EPI3_E_HIP;
-    });
-    if (rc != EPI3_OK) return rc;
-    HIP_OK(hipEventRecord(ev_fin[b], s2));
+  auto passes = [&](int64_t n_all, int64_t stride, PlainOut out) -> int {
+    HIP_OK(hipEventRecord(ev_start, s));
+    HIP_OK(hipStreamWaitEvent(s2, ev_start, 0));
+    int p = 0;
+    for (int64_t n0 = 0; n0 < n_all; n0 += W.pass_tiles, ++p) {
+      const int64_t nn = std::min(W.pass_tiles, n_all - n0);
+      const int b = p & 1;
+      if (p >= 2) HIP_OK(hipStreamWaitEvent(s, ev_fin[b], 0));
+      HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
+      int rc = timed(0, s, [&]() {
+        return launch_count_mfma_plain(W.pjobs, W.job_begin, n, JB, fp4, buf[b], n0 * stride, nn,
+                                       stride, W.queue, s) == hipSuccess
+                   ? EPI3_OK
+                   : EPI3_E_HIP;
+      });
+      if (rc != EPI3_OK) return rc;
+      HIP_OK(hipEventRecord(ev_cnt[b], s));
+      HIP_OK(hipStreamWaitEvent(s2, ev_cnt[b], 0));
+      out.stride = stride;
+      out.sample_base = n0;
+      rc = timed(3, s2, [&]() {
+        return launch_finish_plain(W.pjobs, W.job_begin, n, JB, buf[b], n0 * stride, nn, lf32,
+                                   lf_len, counts, out, s2) == hipSuccess
+                   ? EPI3_OK
+                   : EPI3_E_HIP;
+      });
+      if (rc != EPI3_OK) return rc;
+      HIP_OK(hipEventRecord(ev_fin[b], s2));
+    }
+    HIP_OK(hipEventRecord(ev_fin[0], s2));
+    HIP_OK(hipStreamWaitEvent(s, ev_fin[0], 0));
+    return EPI3_OK;
+  };
+  PlainOut out{};
+  if (!bd) {
+    out.mode = kPermOutPlane;
+    return passes(tiles, 1, out);
   }
-  HIP_OK(hipEventRecord(ev_fin[0], s2));
-  HIP_OK(hipStreamWaitEvent(s, ev_fin[0], 0));
-  return EPI3_OK;
+  if (counts) return EPI3_E_INVALID;
+  // sample pass: slots of no triplet stay +inf
+  HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(bd->sample), 0x7f800000u,
+                         bd->sample_tiles * 4096, s));
+  out.mode = kPermOutSample;
+  out.sample = bd->sample;
+  out.range = &bd->sst->kmin;
+  int rc = passes(bd->sample_tiles, bd->stride, out);
+  if (rc != EPI3_OK) return rc;
+  HIP_OK(launch_select_kth(bd->ssel, 1, bd->sample_tiles * 4096, s));
+  HIP_OK(launch_sample_bound(bd->sel, bd->ssel, 1, s));
+  PlainOut bo{};
+  bo.mode = kPermOutBounded;
+  bo.st = bd->st;
+  bo.ckey = bd->ckey;
+  bo.crank = bd->crank;
+  bo.ccap = bd->ccap;
+  return passes(tiles, 1, bo);
 }
 
 }  // namespace
@@ -877,8 +966,10 @@ int64_t epi3_workspace_bytes(const epi3_dataset *d, int32_t k, int32_t variant, 
   return scan_layout(nullptr, *d, k, cand_cap, variant).total;
 }
 
+// bounded: select by bound (W.bounded; matrix-core variants only) instead of
+// scoring into `score`
 static int enqueue_count(const epi3_dataset &d, int32_t variant, float *score, uint32_t *counts,
-                         const ScanLayout &W, hipStream_t s) {
+                         const ScanLayout &W, hipStream_t s, bool bounded = false) {
   const int v = plain_variant(d, variant);
   if (v < 0) return v;
   if (v == EPI3_VARIANT_MFMA || v == EPI3_VARIANT_MFMA_FP4) {
@@ -887,8 +978,15 @@ static int enqueue_count(const epi3_dataset &d, int32_t variant, float *score, u
     AuxLease lease;
     if (lease.rc != EPI3_OK) return lease.rc;
     const std::vector<MfmaTask> one{{&d, score, counts, W.jprefix, &W.st->kmin}};
+    if (bounded) {
+      const PlainBound bd{W.sample_stride, W.sample_tiles, W.sample, W.ssel, W.sel,
+                          W.sst,           W.st,           W.ckey,   W.crank, W.ccap};
+      return enqueue_count_mfma(one, v == EPI3_VARIANT_MFMA_FP4, pick_JB(d, v), B, s, lease.c,
+                                &bd);
+    }
     return enqueue_count_mfma(one, v == EPI3_VARIANT_MFMA_FP4, pick_JB(d, v), B, s, lease.c);
   }
+  if (bounded) return EPI3_E_UNSUPPORTED;
   const int P = pick_P(d);
   Job J = make_job(d, score, counts, W.jprefix, &W.st->kmin, P);
   HIP_OK(launch_write_jobs(&J, 1, W.job, s));
@@ -910,6 +1008,7 @@ int epi3_scan(const epi3_dataset *d, int32_t k, int32_t variant, int64_t cand_ca
   const int v = plain_variant(*d, variant);
   if (v < 0) return v;
   ScanLayout W = scan_layout(ws_dev, *d, k, cand_cap, variant);
+  if (W.bounded && !W.sample) return EPI3_E_UNSUPPORTED;  // the vector-ALU count writes a plane
   if (ws_bytes < W.total) return EPI3_E_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t T = epi3_n_triplets(d->n_snps);
@@ -918,15 +1017,29 @@ int epi3_scan(const epi3_dataset *d, int32_t k, int32_t variant, int64_t cand_ca
   S.skey = W.skey;
   S.sidx = W.sidx;
   S.sortP = sort_len(W.cap);
+  if (W.bounded) S.sample = 1;  // the list is built before the selection starts
   HIP_OK(launch_write_seljobs(&S, 1, W.sel, s));
   HIP_OK(launch_init_select(W.sel, 1, s));
+  if (W.bounded) {
+    // selection of the k-th smallest sample score (the sample plane read whole)
+    SelJob ss = make_seljob(*d, W.sample, W.sample_tiles * 4096, W.sst, W.shist, nullptr, nullptr,
+                            nullptr, nullptr, 1, k, nullptr, nullptr, 0);
+    ss.sample = 0;
+    HIP_OK(launch_write_seljobs(&ss, 1, W.ssel, s));
+    HIP_OK(launch_init_select(W.ssel, 1, s));
+  }
   if (T > 0) {
-    const int rc = enqueue_count(*d, variant, W.score, nullptr, W, s);
+    const int rc = enqueue_count(*d, variant, W.score, nullptr, W, s, W.bounded);
     if (rc != EPI3_OK) return rc;
   }
+  // a bounded scan's selection reads its list only: size the grids for that;
+  // its sample flag only says that the list exists (the selection's sample
+  // phase reads a score plane, so it runs for plane jobs only)
+  const int64_t sel_T = W.bounded ? W.ccap : T;
+  const bool sampled = S.sample != 0 && S.score != nullptr;
   return timed(1, s, [&]() {
-    return launch_select(W.sel, 1, T, W.cap, k, S.sample != 0, s) == hipSuccess ? EPI3_OK
-                                                                                : EPI3_E_HIP;
+    return launch_select(W.sel, 1, sel_T, W.cap, k, sampled, s) == hipSuccess ? EPI3_OK
+                                                                              : EPI3_E_HIP;
   });
 }
 
@@ -942,6 +1055,12 @@ int epi3_topk(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev, 
   HIP_OK(hipStreamSynchronize(s));
   *n_out = 0;
   if (status & 1) return EPI3_E_GENOTYPE;
+  if (st.done == 3u) {
+    // the bounded list overflowed: 16 x cand_cap entries hold it on a retry
+    const int64_t need = std::max<int64_t>((int64_t)((st.cn + 15) / 16), W.cap + 1);
+    *n_out = (int32_t)std::min<int64_t>(need, 0x7fffffff);
+    return EPI3_E_CAPACITY;
+  }
   if ((int64_t)st.ncand > W.cap) {
     *n_out = (int32_t)std::min<unsigned long long>(st.ncand, 0x7fffffffull);
     return EPI3_E_CAPACITY;
@@ -958,7 +1077,9 @@ int epi3_topk(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev, 
 int epi3_score_plane(const epi3_dataset *d, int32_t k, int64_t cand_cap, void *ws_dev,
                      float **plane_dev) {
   if (!valid_dataset(d) || k <= 0 || !ws_dev || !plane_dev) return EPI3_E_INVALID;
-  *plane_dev = scan_layout(ws_dev, *d, k, cand_cap, EPI3_VARIANT_VALU).score;
+  const ScanLayout W = scan_layout(ws_dev, *d, k, cand_cap, EPI3_VARIANT_VALU);
+  if (W.bounded) return EPI3_E_UNSUPPORTED;
+  *plane_dev = W.score;
   return EPI3_OK;
 }
 
@@ -1726,6 +1847,15 @@ int epi3_set_batch_select(int32_t mode) {
   Tiles &t = tiles();
   std::lock_guard<std::mutex> g(t.mu);
   t.batch_select = mode;
+  ++t.gen;
+  return EPI3_OK;
+}
+
+int epi3_set_scan_select(int32_t mode) {
+  if (mode < EPI3_SCAN_SELECT_AUTO || mode > EPI3_SCAN_SELECT_BOUNDED) return EPI3_E_INVALID;
+  Tiles &t = tiles();
+  std::lock_guard<std::mutex> g(t.mu);
+  t.scan_select = mode;
   ++t.gen;
   return EPI3_OK;
 }

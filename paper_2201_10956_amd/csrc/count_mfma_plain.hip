@@ -18,6 +18,8 @@
 // rows X_i[a] & X_j[b] formed in registers) and two 32-column B tiles
 // (16 k x g).  Operand rows are staged per chunk of 128 bytes (64 for
 // JB = 2) in double-buffered LDS.
+#include <algorithm>
+
 #include "epi3_internal.h"
 
 namespace epi3 {
@@ -173,7 +175,7 @@ struct JobDecoder {
 template <bool FP4, int JB>
 __global__ void __launch_bounds__(256, 2) count_mfma_plain_kernel(
     const PlainJob *__restrict__ jobs, const int64_t *__restrict__ job_begin_p, int n_jobs,
-    uint4 *__restrict__ corners, int64_t tile_begin, int64_t tile_end,
+    uint4 *__restrict__ corners, int64_t tile_begin, int64_t n_tiles, int64_t stride,
     unsigned long long *__restrict__ queue) {
   typedef PlainAcc<FP4> Acc;
   constexpr int KT = 256 / JB;
@@ -206,11 +208,11 @@ __global__ void __launch_bounds__(256, 2) count_mfma_plain_kernel(
 
   for (;;) {
     __syncthreads();
-    if (tid == 0) sTile[0] = tile_begin + (int64_t)atomicAdd(queue, 1ull);
+    if (tid == 0) sTile[0] = (int64_t)atomicAdd(queue, 1ull);
     __syncthreads();
-    const int64_t tg = rfl64q(sTile[0]);
-    if (tg >= tile_end) break;
-    const int64_t slot = tg - tile_begin;
+    const int64_t slot = rfl64q(sTile[0]);  // scratch slot of this launch
+    if (slot >= n_tiles) break;
+    const int64_t tg = tile_begin + slot * stride;
     if (jd.find(job_begin, n_jobs, tg)) {
       const PlainJob &pj = jobs[jd.x];
       M = pj.M;
@@ -407,14 +409,14 @@ __device__ __forceinline__ void flush_range(uint32_t kmin, uint32_t kmax, uint32
   }
 }
 
-template <int JB, bool LDS, bool COUNTS>
+template <int JB, bool LDS, bool COUNTS, int MODE>
 __global__ void __launch_bounds__(256) finish_plain_kernel(const PlainJob *__restrict__ jobs,
                                                            const int64_t *__restrict__ job_begin_p,
                                                            int n_jobs,
                                                            const uint4 *__restrict__ corners,
-                                                           int64_t tile_begin, int64_t tile_end,
+                                                           int64_t tile_begin, int64_t n_tiles,
                                                            const float *__restrict__ lf32,
-                                                           int lf_len) {
+                                                           int lf_len, PlainOut out) {
   constexpr int KT = 256 / JB;
   constexpr int kTile = kPI * JB * KT;  // 4096 triplets
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
@@ -438,7 +440,10 @@ __global__ void __launch_bounds__(256) finish_plain_kernel(const PlainJob *__res
   // key range of this thread's scores of the current job (flushed per job)
   uint32_t kmin = 0xffffffffu, kmax = 0u;
   TileDecoder dec;
-  for (int64_t tg = tile_begin + blockIdx.x; tg < tile_end; tg += gridDim.x) {
+  // bounded: this launch's append bound (set before the launch)
+  const float ub = MODE == kPermOutBounded ? out.st->ub : 0.f;
+  for (int64_t slot = blockIdx.x; slot < n_tiles; slot += gridDim.x) {
+    const int64_t tg = tile_begin + slot * out.stride;
     if (jd.find(job_begin, n_jobs, tg)) {
       if (keyrange) flush_range(kmin, kmax, keyrange);
       kmin = 0xffffffffu;
@@ -454,14 +459,13 @@ __global__ void __launch_bounds__(256) finish_plain_kernel(const PlainJob *__res
       pr = (gptr<i4e>)pj.pairs;
       score = pj.score;
       counts = pj.counts;
-      keyrange = pj.keyrange;
+      keyrange = MODE == kPermOutSample ? out.range : pj.keyrange;
       dec.J = -1;
     }
     const int64_t t = tg - jd.lo;  // tile within its job
     dec.find(pre, nJ, t);
     int i0, j0, k0;
     plain_tile_origin(dec, t, M, JB, i0, j0, k0);
-    const int64_t slot = tg - tile_begin;
     gptr<u4e> cor = (gptr<u4e>)(corners + slot * 2 * (int64_t)kTile);
     // per-SNP counts (the pair tables' diagonals) of the tile's k range in
     // LDS, so each lane's k margin is one conflict-free LDS read instead of a
@@ -509,7 +513,16 @@ __global__ void __launch_bounds__(256) finish_plain_kernel(const PlainJob *__res
           k2 += lf_at(lf32, b0 + b1 + 4) - (lf_at(lf32, b0) + lf_at(lf32, b1));
       }
       const int64_t rank = lex_base(M, i, j) + k;
-      score[rank] = k2;
+      if (MODE == kPermOutPlane) score[rank] = k2;
+      if (MODE == kPermOutSample) out.sample[(out.sample_base + slot) * kTile + x] = k2;
+      if (MODE == kPermOutBounded && k2 <= ub) {
+        // rare (a few thousand of the C(M,3) scores): one atomic per append
+        const unsigned long long pos = atomicAdd(&out.st->cn, 1ull);
+        if ((int64_t)pos < out.ccap) {
+          out.ckey[pos] = f2key(k2);
+          out.crank[pos] = rank;
+        }
+      }
       if (COUNTS) {
         uint32_t *o = counts + rank * 54;
         for (int x2 = 0; x2 < 27; ++x2) {
@@ -555,9 +568,8 @@ static hipError_t cu_count(int *n_cu) {
 
 template <bool FP4, int JB>
 static hipError_t launch_plain_count_t(const PlainJob *jobs, const int64_t *job_begin, int n_jobs,
-                                       uint4 *corners, int64_t tile_begin, int64_t tile_end,
-                                       unsigned long long *queue, hipStream_t s) {
-  const int64_t n = tile_end - tile_begin;
+                                       uint4 *corners, int64_t tile_begin, int64_t n,
+                                       int64_t stride, unsigned long long *queue, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   int n_cu = 0;
   hipError_t e = cu_count(&n_cu);
@@ -569,76 +581,119 @@ static hipError_t launch_plain_count_t(const PlainJob *jobs, const int64_t *job_
   int64_t blocks = (int64_t)n_cu * per_cu;
   if (blocks > n) blocks = n;
   hipLaunchKernelGGL((count_mfma_plain_kernel<FP4, JB>), dim3((unsigned)blocks), dim3(256), 0, s,
-                     jobs, job_begin, n_jobs, corners, tile_begin, tile_end, queue);
+                     jobs, job_begin, n_jobs, corners, tile_begin, n, stride, queue);
   return hipGetLastError();
 }
 
 hipError_t launch_count_mfma_plain(const PlainJob *jobs, const int64_t *job_begin, int32_t n_jobs,
                                    int JB, bool fp4, uint4 *corners, int64_t tile_begin,
-                                   int64_t tile_end, unsigned long long *queue, hipStream_t s) {
+                                   int64_t n_tiles, int64_t stride, unsigned long long *queue,
+                                   hipStream_t s) {
+  if (stride < 1) return hipErrorInvalidValue;
   switch (JB) {
     case 2:
-      return fp4 ? launch_plain_count_t<true, 2>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, queue, s)
-                 : launch_plain_count_t<false, 2>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, queue, s);
+      return fp4 ? launch_plain_count_t<true, 2>(jobs, job_begin, n_jobs, corners, tile_begin, n_tiles, stride, queue, s)
+                 : launch_plain_count_t<false, 2>(jobs, job_begin, n_jobs, corners, tile_begin, n_tiles, stride, queue, s);
     case 4:
-      return fp4 ? launch_plain_count_t<true, 4>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, queue, s)
-                 : launch_plain_count_t<false, 4>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, queue, s);
+      return fp4 ? launch_plain_count_t<true, 4>(jobs, job_begin, n_jobs, corners, tile_begin, n_tiles, stride, queue, s)
+                 : launch_plain_count_t<false, 4>(jobs, job_begin, n_jobs, corners, tile_begin, n_tiles, stride, queue, s);
     case 8:
-      return fp4 ? launch_plain_count_t<true, 8>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, queue, s)
-                 : launch_plain_count_t<false, 8>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, queue, s);
+      return fp4 ? launch_plain_count_t<true, 8>(jobs, job_begin, n_jobs, corners, tile_begin, n_tiles, stride, queue, s)
+                 : launch_plain_count_t<false, 8>(jobs, job_begin, n_jobs, corners, tile_begin, n_tiles, stride, queue, s);
   }
   return hipErrorInvalidValue;
 }
 
-template <int JB, bool LDS, bool COUNTS>
+template <int JB, bool LDS, bool COUNTS, int MODE>
 static hipError_t launch_finish_plain_t(const PlainJob *jobs, const int64_t *job_begin, int n_jobs,
-                                        const uint4 *corners, int64_t tile_begin, int64_t tile_end,
-                                        const float *lf32, int32_t lf_len, hipStream_t s) {
-  const int64_t n = tile_end - tile_begin;
+                                        const uint4 *corners, int64_t tile_begin, int64_t n,
+                                        const float *lf32, int32_t lf_len, const PlainOut &out,
+                                        hipStream_t s) {
   if (n <= 0) return hipSuccess;
   int n_cu = 0;
   hipError_t e = cu_count(&n_cu);
   if (e != hipSuccess) return e;
   const size_t lds = (LDS ? (size_t)(lf_len * 4 + 15) / 16 * 16 : 0) +
                      2 * (256 / JB) * sizeof(int2);  // table, then the tile's k margins
-  e = hipFuncSetAttribute(reinterpret_cast<const void *>(&finish_plain_kernel<JB, LDS, COUNTS>),
+  auto kern = finish_plain_kernel<JB, LDS, COUNTS, MODE>;
+  e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, finish_plain_kernel<JB, LDS, COUNTS>,
-                                                   256, lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, lds);
   if (e != hipSuccess) return e;
   if (per_cu <= 0) per_cu = 1;
   int64_t blocks = (int64_t)n_cu * per_cu;
   if (blocks > n) blocks = n;
-  hipLaunchKernelGGL((finish_plain_kernel<JB, LDS, COUNTS>), dim3((unsigned)blocks), dim3(256), lds,
-                     s, jobs, job_begin, n_jobs, corners, tile_begin, tile_end, lf32, lf_len);
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), lds, s, jobs, job_begin, n_jobs,
+                     corners, tile_begin, n, lf32, lf_len, out);
   return hipGetLastError();
+}
+
+template <int JB, bool LDS>
+static hipError_t launch_finish_plain_l(const PlainJob *jobs, const int64_t *job_begin, int n_jobs,
+                                        const uint4 *corners, int64_t tile_begin, int64_t n,
+                                        const float *lf32, int32_t lf_len, bool counts,
+                                        const PlainOut &out, hipStream_t s) {
+  switch (out.mode) {
+    case kPermOutPlane:
+      return counts ? launch_finish_plain_t<JB, LDS, true, kPermOutPlane>(jobs, job_begin, n_jobs, corners, tile_begin, n, lf32, lf_len, out, s)
+                    : launch_finish_plain_t<JB, LDS, false, kPermOutPlane>(jobs, job_begin, n_jobs, corners, tile_begin, n, lf32, lf_len, out, s);
+    case kPermOutSample:
+      return launch_finish_plain_t<JB, LDS, false, kPermOutSample>(jobs, job_begin, n_jobs, corners, tile_begin, n, lf32, lf_len, out, s);
+    case kPermOutBounded:
+      return launch_finish_plain_t<JB, LDS, false, kPermOutBounded>(jobs, job_begin, n_jobs, corners, tile_begin, n, lf32, lf_len, out, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int JB>
 static hipError_t launch_finish_plain_j(const PlainJob *jobs, const int64_t *job_begin, int n_jobs,
-                                        const uint4 *corners, int64_t tile_begin, int64_t tile_end,
+                                        const uint4 *corners, int64_t tile_begin, int64_t n,
                                         const float *lf32, int32_t lf_len, bool counts,
-                                        hipStream_t s) {
-  if (counts)
-    return lf_in_lds(lf_len)
-               ? launch_finish_plain_t<JB, true, true>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, lf32, lf_len, s)
-               : launch_finish_plain_t<JB, false, true>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, lf32, lf_len, s);
+                                        const PlainOut &out, hipStream_t s) {
   return lf_in_lds(lf_len)
-             ? launch_finish_plain_t<JB, true, false>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, lf32, lf_len, s)
-             : launch_finish_plain_t<JB, false, false>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, lf32, lf_len, s);
+             ? launch_finish_plain_l<JB, true>(jobs, job_begin, n_jobs, corners, tile_begin, n, lf32, lf_len, counts, out, s)
+             : launch_finish_plain_l<JB, false>(jobs, job_begin, n_jobs, corners, tile_begin, n, lf32, lf_len, counts, out, s);
 }
 
 hipError_t launch_finish_plain(const PlainJob *jobs, const int64_t *job_begin, int32_t n_jobs,
-                               int JB, const uint4 *corners, int64_t tile_begin, int64_t tile_end,
-                               const float *lf32, int32_t lf_len, bool counts, hipStream_t s) {
+                               int JB, const uint4 *corners, int64_t tile_begin, int64_t n_tiles,
+                               const float *lf32, int32_t lf_len, bool counts, const PlainOut &out,
+                               hipStream_t s) {
+  if (out.stride < 1 || (counts && out.mode != kPermOutPlane)) return hipErrorInvalidValue;
   switch (JB) {
-    case 2: return launch_finish_plain_j<2>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, lf32, lf_len, counts, s);
-    case 4: return launch_finish_plain_j<4>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, lf32, lf_len, counts, s);
-    case 8: return launch_finish_plain_j<8>(jobs, job_begin, n_jobs, corners, tile_begin, tile_end, lf32, lf_len, counts, s);
+    case 2: return launch_finish_plain_j<2>(jobs, job_begin, n_jobs, corners, tile_begin, n_tiles, lf32, lf_len, counts, out, s);
+    case 4: return launch_finish_plain_j<4>(jobs, job_begin, n_jobs, corners, tile_begin, n_tiles, lf32, lf_len, counts, out, s);
+    case 8: return launch_finish_plain_j<8>(jobs, job_begin, n_jobs, corners, tile_begin, n_tiles, lf32, lf_len, counts, out, s);
   }
   return hipErrorInvalidValue;
+}
+
+int64_t host_plain_sample_valid(int64_t M, int JB, int64_t stride, int64_t *n_sample) {
+  const int KT = 256 / JB;
+  const int64_t nJ = plain_jblocks(M, JB);
+  int64_t t0 = 0, valid = 0, ns = 0;
+  for (int64_t J = 0; J < nJ; ++J) {
+    const int64_t nt = plain_tiles_of_jb(M, J, JB);
+    if (nt == 0) continue;
+    const int64_t j0 = J * JB;
+    const int64_t nkb = (M - 1 - j0 + KT - 1) / KT;
+    // sampled tiles of this j-block: the multiples of stride in [t0, t0 + nt)
+    for (int64_t t = (t0 + stride - 1) / stride * stride; t < t0 + nt; t += stride) {
+      ++ns;
+      const int64_t rr = t - t0, ib = rr / nkb, kb = rr % nkb;
+      const int64_t i0 = ib * kPI, k0 = j0 + 1 + kb * KT;
+      for (int64_t j = j0; j < j0 + JB && j < M; ++j) {
+        const int64_t ni = std::max<int64_t>(0, std::min<int64_t>(i0 + kPI, j) - i0);
+        const int64_t klo = std::max<int64_t>(k0, j + 1), khi = std::min<int64_t>(k0 + KT, M);
+        valid += ni * std::max<int64_t>(0, khi - klo);
+      }
+    }
+    t0 += nt;
+  }
+  if (n_sample) *n_sample = ns;
+  return valid;
 }
 
 struct I64Pack {

@@ -139,6 +139,26 @@ struct PermOut {
   int64_t ccap;
 };
 
+// Where the plain matrix-core finish kernel puts its FP32 scores (modes as
+// for PermOut).  The launch's slots q are global tiles tile_begin + q stride.
+struct PlainOut {
+  int32_t mode;          // kPermOut*
+  int32_t pad;
+  int64_t stride;
+  // sample: the score of triplet x (0 .. 4095, the tile's triplet order) of
+  // slot q goes to sample[(sample_base + q) 4096 + x] (slots of no triplet
+  // keep what the buffer held); its key range to range[0..1]
+  float *sample;
+  int64_t sample_base;
+  uint32_t *range;
+  // bounded: (key, rank) of every score <= st->ub appended to ckey / crank at
+  // positions from st->cn (entries past ccap are dropped, st->cn still counts)
+  SelState *st;
+  uint32_t *ckey;
+  int64_t *crank;
+  int64_t ccap;
+};
+
 // Plain two-class scan on the matrix cores: one SPLIT data set, counted in
 // passes of tiles whose corner cells go through a scratch buffer
 // ([pass tile][class][16 i][JB j][256 / JB k] 8 x uint16 cells).
@@ -578,16 +598,21 @@ constexpr int kPlainI = 16;  // pivots i per plain matrix-core tile (x JB j x 25
 constexpr int64_t kPlainTileScratch = 2ll * kPlainI * 256 * 16;  // bytes per tile, both classes
 hipError_t launch_write_plainjob(const PlainJob &h, PlainJob *dst_dev, hipStream_t s);
 hipError_t launch_plain_prefix(PlainJob *pj_dev, hipStream_t s);
-// Plain matrix-core count / finish of global tiles [tile_begin, tile_end) of
-// n_jobs data sets (same JB and operand type): job x owns global tiles
-// job_begin[x] .. job_begin[x + 1] (device int64 [n_jobs + 1]); tile t's
-// corner cells sit in scratch slot t - tile_begin of `corners`.
+// Plain matrix-core count / finish of the global tiles tile_begin + q stride,
+// q < n_tiles, of n_jobs data sets (same JB and operand type): job x owns
+// global tiles job_begin[x] .. job_begin[x + 1] (device int64 [n_jobs + 1]);
+// slot q's corner cells sit in scratch slot q of `corners`.
 hipError_t launch_count_mfma_plain(const PlainJob *jobs, const int64_t *job_begin, int32_t n_jobs,
                                    int JB, bool fp4, uint4 *corners, int64_t tile_begin,
-                                   int64_t tile_end, unsigned long long *queue, hipStream_t s);
+                                   int64_t n_tiles, int64_t stride, unsigned long long *queue,
+                                   hipStream_t s);
 hipError_t launch_finish_plain(const PlainJob *jobs, const int64_t *job_begin, int32_t n_jobs,
-                               int JB, const uint4 *corners, int64_t tile_begin, int64_t tile_end,
-                               const float *lf32, int32_t lf_len, bool counts, hipStream_t s);
+                               int JB, const uint4 *corners, int64_t tile_begin, int64_t n_tiles,
+                               const float *lf32, int32_t lf_len, bool counts, const PlainOut &out,
+                               hipStream_t s);
+// Triplets (i < j < k < M) in the plain tiles 0, stride, 2 stride, ... of a
+// data set of M SNPs (tile JB); the number of such tiles in *n_sample.
+int64_t host_plain_sample_valid(int64_t M, int JB, int64_t stride, int64_t *n_sample);
 hipError_t launch_write_i64(const int64_t *h, int32_t n, int64_t *dst_dev, hipStream_t s);
 
 int tile_P_default(int32_t M, int32_t N);

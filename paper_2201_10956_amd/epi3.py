@@ -104,6 +104,7 @@ def _load():
         "epi3_batched_bound_list": (ctypes.c_int, [P(CJob), i32, i32, i64, vp, i32, P(vp), P(vp),
                                                    P(i64), P(ctypes.c_float), vp]),
         "epi3_set_batch_select": (ctypes.c_int, [i32]),
+        "epi3_set_scan_select": (ctypes.c_int, [i32]),
         "epi3_scan_tables": (ctypes.c_int, [P(CDataset), i32, vp, vp, vp, i64, vp]),
         "epi3_score_triplets": (ctypes.c_int, [P(CDataset), vp, i64, vp, vp, vp, vp]),
         "epi3_score_plane": (ctypes.c_int, [P(CDataset), i32, i64, vp, P(vp)]),
@@ -144,7 +145,7 @@ _lib = _load()
 EXPORTS = ("epi3_encode_bytes", "epi3_encode", "epi3_workspace_bytes", "epi3_scan", "epi3_topk",
            "epi3_batched_workspace_bytes", "epi3_scan_batched", "epi3_batched_score_plane",
            "epi3_init", "epi3_scan_topk_static", "epi3_scan_tables", "epi3_batched_bound_list",
-           "epi3_set_batch_select",
+           "epi3_set_batch_select", "epi3_set_scan_select",
            "epi3_score_triplets", "epi3_score_plane", "epi3_k2_error_bound", "epi3_n_triplets", "epi3_release",
            "epi3_version", "epi3_timing_enable", "epi3_timing_query", "epi3_timing_reset",
            "epi3_tile_rule", "epi3_tile_rules_clear", "epi3_tile_for", "epi3_set_pass_bytes",
@@ -232,6 +233,12 @@ def set_batch_select(mode: str) -> None:
     """How phenotype batches select: "auto", "plane" (score plane per job) or
     "bounded" (sample pass + bounded list, no plane)."""
     _check(_lib.epi3_set_batch_select(BATCH_SELECT[mode]), "epi3_set_batch_select")
+
+
+def set_scan_select(mode: str) -> None:
+    """How plain scans select: "auto", "plane" (FP32 score plane) or "bounded"
+    (sample pass + bounded list, no plane; matrix-core variants)."""
+    _check(_lib.epi3_set_scan_select(BATCH_SELECT[mode]), "epi3_set_scan_select")
 
 
 def set_compact_cap(n: int) -> None:

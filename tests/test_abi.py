@@ -292,3 +292,31 @@ def test_static_scan_refuses_what_does_not_fit(epi3):
         epi3.E_INVALID
     assert "#define EPI3_STATIC_SCRATCH_BYTES (128ll << 20)" in open(HEADER).read()
     assert epi3.STATIC_SCRATCH_BYTES == 128 << 20
+
+
+def test_scan_select_sizes(epi3):
+    """Selecting by bound drops the 4 C(M,3)-byte score plane from a plain
+    scan's workspace (matrix-core variants keep a sample plane and a list
+    that grow with k, not with C(M,3)); AUTO keeps the plane up to 16 GiB."""
+    lib = epi3._lib
+    d = _fake_dataset(epi3, 2048, 8192, 8192)
+    T = math.comb(2048, 3)
+    try:
+        assert lib.epi3_set_scan_select(7) == epi3.E_INVALID
+        epi3.set_scan_select("plane")
+        plane = lib.epi3_workspace_bytes(ctypes.byref(d), 1000, epi3.VARIANT_MFMA_FP4, 0)
+        epi3.set_scan_select("auto")
+        assert lib.epi3_workspace_bytes(ctypes.byref(d), 1000, epi3.VARIANT_MFMA_FP4, 0) == plane
+        epi3.set_scan_select("bounded")
+        bounded = lib.epi3_workspace_bytes(ctypes.byref(d), 1000, epi3.VARIANT_MFMA_FP4, 0)
+        assert 0 < bounded < plane - 4 * T + (1 << 30)
+        # 8192 SNPs: the plane alone would be 366 GB; AUTO selects by bound
+        big = _fake_dataset(epi3, 8192, 8192, 8192)
+        epi3.set_scan_select("auto")
+        b8 = lib.epi3_workspace_bytes(ctypes.byref(big), 1000, epi3.VARIANT_MFMA_FP4, 0)
+        assert 0 < b8 < 8 << 30
+        # the state and hits sit where epi3_topk looks for them, whatever the variant
+        v8 = lib.epi3_workspace_bytes(ctypes.byref(big), 1000, epi3.VARIANT_VALU, 0)
+        assert 0 < v8 < b8
+    finally:
+        epi3.set_scan_select("auto")
