@@ -41,6 +41,8 @@ WORKLOADS = {
     "plain1": dict(cfg=1, kind="plain", desc="plain scan, 64 SNPs x 1024 samples (512 cases), top-10"),
     "plain2": dict(cfg=2, kind="plain", desc="plain scan, 512 SNPs x 4096 samples (50% cases), top-100"),
     "plain3": dict(cfg=3, kind="plain", desc="plain scan, 2048 SNPs x 16384 samples (50% cases), top-1000"),
+    "plain6": dict(cfg=6, kind="plain", desc="plain scan, 8192 SNPs x 16384 samples (50% cases), top-1000, "
+                   "selected by bound (no score plane)"),
     "perm4": dict(cfg=4, kind="perm", desc="batched permutations: 1024 SNPs x 8192 samples (3277 cases), "
                   "64 phenotype permutations in one launch, top-10 each"),
     "pairs3": dict(cfg=3, kind="pairs", desc="second-order (pair) scan, 2048 SNPs x 16384 samples "
@@ -189,8 +191,9 @@ def run_plain(args, wl):
                            "selection": round(sel_ms, 4)}
     out["best"] = {"ijk": [int(hits["i"][0]), int(hits["j"][0]), int(hits["k"][0])],
                    "k2": float(hits["k2"][0])}
-    sc.run()
-    out["k2_fp32_error"] = plane_k2_error(epi3, ds, sc.score_plane())
+    if epi3.n_triplets(M) * 4 <= (16 << 30):  # a score plane exists (AUTO keeps it up to 16 GiB)
+        sc.run()
+        out["k2_fp32_error"] = plane_k2_error(epi3, ds, sc.score_plane())
     out["k2_fp32_error_hits"] = k2_error(hits["k2_f32"], hits["k2"], epi3.k2_error_bound(N),
                                          f"the {len(hits)} hits")
     if not args.no_cpu_baseline:

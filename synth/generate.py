@@ -178,7 +178,7 @@ def make_uneven(n_datasets: int, seed: int, m_range=(128, 1024), n_range=(1024, 
     return out
 
 
-# Workloads: the five synthetic scan configurations the library is measured on.
+# Workloads: the synthetic scan configurations the library is measured on.
 CONFIGS: Dict[int, dict] = {
     1: dict(kind="plain", M=64, N=1024, case_frac=0.5, maf_lo=0.05, seed=1001, k=10),
     2: dict(kind="plain", M=512, N=4096, case_frac=0.5, maf_lo=0.05, seed=1002, k=100),
@@ -186,6 +186,9 @@ CONFIGS: Dict[int, dict] = {
     4: dict(kind="perm", M=1024, N=8192, case_frac=0.4, maf_lo=0.05, seed=1004, k=10,
             n_perm=64, perm_seed=2000),
     5: dict(kind="uneven", n_datasets=32, seed=3000, k=10),
+    # the largest synthetic shape of the paper's GPU study (8192 SNPs x 16384
+    # samples): its FP32 score plane would take 366 GB, so the scan selects by bound
+    6: dict(kind="plain", M=8192, N=16384, case_frac=0.5, maf_lo=0.01, seed=1006, k=1000),
 }
 
 

@@ -122,3 +122,39 @@ def test_bounded_list_overflow(env):
     h = epi3.Scanner(ds, 50, "mfma_fp4").run()
     ijk, rk2, rcc = oracle.scan_topk(d.geno, d.pheno, 50)
     assert_hits_equal_oracle(h, ijk, rk2, rcc)
+
+
+def test_8192_snps_properties(env):
+    """8192 SNPs x 16384 samples, top-1000 (the paper's largest synthetic GPU
+    shape; the plane would take 366 GB, so AUTO selects by bound too).  The
+    oracle cannot rank 9.2e10 triplets here, so: hits in strict (K2, i, j, k)
+    order with FP64 K2 and all 54 counts equal to the oracle's for the same
+    triplets, and none of 20000 sampled triplets outside the hits ranks before
+    the last hit."""
+    torch, epi3 = env
+    from math import comb
+    c = CONFIGS[6]
+    d = make_config(6)
+    ds = epi3.encode(to_dev(d.geno), d.pheno)
+    epi3.set_scan_select("auto")
+    try:
+        h = epi3.Scanner(ds, c["k"], "mfma_fp4").run()
+    finally:
+        epi3.set_scan_select("bounded")
+    assert len(h) == c["k"]
+    ijk = hits_ijk(h)
+    keys = list(zip(h["k2"].tolist(), ijk[:, 0].tolist(), ijk[:, 1].tolist(), ijk[:, 2].tolist()))
+    assert all(a < b for a, b in zip(keys, keys[1:]))
+    rc, rk = oracle.score_list(d.geno, d.pheno, ijk)
+    np.testing.assert_array_equal(h["k2"], rk)
+    np.testing.assert_array_equal(h["counts"].astype(np.int64), rc.astype(np.int64))
+    T = comb(c["M"], 3)
+    ranks = np.unique((SplitMix64(606, 0).uniform(0, 20000) * T).astype(np.int64))
+    from tests.gpu_util import lex_unrank
+    smp = lex_unrank(c["M"], ranks)
+    _, sk = oracle.score_list(d.geno, d.pheno, smp)
+    hit_set = set(map(tuple, ijk.tolist()))
+    last = keys[-1]
+    for (i, j, k), v in zip(smp.tolist(), sk.tolist()):
+        if (i, j, k) not in hit_set:
+            assert (v, i, j, k) > last, ((i, j, k), v, last)
