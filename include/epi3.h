@@ -489,7 +489,9 @@ int epi3_set_batch_select(int32_t mode);
  *            workspace no longer grows with C(M,3), so one GPU scans data
  *            sets whose plane would not fit in its memory;
  *   AUTO     (default) BOUNDED when the plane would take more than 16 GiB
- *            (beyond about 2900 SNPs).
+ *            (beyond about 2900 SNPs) and the data set has value planes for
+ *            the matrix cores; a vector-ALU scan of such a data set then
+ *            returns EPI3_E_UNSUPPORTED unless PLANE is set.
  * EPI3_E_INVALID for another value. */
 enum { EPI3_SCAN_SELECT_AUTO = 0, EPI3_SCAN_SELECT_PLANE = 1, EPI3_SCAN_SELECT_BOUNDED = 2 };
 int epi3_set_scan_select(int32_t mode);

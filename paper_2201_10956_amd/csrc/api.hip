@@ -267,8 +267,11 @@ ScanLayout scan_layout(void *ws, const epi3_dataset &d, int32_t k, int64_t cand_
   L.st = c.take<SelState>(1);
   L.hist = c.take<uint32_t>(kHistBins);
   const int smode = scan_select_mode();
+  // (AUTO: only data sets the matrix cores can count; a vector-ALU scan of a
+  // larger one needs EPI3_SCAN_SELECT_PLANE)
   L.bounded = T > 0 && (smode == EPI3_SCAN_SELECT_BOUNDED ||
-                        (smode == EPI3_SCAN_SELECT_AUTO && 4 * T > kPlainPlaneMaxBytes));
+                        (smode == EPI3_SCAN_SELECT_AUTO && 4 * T > kPlainPlaneMaxBytes &&
+                         mfma_supported(d)));
   // (epi3_topk reads the state and the hits: their places depend on k,
   // cand_cap and the selection mode only, not on the variant)
   if (!L.bounded) L.score = c.take<float>(T);

@@ -318,5 +318,9 @@ def test_scan_select_sizes(epi3):
         # the state and hits sit where epi3_topk looks for them, whatever the variant
         v8 = lib.epi3_workspace_bytes(ctypes.byref(big), 1000, epi3.VARIANT_VALU, 0)
         assert 0 < v8 < b8
+        # a data set without value planes keeps the plane under AUTO
+        big.bytes = big.nibbles = 0
+        assert lib.epi3_workspace_bytes(ctypes.byref(big), 1000, epi3.VARIANT_VALU, 0) > \
+            4 * math.comb(8192, 3)
     finally:
         epi3.set_scan_select("auto")
