@@ -172,7 +172,10 @@ int64_t epi3_workspace_bytes(const epi3_dataset *d, int32_t k, int32_t variant, 
 
 /* Count + score every triplet and select candidates; asynchronous.
  * variant: EPI3_VARIANT_*.  EPI3_VARIANT_MFMA and _MFMA_FP4 need class sizes
- * of at most 65535 samples (EPI3_E_UNSUPPORTED otherwise).  Selecting by
+ * of at most 65535 samples, value planes of fewer than 2^32 bytes
+ * (2 snp_stride 2 byte_stride) and fewer than 2^32 pair-table entries
+ * (2 snp_stride^2, i.e. up to about 46000 SNPs) (EPI3_E_UNSUPPORTED
+ * otherwise; AUTO then counts on the vector ALU).  Selecting by
  * bound (epi3_set_scan_select) needs a matrix-core variant
  * (EPI3_E_UNSUPPORTED for EPI3_VARIANT_VALU).
  * ws_dev: device workspace of epi3_workspace_bytes(d, k, variant, cand_cap)
@@ -237,9 +240,12 @@ int epi3_scan_topk_static(const epi3_dataset *d, int32_t k, epi3_hit *hits_host,
 
 /* variant: SPLIT jobs run the count kernel each would run in a plain scan
  * with that variant (AUTO follows the tile table per data set; vector-ALU
- * jobs share one persistent launch, matrix-core jobs run their passes one
- * after another); MASKED jobs run on the matrix cores (AUTO = FP4; VALU is
- * EPI3_E_UNSUPPORTED).  The workspace depends on the variant. */
+ * jobs share one persistent launch, and matrix-core jobs of one operand type
+ * and tile shape share one sequence of passes over their tiles, the data
+ * sets with the most samples first); MASKED jobs run on the matrix cores (AUTO = FP4; VALU is
+ * EPI3_E_UNSUPPORTED) and need at most 65535 samples and value planes of
+ * fewer than 2^32 bytes (snp_stride 2 byte_stride), else
+ * EPI3_E_UNSUPPORTED.  The workspace depends on the variant. */
 int64_t epi3_batched_workspace_bytes(const epi3_job *jobs, int32_t n_jobs, int32_t variant,
                                      int64_t cand_cap);
 

@@ -237,8 +237,18 @@ int64_t compact_cap(int64_t T, int64_t cap) {
   return c < T ? c : (T > 0 ? T : 1);
 }
 
+// The matrix-core count kernels address the value planes with 32-bit byte
+// offsets, and the plain finish kernel the two classes' pair tables with
+// 32-bit entry indices.
+bool offsets32_ok(const epi3_dataset &d) {
+  const int64_t classes = d.layout == EPI3_LAYOUT_SPLIT ? 2 : 1;
+  const int64_t value_bytes = classes * d.snp_stride * 2 * (int64_t)d.byte_stride;
+  const int64_t pair_entries = classes * d.snp_stride * (int64_t)d.snp_stride;
+  return value_bytes <= 0xffffffffll && pair_entries <= 0xffffffffll;
+}
+
 bool mfma_supported(const epi3_dataset &d) {
-  return d.bytes && d.nibbles && d.n_cases <= 65535 && d.n_controls <= 65535;
+  return d.bytes && d.nibbles && d.n_cases <= 65535 && d.n_controls <= 65535 && offsets32_ok(d);
 }
 
 // Count-kernel choice for a SPLIT data set (a variant, or a negative status).
@@ -1218,7 +1228,7 @@ int check_jobs(const epi3_job *jobs, int32_t n, int32_t variant) {
     if (layout == EPI3_LAYOUT_MASKED) {
       if (!J.case_mask || !J.d->bytes || !same_dataset(J.d, jobs[0].d)) return EPI3_E_INVALID;
       // counted cells and case pair tables are 16-bit
-      if (J.d->n_samples > 65535) return EPI3_E_UNSUPPORTED;
+      if (J.d->n_samples > 65535 || !offsets32_ok(*J.d)) return EPI3_E_UNSUPPORTED;
     }
   }
   return EPI3_OK;

@@ -324,3 +324,21 @@ def test_scan_select_sizes(epi3):
             4 * math.comb(8192, 3)
     finally:
         epi3.set_scan_select("auto")
+
+
+def test_matrix_core_offset_limits(epi3):
+    """The matrix-core kernels use 32-bit offsets into the value planes and
+    pair tables: shapes beyond them are refused for the matrix-core
+    variants, and AUTO counts them on the vector ALU."""
+    lib = epi3._lib
+    ok = _fake_dataset(epi3, 40000, 8192, 8192)  # 2 x 40064^2 pair entries < 2^32
+    assert lib.epi3_workspace_bytes(ctypes.byref(ok), 10, epi3.VARIANT_MFMA_FP4, 0) > 0
+    wide = _fake_dataset(epi3, 46400, 8192, 8192)  # 2 x 46464^2 > 2^32
+    assert lib.epi3_workspace_bytes(ctypes.byref(wide), 10, epi3.VARIANT_MFMA_FP4, 0) == epi3.E_UNSUPPORTED
+    assert lib.epi3_workspace_bytes(ctypes.byref(wide), 10, epi3.VARIANT_MFMA, 0) == epi3.E_UNSUPPORTED
+    assert lib.epi3_workspace_bytes(ctypes.byref(wide), 10, epi3.VARIANT_AUTO, 0) == \
+        lib.epi3_workspace_bytes(ctypes.byref(wide), 10, epi3.VARIANT_VALU, 0)
+    # value planes of 2 x 20032 x 2 x 65536 bytes > 2^32
+    deep = _fake_dataset(epi3, 20000, 65535, 65535)
+    assert lib.epi3_workspace_bytes(ctypes.byref(deep), 10, epi3.VARIANT_MFMA_FP4, 0) == epi3.E_UNSUPPORTED
+    assert lib.epi3_workspace_bytes(ctypes.byref(deep), 10, epi3.VARIANT_VALU, 0) > 0
