@@ -243,6 +243,21 @@ def test_phenotype_batches_limit_sample_count(epi3):
         assert (r > 0) if want_ok else (r == epi3.E_UNSUPPORTED), r
 
 
+def test_phenotype_batches_limit_value_plane_bytes(epi3):
+    """The phenotype count addresses the value planes (snp_stride x 2 x
+    byte_stride bytes) with 32-bit offsets: 33000 SNPs x 65535 samples
+    (4.3e9 bytes) is EPI3_E_UNSUPPORTED, 30000 SNPs (3.9e9) is not."""
+    lib = epi3._lib
+    for M, want_ok in ((30000, True), (33000, False)):
+        d = _fake_dataset(epi3, M, 65535, 0, layout=1)
+        jobs = (epi3.CJob * 1)()
+        jobs[0].d = ctypes.pointer(d)
+        jobs[0].case_mask = ctypes.c_void_p(4096)
+        jobs[0].k = 5
+        r = lib.epi3_batched_workspace_bytes(jobs, 1, epi3.VARIANT_MFMA_FP4, 0)
+        assert (r > 0) if want_ok else (r == epi3.E_UNSUPPORTED), (M, r)
+
+
 def test_bounded_batches_need_no_plane(epi3):
     """A phenotype batch of 1024 SNPs x 8192 samples x 64 masks: selected by
     bound (the default at this size) its workspace does not hold the
