@@ -48,6 +48,22 @@ def test_bounded_equals_oracle(env, variant, M, N, p, k):
     assert_hits_equal_oracle(h, ijk, rk2, rcc)
 
 
+@pytest.mark.parametrize("variant", ["mfma", "mfma_fp4"])
+@pytest.mark.parametrize("M,N,p,k", [(2, 30, 0.5, 5), (3, 40, 0.5, 1), (4, 50, 0.4, 10),
+                                     (5, 31, 0.3, 10), (12, 3, 0.5, 7), (30, 64, 0.0, 5),
+                                     (30, 64, 1.0, 5)])
+def test_bounded_edges(env, variant, M, N, p, k):
+    """No triplet, one triplet, k at and above C(M,3), three samples, and a
+    class with no samples (all controls, all cases)."""
+    torch, epi3 = env
+    print(f"[case] bounded edge {variant} M={M} N={N} p={p} k={k}", flush=True)
+    geno, pheno = _tiny(7 * M + N, M, N, p)
+    ds = epi3.encode(to_dev(geno), pheno)
+    h = epi3.Scanner(ds, k, variant).run()
+    ijk, rk2, rcc = oracle.scan_topk(geno, pheno, k)
+    assert_hits_equal_oracle(h, ijk, rk2, rcc)
+
+
 def test_bounded_ties(env):
     """Runs of identical SNP rows give exactly equal K2: ties broken by index."""
     torch, epi3 = env
