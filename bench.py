@@ -509,12 +509,15 @@ def run_perm(args, wl):
                          "how": f"64 x (encode + {best_variant} plain scan + top-k), same data",
                          "hits_equal_to_batched": bool(same_best)}
     peak = MFMA_FP4_PEAK_TFLOPS if variant == "mfma_fp4" else MFMA_I8_PEAK_TOPS
+    # no finish launches: the library counted and scored in one kernel
+    fused = fin_ms == 0.0
     out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                        "unit": "TFLOP/s (fp4)" if variant == "mfma_fp4" else "TOP/s (int8)",
                        "frac": round(achieved / peak, 4),
-                       "traffic": recorded_traffic(f"{args.workload}|{variant}"),
+                       "traffic": recorded_traffic(f"{args.workload}|{variant}" + ("|fused" if fused else "")),
                        "traffic_unit": "bytes per launch (FETCH_SIZE x2 + WRITE_SIZE x1, copy-calibrated)",
-                       "kernel": "count_mfma_perm_kernel", "kernel_ms": round(k_ms / max(k_n, 1), 4),
+                       "kernel": "count_score_perm_kernel" if fused else "count_mfma_perm_kernel",
+                       "kernel_ms": round(k_ms / max(k_n, 1), 4),
                        "launches_per_step": k_n,
                        "ops_per_launch": MFMA_OPS_PER_STQ * T * N * Q / max(k_n, 1)}
     out["breakdown_ms"] = {"count_kernels": round(k_ms, 3), "finish_kernels": round(fin_ms, 3),

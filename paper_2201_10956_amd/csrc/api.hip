@@ -1291,8 +1291,6 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
     const int64_t tiles = host_perm_tiles(d.n_snps);
     L.pass_tiles = std::max<int64_t>(
         1, std::min<int64_t>(tiles, pass_bytes(kPermPassBytes) / kPermTileScratch));
-    // two buffers: the count kernel of pass p + 1 runs while pass p is scored
-    L.perm_scratch = c.take<uint8_t>(2 * L.pass_tiles * kPermTileScratch);
     int32_t max_k = 0;
     for (int x = 0; x < n; ++x) max_k = std::max(max_k, jobs[x].k);
     const int64_t T = epi3_n_triplets(d.n_snps);
@@ -1314,6 +1312,11 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
         L.shist = c.take<uint32_t>((int64_t)n * kHistBins);
       }
     }
+    // two buffers: the count kernel of pass p + 1 runs while pass p is
+    // scored; not needed where FP4 passes count and score in one kernel
+    const bool fp4 = variant != EPI3_VARIANT_MFMA;
+    if (!(L.bounded && fp4 && perm_fused_ok(d.n_samples + 2)))
+      L.perm_scratch = c.take<uint8_t>(2 * L.pass_tiles * kPermTileScratch);
   }
   L.jprefix.resize(n);
   L.score.resize(n);
@@ -1516,8 +1519,14 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
       pj.n1 = W.n1 + (int64_t)g * kPermGroup;
       pj.score = W.score[g * kPermGroup];
       pj.jprefix = W.perm_prefix;
-      pj.corners = reinterpret_cast<uint4 *>(W.perm_scratch);
-      pj.totals = reinterpret_cast<uint4 *>(W.perm_scratch + W.pass_tiles * 64 * 64 * 16);
+      // no scratch where the passes count and score in one kernel
+      uint8_t *scr[2] = {nullptr, nullptr};
+      if (W.perm_scratch) {
+        scr[0] = W.perm_scratch;
+        scr[1] = W.perm_scratch + W.pass_tiles * kPermTileScratch;
+      }
+      pj.corners = reinterpret_cast<uint4 *>(scr[0]);
+      pj.totals = scr[0] ? reinterpret_cast<uint4 *>(scr[0] + W.pass_tiles * 64 * 64 * 16) : nullptr;
       pj.n_tiles = tiles;
       pj.T = epi3_n_triplets(d.n_snps);
       pj.M = d.n_snps;
@@ -1538,9 +1547,8 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
       hipEvent_t ev_start = lease.c->ev[0], ev_cnt[2] = {lease.c->ev[1], lease.c->ev[2]},
                  ev_fin[2] = {lease.c->ev[3], lease.c->ev[4]};
       PermJob pjb[2] = {pj, pj};
-      pjb[1].corners = reinterpret_cast<uint4 *>(W.perm_scratch + W.pass_tiles * kPermTileScratch);
-      pjb[1].totals = reinterpret_cast<uint4 *>(W.perm_scratch + W.pass_tiles * kPermTileScratch +
-                                                W.pass_tiles * 64 * 64 * 16);
+      pjb[1].corners = reinterpret_cast<uint4 *>(scr[1]);
+      pjb[1].totals = scr[1] ? reinterpret_cast<uint4 *>(scr[1] + W.pass_tiles * 64 * 64 * 16) : nullptr;
       HIP_OK(launch_write_permjob(pjb[1], W.pjobs_alt + g, s));
       const PermJob *pdev[2] = {W.pjobs + g, W.pjobs_alt + g};
       // Passes over the tiles n * stride, n < n_all: pass p counts into scratch
@@ -1549,6 +1557,20 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
       // buffer).  Events order the two streams (also when captured); the join
       // at the end puts everything on `s` again.
       auto passes = [&](int64_t n_all, int64_t stride, SelState *fst, PermOut out) -> int {
+        if (fp4 && out.mode != kPermOutPlane && perm_fused_ok(d.n_samples + 2)) {
+          // counted and scored by one persistent kernel over all the tiles:
+          // no scratch, no second stream
+          if (n_all <= 0) return EPI3_OK;
+          HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
+          out.sample_base = 0;
+          return timed(0, s, [&]() {
+            return launch_count_score_perm(W.pjobs + g, 0, n_all, stride, W.queue, fst, d.lf32,
+                                           d.n_samples + 2, out, s) == hipSuccess
+                       ? EPI3_OK
+                       : EPI3_E_HIP;
+          });
+        }
+        if (!W.perm_scratch) return EPI3_E_INVALID;  // the layout and the passes disagree
         HIP_OK(hipEventRecord(ev_start, s));
         HIP_OK(hipStreamWaitEvent(s2, ev_start, 0));
         int p = 0;

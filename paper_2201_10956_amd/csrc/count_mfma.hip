@@ -187,6 +187,17 @@ constexpr int kStageBytes = kRowsAll * kRow; // one buffer
 template <typename T>
 using gptr = const __attribute__((address_space(1))) T *;
 
+// Bytes of an FP32 log-factorial table of lf_len entries in LDS (16-byte multiple).
+__host__ __device__ __forceinline__ int finish_perm_table_bytes(int lf_len) {
+  return (lf_len * 4 + 15) / 16 * 16;
+}
+// LDS of the count-and-score kernel: the table, then staging, tile slot,
+// totals exchange, the tile's all-sample cells and the key ranges.
+__host__ __device__ __forceinline__ int perm_score_lds_bytes(int lf_len) {
+  return finish_perm_table_bytes(lf_len) + 2 * kStageBytes + 2 * 8 + 2 * 64 * 4 * 4 + 4 * kPermKB * 16 +
+         64 * 2 * 4;
+}
+
 // Workgroup tile: pivot j, four pivots i = 4 ib + wave (one per wave), 16
 // consecutive k > j, 64 phenotypes.  Phenotype bytes, the k planes and the
 // pair words are staged per chunk of kKC samples in double-buffered LDS; each
@@ -242,20 +253,174 @@ __device__ __forceinline__ v4i quad_bcast(v4i x) {
   return y;
 }
 
-template <bool FP4>
-__global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
-    const PermJob *__restrict__ pjp, int64_t tile_begin, int64_t n_tiles, int64_t stride,
-    unsigned long long *__restrict__ queue) {
-  typedef PermAcc<FP4> Acc;
-  __shared__ __attribute__((aligned(16))) unsigned char stage[2 * kStageBytes];
-  __shared__ int64_t sTile[2];
-  // FP4: all-sample corner counts of half the samples from the waves of the
-  // second half, added by the waves of the first half
-  __shared__ float sTot[2][64][4];
+// Completes and scores, in the count kernel, the 16 x 64 (triplet,
+// phenotype) case tables of one wave's pivot i of a tile (k = k0 .. k0 + 15,
+// lane = phenotype), as finish_perm_kernel does from the corner scratch: the
+// same cells, the same FP32 row order, the same outputs.  The accumulators
+// hold, in lane (q, h), the case cells with genotype h at SNP k of phenotype
+// q mod 32 + 32 qb; one lane-half swap per register pair (qb = 0, 1) leaves
+// lane q with both genotypes of phenotype q.  Lanes 0..15 complete the
+// all-sample tables (cells from the tile's totals in LDS) and write, per k,
+// the 27 cells x 4 and their L[cell + 1] to the wave's part of the idle
+// staging buffer (`row`, 224 bytes per k), which every lane then reads as
+// broadcasts.  The log-factorial table sits at LDS address 0.
+template <int FUSE>
+__device__ __forceinline__ void fused_score(const PermJob &pj, v16f (&acc)[kPermT][2],
+                                            const uint4 *tot16, uint32_t *rows,
+                                            SelState *__restrict__ st, const PermOut &out, int i,
+                                            int j, int k0, int64_t slot, int wave, int lane,
+                                            uint32_t &kmin, uint32_t &kmax) {
+  // the pivot is uniform over the wave: scalar row addresses below
+  i = __builtin_amdgcn_readfirstlane(i);
+  wave = __builtin_amdgcn_readfirstlane(wave);
+  const int M = pj.M, Mp = pj.Mp, Q = pj.Q, Qp = pj.Qp;
+  const int kk_lo = j + 1 - k0 > 0 ? j + 1 - k0 : 0;
+  const int kk_hi = M - k0 < kPermKB ? M - k0 : kPermKB;
+  // case cells of phenotype q = lane: genotype 0 of SNP k in the low half,
+  // genotype 1 in the high half of each register, (a, b) = v % 4
+  uint32_t cc[kPermT][16];
+#pragma unroll
+  for (int tt = 0; tt < kPermT; ++tt)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const auto sw = __builtin_amdgcn_permlane32_swap((uint32_t)acc[tt][0][v],
+                                                       (uint32_t)acc[tt][1][v], false, false);
+      cc[tt][v] = sw[0] | (sw[1] << 16);
+    }
+  // all-sample tables, lane kk = triplet (i, j, k0 + kk)
+  if (lane >= kk_lo && lane < kk_hi) {
+    const int4 *tp = reinterpret_cast<const int4 *>(pj.tot_pairs);
+    const int k = k0 + lane;
+    const uint4 tq = tot16[lane];
+    const uint32_t tn[8] = {(tq.x & 0xffffu) << 2, (tq.x >> 16) << 2, (tq.y & 0xffffu) << 2,
+                            (tq.y >> 16) << 2, (tq.z & 0xffffu) << 2, (tq.z >> 16) << 2,
+                            (tq.w & 0xffffu) << 2, (tq.w >> 16) << 2};
+    const int4 a = tp[(int64_t)i * Mp + j], b = tp[(int64_t)i * Mp + k], c = tp[(int64_t)j * Mp + k];
+    const int4 ii4 = tp[(int64_t)i * Mp + i], jj4 = tp[(int64_t)j * Mp + j], kk4 = tp[(int64_t)k * Mp + k];
+    const int tij[4] = {a.x << 2, a.y << 2, a.z << 2, a.w << 2};
+    const int tik[4] = {b.x << 2, b.y << 2, b.z << 2, b.w << 2};
+    const int tjk[4] = {c.x << 2, c.y << 2, c.z << 2, c.w << 2};
+    const int mi[2] = {ii4.x << 2, ii4.w << 2}, mj[2] = {jj4.x << 2, jj4.w << 2};
+    const int mk[2] = {kk4.x << 2, kk4.w << 2};
+    int t4[27];
+    complete_table(tn, tij, tik, tjk, mi, mj, mk, pj.N << 2, t4);
+    uint32_t *row = rows + lane * 56;
+#pragma unroll
+    for (int x = 0; x < 27; ++x) {
+      row[x] = (uint32_t)t4[x];
+      row[28 + x] = __float_as_uint(lf_at_lds0(t4[x] + 4));
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  typedef unsigned u2e __attribute__((ext_vector_type(2)));
+  gptr<u2e> cp = (gptr<u2e>)pj.case_pairs;
+  auto cp_row = [&](int x, int y) { return cp + ((int64_t)x * Mp + y) * Qp; };
+  auto lo4 = [](unsigned v) { return (int)((v & 0xffffu) << 2); };
+  auto hi4 = [](unsigned v) { return (int)((v >> 16) << 2); };
+  const int q = lane, qc = q < Q ? q : 0;
+  const int n1x4 = pj.n1[qc] << 2;
+  const float ubq = FUSE == kPermOutBounded ? st[qc].ub : 0.f;
+  const u2e cij = cp_row(i, j)[qc];
+  const u2e cii = cp_row(i, i)[qc], cjj = cp_row(j, j)[qc];
+  const int aij[4] = {lo4(cij.x), hi4(cij.x), lo4(cij.y), hi4(cij.y)};
+  const int mi[2] = {lo4(cii.x), hi4(cii.y)}, mj[2] = {lo4(cjj.x), hi4(cjj.y)};
+  const int64_t base = lex_base(M, i, j) + k0;
+  // rows k0 .. k0 + 15 lie below the padded stride Mp (k0 + 15 < M + 16):
+  // loaded for every k, used for k in (j, M) only; one k ahead, through
+  // uniform row pointers advanced by one k per step
+  gptr<u2e> pik = cp_row(i, k0), pjk = cp_row(j, k0), pkk = cp_row(k0, k0);
+  const int64_t dkk = (int64_t)(Mp + 1) * Qp;
+  u2e cik_n = pik[qc], cjk_n = pjk[qc], ckk_n = pkk[qc];
+#pragma unroll
+  for (int tt = 0; tt < kPermT; ++tt)
+#pragma unroll
+    for (int t4 = 0; t4 < 4; ++t4) {
+      const int kk = 4 * tt + t4;
+      const u2e cik = cik_n, cjk = cjk_n, ckk = ckk_n;
+      if (kk + 1 < kPermKB) {
+        pik += Qp;
+        pjk += Qp;
+        pkk += dkk;
+        cik_n = pik[qc];
+        cjk_n = pjk[qc];
+        ckk_n = pkk[qc];
+      }
+      if (kk < kk_lo || kk >= kk_hi) continue;  // wave-uniform
+      int c4[27];
+      {
+        uint32_t cn[8];  // corner index 4 a + 2 b + c, x 4
+#pragma unroll
+        for (int ab = 0; ab < 4; ++ab) {
+          const uint32_t w = cc[tt][4 * t4 + ab];
+          cn[2 * ab] = (w << 2) & 0x3fffcu;
+          cn[2 * ab + 1] = (w >> 14) & 0x3fffcu;
+        }
+        const int aik[4] = {lo4(cik.x), hi4(cik.x), lo4(cik.y), hi4(cik.y)};
+        const int ajk[4] = {lo4(cjk.x), hi4(cjk.x), lo4(cjk.y), hi4(cjk.y)};
+        const int mk[2] = {lo4(ckk.x), hi4(ckk.y)};
+        complete_table(cn, aij, aik, ajk, mi, mj, mk, n1x4, c4);
+      }
+      // cells x 4 in words 0..27, their L[cell + 1] in words 28..55 (same
+      // address in all lanes: broadcast reads), four rows at a time
+      const uint4 *rk = reinterpret_cast<const uint4 *>(rows + kk * 56);
+      float k2 = 0.f;  // rows in order: L[r + 1] - (L[r_0] + L[r_1]), r_1 = cases
+#pragma unroll
+      for (int x4 = 0; x4 < 7; ++x4) {
+        const uint4 tv = rk[x4], lv = rk[7 + x4];
+        const uint32_t ta[4] = {tv.x, tv.y, tv.z, tv.w}, la[4] = {lv.x, lv.y, lv.z, lv.w};
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          const int x = 4 * x4 + y;
+          if (x < 27) {
+            const int r0 = (int)ta[y] - c4[x];
+            k2 += __uint_as_float(la[y]) - (lf_at_lds0(r0) + lf_at_lds0(c4[x]));
+          }
+        }
+      }
+      const uint32_t key = f2key(k2);
+      kmin = key < kmin ? key : kmin;
+      kmax = key > kmax ? key : kmax;
+      if (FUSE == kPermOutSample && q < Q)
+        out.sample[(int64_t)q * out.sample_T + (out.sample_base + slot) * 64 + wave * kPermKB + kk] = k2;
+      if (FUSE == kPermOutBounded && q < Q && k2 <= ubq) {
+        const unsigned long long pos = atomicAdd(&st[q].cn, 1ull);
+        if ((int64_t)pos < out.ccap) {
+          out.ckey[(int64_t)q * out.ccap + pos] = key;
+          out.crank[(int64_t)q * out.ccap + pos] = base + kk;
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);  // one k at a time: short live ranges
+    }
+}
 
+// FUSE = kPermOutSample / kPermOutBounded (FP4 only): each wave completes
+// and scores its own pivot's 16 x 64 (triplet, phenotype) tables right after
+// the tile's counts, from the accumulators (as the finish kernel does from
+// the corner scratch), with the log-factorial table at LDS address 0;
+// nothing goes to the scratch.  FUSE = 0: corner cells out, finish_perm_kernel
+// after.  The kernels below give the LDS arrays.
+template <bool FP4, int FUSE>
+__device__ __forceinline__ void count_perm_body(
+    const PermJob *__restrict__ pjp, int64_t tile_begin, int64_t n_tiles, int64_t stride,
+    unsigned long long *__restrict__ queue, SelState *__restrict__ st,
+    const float *__restrict__ lf32, int lf_len, const PermOut &out, unsigned char *stage,
+    int64_t *sTile, float (*sTot)[64][4], uint4 (*sT16)[kPermKB], uint32_t (*sRange)[2],
+    float *sLf) {
+  static_assert(FUSE == 0 || FP4, "fused scoring takes FP4 accumulators");
+  typedef PermAcc<FP4> Acc;
   const PermJob pj = *pjp;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
+  if constexpr (FUSE != 0) {
+    for (int x = tid; x < lf_len; x += 256) sLf[x] = lf32[x];
+    if (tid < 64) {
+      sRange[tid][0] = 0xffffffffu;
+      sRange[tid][1] = 0u;
+    }
+  }
+  uint32_t kmin = 0xffffffffu, kmax = 0u;  // FUSE: this lane's phenotype's key range
   const int r = lane & 31, g = lane >> 5;
   // A row r of a row tile = (triplet ta = r / 8, corner c = (r / 4) % 2,
   // a = (r / 2) % 2, b = r % 2): the four lanes of a quad share (ta, c) and
@@ -490,15 +655,23 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
       if (tsh == 0) {
         const int p = lane >> 4;
         if (4 * ib + p < j) {
-          uint16_t *t16 = reinterpret_cast<uint16_t *>(pj.totals + (slot * 4 + p) * (int64_t)kPermKB);
+          uint16_t *t16 = FUSE ? reinterpret_cast<uint16_t *>(&sT16[p][0])
+                               : reinterpret_cast<uint16_t *>(pj.totals + (slot * 4 + p) * (int64_t)kPermKB);
           const int kl = 8 * tkh + ((lane & 15) >> 1), c = lane & 1;
 #pragma unroll
           for (int v = 0; v < 4; ++v)
             t16[kl * 8 + 2 * v + c] = (uint16_t)(uint32_t)(tacc[v] + sTot[tkh][lane][v]);
         }
       }
+      if constexpr (FUSE != 0) __syncthreads();  // sT16 complete
     }
     if (i >= j) continue;  // padding pivot of the last i-block: nothing to write
+    if constexpr (FUSE != 0) {
+      // the staging buffers are idle until the next tile's first store
+      fused_score<FUSE>(pj, acc, sT16[wave], reinterpret_cast<uint32_t *>(stage + wave * 4096), st,
+                        out, i, j, kbase, slot, wave, lane, kmin, kmax);
+      continue;
+    }
 
     // ---- counts out: all-sample corner cells per triplet, case corner cells
     // per (triplet, phenotype); the finish kernel completes tables and scores.
@@ -527,6 +700,51 @@ __global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
           cor2[((4 * tt + t4) * 64 + qb * 32 + r) * 2 + g] = make_uint2(c0 | (c1 << 16), c2 | (c3 << 16));
         }
   }
+  if constexpr (FUSE != 0) {
+    const int Q = pj.Q;
+    if (lane < Q && kmax != 0u) {
+      atomicMin(&sRange[lane][0], kmin);
+      atomicMax(&sRange[lane][1], kmax);
+    }
+    __syncthreads();
+    if (tid < 64 && tid < Q && sRange[tid][1] != 0u) {
+      atomicMin(&st[tid].kmin, sRange[tid][0]);
+      atomicMax(&st[tid].kmax, sRange[tid][1]);
+    }
+  }
+}
+
+// LDS: double-buffered staging, the tile slot, the FP4 totals exchange.
+template <bool FP4>
+__global__ void __launch_bounds__(256, 2) count_mfma_perm_kernel(
+    const PermJob *__restrict__ pjp, int64_t tile_begin, int64_t n_tiles, int64_t stride,
+    unsigned long long *__restrict__ queue) {
+  __shared__ __attribute__((aligned(16))) unsigned char stage[2 * kStageBytes];
+  __shared__ int64_t sTile[2];
+  // FP4: all-sample corner counts of half the samples from the waves of the
+  // second half, added by the waves of the first half
+  __shared__ float sTot[2][64][4];
+  const PermOut none{};
+  count_perm_body<FP4, 0>(pjp, tile_begin, n_tiles, stride, queue, nullptr, nullptr, 0, none, stage,
+                          sTile, sTot, nullptr, nullptr, nullptr);
+}
+
+// Dynamic LDS only, so the log-factorial table starts at LDS address 0 and a
+// lookup is one ds_read at the byte offset: [table][staging][tile slot]
+// [totals exchange][the tile's all-sample cells][key ranges].
+template <int FUSE>
+__global__ void __launch_bounds__(256, 2) count_score_perm_kernel(
+    const PermJob *__restrict__ pjp, int64_t tile_begin, int64_t n_tiles, int64_t stride,
+    unsigned long long *__restrict__ queue, SelState *__restrict__ st,
+    const float *__restrict__ lf32, int lf_len, PermOut out) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  unsigned char *stage = lds + finish_perm_table_bytes(lf_len);
+  int64_t *sTile = reinterpret_cast<int64_t *>(stage + 2 * kStageBytes);
+  float(*sTot)[64][4] = reinterpret_cast<float(*)[64][4]>(sTile + 2);
+  uint4(*sT16)[kPermKB] = reinterpret_cast<uint4(*)[kPermKB]>(sTot + 2);
+  uint32_t(*sRange)[2] = reinterpret_cast<uint32_t(*)[2]>(sT16 + 4);
+  count_perm_body<true, FUSE>(pjp, tile_begin, n_tiles, stride, queue, st, lf32, lf_len, out, stage,
+                              sTile, sTot, sT16, sRange, reinterpret_cast<float *>(lds));
 }
 
 // Completes the tables of one pass of tiles and scores them.  Workgroup per
@@ -554,9 +772,6 @@ struct FinishPermLds {
 // score staging out (more workgroups per CU).
 __host__ __device__ constexpr size_t finish_perm_lds_bytes(int mode) {
   return mode == kPermOutPlane ? sizeof(FinishPermLds) : offsetof(FinishPermLds, score);
-}
-__host__ __device__ __forceinline__ int finish_perm_table_bytes(int lf_len) {
-  return (lf_len * 4 + 15) / 16 * 16;
 }
 
 template <bool LDS, int MODE>
@@ -794,9 +1009,11 @@ int64_t host_perm_tiles(int64_t M) {
   return n;
 }
 
-template <bool FP4>
+template <bool FP4, int FUSE>
 static hipError_t launch_count_t(const PermJob *pj_dev, int64_t tile_begin, int64_t n_tiles,
-                                 int64_t stride, unsigned long long *queue, hipStream_t s) {
+                                 int64_t stride, unsigned long long *queue, SelState *st,
+                                 const float *lf32, int32_t lf_len, const PermOut &out,
+                                 hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   int dev = 0, n_cu = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -804,21 +1021,56 @@ static hipError_t launch_count_t(const PermJob *pj_dev, int64_t tile_begin, int6
   e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, count_mfma_perm_kernel<FP4>, 256, 0);
-  if (e != hipSuccess) return e;
-  if (per_cu <= 0) per_cu = 1;
-  int64_t blocks = (int64_t)n_cu * per_cu;
-  if (blocks > n_tiles) blocks = n_tiles;
-  hipLaunchKernelGGL(count_mfma_perm_kernel<FP4>, dim3((unsigned)blocks), dim3(256), 0, s, pj_dev,
-                     tile_begin, n_tiles, stride, queue);
+  if constexpr (FUSE == 0) {
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, count_mfma_perm_kernel<FP4>, 256, 0);
+    if (e != hipSuccess) return e;
+    if (per_cu <= 0) per_cu = 1;
+    int64_t blocks = (int64_t)n_cu * per_cu;
+    if (blocks > n_tiles) blocks = n_tiles;
+    hipLaunchKernelGGL(count_mfma_perm_kernel<FP4>, dim3((unsigned)blocks), dim3(256), 0, s, pj_dev,
+                       tile_begin, n_tiles, stride, queue);
+  } else {
+    const size_t lds = (size_t)perm_score_lds_bytes(lf_len);
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&count_score_perm_kernel<FUSE>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, count_score_perm_kernel<FUSE>, 256, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu <= 0) per_cu = 1;
+    int64_t blocks = (int64_t)n_cu * per_cu;
+    if (blocks > n_tiles) blocks = n_tiles;
+    hipLaunchKernelGGL(count_score_perm_kernel<FUSE>, dim3((unsigned)blocks), dim3(256), lds, s,
+                       pj_dev, tile_begin, n_tiles, stride, queue, st, lf32, lf_len, out);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t n_tiles,
                                   int64_t stride, unsigned long long *queue, bool fp4,
                                   hipStream_t s) {
-  return fp4 ? launch_count_t<true>(pj_dev, tile_begin, n_tiles, stride, queue, s)
-             : launch_count_t<false>(pj_dev, tile_begin, n_tiles, stride, queue, s);
+  const PermOut none{};
+  return fp4 ? launch_count_t<true, 0>(pj_dev, tile_begin, n_tiles, stride, queue, nullptr, nullptr,
+                                       0, none, s)
+             : launch_count_t<false, 0>(pj_dev, tile_begin, n_tiles, stride, queue, nullptr,
+                                        nullptr, 0, none, s);
+}
+
+bool perm_fused_ok(int32_t lf_len) {
+  return lf_len > 0 && perm_score_lds_bytes(lf_len) <= 80 * 1024;  // two workgroups per CU
+}
+
+hipError_t launch_count_score_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t n_tiles,
+                                   int64_t stride, unsigned long long *queue, SelState *st,
+                                   const float *lf32, int32_t lf_len, const PermOut &out,
+                                   hipStream_t s) {
+  if (!perm_fused_ok(lf_len)) return hipErrorInvalidValue;
+  if (out.mode == kPermOutSample)
+    return launch_count_t<true, kPermOutSample>(pj_dev, tile_begin, n_tiles, stride, queue, st, lf32,
+                                                lf_len, out, s);
+  if (out.mode == kPermOutBounded)
+    return launch_count_t<true, kPermOutBounded>(pj_dev, tile_begin, n_tiles, stride, queue, st, lf32,
+                                                 lf_len, out, s);
+  return hipErrorInvalidValue;
 }
 
 template <bool LDS, int MODE>

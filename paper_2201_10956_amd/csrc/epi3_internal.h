@@ -586,6 +586,13 @@ hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t tile_begin, int
 hipError_t launch_finish_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t n_tiles,
                               int64_t stride, SelState *st, const float *lf32, int32_t lf_len,
                               const PermOut &out, hipStream_t s);
+// Count and score in one kernel (FP4 operands, sample or bounded output, the
+// log-factorial table of lf_len entries in LDS: perm_fused_ok); no scratch.
+bool perm_fused_ok(int32_t lf_len);
+hipError_t launch_count_score_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t n_tiles,
+                                   int64_t stride, unsigned long long *queue, SelState *st,
+                                   const float *lf32, int32_t lf_len, const PermOut &out,
+                                   hipStream_t s);
 // Triplets (i < j < k < M) in the phenotype-batch tiles 0, stride, 2 stride, ...
 int64_t host_perm_sample_valid(int64_t M, int64_t stride);
 constexpr int64_t kPermTileScratch = 64 * 64 * 16 + 64 * 16;  // bytes per tile (corners + totals)
