@@ -115,3 +115,18 @@ def test_bounded_more_hits_than_triplets(env):
     for q in range(2):
         assert len(res[q]) == 20
         assert_hits_equal_oracle(res[q], *oracle.scan_topk(d.geno, perms[q], 30))
+
+
+@pytest.mark.parametrize("N", [11400, 11600])
+def test_bounded_on_both_sides_of_the_one_kernel_limit(env, N):
+    """FP4 batches selected by bound count and score in one kernel while the
+    log-factorial table fits beside the staging in LDS (up to about 11500
+    samples) and in two kernels above: both give the oracle's hits."""
+    torch, epi3 = env
+    print(f"[case] bounded fp4 N={N}", flush=True)
+    d = make_dataset(40, N, 0.45, 0.05, seed=N)
+    perms = make_permutations(d.pheno, 3, seed=N + 1)
+    ds = epi3.encode(to_dev(d.geno), d.pheno, layout="masked")
+    _, res = _run(epi3, ds, 4, _masks(epi3, perms), "mfma_fp4", "bounded")
+    for q in range(3):
+        assert_hits_equal_oracle(res[q], *oracle.scan_topk(d.geno, perms[q], 4))
