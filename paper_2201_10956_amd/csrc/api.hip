@@ -1243,7 +1243,7 @@ BatchLayout batch_layout(void *ws, const epi3_job *jobs, int32_t n, int64_t cand
   L.sel = c.take<SelJob>(n);
   L.st = c.take<SelState>(n);
   L.hist = c.take<uint32_t>((int64_t)n * kHistBins);
-  L.queue = c.take<unsigned long long>(4);
+  L.queue = c.take<unsigned long long>(8);  // tile counters (the phenotype count: one per XCD)
   L.hit_off.resize(n);
   for (int x = 0; x < n; ++x) {
     L.hit_off[x] = L.total_k;
@@ -1561,7 +1561,7 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
           // counted and scored by one persistent kernel over all the tiles:
           // no scratch, no second stream
           if (n_all <= 0) return EPI3_OK;
-          HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
+          HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 16, s));
           out.sample_base = 0;
           return timed(0, s, [&]() {
             return launch_count_score_perm(W.pjobs + g, 0, n_all, stride, W.queue, fst, d.lf32,
@@ -1578,7 +1578,7 @@ int enqueue_batched(const epi3_job *jobs, int32_t n, const BatchLayout &W, int32
           const int64_t nn = std::min(W.pass_tiles, n_all - n0);
           const int b = p & 1;
           if (p >= 2) HIP_OK(hipStreamWaitEvent(s, ev_fin[b], 0));
-          HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 2, s));
+          HIP_OK(launch_fill_u32(reinterpret_cast<uint32_t *>(W.queue), 0u, 16, s));
           int rc = timed(0, s, [&]() {
             return launch_count_mfma_perm(pdev[b], n0 * stride, nn, stride, W.queue, fp4, s) ==
                            hipSuccess

@@ -36,6 +36,18 @@ __host__ __device__ __forceinline__ int perm_kb_lo(int64_t j) { return (int)((j 
 __host__ __device__ __forceinline__ int perm_nkb(int64_t M, int64_t j) {
   return (int)((M - 1) / kPermKB) - perm_kb_lo(j) + 1;
 }
+// i-block and k-block of tile rr of pivot j: bands of 8 i-blocks, k-block
+// major within a band, so the tiles one XCD works on at a time share the
+// operand rows of 8 i-blocks and of a few k-blocks (and their case pair rows).
+__host__ __device__ __forceinline__ void perm_tile_ib_kb(int rr, int j, int nkb, int &ib, int &kb) {
+  const int nib = (j + 3) / 4;
+  const int band = rr / (8 * nkb);
+  const int rest = nib - 8 * band;
+  const int bcnt = rest < 8 ? rest : 8;
+  const int pos = rr - band * 8 * nkb;
+  kb = pos / bcnt;
+  ib = 8 * band + (pos - kb * bcnt);
+}
 __host__ __device__ __forceinline__ int64_t perm_tiles_of_j(int64_t M, int64_t j) {
   if (j < 1 || j > M - 2) return 0;
   return ((j + 3) / 4) * perm_nkb(M, j);
@@ -435,9 +447,27 @@ __device__ __forceinline__ void count_perm_body(
   int j = -1;
   int64_t jlo = 0, jhi = 0;
 
+  // Tile slots: the pass is cut into 8 contiguous parts, one per XCD
+  // (workgroups go to the XCDs round robin, so workgroup b runs on XCD
+  // b mod 8), each with its own counter in queue[0..7]; a workgroup takes the
+  // next slot of its XCD's part, and once that part is done those of the
+  // other parts in turn.  Consecutive slots share operand rows, which then
+  // stay in one XCD's L2.  Every workgroup ends after at most 8 empty draws.
+  int xq = 0;
+  const int xcd = blockIdx.x & 7;
   for (;;) {
     __syncthreads();  // previous tile's readers of sTile / stage are done
-    if (tid == 0) sTile[0] = (int64_t)atomicAdd(queue, 1ull);
+    if (tid == 0) {
+      int64_t sl = -1;
+      while (xq < 8) {
+        const int y = (xcd + xq) & 7;
+        const int64_t lo = n_tiles * y / 8, hi = n_tiles * (y + 1) / 8;
+        const int64_t c = (int64_t)atomicAdd(queue + y, 1ull);
+        if (lo + c < hi) { sl = lo + c; break; }
+        ++xq;
+      }
+      sTile[0] = sl < 0 ? n_tiles : sl;
+    }
     __syncthreads();
     const int64_t slot = rfl64p(sTile[0]);  // scratch slot of this launch
     if (slot >= n_tiles) break;
@@ -454,7 +484,8 @@ __device__ __forceinline__ void count_perm_body(
     }
     const int nkb = perm_nkb(M, j);
     const int rr = (int)(t - jlo);
-    const int ib = rr / nkb, kb = rr - ib * nkb;
+    int ib, kb;
+    perm_tile_ib_kb(rr, j, nkb, ib, kb);
     const int i = 4 * ib + wave;  // may be >= j (then the wave's results are dropped)
     const int kbase = (perm_kb_lo(j) + kb) * kPermKB;  // k <= j or k >= M: dropped later
 
@@ -830,8 +861,10 @@ __global__ void __launch_bounds__(256) finish_perm_kernel(const PermJob *__restr
     // the quotient comes out of vector instructions: taken back to a scalar
     // register, so the row addresses below are formed by scalar arithmetic
     const int nkb_j = perm_nkb(M, j);
-    const int ib = __builtin_amdgcn_readfirstlane((int)rr / nkb_j);
-    const int kbg = perm_kb_lo(j) + ((int)rr - ib * nkb_j);
+    int ib_, kb_;
+    perm_tile_ib_kb((int)rr, j, nkb_j, ib_, kb_);
+    const int ib = __builtin_amdgcn_readfirstlane(ib_);
+    const int kbg = perm_kb_lo(j) + __builtin_amdgcn_readfirstlane(kb_);
     const int i = 4 * ib + wave;
     const int k0 = kbg * kPermKB;
     if (i >= j) continue;  // wave-uniform
@@ -1045,6 +1078,7 @@ static hipError_t launch_count_t(const PermJob *pj_dev, int64_t tile_begin, int6
   return hipGetLastError();
 }
 
+// queue: 8 zeroed 64-bit counters (one per XCD part of the pass).
 hipError_t launch_count_mfma_perm(const PermJob *pj_dev, int64_t tile_begin, int64_t n_tiles,
                                   int64_t stride, unsigned long long *queue, bool fp4,
                                   hipStream_t s) {
@@ -1132,7 +1166,9 @@ int64_t host_perm_sample_valid(int64_t M, int64_t stride) {
       const int nkb = perm_nkb(M, j);
       for (int64_t t = (pre + stride - 1) / stride * stride; t < pre + nt; t += stride) {
         const int64_t rr = t - pre;
-        const int64_t ib = rr / nkb, kb = rr % nkb;
+        int ib_, kb_;
+        perm_tile_ib_kb((int)rr, (int)j, nkb, ib_, kb_);
+        const int64_t ib = ib_, kb = kb_;
         const int64_t ni = std::max<int64_t>(0, std::min<int64_t>(4, j - 4 * ib));
         const int64_t kbase = (perm_kb_lo(j) + kb) * kPermKB;
         const int64_t nk = std::max<int64_t>(
