@@ -13,6 +13,12 @@
 // (cases + controls) come from byte popcounts of the same operand, so
 // controls = totals - cases.
 //
+// FP4 (E2M1) operands run the same products on the scaled f8f6f4 matrix
+// instructions.  Batches selected by bound count and score in one kernel
+// (count_score_perm_kernel): each wave scores its tile's tables from its
+// accumulators; otherwise the corner cells go through a scratch buffer to
+// finish_perm_kernel.
+//
 // Fragment layout of v_mfma_i32_32x32x32_i8 (gfx950, checked on hardware):
 // lane l supplies A row l % 32 and B column l % 32 with 16 consecutive K
 // values starting at 16 (l / 32); the result of row r, column c is in lane
