@@ -282,7 +282,15 @@ def test_bounded_batches_need_no_plane(epi3):
         epi3.set_batch_select("auto")
     assert auto == bounded
     assert plane - bounded > 64 * T * 4 * 0.99
-    assert bounded < 10 * (1 << 30)  # the pass scratch (2 x 4 GiB) dominates
+    # FP4 batches selected by bound count and score in one kernel: no pass
+    # scratch (int8 operands keep the 2 x 4 GiB of corner cells)
+    assert bounded < 1 << 30
+    try:
+        epi3.set_batch_select("bounded")
+        int8 = lib.epi3_batched_workspace_bytes(jobs, 64, epi3.VARIANT_MFMA, 0)
+    finally:
+        epi3.set_batch_select("auto")
+    assert int8 - bounded > 7 * (1 << 30)
     assert lib.epi3_set_batch_select(3) == epi3.E_INVALID
     assert lib.epi3_set_batch_select(-1) == epi3.E_INVALID
 
