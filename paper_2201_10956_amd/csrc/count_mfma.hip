@@ -476,6 +476,10 @@ __device__ __forceinline__ void count_perm_body(
     }
     __syncthreads();
     const int64_t slot = rfl64p(sTile[0]);  // scratch slot of this launch
+    // FUSE: a wave that counts issues ahead of the other workgroup's waves
+    // that score (their vector instructions and the matrix products share
+    // the SIMD's issue), so the matrix cores stay fed while one scores
+    if constexpr (FUSE != 0) __builtin_amdgcn_s_setprio(1);
     if (slot >= n_tiles) break;
     const int64_t t = tile_begin + slot * stride;
     if (j < 0 || t < jlo || t >= jhi) {
@@ -705,6 +709,7 @@ __device__ __forceinline__ void count_perm_body(
     if (i >= j) continue;  // padding pivot of the last i-block: nothing to write
     if constexpr (FUSE != 0) {
       // the staging buffers are idle until the next tile's first store
+      __builtin_amdgcn_s_setprio(0);
       fused_score<FUSE>(pj, acc, sT16[wave], reinterpret_cast<uint32_t *>(stage + wave * 4096), st,
                         out, i, j, kbase, slot, wave, lane, kmin, kmax);
       continue;
